@@ -1,0 +1,27 @@
+"""Double-precision CPU oracle of the micro-DPD hot path.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The product path never imports
+this package.  See ``lhmm_oracle.c`` for what each function follows.
+"""
+from .oracle import (  # noqa: F401
+    ERR_ARG,
+    ERR_BOND,
+    ERR_CELL,
+    ERR_NONFINITE,
+    OracleBox,
+    build,
+    check_gradient,
+    expL,
+    forces,
+    lib,
+    max_threads,
+    pairs,
+    philox4x32_10,
+    reduce_cell,
+    run_batch,
+    run_box,
+    theta,
+    uniform23,
+    widths,
+)

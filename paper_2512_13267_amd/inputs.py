@@ -1,0 +1,291 @@
+"""Seeded synthetic workloads for the micro-DPD path.
+
+This module only draws inputs: initial particle states, box shapes, velocity
+gradients.  It holds none of the method's arithmetic and imports neither the
+HIP binding nor the oracle; both sides receive identical arrays from here.
+
+Every particle coordinate and velocity it returns is exactly representable
+in single precision, so a single-precision device state and a
+double-precision reference start from the same numbers.
+
+Workloads (the micro-box parameters are those of the polymer model of the
+micro-scale section, with the solvent/chain composition and the 3-D periodic
+box of the benchmark workloads):
+  * ``single_box``: one cubic box of edge 10 rc at number density 3
+    (3000 particles, 30 chains of 10 beads), simple shear at rate 0.1;
+  * ``batch``: 256 boxes of edge ~U(8, 16) rc at density 3 (1.5k-12k
+    particles), polymer fraction ~U(0.1, 0.3) in 10-bead chains, each with a
+    constant in-plane traceless gradient whose entries are ~U(-0.5, 0.5).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+SEED_BASE = 0x4C484D4D0000  # per-workload seeds are SEED_BASE + k
+
+
+def default_params(**over) -> dict:
+    """DPD/FENE parameters in reduced units (m = rc = kBT = 1)."""
+    p = dict(a=25.0, gamma=4.5, sigma=3.0, kBT=1.0, mass=1.0, rc=1.0, dt=0.01, H=30.0, R0=1.5,
+             chain_len=10, seed=SEED_BASE + 0)
+    p.update(over)
+    return p
+
+
+@dataclass
+class BoxInit:
+    """Initial state of one micro-box (float64 arrays holding float32 values)."""
+    s: np.ndarray          # N x 3 fractional coordinates in [0, 1)
+    c: np.ndarray          # N x 3 peculiar velocities
+    h: np.ndarray          # 3 x 3 cell, columns are lattice vectors (r = h s)
+    n_chains: int
+    L: np.ndarray          # 3 x 3 velocity gradient, u = L r
+    edge: float = 0.0
+    phi: float = 0.0
+
+    @property
+    def N(self) -> int:
+        return int(self.s.shape[0])
+
+
+@dataclass
+class Workload:
+    name: str
+    params: dict
+    boxes: List[BoxInit] = field(default_factory=list)
+    n_steps: int = 0
+
+    @property
+    def n_particles(self) -> int:
+        return sum(b.N for b in self.boxes)
+
+
+def _f32(x: np.ndarray) -> np.ndarray:
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def _wrap_f32(s: np.ndarray) -> np.ndarray:
+    s = s - np.floor(s)
+    s32 = s.astype(np.float32)
+    s32[s32 >= np.float32(1.0)] = np.float32(0.0)
+    s32[s32 < np.float32(0.0)] = np.float32(0.0)
+    return s32.astype(np.float64)
+
+
+def random_box(rng: np.random.Generator, h: np.ndarray, N: int, n_chains: int, chain_len: int,
+               kBT: float = 1.0, mass: float = 1.0, b0: float = 0.9) -> tuple:
+    """Random positions (chains first, as random walks of step b0), Maxwell
+    velocities with the mean removed.  Returns (s, c)."""
+    h = np.asarray(h, dtype=np.float64).reshape(3, 3)
+    hinv = np.linalg.inv(h)
+    s = rng.random((N, 3))
+    n_beads = n_chains * chain_len
+    if n_beads > N:
+        raise ValueError("more chain beads than particles")
+    for ch in range(n_chains):
+        base = ch * chain_len
+        r = h @ s[base]
+        for k in range(1, chain_len):
+            u = rng.normal(size=3)
+            u /= np.linalg.norm(u)
+            r = r + b0 * u
+            s[base + k] = hinv @ r
+    s = _wrap_f32(s)
+    c = rng.normal(scale=math.sqrt(kBT / mass), size=(N, 3))
+    c -= c.mean(axis=0, keepdims=True)
+    return s, _f32(c)
+
+
+def shear_gradient(rate: float) -> np.ndarray:
+    """Simple shear u_x = rate * y."""
+    L = np.zeros((3, 3))
+    L[0, 1] = rate
+    return L
+
+
+def planar_gradient(a: float, b: float, c: float) -> np.ndarray:
+    """In-plane traceless gradient [[a, b, 0], [c, -a, 0], [0, 0, 0]]."""
+    return np.array([[a, b, 0.0], [c, -a, 0.0], [0.0, 0.0, 0.0]])
+
+
+def cubic_cell(edge: float) -> np.ndarray:
+    return np.diag([edge, edge, edge]).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Box shapes that survive a constant hyperbolic gradient
+# ---------------------------------------------------------------------------
+
+def _lattice_min_width(B: np.ndarray, K: int = 12) -> float:
+    """Largest achievable minimum perpendicular width of the 2-D lattice with
+    basis columns B: area / (second successive minimum), found by
+    enumerating lattice vectors m b1 + n b2 with |m|, |n| <= K."""
+    area = abs(np.linalg.det(B))
+    m, n = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    m = m.ravel()
+    n = n.ravel()
+    keep = (m != 0) | (n != 0)
+    m, n = m[keep], n[keep]
+    V = np.outer(B[:, 0], m) + np.outer(B[:, 1], n)
+    lens = np.hypot(V[0], V[1])
+    order = np.argsort(lens, kind="stable")
+    v1 = V[:, order[0]]
+    for k in order[1:]:
+        v = V[:, k]
+        if abs(v1[0] * v[1] - v1[1] * v[0]) > 1e-9 * lens[order[0]] * lens[k]:
+            return area / lens[k]
+    return 0.0
+
+
+def _flow_map(L2: np.ndarray, t: float) -> np.ndarray:
+    from scipy.linalg import expm
+    return expm(L2 * t)
+
+
+def _min_width_over(L2: np.ndarray, B: np.ndarray, t_end: float, samples: int) -> float:
+    w = np.inf
+    for t in np.linspace(0.0, t_end, samples):
+        w = min(w, _lattice_min_width(_flow_map(L2, t) @ B))
+    return w
+
+
+def kr_cell(L: np.ndarray, edge: float, t_run: float, min_width: float = 3.5,
+            ratios: Optional[np.ndarray] = None) -> tuple:
+    """Initial in-plane lattice for a constant in-plane gradient L.
+
+    Returns (h0, kind) with kind "cubic" or "kr".  A cubic cell is kept when
+    its reduced lattice stays at least ``min_width`` wide over ``t_run``.
+    Otherwise, for a hyperbolic L (a^2 + bc > 0), the lattice is aligned in
+    the manner of Kraynik and Reinelt: its basis P satisfies
+    exp(L T) P = P M with M = [[2, 1], [1, 1]], so the flow maps the lattice
+    onto itself every period T = ln(mu)/k, mu = (3 + sqrt 5)/2.  Among the
+    one-parameter family P = V diag(d1, d2) W^-1 (V, W eigenvectors of L and
+    M) of area edge^2, the member whose minimum width over one period is
+    largest is chosen.  The z extent stays ``edge``."""
+    L2 = np.asarray(L, dtype=np.float64)[:2, :2]
+    cube = np.eye(2) * edge
+    w_cube = _min_width_over(L2, cube, t_run, 81)
+    if w_cube >= min_width:
+        return cubic_cell(edge), "cubic"
+    a, b, c = L2[0, 0], L2[0, 1], L2[1, 0]
+    k2 = a * a + b * c
+    if k2 <= 0.0:
+        return cubic_cell(edge), "cubic"
+    k = math.sqrt(k2)
+    evals, V = np.linalg.eig(L2)
+    V = np.real(V[:, np.argsort(-np.real(evals))])  # columns: +k, -k
+    mu = (3.0 + math.sqrt(5.0)) / 2.0
+    M = np.array([[2.0, 1.0], [1.0, 1.0]])
+    W = np.array([[1.0, 1.0], [mu - 2.0, 1.0 / mu - 2.0]])  # columns: mu, 1/mu
+    Winv = np.linalg.inv(W)
+    T = math.log(mu) / k
+    if ratios is None:
+        ratios = np.exp(np.linspace(-4.0, 4.0, 161))
+    best, bestP = -1.0, None
+    for sgn in (1.0, -1.0):
+        for r in ratios:
+            D = np.diag([r, sgn])
+            P = V @ D @ Winv
+            det = np.linalg.det(P)
+            if abs(det) < 1e-300:
+                continue
+            P = P * math.sqrt(edge * edge / abs(det))
+            if np.linalg.det(P) < 0:
+                P = P[:, ::-1].copy()
+            w = _min_width_over(L2, P, T, 33)
+            if w > best:
+                best, bestP = w, P
+    assert np.allclose(np.linalg.inv(bestP) @ _flow_map(L2, T) @ bestP,
+                       np.round(np.linalg.inv(bestP) @ _flow_map(L2, T) @ bestP), atol=1e-6)
+    h = np.zeros((3, 3))
+    h[:2, :2] = _short_basis(bestP)
+    h[2, 2] = edge
+    return h, "kr"
+
+
+def _short_basis(B: np.ndarray, K: int = 12) -> np.ndarray:
+    """The lattice's two successive minima (a reduced basis of the same 2-D
+    lattice), oriented with positive determinant."""
+    m, n = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
+    m = m.ravel()
+    n = n.ravel()
+    keep = (m != 0) | (n != 0)
+    m, n = m[keep], n[keep]
+    V = np.outer(B[:, 0], m) + np.outer(B[:, 1], n)
+    lens = np.hypot(V[0], V[1])
+    order = np.argsort(lens, kind="stable")
+    v1 = V[:, order[0]]
+    for k in order[1:]:
+        v2 = V[:, k]
+        cross = v1[0] * v2[1] - v1[1] * v2[0]
+        if abs(cross) > 1e-9 * lens[order[0]] * lens[k]:
+            if cross < 0:
+                v2 = -v2
+            out = np.stack([v1, v2], axis=1)
+            assert abs(abs(np.linalg.det(out)) - abs(np.linalg.det(B))) < 1e-9 * abs(np.linalg.det(B))
+            return out
+    raise ValueError("degenerate lattice")
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+
+def single_box(seed_k: int = 0, edge: float = 10.0, density: float = 3.0, polymer_fraction: float = 0.1,
+               shear_rate: float = 0.1, n_steps: int = 500, **param_over) -> Workload:
+    """One cubic box in simple shear (3000 particles, 30 chains at edge 10)."""
+    p = default_params(seed=SEED_BASE + seed_k, **param_over)
+    rng = np.random.default_rng(SEED_BASE + seed_k)
+    N = int(round(density * edge ** 3))
+    n_chains = int(round(polymer_fraction * N / p["chain_len"]))
+    h = cubic_cell(edge)
+    s, c = random_box(rng, h, N, n_chains, p["chain_len"], p["kBT"], p["mass"])
+    box = BoxInit(s=s, c=c, h=h, n_chains=n_chains, L=shear_gradient(shear_rate), edge=edge,
+                  phi=polymer_fraction)
+    return Workload("single_box", p, [box], n_steps)
+
+
+def batch(n_boxes: int = 256, seed_k: int = 1, edge_range=(8.0, 16.0), density: float = 3.0,
+          phi_range=(0.1, 0.3), grad_range: float = 0.5, n_steps: int = 2000, kr: bool = True,
+          **param_over) -> Workload:
+    """Boxes of uneven size, each under its own constant in-plane gradient."""
+    p = default_params(seed=SEED_BASE + seed_k, **param_over)
+    rng = np.random.default_rng(SEED_BASE + seed_k)
+    boxes = []
+    t_run = n_steps * p["dt"]
+    for _ in range(n_boxes):
+        edge = float(rng.uniform(*edge_range))
+        N = int(round(density * edge ** 3))
+        phi = float(rng.uniform(*phi_range))
+        n_chains = int(round(phi * N / p["chain_len"]))
+        a, b, c = rng.uniform(-grad_range, grad_range, size=3)
+        L = planar_gradient(a, b, c)
+        if kr:
+            h, _ = kr_cell(L, edge, t_run)
+        else:
+            h = cubic_cell(edge)
+        s, cc = random_box(rng, h, N, n_chains, p["chain_len"], p["kBT"], p["mass"])
+        boxes.append(BoxInit(s=s, c=cc, h=h, n_chains=n_chains, L=L, edge=edge, phi=phi))
+    return Workload("batch", p, boxes, n_steps)
+
+
+def tiny_boxes(n_boxes: int, seed_k: int = 7, edges=(4.2, 5.0, 6.3), density: float = 3.0,
+               phi: float = 0.2, grad_scale: float = 0.3, **param_over) -> Workload:
+    """Small ragged boxes for parity tests (sizes cycle through ``edges``)."""
+    p = default_params(seed=SEED_BASE + seed_k, **param_over)
+    rng = np.random.default_rng(SEED_BASE + seed_k)
+    boxes = []
+    for b in range(n_boxes):
+        edge = float(edges[b % len(edges)])
+        N = int(round(density * edge ** 3))
+        n_chains = int(round(phi * N / p["chain_len"]))
+        a, bb, c = rng.uniform(-grad_scale, grad_scale, size=3)
+        L = planar_gradient(a, bb, c)
+        h = cubic_cell(edge)
+        s, cc = random_box(rng, h, N, n_chains, p["chain_len"], p["kBT"], p["mass"])
+        boxes.append(BoxInit(s=s, c=cc, h=h, n_chains=n_chains, L=L, edge=edge, phi=phi))
+    return Workload("tiny_boxes", p, boxes, 0)
