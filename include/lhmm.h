@@ -1,0 +1,187 @@
+/*
+ * lhmm.h -- C ABI of the MI355X (gfx950) micro-DPD engine of the Lagrangian
+ * Heterogeneous Multiscale Method (LHMM, DPD-SPH).
+ *
+ * The engine advances many independent periodic micro-boxes, one per SPH
+ * macro particle.  Each box holds DPD solvent and FENE bead-spring chains;
+ * each is driven by its particle's velocity gradient and returns the
+ * Irving-Kirkwood stress averaged over the exchange interval:
+ *   - pair forces: conservative, dissipative and random forces of the
+ *     micro-scale model (paper Sec. "Microscale: Polymer Melt Model -- DPD
+ *     and FENE", Eqs. F_DPD, conservative, dissipative, random) with
+ *     w^D = (w^R)^2, w^R = 1 - r/rc, sigma^2 = 2 gamma kBT and the discrete
+ *     random force scaled by 1/sqrt(dt);
+ *   - bonds: attractive FENE springs (Eq. fene_force);
+ *   - integration: velocity-Verlet of Eq. (motion) (Appendix "Detailed
+ *     Coupling Protocol", Step 3) in a periodic cell deformed by the imposed
+ *     gradient, dh/dt = L h, with peculiar velocities c = v - L r;
+ *   - imposed flow: the macro-to-micro coupling of Eq. (micro_bc), v = L r,
+ *     applied homogeneously through the deforming cell (Lees-Edwards for
+ *     simple shear);
+ *   - stress: Eqs. (IKtotal), (kinetic_stress), (potential_stress); with a
+ *     uniform weight over the periodic cell the Irving-Kirkwood stress is the
+ *     virial stress  sigma = -(sum m c (x) c + sum_pairs d (x) f) / V,
+ *     tension positive, averaged over the steps of the exchange interval
+ *     (Sec. "Micro-to-macro Coupling");
+ *   - micro boxes persist between calls (continuous-intermittent coupling,
+ *     Sec. "Temporal Coupling Scheme").
+ *
+ * Conventions
+ *   - Matrices are 3x3 row-major doubles.  A cell h has the lattice vectors
+ *     as columns (r = h s, s in [0,1)^3).  A velocity gradient L maps
+ *     position to streaming velocity, u = L r; it must be in-plane (zero
+ *     z row and column) and traceless.  Simple shear u_x = g y is L[1] = g.
+ *   - Stress vectors are (xx, yy, zz, xy, xz, yz).
+ *   - Particles of all boxes are concatenated in box order; inside a box,
+ *     particle k has id k; ids 0 .. n_chains*chain_len-1 form chains of
+ *     chain_len consecutive ids, the rest are solvent.
+ *   - Every function returns LHMM_OK (0) or a negative LHMM_ERR_* code and
+ *     never aborts; lhmm_last_error() returns a thread-local message.
+ *   - Per-box physics flags (LHMM_FLAG_*) are sticky and are read with
+ *     lhmm_micro_flags; a flagged box does not stop the batch.
+ *   - The engine owns all device memory it allocates.  Pointer arguments
+ *     are borrowed for the duration of the call.  Which arguments are host
+ *     and which are device pointers is stated per function.
+ *   - Device work runs on a stream the engine creates (default priority).
+ *     Calls taking device pointers are ordered after prior work on the
+ *     caller's stream and make the caller's stream wait for their results.
+ */
+#ifndef LHMM_H
+#define LHMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LHMM_OK 0
+#define LHMM_ERR_ARG (-1)   /* invalid argument (shape, range, NaN, null)   */
+#define LHMM_ERR_HIP (-2)   /* a HIP runtime call failed                     */
+#define LHMM_ERR_OOM (-3)   /* device or host allocation failed              */
+#define LHMM_ERR_STATE (-4) /* call out of order (e.g. step before state)    */
+
+#define LHMM_FLAG_BOND 1u      /* a bond reached r >= R0 (force clamped)    */
+#define LHMM_FLAG_CELL 2u      /* a cell width fell below 3 rc              */
+#define LHMM_FLAG_NONFINITE 4u /* a stress sample was not finite            */
+#define LHMM_FLAG_ARG 8u       /* the box's gradient was rejected (L := 0)  */
+
+#define LHMM_FP32 0 /* single-precision particle state and pair forces     */
+#define LHMM_FP64 1 /* double-precision particle state and pair forces     */
+
+#define LHMM_OPT_NO_GRAPH 1 /* launch every kernel eagerly (no HIP graphs) */
+
+typedef struct lhmm_micro lhmm_micro;
+
+/* Model parameters, shared by every box (reduced units m = rc = kBT = 1 in
+ * the paper's Table "DPD and FENE simulation parameters"). */
+typedef struct {
+    double a;        /* conservative amplitude a_ij                          */
+    double gamma;    /* dissipative amplitude gamma^D                        */
+    double sigma;    /* random amplitude sigma^R (= sqrt(2 gamma kBT))       */
+    double kBT;      /* thermal energy                                       */
+    double mass;     /* bead mass                                            */
+    double rc;       /* cutoff radius                                        */
+    double dt;       /* micro time step                                      */
+    double H;        /* FENE spring constant                                 */
+    double R0;       /* FENE maximum extension                               */
+    uint64_t seed;   /* key of the counter-based random stream               */
+    int32_t chain_len;  /* beads per chain N_d (>= 2)                        */
+    int32_t precision;  /* LHMM_FP32 or LHMM_FP64                            */
+    int32_t flags;      /* LHMM_OPT_* bits                                   */
+} lhmm_params;
+
+/* One micro-box. */
+typedef struct {
+    int32_t n_particles; /* >= 2                                             */
+    int32_t n_chains;    /* n_chains * chain_len <= n_particles              */
+    uint32_t rng_id;     /* box word of the random-force counter, usually the */
+                         /* SPH particle index; equal ids draw equal noise    */
+    int32_t reserved;    /* must be 0                                         */
+    double h0[9];        /* initial cell; in-plane basis in columns 0-1, z   */
+                         /* extent h0[8] > 0, zero z coupling, det > 0        */
+} lhmm_box;
+
+/* Allocate an engine for n_boxes boxes.  p, boxes: host.  stream: the
+ * caller's hipStream_t (may be NULL for the null stream).  The particle
+ * state is undefined until lhmm_micro_set_state.  Errors: ARG, HIP, OOM. */
+int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_boxes, void* stream,
+                      lhmm_micro** out);
+
+/* Load the particle state of every box.  s, c: host, n_total x 3 doubles
+ * (row per particle, boxes concatenated): fractional coordinates in [0,1)
+ * and peculiar velocities.  f: host n_total x 3, the forces the next step
+ * starts from (as returned by lhmm_micro_get_state, for an exact resume),
+ * or NULL to recompute them at the next step call with that call's
+ * gradient.  h: host, n_boxes x 9, current cells (NULL keeps the cells).
+ * step: completed steps (the random-force counter).  Values are rounded to
+ * the engine's precision.  Synchronous.  Errors: ARG (NaN, s outside [0,1),
+ * bad cell). */
+int lhmm_micro_set_state(lhmm_micro* m, const double* s, const double* c, const double* f, const double* h,
+                         uint64_t step);
+
+/* Read the particle state back.  s, c, f: host n_total x 3 (f: the forces
+ * carried into the next step); h: host n_boxes x 9; step: host.  Any of
+ * them may be NULL.  Synchronous. */
+int lhmm_micro_get_state(lhmm_micro* m, double* s, double* c, double* f, double* h, uint64_t* step);
+
+/* Advance every box by n_steps velocity-Verlet steps under its own constant
+ * gradient and write the mean stress over those steps.
+ *   gradL: DEVICE pointer, n_boxes x 9 doubles (u = L r per box);
+ *   stress_out: DEVICE pointer, n_boxes x 6 doubles.
+ * A gradient that is not finite, in-plane and traceless sets LHMM_FLAG_ARG
+ * on its box, which then advances with L = 0.  Asynchronous with respect to
+ * the host; ordered on the caller's stream.  Errors: ARG (n_steps <= 0),
+ * STATE (no state loaded), HIP. */
+int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double* stress_out);
+
+/* Forces at the current state with random-force counter = current step,
+ * without advancing: f_out host n_total x 3; virial_out host n_boxes x 12
+ * (sum over pairs of d (x) f for the DPD pairs, then for the FENE bonds,
+ * each xx,yy,zz,xy,xz,yz; may be NULL).  gradL: host n_boxes x 9.
+ * Synchronous.  Errors: ARG, STATE, HIP. */
+int lhmm_micro_forces(lhmm_micro* m, const double* gradL, double* f_out, double* virial_out);
+
+/* Mean stress parts of the last lhmm_micro_step call: host n_boxes x 3 x 6
+ * (kinetic, DPD pairs, FENE bonds; their sum is the stress).  Synchronous. */
+int lhmm_micro_stress_parts(lhmm_micro* m, double* parts_out);
+
+/* Unordered DPD pairs within the cutoff, summed over the steps of the last
+ * lhmm_micro_step call: host n_boxes uint64.  Synchronous. */
+int lhmm_micro_pair_counts(lhmm_micro* m, uint64_t* pairs_out);
+
+/* Sticky physics flags per box: host n_boxes uint32 (LHMM_FLAG_*).
+ * clear != 0 resets them after reading.  Synchronous. */
+int lhmm_micro_flags(lhmm_micro* m, uint32_t* flags_out, int32_t clear);
+
+/* Kernels of one micro step, in launch order (indices of lhmm_micro_time). */
+#define LHMM_K_CELL 0       /* cell deformation, reduction, grid (per box)   */
+#define LHMM_K_KICK_DRIFT 1 /* half kick, drift, wrap, cell index            */
+#define LHMM_K_BIN 2        /* counting sort by cell (per box)               */
+#define LHMM_K_FORCES 3     /* DPD pair forces, FENE bonds, virial           */
+#define LHMM_K_KICK2 4      /* second half kick, kinetic stress              */
+#define LHMM_K_STRESS 5     /* per-box stress of the step, accumulation      */
+#define LHMM_N_KERNELS 6
+
+/* Advance like lhmm_micro_step (same kernels, grids and state update) but
+ * launch eagerly with a HIP event pair around every kernel on the engine's
+ * stream, and return each kernel's mean duration in milliseconds.
+ *   gradL: DEVICE pointer n_boxes x 9; avg_ms: host LHMM_N_KERNELS doubles;
+ *   stress_out: DEVICE pointer n_boxes x 6 (may be NULL).
+ * Synchronous.  Errors: ARG, STATE, HIP. */
+int lhmm_micro_time(lhmm_micro* m, const double* gradL, int32_t n_steps, double* avg_ms, double* stress_out);
+
+/* Sizes: total particles and boxes.  Host pointers, may be NULL. */
+int lhmm_micro_sizes(const lhmm_micro* m, int64_t* n_total, int32_t* n_boxes);
+
+/* Release every resource of the engine (waits for its stream).  NULL ok. */
+int lhmm_micro_destroy(lhmm_micro* m);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lhmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LHMM_H */

@@ -392,7 +392,7 @@ long oracle_pairs(int N, const double *s, const double h[9], double rc, int mode
  * to brute force when the grid has fewer than 3 cells along an axis). */
 int oracle_forces(const double *P, uint64_t seed, int chain_len, uint32_t box, int N, int n_chains,
                   const double *s, const double *c, const double h[9], const double L[9], uint32_t step,
-                  double *F, double W[24], uint32_t *err, int mode)
+                  double *F, double W[24], uint32_t *err, int mode, long long *npairs)
 {
     const double a = P[P_A], gamma = P[P_GAMMA], sigma = P[P_SIGMA], rc = P[P_RC], dt = P[P_DT];
     const double Hf = P[P_H], R0 = P[P_R0];
@@ -405,6 +405,7 @@ int oracle_forces(const double *P, uint64_t seed, int chain_len, uint32_t box, i
         pl.n = 0;
         pairs_brute(N, s, h, rc, &pl);
     }
+    if (npairs) *npairs += pl.n;
     for (long q = 0; q < pl.n; ++q) {
         int i = pl.p[q].i, j = pl.p[q].j;
         const double *d = pl.p[q].d;
@@ -489,7 +490,7 @@ static void wrap01(double *x)
 int oracle_run_box(const double *P, uint64_t seed, int chain_len, uint32_t box, int N, int n_chains,
                    double *s, double *c, double *F, int *fvalid, double h[9], uint64_t *step,
                    const double L[9], int nsteps, double *stress_mean, double *parts_mean, double *series,
-                   uint32_t *err, int mode)
+                   uint32_t *err, int mode, long long *npairs)
 {
     const double m = P[P_MASS], dt = P[P_DT], rc = P[P_RC];
     double W[24];
@@ -498,7 +499,7 @@ int oracle_run_box(const double *P, uint64_t seed, int chain_len, uint32_t box, 
         return -1;
     }
     if (!*fvalid) {
-        oracle_forces(P, seed, chain_len, box, N, n_chains, s, c, h, L, (uint32_t)*step, F, W, err, mode);
+        oracle_forces(P, seed, chain_len, box, N, n_chains, s, c, h, L, (uint32_t)*step, F, W, err, mode, NULL);
         *fvalid = 1;
     }
     double E[9], Eh[9];
@@ -540,7 +541,8 @@ int oracle_run_box(const double *P, uint64_t seed, int chain_len, uint32_t box, 
         oracle_widths(h, w);
         if (w[0] < 3.0 * rc || w[1] < 3.0 * rc || w[2] < 3.0 * rc) *err |= ORACLE_ERR_CELL;
 
-        oracle_forces(P, seed, chain_len, box, N, n_chains, s, c, h, L, (uint32_t)*step, F, W, err, mode);
+        oracle_forces(P, seed, chain_len, box, N, n_chains, s, c, h, L, (uint32_t)*step, F, W, err, mode,
+                      npairs);
 
         /* second half kick */
         for (int i = 0; i < N; ++i) {
@@ -581,7 +583,7 @@ int oracle_run_box(const double *P, uint64_t seed, int chain_len, uint32_t box, 
 int oracle_run_batch(const double *P, uint64_t seed, int chain_len, int n_boxes, const int *off,
                      const int *n_chains, const uint32_t *box_ids, double *s, double *c, double *F,
                      int *fvalid, double *h, uint64_t *step, const double *L, int nsteps,
-                     double *stress_mean, double *parts_mean, uint32_t *err, int mode)
+                     double *stress_mean, double *parts_mean, uint32_t *err, int mode, long long *npairs)
 {
     int status = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : status)
@@ -590,7 +592,8 @@ int oracle_run_batch(const double *P, uint64_t seed, int chain_len, int n_boxes,
         int rc = oracle_run_box(P, seed, chain_len, box_ids[b], N, n_chains[b], s + 3 * (long)o,
                                 c + 3 * (long)o, F + 3 * (long)o, &fvalid[b], h + 9 * b, &step[b],
                                 L + 9 * b, nsteps, stress_mean ? stress_mean + 6 * b : NULL,
-                                parts_mean ? parts_mean + 30 * b : NULL, NULL, &err[b], mode);
+                                parts_mean ? parts_mean + 30 * b : NULL, NULL, &err[b], mode,
+                                npairs ? &npairs[b] : NULL);
         if (rc != 0) status = 1;
     }
     return status ? -1 : 0;

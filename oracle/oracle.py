@@ -62,13 +62,14 @@ def lib():
         L.oracle_pairs.argtypes = [C.c_int, dp, dp, C.c_double, C.c_int, ip, dp, C.c_long]
         L.oracle_pairs.restype = C.c_long
         L.oracle_forces.argtypes = [dp, C.c_uint64, C.c_int, C.c_uint32, C.c_int, C.c_int, dp, dp, dp,
-                                    dp, C.c_uint32, dp, dp, up, C.c_int]
+                                    dp, C.c_uint32, dp, dp, up, C.c_int, C.POINTER(C.c_longlong)]
         L.oracle_forces.restype = C.c_int
         L.oracle_run_box.argtypes = [dp, C.c_uint64, C.c_int, C.c_uint32, C.c_int, C.c_int, dp, dp, dp,
-                                     ip, dp, u64p, dp, C.c_int, dp, dp, dp, up, C.c_int]
+                                     ip, dp, u64p, dp, C.c_int, dp, dp, dp, up, C.c_int,
+                                     C.POINTER(C.c_longlong)]
         L.oracle_run_box.restype = C.c_int
         L.oracle_run_batch.argtypes = [dp, C.c_uint64, C.c_int, C.c_int, ip, ip, up, dp, dp, dp, ip, dp,
-                                       u64p, dp, C.c_int, dp, dp, up, C.c_int]
+                                       u64p, dp, C.c_int, dp, dp, up, C.c_int, C.POINTER(C.c_longlong)]
         L.oracle_run_batch.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
         _lib = L
@@ -168,7 +169,7 @@ def forces(p, seed, chain_len, box, n_chains, s, c, h, L, step, mode=1):
     W = np.zeros(24)
     err = np.zeros(1, dtype=np.uint32)
     lib().oracle_forces(_d(P), int(seed), int(chain_len), int(box), N, int(n_chains), _d(s), _d(c),
-                        _d(_f64(h, (9,))), _d(_f64(L, (9,))), int(step), _d(F), _d(W), _u(err), int(mode))
+                        _d(_f64(h, (9,))), _d(_f64(L, (9,))), int(step), _d(F), _d(W), _u(err), int(mode), None)
     return F, W.reshape(4, 6), int(err[0])
 
 
@@ -206,7 +207,8 @@ def run_box(p, seed, chain_len, box: OracleBox, L, nsteps, mode=1, series=False)
     ser = np.zeros(6 * nsteps) if series else None
     rc = lib().oracle_run_box(_d(P), int(seed), int(chain_len), int(box.box_id), N, int(box.n_chains),
                               _d(box.s), _d(box.c), _d(box.F), _i(fv), _d(h), _u64(st), _d(_f64(L, (9,))),
-                              int(nsteps), _d(mean), _d(parts), _d(ser) if series else None, _u(err), int(mode))
+                              int(nsteps), _d(mean), _d(parts), _d(ser) if series else None, _u(err), int(mode),
+                              None)
     box.h = h.reshape(3, 3)
     box.fvalid = int(fv[0])
     box.step = int(st[0])
@@ -216,8 +218,9 @@ def run_box(p, seed, chain_len, box: OracleBox, L, nsteps, mode=1, series=False)
     return mean, parts.reshape(5, 6), (ser.reshape(nsteps, 6) if series else None)
 
 
-def run_batch(p, seed, chain_len, boxes, Ls, nsteps, mode=1):
-    """Advance a list of OracleBox in one OpenMP call; returns (means (B,6), parts (B,5,6))."""
+def run_batch(p, seed, chain_len, boxes, Ls, nsteps, mode=1, count_pairs=False):
+    """Advance a list of OracleBox in one OpenMP call; returns (means (B,6),
+    parts (B,5,6)) and, with count_pairs, the pairs evaluated per box."""
     P = params_vector(p)
     B = len(boxes)
     off = np.zeros(B + 1, dtype=np.int32)
@@ -238,9 +241,10 @@ def run_batch(p, seed, chain_len, boxes, Ls, nsteps, mode=1):
     Lv = np.ascontiguousarray(_f64(Ls).reshape(B, 9))
     mean = np.zeros((B, 6))
     parts = np.zeros((B, 30))
+    npairs = np.zeros(B, dtype=np.int64)
     rc = lib().oracle_run_batch(_d(P), int(seed), int(chain_len), B, _i(off), _i(nch), _u(ids), _d(s), _d(c),
                                 _d(F), _i(fv), _d(h), _u64(st), _d(Lv), int(nsteps), _d(mean), _d(parts),
-                                _u(err), int(mode))
+                                _u(err), int(mode), npairs.ctypes.data_as(C.POINTER(C.c_longlong)))
     for b, bx in enumerate(boxes):
         bx.s = s[off[b]:off[b + 1]].copy()
         bx.c = c[off[b]:off[b + 1]].copy()
@@ -251,6 +255,8 @@ def run_batch(p, seed, chain_len, boxes, Ls, nsteps, mode=1):
         bx.err = int(err[b])
     if rc != 0:
         raise ValueError("oracle_run_batch rejected its arguments")
+    if count_pairs:
+        return mean, parts.reshape(B, 5, 6), npairs
     return mean, parts.reshape(B, 5, 6)
 
 

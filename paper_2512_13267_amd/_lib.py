@@ -1,0 +1,90 @@
+"""Loading of the in-tree HIP library (liblhmm.so) and its C signatures.
+
+The library is built by ``paper_2512_13267_amd.build`` (hipcc, gfx950).  There
+is no fallback: if the library is missing or fails to load, every entry point
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblhmm.so")
+
+LHMM_OK = 0
+LHMM_ERR_ARG = -1
+LHMM_ERR_HIP = -2
+LHMM_ERR_OOM = -3
+LHMM_ERR_STATE = -4
+
+FLAG_BOND = 1
+FLAG_CELL = 2
+FLAG_NONFINITE = 4
+FLAG_ARG = 8
+
+FP32 = 0
+FP64 = 1
+OPT_NO_GRAPH = 1
+
+# every symbol include/lhmm.h declares
+EXPORTS = (
+    "lhmm_micro_create", "lhmm_micro_set_state", "lhmm_micro_get_state", "lhmm_micro_step",
+    "lhmm_micro_forces", "lhmm_micro_stress_parts", "lhmm_micro_pair_counts", "lhmm_micro_flags",
+    "lhmm_micro_sizes", "lhmm_micro_destroy", "lhmm_last_error", "lhmm_micro_time",
+)
+KERNEL_NAMES = ("cell_step", "kick_drift", "bin_box", "forces", "kick2", "box_stress")
+
+
+class LhmmParams(C.Structure):
+    _fields_ = [("a", C.c_double), ("gamma", C.c_double), ("sigma", C.c_double), ("kBT", C.c_double),
+                ("mass", C.c_double), ("rc", C.c_double), ("dt", C.c_double), ("H", C.c_double),
+                ("R0", C.c_double), ("seed", C.c_uint64), ("chain_len", C.c_int32),
+                ("precision", C.c_int32), ("flags", C.c_int32)]
+
+
+class LhmmBox(C.Structure):
+    _fields_ = [("n_particles", C.c_int32), ("n_chains", C.c_int32), ("rng_id", C.c_uint32),
+                ("reserved", C.c_int32), ("h0", C.c_double * 9)]
+
+
+class LhmmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lhmm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2512_13267_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, u64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)
+        L.lhmm_micro_create.argtypes = [C.POINTER(LhmmParams), C.POINTER(LhmmBox), C.c_int32, vp, C.POINTER(vp)]
+        L.lhmm_micro_set_state.argtypes = [vp, dp, dp, dp, dp, C.c_uint64]
+        L.lhmm_micro_get_state.argtypes = [vp, dp, dp, dp, dp, u64p]
+        L.lhmm_micro_step.argtypes = [vp, vp, C.c_int32, vp]
+        L.lhmm_micro_forces.argtypes = [vp, dp, dp, dp]
+        L.lhmm_micro_stress_parts.argtypes = [vp, dp]
+        L.lhmm_micro_pair_counts.argtypes = [vp, u64p]
+        L.lhmm_micro_flags.argtypes = [vp, C.POINTER(C.c_uint32), C.c_int32]
+        L.lhmm_micro_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+        L.lhmm_micro_destroy.argtypes = [vp]
+        L.lhmm_micro_time.argtypes = [vp, vp, C.c_int32, dp, vp]
+        L.lhmm_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "lhmm_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(code: int) -> None:
+    if code != LHMM_OK:
+        msg = lib().lhmm_last_error().decode(errors="replace")
+        raise LhmmError(code, msg)

@@ -1,0 +1,1240 @@
+// lhmm_micro.hip -- gfx950 kernels and runtime of the batched micro-DPD
+// engine behind include/lhmm.h.
+//
+// One step of every box (velocity-Verlet of the micro-scale equation of
+// motion, Eq. motion, in a periodic cell deformed by the box's velocity
+// gradient; Appendix "Detailed Coupling Protocol", Step 3) is six launches
+// over a flattened index of all boxes:
+//   k_cell_step    one thread per box, FP64: mid-step cell inverse, cell
+//                  deformation h <- exp(L dt) h, Lagrange-Gauss reduction of
+//                  the in-plane basis, cell-grid size, width guard;
+//   k_kick_drift   per particle: half kick c += dt/2 (F/m - L c), drift of
+//                  the fractional coordinate with the mid-step cell, remap
+//                  by the reduction, wrap, cell index;
+//   k_bin_box      one workgroup per box: counting sort of the particles by
+//                  cell in LDS (histogram, scan, scatter), then each cell's
+//                  list sorted by id so every sum has a fixed order;
+//   k_forces       per particle: conservative + dissipative + random pair
+//                  forces (Eqs. conservative, dissipative, random) over the
+//                  27 neighbour cells, FENE springs (Eq. fene_force), and the
+//                  block's virial partial sums in FP64;
+//   k_kick2        per particle: second half kick, kinetic partial sums;
+//   k_box_stress   one thread per box: virial stress of the step (Eqs.
+//                  IKtotal, kinetic_stress, potential_stress with a uniform
+//                  weight over the cell), accumulated over the call.
+// The per-particle kernels run over work blocks of BS particles; a block
+// never straddles two boxes, so per-box quantities are uniform in a block
+// and reductions stay deterministic.  The step loop is captured in HIP
+// graphs.  Particle state is single or double precision (template
+// parameter); cells, gradients and stress sums are always double.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lhmm.h"
+
+namespace {
+
+constexpr int BS = 256;                 // particles per work block
+constexpr int BIN_THREADS = 1024;       // threads of the per-box binning workgroup
+constexpr int MAX_CELLS_PER_BOX = 15360;  // LDS histogram capacity (60 KiB)
+constexpr int GRAPH_CHUNK = 50;         // steps per captured graph
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) return fail(LHMM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct BoxInfo {
+    int off;       // first particle (global index)
+    int n;         // particles
+    int n_beads;   // n_chains * chain_len
+    int cell_off;  // first slot in cell_start (cap + 1 slots per box)
+    int cell_cap;  // cell capacity
+    int blk_off;   // first work block
+    int nblk;      // work blocks
+    unsigned rng_id;  // box word of the random-force counter
+};
+
+struct BoxDyn {  // per-box FP64 state, rewritten every step
+    double h[9];
+    double L[9];
+    double E[9];
+    double Eh[9];
+    double hmi[9];  // inverse of the mid-step cell
+    double vol;
+    int U[4];       // in-plane reduction of this step, h_new = h U
+    int nc[3];      // cell grid of this step
+    int changed;
+};
+
+struct Ctx {
+    int n_total, n_boxes, n_blocks, chain_len;
+    const BoxInfo* box;
+    BoxDyn* dyn;
+    unsigned* flags;
+    const int* blk_box;
+    const int* blk_first;
+    void* s;  // SoA: component k of particle i at [k * n_total + i]
+    void* c;
+    void* f;
+    int* pcell;
+    int* cell_start;
+    int* cell_list;
+    double* part_vir;   // n_blocks x 12: pair virial (ordered pairs), FENE virial
+    double* part_kin;   // n_blocks x 6
+    unsigned* part_pairs;  // n_blocks: ordered pairs within the cutoff
+    double* acc;        // n_boxes x 18: kinetic, pair, FENE stress sums
+    unsigned long long* acc_pairs;  // n_boxes
+    unsigned long long* step;       // completed steps
+    double a, gamma, sigma, rdt, dt, mass, inv_mass, rc, rc2, H, inv_R02;
+    unsigned key0, key1;
+};
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed
+// by the seed, counter (min id, max id, step, box); a Box-Muller normal from
+// the top 23 bits of the first two output words.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void philox4x32_10(unsigned& x0, unsigned& x1, unsigned& x2, unsigned& x3,
+                                              unsigned k0, unsigned k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const unsigned long long p0 = (unsigned long long)0xD2511F53u * x0;
+        const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * x2;
+        const unsigned y0 = (unsigned)(p1 >> 32) ^ x1 ^ k0;
+        const unsigned y2 = (unsigned)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (unsigned)p1;
+        x3 = (unsigned)p0;
+        x0 = y0;
+        x2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+template <typename real>
+__device__ __forceinline__ real box_muller(unsigned w0, unsigned w1);
+
+template <>
+__device__ __forceinline__ float box_muller<float>(unsigned w0, unsigned w1) {
+    const float u0 = ((float)(w0 >> 9) + 0.5f) * 1.1920928955078125e-07f;  // 2^-23
+    const float u1 = ((float)(w1 >> 9) + 0.5f) * 1.1920928955078125e-07f;
+    // v_log_f32 is log2; v_cos_f32 takes its argument in revolutions
+    const float r = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));  // -2 ln u0
+    return r * __builtin_amdgcn_cosf(u1);
+}
+
+template <>
+__device__ __forceinline__ double box_muller<double>(unsigned w0, unsigned w1) {
+    const double u0 = ((double)(w0 >> 9) + 0.5) * 1.1920928955078125e-07;
+    const double u1 = ((double)(w1 >> 9) + 0.5) * 1.1920928955078125e-07;
+    return sqrt(-2.0 * log(u0)) * cos(2.0 * M_PI * u1);
+}
+
+template <typename real>
+__device__ __forceinline__ real pair_theta(unsigned id_i, unsigned id_j, unsigned step, unsigned box,
+                                           unsigned k0, unsigned k1) {
+    unsigned x0 = min(id_i, id_j), x1 = max(id_i, id_j), x2 = step, x3 = box;
+    philox4x32_10(x0, x1, x2, x3, k0, k1);
+    return box_muller<real>(x0, x1);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 cell algebra (row-major 3x3; columns are lattice vectors)
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline void m3_mul(const double* A, const double* B, double* C) {
+    double T[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            T[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+    for (int k = 0; k < 9; ++k) C[k] = T[k];
+}
+
+__host__ __device__ inline double m3_det(const double* A) {
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+__host__ __device__ inline void m3_inv(const double* A, double* B) {
+    const double id = 1.0 / m3_det(A);
+    double T[9];
+    T[0] = (A[4] * A[8] - A[5] * A[7]) * id;
+    T[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+    T[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+    T[3] = (A[5] * A[6] - A[3] * A[8]) * id;
+    T[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+    T[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+    T[6] = (A[3] * A[7] - A[4] * A[6]) * id;
+    T[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+    T[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+    for (int k = 0; k < 9; ++k) B[k] = T[k];
+}
+
+// perpendicular widths w_a = V / |h_b x h_c|
+__host__ __device__ inline void m3_widths(const double* h, double* w) {
+    const double V = fabs(m3_det(h));
+    for (int a = 0; a < 3; ++a) {
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        const double ux = h[b], uy = h[3 + b], uz = h[6 + b];
+        const double vx = h[c], vy = h[3 + c], vz = h[6 + c];
+        const double x = uy * vz - uz * vy, y = uz * vx - ux * vz, z = ux * vy - uy * vx;
+        w[a] = V / sqrt(x * x + y * y + z * z);
+    }
+}
+
+// Is L finite, in-plane and traceless?
+__host__ __device__ inline bool gradient_ok(const double* L) {
+    double scale = 1.0;
+    for (int k = 0; k < 9; ++k) {
+        if (!(fabs(L[k]) <= 1e300)) return false;
+        scale += fabs(L[k]);
+    }
+    if (L[2] != 0.0 || L[5] != 0.0 || L[6] != 0.0 || L[7] != 0.0 || L[8] != 0.0) return false;
+    return fabs(L[0] + L[4]) <= 1e-12 * scale;
+}
+
+// exp(L tau) for in-plane traceless L: in the plane L^2 = k^2 I, k^2 = a^2 + bc,
+// so exp(L tau) = f0 I + f1 L with (cosh, sinh/k), (cos, sin/w) or (1, tau).
+__host__ __device__ inline void expm_planar(const double* L, double tau, double* E) {
+    const double a = 0.5 * (L[0] - L[4]), b = L[1], c = L[3];
+    const double k2 = a * a + b * c;
+    double f0, f1;
+    if (k2 > 0.0) {
+        const double k = sqrt(k2);
+        f0 = cosh(k * tau);
+        f1 = sinh(k * tau) / k;
+    } else if (k2 < 0.0) {
+        const double w = sqrt(-k2);
+        f0 = cos(w * tau);
+        f1 = sin(w * tau) / w;
+    } else {
+        f0 = 1.0;
+        f1 = tau;
+    }
+    E[0] = f0 + f1 * a; E[1] = f1 * b;      E[2] = 0.0;
+    E[3] = f1 * c;      E[4] = f0 - f1 * a; E[5] = 0.0;
+    E[6] = 0.0;         E[7] = 0.0;         E[8] = 1.0;
+}
+
+// Lagrange-Gauss reduction of the in-plane basis (columns 0 and 1 of h);
+// swaps as (b1, b2) -> (b2, -b1), size reductions b2 -= m b1 with
+// m = floor(mu + 1/2).  U accumulates h_new = h U (det U = +1).
+__host__ __device__ inline int reduce_planar(double* h, int* U) {
+    double b1x = h[0], b1y = h[3], b2x = h[1], b2y = h[4];
+    long long u00 = 1, u01 = 0, u10 = 0, u11 = 1;
+    int changed = 0;
+    for (int it = 0; it < 256; ++it) {
+        const double n1 = b1x * b1x + b1y * b1y, n2 = b2x * b2x + b2y * b2y;
+        if (n2 < n1) {
+            const double tx = b1x, ty = b1y;
+            b1x = b2x; b1y = b2y;
+            b2x = -tx; b2y = -ty;
+            const long long a0 = u01, a1 = -u00, c0 = u11, c1 = -u10;
+            u00 = a0; u01 = a1; u10 = c0; u11 = c1;
+            changed = 1;
+            continue;
+        }
+        const long long m = (long long)floor((b1x * b2x + b1y * b2y) / n1 + 0.5);
+        if (m == 0) break;
+        b2x -= (double)m * b1x;
+        b2y -= (double)m * b1y;
+        u01 -= m * u00;
+        u11 -= m * u10;
+        changed = 1;
+    }
+    h[0] = b1x; h[3] = b1y; h[1] = b2x; h[4] = b2y;
+    U[0] = (int)u00; U[1] = (int)u01; U[2] = (int)u10; U[3] = (int)u11;
+    return changed;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+
+// Sum NV doubles over the workgroup (BS threads); thread 0 returns the sums.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* NV * (BS/64) */) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[wv * NV + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double t = 0.0;
+            for (int w = 0; w < BS / 64; ++w) t += sh[w * NV + k];
+            v[k] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Per call: take each box's gradient (device array n_boxes x 9), validate,
+// and form exp(L dt), exp(L dt/2).
+__global__ void k_setup_call(Ctx C, const double* __restrict__ gradL) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= C.n_boxes) return;
+    BoxDyn& D = C.dyn[b];
+    double L[9];
+    for (int k = 0; k < 9; ++k) L[k] = gradL[9 * b + k];
+    if (!gradient_ok(L)) {
+        for (int k = 0; k < 9; ++k) L[k] = 0.0;
+        C.flags[b] |= LHMM_FLAG_ARG;
+    }
+    for (int k = 0; k < 9; ++k) D.L[k] = L[k];
+    expm_planar(L, C.dt, D.E);
+    expm_planar(L, 0.5 * C.dt, D.Eh);
+}
+
+__global__ void k_zero_acc(Ctx C) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 18 * C.n_boxes) C.acc[t] = 0.0;
+    if (t < C.n_boxes) C.acc_pairs[t] = 0ull;
+}
+
+// One thread per box.  advance = 1: mid-step inverse, deformation and
+// reduction of this step; advance = 0: grid for the current cell only.
+__global__ void k_cell_step(Ctx C, int advance) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= C.n_boxes) return;
+    BoxDyn& D = C.dyn[b];
+    double h[9];
+    for (int k = 0; k < 9; ++k) h[k] = D.h[k];
+    int U[4] = {1, 0, 0, 1};
+    int changed = 0;
+    if (advance) {
+        double hm[9];
+        m3_mul(D.Eh, h, hm);
+        m3_inv(hm, D.hmi);
+        m3_mul(D.E, h, h);
+        changed = reduce_planar(h, U);
+        for (int k = 0; k < 9; ++k) D.h[k] = h[k];
+    }
+    for (int k = 0; k < 4; ++k) D.U[k] = U[k];
+    D.changed = changed;
+    D.vol = fabs(m3_det(h));
+    double w[3];
+    m3_widths(h, w);
+    int nc[3];
+    bool narrow = false;
+    for (int a = 0; a < 3; ++a) {
+        int n = (int)floor(w[a] / C.rc);
+        if (!(w[a] >= 3.0 * C.rc)) narrow = true;
+        if (n < 3) n = 3;
+        nc[a] = n;
+    }
+    const int cap = C.box[b].cell_cap;
+    while ((long long)nc[0] * nc[1] * nc[2] > cap) {  // only reachable for a flagged (narrow) cell
+        int a = nc[0] >= nc[1] ? 0 : 1;
+        if (nc[a] <= 3) a = 2;
+        if (nc[a] <= 3) break;
+        nc[a] -= 1;
+    }
+    if (narrow) C.flags[b] |= LHMM_FLAG_CELL;
+    D.nc[0] = nc[0]; D.nc[1] = nc[1]; D.nc[2] = nc[2];
+}
+
+template <typename real>
+__device__ __forceinline__ int cell_of(real s0, real s1, real s2, const int* nc) {
+    int k0 = (int)(s0 * (real)nc[0]), k1 = (int)(s1 * (real)nc[1]), k2 = (int)(s2 * (real)nc[2]);
+    k0 = min(max(k0, 0), nc[0] - 1);
+    k1 = min(max(k1, 0), nc[1] - 1);
+    k2 = min(max(k2, 0), nc[2] - 1);
+    return (k0 * nc[1] + k1) * nc[2] + k2;
+}
+
+template <typename real>
+__device__ __forceinline__ real wrap01(real x) {
+    x -= floor(x);
+    return x >= (real)1 ? (real)0 : x;
+}
+
+template <typename real>
+__global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
+    const int blk = blockIdx.x;
+    const int b = C.blk_box[blk];
+    const BoxInfo B = C.box[b];
+    const int i = C.blk_first[blk] + (int)threadIdx.x;
+    if (i >= B.off + B.n) return;
+    const BoxDyn& D = C.dyn[b];
+    const int N = C.n_total;
+    real* s = (real*)C.s;
+    real* c = (real*)C.c;
+    const real* f = (const real*)C.f;
+    real s0 = s[i], s1 = s[N + i], s2 = s[2 * N + i];
+    if (advance) {
+        const real hdt = (real)(0.5 * C.dt), im = (real)C.inv_mass, dt = (real)C.dt;
+        real c0 = c[i], c1 = c[N + i], c2 = c[2 * N + i];
+        const real L0 = (real)D.L[0], L1 = (real)D.L[1], L3 = (real)D.L[3], L4 = (real)D.L[4];
+        // in-plane L: (L c)_z = 0
+        const real lc0 = L0 * c0 + L1 * c1, lc1 = L3 * c0 + L4 * c1;
+        c0 += hdt * (f[i] * im - lc0);
+        c1 += hdt * (f[N + i] * im - lc1);
+        c2 += hdt * (f[2 * N + i] * im);
+        c[i] = c0; c[N + i] = c1; c[2 * N + i] = c2;
+        const double* M = D.hmi;
+        s0 += dt * ((real)M[0] * c0 + (real)M[1] * c1 + (real)M[2] * c2);
+        s1 += dt * ((real)M[3] * c0 + (real)M[4] * c1 + (real)M[5] * c2);
+        s2 += dt * ((real)M[6] * c0 + (real)M[7] * c1 + (real)M[8] * c2);
+        if (D.changed) {  // s <- U^{-1} s in the plane, U^{-1} = [[u11, -u01], [-u10, u00]]
+            const real x = s0, y = s1;
+            s0 = (real)D.U[3] * x - (real)D.U[1] * y;
+            s1 = -(real)D.U[2] * x + (real)D.U[0] * y;
+        }
+        s0 = wrap01(s0); s1 = wrap01(s1); s2 = wrap01(s2);
+        s[i] = s0; s[N + i] = s1; s[2 * N + i] = s2;
+    }
+    C.pcell[i] = cell_of(s0, s1, s2, D.nc);
+}
+
+// One workgroup per box: counting sort by cell in LDS, then every cell's
+// list sorted by particle index.
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
+    __shared__ int cnt[MAX_CELLS_PER_BOX];
+    __shared__ int wsum[BIN_THREADS / 64];
+    const int b = blockIdx.x;
+    const BoxInfo B = C.box[b];
+    const BoxDyn& D = C.dyn[b];
+    const int ncell = D.nc[0] * D.nc[1] * D.nc[2];
+    for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) cnt[k] = 0;
+    __syncthreads();
+    const int* pc = C.pcell + B.off;
+    for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) atomicAdd(&cnt[pc[k]], 1);
+    __syncthreads();
+    // exclusive scan of cnt[0 .. ncell) in chunks of BIN_THREADS
+    int* start = C.cell_start + B.cell_off;
+    int carry = 0;
+    for (int base = 0; base < ncell; base += BIN_THREADS) {
+        const int k = base + (int)threadIdx.x;
+        const int v = k < ncell ? cnt[k] : 0;
+        int x = v;  // inclusive scan within the wave
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wv; ++w) before += wsum[w];
+        int total = 0;
+        for (int w = 0; w < BIN_THREADS / 64; ++w) total += wsum[w];
+        const int excl = carry + before + x - v;
+        __syncthreads();
+        if (k < ncell) {
+            start[k] = excl;
+            cnt[k] = excl;  // becomes the fill cursor
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) start[ncell] = carry;
+    __syncthreads();
+    int* list = C.cell_list + B.off;
+    for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) {
+        const int pos = atomicAdd(&cnt[pc[k]], 1);
+        list[pos] = B.off + k;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) {
+        const int q0 = start[k], q1 = start[k + 1];
+        for (int q = q0 + 1; q < q1; ++q) {  // insertion sort, a few entries
+            const int v = list[q];
+            int r = q - 1;
+            while (r >= q0 && list[r] > v) {
+                list[r + 1] = list[r];
+                --r;
+            }
+            list[r + 1] = v;
+        }
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
+    __shared__ double sh[13 * (BS / 64)];
+    const int blk = blockIdx.x;
+    const int b = C.blk_box[blk];
+    const BoxInfo B = C.box[b];
+    const BoxDyn& D = C.dyn[b];
+    const int i = C.blk_first[blk] + (int)threadIdx.x;
+    const bool act = i < B.off + B.n;
+    const int N = C.n_total;
+    const real* s = (const real*)C.s;
+    const real* c = (const real*)C.c;
+    real* f = (real*)C.f;
+    real h[9], L[4];
+    for (int k = 0; k < 9; ++k) h[k] = (real)D.h[k];
+    L[0] = (real)D.L[0]; L[1] = (real)D.L[1]; L[2] = (real)D.L[3]; L[3] = (real)D.L[4];
+    const int n0 = D.nc[0], n1 = D.nc[1], n2 = D.nc[2];
+    const unsigned stepc = (unsigned)(*C.step + (unsigned long long)step_offset);
+    const real a = (real)C.a, gam = (real)C.gamma, sig = (real)(C.sigma * C.rdt), rc = (real)C.rc;
+    const real rc2 = (real)C.rc2, irc = (real)(1.0 / C.rc);
+
+    real fx = 0, fy = 0, fz = 0;
+    real w[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned npairs = 0;
+    if (act) {
+        const unsigned id_i = (unsigned)(i - B.off);
+        const real si0 = s[i], si1 = s[N + i], si2 = s[2 * N + i];
+        const real ci0 = c[i], ci1 = c[N + i], ci2 = c[2 * N + i];
+        const int pc = C.pcell[i];
+        const int k2 = pc % n2, k1 = (pc / n2) % n1, k0 = pc / (n1 * n2);
+        const int* start = C.cell_start + B.cell_off;
+        const int* list = C.cell_list + B.off;
+        for (int d0 = -1; d0 <= 1; ++d0) {
+            int m0 = k0 + d0;
+            real sh0 = 0;
+            if (m0 < 0) { m0 += n0; sh0 = -1; }
+            if (m0 >= n0) { m0 -= n0; sh0 = 1; }
+            for (int d1 = -1; d1 <= 1; ++d1) {
+                int m1 = k1 + d1;
+                real sh1 = 0;
+                if (m1 < 0) { m1 += n1; sh1 = -1; }
+                if (m1 >= n1) { m1 -= n1; sh1 = 1; }
+                for (int d2 = -1; d2 <= 1; ++d2) {
+                    int m2 = k2 + d2;
+                    real sh2 = 0;
+                    if (m2 < 0) { m2 += n2; sh2 = -1; }
+                    if (m2 >= n2) { m2 -= n2; sh2 = 1; }
+                    const int cc = (m0 * n1 + m1) * n2 + m2;
+                    const int q1 = start[cc + 1];
+                    for (int q = start[cc]; q < q1; ++q) {
+                        const int j = list[q];
+                        if (j == i) continue;
+                        const real ds0 = si0 - (s[j] + sh0);
+                        const real ds1 = si1 - (s[N + j] + sh1);
+                        const real ds2 = si2 - (s[2 * N + j] + sh2);
+                        const real dx = h[0] * ds0 + h[1] * ds1 + h[2] * ds2;
+                        const real dy = h[3] * ds0 + h[4] * ds1 + h[5] * ds2;
+                        const real dz = h[6] * ds0 + h[7] * ds1 + h[8] * ds2;
+                        const real r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 < rc2 && r2 > (real)0) {
+                            const real r = sqrt(r2);
+                            const real ir = (real)1 / r;
+                            const real ex = dx * ir, ey = dy * ir, ez = dz * ir;
+                            const real wR = (real)1 - r * irc;
+                            // relative velocity of i and the image of j
+                            const real vx = ci0 - c[j] + L[0] * dx + L[1] * dy;
+                            const real vy = ci1 - c[N + j] + L[2] * dx + L[3] * dy;
+                            const real vz = ci2 - c[2 * N + j];
+                            const real ev = ex * vx + ey * vy + ez * vz;
+                            const real th = pair_theta<real>(id_i, (unsigned)(j - B.off), stepc, B.rng_id,
+                                                             C.key0, C.key1);
+                            const real mag = wR * (a - gam * wR * ev + sig * th);
+                            const real gx = mag * ex, gy = mag * ey, gz = mag * ez;
+                            fx += gx; fy += gy; fz += gz;
+                            w[0] += dx * gx; w[1] += dy * gy; w[2] += dz * gz;
+                            w[3] += dx * gy; w[4] += dx * gz; w[5] += dy * gz;
+                            ++npairs;
+                        }
+                    }
+                }
+            }
+        }
+        // FENE springs to the chain neighbours
+        if ((int)id_i < B.n_beads) {
+            const int bead = (int)id_i % C.chain_len;
+            const real Hf = (real)C.H, iR02 = (real)C.inv_R02;
+            for (int side = 0; side < 2; ++side) {
+                if (side == 0 && bead == 0) continue;
+                if (side == 1 && bead == C.chain_len - 1) continue;
+                const int j = side == 0 ? i - 1 : i + 1;
+                real ds0 = si0 - s[j], ds1 = si1 - s[N + j], ds2 = si2 - s[2 * N + j];
+                ds0 -= rint(ds0); ds1 -= rint(ds1); ds2 -= rint(ds2);
+                const real dx = h[0] * ds0 + h[1] * ds1 + h[2] * ds2;
+                const real dy = h[3] * ds0 + h[4] * ds1 + h[5] * ds2;
+                const real dz = h[6] * ds0 + h[7] * ds1 + h[8] * ds2;
+                real den = (real)1 - (dx * dx + dy * dy + dz * dz) * iR02;
+                if (den <= (real)0) atomicOr(&C.flags[b], LHMM_FLAG_BOND);
+                if (den < (real)0.01) den = (real)0.01;
+                const real k = -Hf / den;
+                const real gx = k * dx, gy = k * dy, gz = k * dz;
+                fx += gx; fy += gy; fz += gz;
+                if (side == 1) {  // each bond's virial once, by its lower bead
+                    w[6] += dx * gx; w[7] += dy * gy; w[8] += dz * gz;
+                    w[9] += dx * gy; w[10] += dx * gz; w[11] += dy * gz;
+                }
+            }
+        }
+        f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
+    }
+    double v[13];
+    for (int k = 0; k < 12; ++k) v[k] = (double)w[k];
+    v[12] = (double)npairs;
+    block_sum<13>(v, sh);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 12; ++k) C.part_vir[12 * blk + k] = v[k];
+        C.part_pairs[blk] = (unsigned)v[12];
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(BS) void k_kick2(Ctx C) {
+    __shared__ double sh[6 * (BS / 64)];
+    const int blk = blockIdx.x;
+    const int b = C.blk_box[blk];
+    const BoxInfo B = C.box[b];
+    const BoxDyn& D = C.dyn[b];
+    const int i = C.blk_first[blk] + (int)threadIdx.x;
+    const int N = C.n_total;
+    double k6[6] = {0, 0, 0, 0, 0, 0};
+    if (i < B.off + B.n) {
+        real* c = (real*)C.c;
+        const real* f = (const real*)C.f;
+        const real hdt = (real)(0.5 * C.dt), im = (real)C.inv_mass;
+        real c0 = c[i], c1 = c[N + i], c2 = c[2 * N + i];
+        const real L0 = (real)D.L[0], L1 = (real)D.L[1], L3 = (real)D.L[3], L4 = (real)D.L[4];
+        const real lc0 = L0 * c0 + L1 * c1, lc1 = L3 * c0 + L4 * c1;
+        c0 += hdt * (f[i] * im - lc0);
+        c1 += hdt * (f[N + i] * im - lc1);
+        c2 += hdt * (f[2 * N + i] * im);
+        c[i] = c0; c[N + i] = c1; c[2 * N + i] = c2;
+        const double m = C.mass, x = (double)c0, y = (double)c1, z = (double)c2;
+        k6[0] = m * x * x; k6[1] = m * y * y; k6[2] = m * z * z;
+        k6[3] = m * x * y; k6[4] = m * x * z; k6[5] = m * y * z;
+    }
+    block_sum<6>(k6, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) C.part_kin[6 * blk + k] = k6[k];
+}
+
+// One thread per box: the step's stress, sigma = -(K + W)/V, by part.
+__global__ void k_box_stress(Ctx C) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < C.n_boxes) {
+        const BoxInfo B = C.box[b];
+        double K[6] = {0, 0, 0, 0, 0, 0}, W[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        unsigned long long np = 0;
+        for (int k = 0; k < B.nblk; ++k) {
+            const int blk = B.blk_off + k;
+            for (int q = 0; q < 6; ++q) K[q] += C.part_kin[6 * blk + q];
+            for (int q = 0; q < 12; ++q) W[q] += C.part_vir[12 * blk + q];
+            np += C.part_pairs[blk];
+        }
+        const double iv = 1.0 / C.dyn[b].vol;
+        double* acc = C.acc + 18 * b;
+        bool finite = true;
+        for (int q = 0; q < 6; ++q) {
+            const double sk = -K[q] * iv, sp = -0.5 * W[q] * iv, sf = -W[6 + q] * iv;
+            acc[q] += sk;
+            acc[6 + q] += sp;
+            acc[12 + q] += sf;
+            if (!(fabs(sk + sp + sf) <= 1e300)) finite = false;
+        }
+        if (!finite) C.flags[b] |= LHMM_FLAG_NONFINITE;
+        C.acc_pairs[b] += np / 2;
+    }
+    if (b == 0) *C.step += 1ull;
+}
+
+__global__ void k_finalize(Ctx C, double* __restrict__ stress_out, double* __restrict__ parts_out,
+                           double inv_steps) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= C.n_boxes) return;
+    const double* acc = C.acc + 18 * b;
+    for (int q = 0; q < 6; ++q) stress_out[6 * b + q] = (acc[q] + acc[6 + q] + acc[12 + q]) * inv_steps;
+    for (int q = 0; q < 18; ++q) parts_out[18 * b + q] = acc[q] * inv_steps;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+
+struct lhmm_micro {
+    lhmm_params p{};
+    int n_boxes = 0, n_blocks = 0, precision = LHMM_FP32;
+    long long n_total = 0;
+    size_t real_size = 4;
+    std::vector<BoxInfo> box;
+    std::vector<int> blk_box, blk_first;
+    hipStream_t user_stream = nullptr, stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // device buffers
+    BoxInfo* d_box = nullptr;
+    BoxDyn* d_dyn = nullptr;
+    unsigned* d_flags = nullptr;
+    int *d_blk_box = nullptr, *d_blk_first = nullptr;
+    void *d_s = nullptr, *d_c = nullptr, *d_f = nullptr;
+    int *d_pcell = nullptr, *d_cell_start = nullptr, *d_cell_list = nullptr;
+    double *d_part_vir = nullptr, *d_part_kin = nullptr;
+    unsigned* d_part_pairs = nullptr;
+    double *d_acc = nullptr, *d_parts = nullptr, *d_gradL = nullptr;
+    unsigned long long *d_acc_pairs = nullptr, *d_step = nullptr;
+    bool have_state = false, forces_valid = false;
+    std::map<int, hipGraphExec_t> graphs;
+    Ctx ctx{};
+};
+
+namespace {
+
+template <typename real>
+void launch_step_kernels(lhmm_micro* m, int step_offset, bool advance, bool full_step) {
+    const Ctx& C = m->ctx;
+    const int bt = 256, bg = (m->n_boxes + bt - 1) / bt;
+    k_cell_step<<<bg, bt, 0, m->stream>>>(C, advance ? 1 : 0);
+    k_kick_drift<real><<<m->n_blocks, BS, 0, m->stream>>>(C, advance ? 1 : 0);
+    k_bin_box<<<m->n_boxes, BIN_THREADS, 0, m->stream>>>(C);
+    k_forces<real><<<m->n_blocks, BS, 0, m->stream>>>(C, step_offset);
+    if (full_step) {
+        k_kick2<real><<<m->n_blocks, BS, 0, m->stream>>>(C);
+        k_box_stress<<<bg, bt, 0, m->stream>>>(C);
+    }
+}
+
+// One step with an event pair around each kernel (ev: 2 * LHMM_N_KERNELS events).
+template <typename real>
+void launch_step_timed(lhmm_micro* m, hipEvent_t* ev) {
+    const Ctx& C = m->ctx;
+    const int bt = 256, bg = (m->n_boxes + bt - 1) / bt;
+    hipStream_t st = m->stream;
+    (void)hipEventRecord(ev[0], st);
+    k_cell_step<<<bg, bt, 0, st>>>(C, 1);
+    (void)hipEventRecord(ev[1], st);
+    (void)hipEventRecord(ev[2], st);
+    k_kick_drift<real><<<m->n_blocks, BS, 0, st>>>(C, 1);
+    (void)hipEventRecord(ev[3], st);
+    (void)hipEventRecord(ev[4], st);
+    k_bin_box<<<m->n_boxes, BIN_THREADS, 0, st>>>(C);
+    (void)hipEventRecord(ev[5], st);
+    (void)hipEventRecord(ev[6], st);
+    k_forces<real><<<m->n_blocks, BS, 0, st>>>(C, 1);
+    (void)hipEventRecord(ev[7], st);
+    (void)hipEventRecord(ev[8], st);
+    k_kick2<real><<<m->n_blocks, BS, 0, st>>>(C);
+    (void)hipEventRecord(ev[9], st);
+    (void)hipEventRecord(ev[10], st);
+    k_box_stress<<<bg, bt, 0, st>>>(C);
+    (void)hipEventRecord(ev[11], st);
+}
+
+void launch_one_step(lhmm_micro* m) {
+    if (m->precision == LHMM_FP64)
+        launch_step_kernels<double>(m, 1, true, true);
+    else
+        launch_step_kernels<float>(m, 1, true, true);
+}
+
+void launch_force_eval(lhmm_micro* m) {
+    if (m->precision == LHMM_FP64)
+        launch_step_kernels<double>(m, 0, false, false);
+    else
+        launch_step_kernels<float>(m, 0, false, false);
+}
+
+int get_graph(lhmm_micro* m, int nsteps, hipGraphExec_t* out) {
+    auto it = m->graphs.find(nsteps);
+    if (it != m->graphs.end()) {
+        *out = it->second;
+        return LHMM_OK;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < nsteps; ++k) launch_one_step(m);
+    HIPCHK(hipStreamEndCapture(m->stream, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LHMM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    m->graphs[nsteps] = ex;
+    *out = ex;
+    return LHMM_OK;
+}
+
+bool cell_ok(const double* h) {
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(h[k])) return false;
+    if (h[2] != 0.0 || h[5] != 0.0 || h[6] != 0.0 || h[7] != 0.0) return false;
+    if (!(h[8] > 0.0)) return false;
+    return m3_det(h) > 0.0;
+}
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) return fail(LHMM_ERR_OOM, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
+    return LHMM_OK;
+}
+
+void release(lhmm_micro* m) {
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
+    m->graphs.clear();
+    void* bufs[] = {m->d_box, m->d_dyn, m->d_flags, m->d_blk_box, m->d_blk_first, m->d_s, m->d_c, m->d_f,
+                    m->d_pcell, m->d_cell_start, m->d_cell_list, m->d_part_vir, m->d_part_kin,
+                    m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_step};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (m->ev_in) (void)hipEventDestroy(m->ev_in);
+    if (m->ev_out) (void)hipEventDestroy(m->ev_out);
+    if (m->stream) (void)hipStreamDestroy(m->stream);
+}
+
+int sync_engine(lhmm_micro* m) {
+    HIPCHK(hipStreamSynchronize(m->stream));
+    HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lhmm_last_error(void) { return g_err.c_str(); }
+
+int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_boxes, void* stream,
+                      lhmm_micro** out) {
+    g_err.clear();
+    if (!p || !boxes || !out) return fail(LHMM_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (n_boxes <= 0) return fail(LHMM_ERR_ARG, "n_boxes must be positive (got %d)", n_boxes);
+    const double vals[9] = {p->a, p->gamma, p->sigma, p->kBT, p->mass, p->rc, p->dt, p->H, p->R0};
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(LHMM_ERR_ARG, "non-finite parameter");
+    if (!(p->dt > 0) || !(p->rc > 0) || !(p->mass > 0) || !(p->R0 > 0) || p->gamma < 0 || p->sigma < 0 || p->H < 0)
+        return fail(LHMM_ERR_ARG, "parameters out of range (dt, rc, mass, R0 > 0; gamma, sigma, H >= 0)");
+    if (p->chain_len < 2) return fail(LHMM_ERR_ARG, "chain_len must be >= 2");
+    if (p->precision != LHMM_FP32 && p->precision != LHMM_FP64) return fail(LHMM_ERR_ARG, "bad precision");
+
+    lhmm_micro* m = new (std::nothrow) lhmm_micro();
+    if (!m) return fail(LHMM_ERR_OOM, "host allocation failed");
+    m->p = *p;
+    m->n_boxes = n_boxes;
+    m->precision = p->precision;
+    m->real_size = p->precision == LHMM_FP64 ? sizeof(double) : sizeof(float);
+    m->user_stream = (hipStream_t)stream;
+
+    long long off = 0;
+    int cell_off = 0, blk_off = 0;
+    m->box.resize(n_boxes);
+    for (int b = 0; b < n_boxes; ++b) {
+        const lhmm_box& in = boxes[b];
+        if (in.n_particles < 2 || in.n_chains < 0 || (long long)in.n_chains * p->chain_len > in.n_particles) {
+            delete m;
+            return fail(LHMM_ERR_ARG, "box %d: bad particle/chain counts", b);
+        }
+        if (in.reserved != 0) {
+            delete m;
+            return fail(LHMM_ERR_ARG, "box %d: reserved field must be 0", b);
+        }
+        if (!cell_ok(in.h0)) {
+            delete m;
+            return fail(LHMM_ERR_ARG, "box %d: cell must be finite, in-plane, with det > 0", b);
+        }
+        // n0 n1 <= w0 w1 <= area and n2 = floor(z extent / rc): the grid never needs more
+        const double area = fabs(in.h0[0] * in.h0[4] - in.h0[1] * in.h0[3]);
+        const long long inplane = (long long)std::floor(area / (p->rc * p->rc) * (1.0 + 1e-9));
+        const long long nz = (long long)std::floor(in.h0[8] / p->rc * (1.0 + 1e-9));
+        long long cap = std::max(27LL, std::max(inplane, 9LL) * std::max(nz, 3LL));
+        if (cap > MAX_CELLS_PER_BOX) {
+            delete m;
+            return fail(LHMM_ERR_ARG, "box %d: needs %lld cells, more than %d", b, cap, MAX_CELLS_PER_BOX);
+        }
+        BoxInfo& B = m->box[b];
+        B.off = (int)off;
+        B.n = in.n_particles;
+        B.n_beads = in.n_chains * p->chain_len;
+        B.cell_off = cell_off;
+        B.cell_cap = (int)cap;
+        B.blk_off = blk_off;
+        B.nblk = (in.n_particles + BS - 1) / BS;
+        B.rng_id = in.rng_id;
+        for (int k = 0; k < B.nblk; ++k) {
+            m->blk_box.push_back(b);
+            m->blk_first.push_back(B.off + k * BS);
+        }
+        off += in.n_particles;
+        cell_off += (int)cap + 1;
+        blk_off += B.nblk;
+        if (off > (1LL << 30)) {
+            delete m;
+            return fail(LHMM_ERR_ARG, "too many particles");
+        }
+    }
+    m->n_total = off;
+    m->n_blocks = blk_off;
+    const size_t N = (size_t)m->n_total;
+    int rc = LHMM_OK;
+#define ALLOC(ptr, cnt)                     \
+    if (rc == LHMM_OK) rc = dalloc(&(ptr), (cnt));
+    ALLOC(m->d_box, (size_t)n_boxes);
+    ALLOC(m->d_dyn, (size_t)n_boxes);
+    ALLOC(m->d_flags, (size_t)n_boxes);
+    ALLOC(m->d_blk_box, (size_t)m->n_blocks);
+    ALLOC(m->d_blk_first, (size_t)m->n_blocks);
+    ALLOC(m->d_pcell, N);
+    ALLOC(m->d_cell_start, (size_t)cell_off);
+    ALLOC(m->d_cell_list, N);
+    ALLOC(m->d_part_vir, (size_t)m->n_blocks * 12);
+    ALLOC(m->d_part_kin, (size_t)m->n_blocks * 6);
+    ALLOC(m->d_part_pairs, (size_t)m->n_blocks);
+    ALLOC(m->d_acc, (size_t)n_boxes * 18);
+    ALLOC(m->d_parts, (size_t)n_boxes * 18);
+    ALLOC(m->d_gradL, (size_t)n_boxes * 9);
+    ALLOC(m->d_acc_pairs, (size_t)n_boxes);
+    ALLOC(m->d_step, (size_t)1);
+#undef ALLOC
+    if (rc == LHMM_OK) {
+        const size_t bytes = 3 * N * m->real_size;
+        for (void** pp : {&m->d_s, &m->d_c, &m->d_f}) {
+            if (hipMalloc(pp, bytes ? bytes : 1) != hipSuccess) {
+                rc = fail(LHMM_ERR_OOM, "hipMalloc of particle arrays failed");
+                break;
+            }
+        }
+    }
+    if (rc != LHMM_OK) {
+        release(m);
+        delete m;
+        return rc;
+    }
+    auto setup = [&]() -> int {
+        HIPCHK(hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming));
+        HIPCHK(hipMemcpy(m->d_box, m->box.data(), n_boxes * sizeof(BoxInfo), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(m->d_blk_box, m->blk_box.data(), m->n_blocks * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(m->d_blk_first, m->blk_first.data(), m->n_blocks * sizeof(int), hipMemcpyHostToDevice));
+        std::vector<BoxDyn> dyn(n_boxes);
+        for (int b = 0; b < n_boxes; ++b) {
+            memset(&dyn[b], 0, sizeof(BoxDyn));
+            for (int k = 0; k < 9; ++k) dyn[b].h[k] = boxes[b].h0[k];
+        }
+        HIPCHK(hipMemcpy(m->d_dyn, dyn.data(), n_boxes * sizeof(BoxDyn), hipMemcpyHostToDevice));
+        HIPCHK(hipMemset(m->d_flags, 0, n_boxes * sizeof(unsigned)));
+        HIPCHK(hipMemset(m->d_acc, 0, n_boxes * 18 * sizeof(double)));
+        HIPCHK(hipMemset(m->d_parts, 0, n_boxes * 18 * sizeof(double)));
+        HIPCHK(hipMemset(m->d_acc_pairs, 0, n_boxes * sizeof(unsigned long long)));
+        HIPCHK(hipMemset(m->d_step, 0, sizeof(unsigned long long)));
+        if (N) HIPCHK(hipMemset(m->d_f, 0, 3 * N * m->real_size));
+        return LHMM_OK;
+    };
+    rc = setup();
+    if (rc != LHMM_OK) {
+        release(m);
+        delete m;
+        return rc;
+    }
+    Ctx& C = m->ctx;
+    C.n_total = (int)m->n_total;
+    C.n_boxes = n_boxes;
+    C.n_blocks = m->n_blocks;
+    C.chain_len = p->chain_len;
+    C.box = m->d_box;
+    C.dyn = m->d_dyn;
+    C.flags = m->d_flags;
+    C.blk_box = m->d_blk_box;
+    C.blk_first = m->d_blk_first;
+    C.s = m->d_s;
+    C.c = m->d_c;
+    C.f = m->d_f;
+    C.pcell = m->d_pcell;
+    C.cell_start = m->d_cell_start;
+    C.cell_list = m->d_cell_list;
+    C.part_vir = m->d_part_vir;
+    C.part_kin = m->d_part_kin;
+    C.part_pairs = m->d_part_pairs;
+    C.acc = m->d_acc;
+    C.acc_pairs = m->d_acc_pairs;
+    C.step = m->d_step;
+    C.a = p->a;
+    C.gamma = p->gamma;
+    C.sigma = p->sigma;
+    C.rdt = 1.0 / std::sqrt(p->dt);
+    C.dt = p->dt;
+    C.mass = p->mass;
+    C.inv_mass = 1.0 / p->mass;
+    C.rc = p->rc;
+    C.rc2 = p->rc * p->rc;
+    C.H = p->H;
+    C.inv_R02 = 1.0 / (p->R0 * p->R0);
+    C.key0 = (unsigned)(p->seed & 0xFFFFFFFFull);
+    C.key1 = (unsigned)(p->seed >> 32);
+    *out = m;
+    return LHMM_OK;
+}
+
+int lhmm_micro_set_state(lhmm_micro* m, const double* s, const double* c, const double* f, const double* h,
+                         uint64_t step) {
+    g_err.clear();
+    if (!m || !s || !c) return fail(LHMM_ERR_ARG, "null argument");
+    const size_t N = (size_t)m->n_total;
+    for (size_t k = 0; k < 3 * N; ++k) {
+        if (!(s[k] >= 0.0 && s[k] < 1.0)) return fail(LHMM_ERR_ARG, "s[%zu] = %g outside [0, 1)", k, s[k]);
+        if (!std::isfinite(c[k])) return fail(LHMM_ERR_ARG, "c[%zu] is not finite", k);
+        if (f && !std::isfinite(f[k])) return fail(LHMM_ERR_ARG, "f[%zu] is not finite", k);
+    }
+    if (h)
+        for (int b = 0; b < m->n_boxes; ++b)
+            if (!cell_ok(h + 9 * b)) return fail(LHMM_ERR_ARG, "box %d: bad cell", b);
+    HIPCHK(hipStreamSynchronize(m->stream));
+    // AoS double -> SoA real
+    std::vector<char> buf(3 * N * m->real_size + 1);
+    const double* srcs[3] = {s, c, f};
+    void* dsts[3] = {m->d_s, m->d_c, m->d_f};
+    for (int which = 0; which < 3; ++which) {
+        const double* src = srcs[which];
+        if (!src) continue;
+        for (size_t i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) {
+                const double v = src[3 * i + k];
+                if (m->precision == LHMM_FP64) {
+                    ((double*)buf.data())[k * N + i] = v;
+                } else {
+                    float x = (float)v;
+                    if (which == 0 && x >= 1.0f) x = 0.0f;
+                    ((float*)buf.data())[k * N + i] = x;
+                }
+            }
+        HIPCHK(hipMemcpy(dsts[which], buf.data(), 3 * N * m->real_size, hipMemcpyHostToDevice));
+    }
+    if (h) {
+        std::vector<BoxDyn> dyn(m->n_boxes);
+        HIPCHK(hipMemcpy(dyn.data(), m->d_dyn, m->n_boxes * sizeof(BoxDyn), hipMemcpyDeviceToHost));
+        for (int b = 0; b < m->n_boxes; ++b)
+            for (int k = 0; k < 9; ++k) dyn[b].h[k] = h[9 * b + k];
+        HIPCHK(hipMemcpy(m->d_dyn, dyn.data(), m->n_boxes * sizeof(BoxDyn), hipMemcpyHostToDevice));
+    }
+    unsigned long long st = step;
+    HIPCHK(hipMemcpy(m->d_step, &st, sizeof st, hipMemcpyHostToDevice));
+    m->have_state = true;
+    m->forces_valid = f != nullptr;
+    return LHMM_OK;
+}
+
+int lhmm_micro_get_state(lhmm_micro* m, double* s, double* c, double* f, double* h, uint64_t* step) {
+    g_err.clear();
+    if (!m) return fail(LHMM_ERR_ARG, "null engine");
+    int rc = sync_engine(m);
+    if (rc != LHMM_OK) return rc;
+    const size_t N = (size_t)m->n_total;
+    std::vector<char> buf(3 * N * m->real_size + 1);
+    double* dsts[3] = {s, c, f};
+    const void* srcs[3] = {m->d_s, m->d_c, m->d_f};
+    for (int which = 0; which < 3; ++which) {
+        double* dst = dsts[which];
+        if (!dst) continue;
+        HIPCHK(hipMemcpy(buf.data(), srcs[which], 3 * N * m->real_size, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k)
+                dst[3 * i + k] = m->precision == LHMM_FP64 ? ((double*)buf.data())[k * N + i]
+                                                           : (double)((float*)buf.data())[k * N + i];
+    }
+    if (h) {
+        std::vector<BoxDyn> dyn(m->n_boxes);
+        HIPCHK(hipMemcpy(dyn.data(), m->d_dyn, m->n_boxes * sizeof(BoxDyn), hipMemcpyDeviceToHost));
+        for (int b = 0; b < m->n_boxes; ++b)
+            for (int k = 0; k < 9; ++k) h[9 * b + k] = dyn[b].h[k];
+    }
+    if (step) {
+        unsigned long long st = 0;
+        HIPCHK(hipMemcpy(&st, m->d_step, sizeof st, hipMemcpyDeviceToHost));
+        *step = st;
+    }
+    return LHMM_OK;
+}
+
+int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double* stress_out) {
+    g_err.clear();
+    if (!m || !gradL || !stress_out) return fail(LHMM_ERR_ARG, "null argument");
+    if (n_steps <= 0) return fail(LHMM_ERR_ARG, "n_steps must be positive (got %d)", n_steps);
+    if (!m->have_state) return fail(LHMM_ERR_STATE, "no particle state loaded");
+    const int bt = 256, bg = (m->n_boxes + bt - 1) / bt;
+    HIPCHK(hipEventRecord(m->ev_in, m->user_stream));
+    HIPCHK(hipStreamWaitEvent(m->stream, m->ev_in, 0));
+    k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, gradL);
+    k_zero_acc<<<(18 * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
+    if (!m->forces_valid) {
+        launch_force_eval(m);
+        m->forces_valid = true;
+    }
+    HIPCHK(hipGetLastError());
+    if (m->p.flags & LHMM_OPT_NO_GRAPH) {
+        for (int k = 0; k < n_steps; ++k) launch_one_step(m);
+    } else {
+        const int chunk = n_steps < GRAPH_CHUNK ? n_steps : GRAPH_CHUNK;
+        const int full = n_steps / chunk, rest = n_steps % chunk;
+        hipGraphExec_t g = nullptr;
+        int rc = get_graph(m, chunk, &g);
+        if (rc != LHMM_OK) return rc;
+        for (int k = 0; k < full; ++k) HIPCHK(hipGraphLaunch(g, m->stream));
+        if (rest) {
+            rc = get_graph(m, rest, &g);
+            if (rc != LHMM_OK) return rc;
+            HIPCHK(hipGraphLaunch(g, m->stream));
+        }
+    }
+    k_finalize<<<bg, bt, 0, m->stream>>>(m->ctx, stress_out, m->d_parts, 1.0 / n_steps);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(m->ev_out, m->stream));
+    HIPCHK(hipStreamWaitEvent(m->user_stream, m->ev_out, 0));
+    return LHMM_OK;
+}
+
+int lhmm_micro_forces(lhmm_micro* m, const double* gradL, double* f_out, double* virial_out) {
+    g_err.clear();
+    if (!m || !gradL || !f_out) return fail(LHMM_ERR_ARG, "null argument");
+    if (!m->have_state) return fail(LHMM_ERR_STATE, "no particle state loaded");
+    for (int k = 0; k < 9 * m->n_boxes; ++k)
+        if (!std::isfinite(gradL[k])) return fail(LHMM_ERR_ARG, "gradient not finite");
+    int rc = sync_engine(m);
+    if (rc != LHMM_OK) return rc;
+    HIPCHK(hipMemcpy(m->d_gradL, gradL, 9 * m->n_boxes * sizeof(double), hipMemcpyHostToDevice));
+    const int bt = 256, bg = (m->n_boxes + bt - 1) / bt;
+    k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, m->d_gradL);
+    launch_force_eval(m);
+    HIPCHK(hipGetLastError());
+    rc = sync_engine(m);
+    if (rc != LHMM_OK) return rc;
+    m->forces_valid = false;  // the next step recomputes forces with its own gradient
+    const size_t N = (size_t)m->n_total;
+    std::vector<char> buf(3 * N * m->real_size + 1);
+    HIPCHK(hipMemcpy(buf.data(), m->d_f, 3 * N * m->real_size, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < N; ++i)
+        for (int k = 0; k < 3; ++k)
+            f_out[3 * i + k] = m->precision == LHMM_FP64 ? ((double*)buf.data())[k * N + i]
+                                                         : (double)((float*)buf.data())[k * N + i];
+    if (virial_out) {
+        std::vector<double> pv((size_t)m->n_blocks * 12);
+        HIPCHK(hipMemcpy(pv.data(), m->d_part_vir, pv.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int b = 0; b < m->n_boxes; ++b) {
+            double* o = virial_out + 12 * b;
+            for (int q = 0; q < 12; ++q) o[q] = 0.0;
+            for (int k = 0; k < m->box[b].nblk; ++k)
+                for (int q = 0; q < 12; ++q) o[q] += pv[12 * (size_t)(m->box[b].blk_off + k) + q];
+            for (int q = 0; q < 6; ++q) o[q] *= 0.5;  // ordered pairs count each pair twice
+        }
+    }
+    return LHMM_OK;
+}
+
+int lhmm_micro_time(lhmm_micro* m, const double* gradL, int32_t n_steps, double* avg_ms, double* stress_out) {
+    g_err.clear();
+    if (!m || !gradL || !avg_ms) return fail(LHMM_ERR_ARG, "null argument");
+    if (n_steps <= 0) return fail(LHMM_ERR_ARG, "n_steps must be positive (got %d)", n_steps);
+    if (!m->have_state) return fail(LHMM_ERR_STATE, "no particle state loaded");
+    const int bt = 256, bg = (m->n_boxes + bt - 1) / bt;
+    hipEvent_t ev[2 * LHMM_N_KERNELS];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(m->ev_in, m->user_stream));
+    HIPCHK(hipStreamWaitEvent(m->stream, m->ev_in, 0));
+    k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, gradL);
+    k_zero_acc<<<(18 * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
+    if (!m->forces_valid) {
+        launch_force_eval(m);
+        m->forces_valid = true;
+    }
+    double sum[LHMM_N_KERNELS] = {0, 0, 0, 0, 0, 0};
+    int rc = LHMM_OK;
+    for (int k = 0; k < n_steps && rc == LHMM_OK; ++k) {
+        if (m->precision == LHMM_FP64)
+            launch_step_timed<double>(m, ev);
+        else
+            launch_step_timed<float>(m, ev);
+        hipError_t e = hipEventSynchronize(ev[2 * LHMM_N_KERNELS - 1]);
+        if (e != hipSuccess) {
+            rc = fail(LHMM_ERR_HIP, "hipEventSynchronize: %s", hipGetErrorString(e));
+            break;
+        }
+        for (int q = 0; q < LHMM_N_KERNELS; ++q) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]) != hipSuccess) {
+                rc = fail(LHMM_ERR_HIP, "hipEventElapsedTime failed");
+                break;
+            }
+            sum[q] += ms;
+        }
+    }
+    if (rc == LHMM_OK) {
+        for (int q = 0; q < LHMM_N_KERNELS; ++q) avg_ms[q] = sum[q] / n_steps;
+        if (stress_out) k_finalize<<<bg, bt, 0, m->stream>>>(m->ctx, stress_out, m->d_parts, 1.0 / n_steps);
+        hipError_t e = hipStreamSynchronize(m->stream);
+        if (e != hipSuccess) rc = fail(LHMM_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
+int lhmm_micro_stress_parts(lhmm_micro* m, double* parts_out) {
+    g_err.clear();
+    if (!m || !parts_out) return fail(LHMM_ERR_ARG, "null argument");
+    int rc = sync_engine(m);
+    if (rc != LHMM_OK) return rc;
+    HIPCHK(hipMemcpy(parts_out, m->d_parts, 18 * m->n_boxes * sizeof(double), hipMemcpyDeviceToHost));
+    return LHMM_OK;
+}
+
+int lhmm_micro_pair_counts(lhmm_micro* m, uint64_t* pairs_out) {
+    g_err.clear();
+    if (!m || !pairs_out) return fail(LHMM_ERR_ARG, "null argument");
+    int rc = sync_engine(m);
+    if (rc != LHMM_OK) return rc;
+    std::vector<unsigned long long> v(m->n_boxes);
+    HIPCHK(hipMemcpy(v.data(), m->d_acc_pairs, m->n_boxes * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (int b = 0; b < m->n_boxes; ++b) pairs_out[b] = v[b];
+    return LHMM_OK;
+}
+
+int lhmm_micro_flags(lhmm_micro* m, uint32_t* flags_out, int32_t clear) {
+    g_err.clear();
+    if (!m || !flags_out) return fail(LHMM_ERR_ARG, "null argument");
+    int rc = sync_engine(m);
+    if (rc != LHMM_OK) return rc;
+    HIPCHK(hipMemcpy(flags_out, m->d_flags, m->n_boxes * sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (clear) HIPCHK(hipMemset(m->d_flags, 0, m->n_boxes * sizeof(unsigned)));
+    return LHMM_OK;
+}
+
+int lhmm_micro_sizes(const lhmm_micro* m, int64_t* n_total, int32_t* n_boxes) {
+    g_err.clear();
+    if (!m) return fail(LHMM_ERR_ARG, "null engine");
+    if (n_total) *n_total = m->n_total;
+    if (n_boxes) *n_boxes = m->n_boxes;
+    return LHMM_OK;
+}
+
+int lhmm_micro_destroy(lhmm_micro* m) {
+    g_err.clear();
+    if (!m) return LHMM_OK;
+    release(m);
+    delete m;
+    return LHMM_OK;
+}
+
+}  // extern "C"

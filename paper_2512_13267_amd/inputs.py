@@ -86,14 +86,14 @@ def random_box(rng: np.random.Generator, h: np.ndarray, N: int, n_chains: int, c
     n_beads = n_chains * chain_len
     if n_beads > N:
         raise ValueError("more chain beads than particles")
-    for ch in range(n_chains):
-        base = ch * chain_len
-        r = h @ s[base]
-        for k in range(1, chain_len):
-            u = rng.normal(size=3)
-            u /= np.linalg.norm(u)
-            r = r + b0 * u
-            s[base + k] = hinv @ r
+    if n_chains > 0:
+        # random walks of step b0 from a uniform first bead
+        u = rng.normal(size=(n_chains, chain_len - 1, 3))
+        u /= np.linalg.norm(u, axis=2, keepdims=True)
+        first = s[0:n_beads:chain_len] @ h.T  # (n_chains, 3)
+        walk = first[:, None, :] + np.concatenate([np.zeros((n_chains, 1, 3)), np.cumsum(b0 * u, axis=1)],
+                                                  axis=1)
+        s[:n_beads] = walk.reshape(n_beads, 3) @ hinv.T
     s = _wrap_f32(s)
     c = rng.normal(scale=math.sqrt(kBT / mass), size=(N, 3))
     c -= c.mean(axis=0, keepdims=True)
@@ -120,37 +120,51 @@ def cubic_cell(edge: float) -> np.ndarray:
 # Box shapes that survive a constant hyperbolic gradient
 # ---------------------------------------------------------------------------
 
-def _lattice_min_width(B: np.ndarray, K: int = 12) -> float:
-    """Largest achievable minimum perpendicular width of the 2-D lattice with
-    basis columns B: area / (second successive minimum), found by
-    enumerating lattice vectors m b1 + n b2 with |m|, |n| <= K."""
-    area = abs(np.linalg.det(B))
+_ENUM_K = 8
+
+
+def _enum_coeffs(K: int = _ENUM_K) -> np.ndarray:
     m, n = np.meshgrid(np.arange(-K, K + 1), np.arange(-K, K + 1), indexing="ij")
-    m = m.ravel()
-    n = n.ravel()
-    keep = (m != 0) | (n != 0)
-    m, n = m[keep], n[keep]
-    V = np.outer(B[:, 0], m) + np.outer(B[:, 1], n)
-    lens = np.hypot(V[0], V[1])
-    order = np.argsort(lens, kind="stable")
-    v1 = V[:, order[0]]
-    for k in order[1:]:
-        v = V[:, k]
-        if abs(v1[0] * v[1] - v1[1] * v[0]) > 1e-9 * lens[order[0]] * lens[k]:
-            return area / lens[k]
-    return 0.0
+    mn = np.stack([m.ravel(), n.ravel()], axis=0).astype(np.float64)
+    return mn[:, (mn[0] != 0) | (mn[1] != 0)]
+
+
+def _lattice_min_widths(B: np.ndarray, K: int = _ENUM_K) -> np.ndarray:
+    """Largest achievable minimum perpendicular width of each 2-D lattice in
+    the stack B (..., 2, 2) (basis in columns): area / (second successive
+    minimum), found by enumerating lattice vectors m b1 + n b2 with
+    |m|, |n| <= K."""
+    B = np.asarray(B, dtype=np.float64)
+    shp = B.shape[:-2]
+    B = B.reshape(-1, 2, 2)
+    area = np.abs(B[:, 0, 0] * B[:, 1, 1] - B[:, 0, 1] * B[:, 1, 0])
+    V = B @ _enum_coeffs(K)  # (n, 2, M)
+    lens = np.hypot(V[:, 0], V[:, 1])
+    k1 = np.argmin(lens, axis=1)
+    v1 = V[np.arange(len(B)), :, k1]  # (n, 2)
+    l1 = lens[np.arange(len(B)), k1]
+    cross = v1[:, :1] * V[:, 1] - v1[:, 1:] * V[:, 0]
+    indep = np.abs(cross) > 1e-9 * l1[:, None] * lens
+    l2 = np.where(indep, lens, np.inf).min(axis=1)
+    return (area / l2).reshape(shp)
+
+
+def _lattice_min_width(B: np.ndarray, K: int = _ENUM_K) -> float:
+    return float(_lattice_min_widths(np.asarray(B)[None], K)[0])
+
+
+def _flow_maps(L2: np.ndarray, ts: np.ndarray) -> np.ndarray:
+    from scipy.linalg import expm
+    return expm(np.asarray(L2)[None] * np.asarray(ts)[:, None, None])
 
 
 def _flow_map(L2: np.ndarray, t: float) -> np.ndarray:
-    from scipy.linalg import expm
-    return expm(L2 * t)
+    return _flow_maps(L2, np.array([t]))[0]
 
 
 def _min_width_over(L2: np.ndarray, B: np.ndarray, t_end: float, samples: int) -> float:
-    w = np.inf
-    for t in np.linspace(0.0, t_end, samples):
-        w = min(w, _lattice_min_width(_flow_map(L2, t) @ B))
-    return w
+    E = _flow_maps(L2, np.linspace(0.0, t_end, samples))
+    return float(_lattice_min_widths(E @ B).min())
 
 
 def kr_cell(L: np.ndarray, edge: float, t_run: float, min_width: float = 3.5,
@@ -165,11 +179,11 @@ def kr_cell(L: np.ndarray, edge: float, t_run: float, min_width: float = 3.5,
     onto itself every period T = ln(mu)/k, mu = (3 + sqrt 5)/2.  Among the
     one-parameter family P = V diag(d1, d2) W^-1 (V, W eigenvectors of L and
     M) of area edge^2, the member whose minimum width over one period is
-    largest is chosen.  The z extent stays ``edge``."""
+    largest is chosen; the returned basis is the lattice's reduced one.  The
+    z extent stays ``edge``."""
     L2 = np.asarray(L, dtype=np.float64)[:2, :2]
     cube = np.eye(2) * edge
-    w_cube = _min_width_over(L2, cube, t_run, 81)
-    if w_cube >= min_width:
+    if _min_width_over(L2, cube, t_run, 61) >= min_width:
         return cubic_cell(edge), "cubic"
     a, b, c = L2[0, 0], L2[0, 1], L2[1, 0]
     k2 = a * a + b * c
@@ -179,28 +193,28 @@ def kr_cell(L: np.ndarray, edge: float, t_run: float, min_width: float = 3.5,
     evals, V = np.linalg.eig(L2)
     V = np.real(V[:, np.argsort(-np.real(evals))])  # columns: +k, -k
     mu = (3.0 + math.sqrt(5.0)) / 2.0
-    M = np.array([[2.0, 1.0], [1.0, 1.0]])
-    W = np.array([[1.0, 1.0], [mu - 2.0, 1.0 / mu - 2.0]])  # columns: mu, 1/mu
+    W = np.array([[1.0, 1.0], [mu - 2.0, 1.0 / mu - 2.0]])  # eigenvectors of M for mu, 1/mu
     Winv = np.linalg.inv(W)
     T = math.log(mu) / k
     if ratios is None:
-        ratios = np.exp(np.linspace(-4.0, 4.0, 161))
-    best, bestP = -1.0, None
+        ratios = np.exp(np.linspace(-4.0, 4.0, 81))
+    E = _flow_maps(L2, np.linspace(0.0, T, 25))  # (25, 2, 2)
+    cands = []
     for sgn in (1.0, -1.0):
         for r in ratios:
-            D = np.diag([r, sgn])
-            P = V @ D @ Winv
+            P = V @ np.diag([r, sgn]) @ Winv
             det = np.linalg.det(P)
             if abs(det) < 1e-300:
                 continue
             P = P * math.sqrt(edge * edge / abs(det))
             if np.linalg.det(P) < 0:
                 P = P[:, ::-1].copy()
-            w = _min_width_over(L2, P, T, 33)
-            if w > best:
-                best, bestP = w, P
-    assert np.allclose(np.linalg.inv(bestP) @ _flow_map(L2, T) @ bestP,
-                       np.round(np.linalg.inv(bestP) @ _flow_map(L2, T) @ bestP), atol=1e-6)
+            cands.append(P)
+    cands = np.stack(cands)  # (C, 2, 2)
+    widths = _lattice_min_widths(E[:, None] @ cands[None]).min(axis=0)  # (C,)
+    bestP = cands[int(np.argmax(widths))]
+    M = np.linalg.inv(bestP) @ _flow_map(L2, T) @ bestP
+    assert np.allclose(M, np.round(M), atol=1e-6)
     h = np.zeros((3, 3))
     h[:2, :2] = _short_basis(bestP)
     h[2, 2] = edge

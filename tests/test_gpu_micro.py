@@ -1,0 +1,334 @@
+"""GPU parity of the micro-DPD engine against the FP64 oracle, through the C ABI.
+
+Tolerances:
+  * forces from one state: ||F_gpu - F_ref|| / ||F_ref|| <= 1e-5 in FP32
+    (single-precision rounding of ~25 pair terms of size ~a), <= 1e-12 in
+    FP64;
+  * trajectories: the DPD dynamics amplify a perturbation by ~1e5 over 200
+    steps (measured on the oracle itself, a 1e-7 relative kick grows to
+    ~1e-2), so 200-step trajectories are compared in FP64, where the two
+    sides differ only by rounding order: max |dr| <= 1e-4 rc and
+    max |dc| <= 1e-4;
+  * FP32 trajectories: compared for 20 steps, max |dr|, |dc| <= 1e-3, and
+    stresses statistically: |mean_gpu - mean_oracle| <= 2 sqrt(SE_g^2 +
+    SE_o^2) per component over 10 blocks of 50 steps;
+  * pair counts (integers decided in FP64 on both sides): exact.
+Every input comes from the seeded generator; the oracle never sees device
+output.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _mod():
+    from paper_2512_13267_amd import _lib, inputs, micro
+
+    return _lib, inputs, micro
+
+
+def _grads(torch, wl):
+    return torch.tensor(np.stack([b.L for b in wl.boxes]), dtype=torch.float64, device="cuda").contiguous()
+
+
+def _oracle_boxes(orc, wl, ids=None):
+    ids = range(len(wl.boxes)) if ids is None else ids
+    return [orc.OracleBox(s=b.s, c=b.c, h=b.h, n_chains=b.n_chains, box_id=k) for b, k in zip(wl.boxes, ids)]
+
+
+def _offsets(wl):
+    return np.concatenate([[0], np.cumsum([b.N for b in wl.boxes])])
+
+
+def _min_image_dr(s1, s2, h):
+    ds = s1 - s2
+    ds -= np.round(ds)
+    return np.abs(ds @ np.asarray(h).reshape(3, 3).T).max()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-12)])
+def test_forces_match_oracle_ragged_boxes(torch_gpu, orc, precision, tol):
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(5)
+    p = wl.params
+    m = micro.from_workload(wl, precision=precision)
+    Ls = np.stack([b.L for b in wl.boxes])
+    f, vir = m.forces(Ls)
+    off = _offsets(wl)
+    for k, b in enumerate(wl.boxes):
+        Fr, Wr, err = orc.forces(p, p["seed"], p["chain_len"], k, b.n_chains, b.s, b.c, b.h, b.L, 0)
+        Fg = f[off[k]:off[k + 1]]
+        rel = np.linalg.norm(Fg - Fr) / np.linalg.norm(Fr)
+        assert rel <= tol, (k, rel)
+        Wpair = Wr[:3].sum(axis=0)
+        assert np.abs(vir[k, 0] - Wpair).max() <= 10 * tol * np.abs(Wpair).max() + 1e-9
+        assert np.abs(vir[k, 1] - Wr[3]).max() <= 10 * tol * np.abs(Wr[3]).max() + 1e-9
+    m.close()
+
+
+def test_forces_match_oracle_large_box_and_rng_id(torch_gpu, orc):
+    """A 24-rc box (41,472 particles, close to the per-box cell limit) with a
+    non-default random-stream id and a sheared cell."""
+    _lib, inputs, micro = _mod()
+    wl = inputs.single_box(seed_k=3, edge=24.0, polymer_fraction=0.2, shear_rate=0.3)
+    b = wl.boxes[0]
+    h = b.h.copy()
+    h[0, 1] = 0.3 * 24.0
+    s, c = inputs.random_box(np.random.default_rng(17), h, b.N, b.n_chains, 10)
+    p = wl.params
+    m = micro.Micro(p, [(b.N, b.n_chains, h, 4242)], precision="fp32")
+    m.set_state(s, c, h, step=123)
+    f, vir = m.forces(b.L.reshape(1, 9))
+    Fr, Wr, _ = orc.forces(p, p["seed"], 10, 4242, b.n_chains, s, c, h, b.L, 123)
+    assert np.linalg.norm(f - Fr) / np.linalg.norm(Fr) <= 1e-5
+    m.close()
+
+
+def test_fp64_trajectory_200_steps_single_box(torch_gpu, orc):
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.single_box()  # 3000 particles, 30 chains, shear rate 0.1
+    p = wl.params
+    m = micro.from_workload(wl, precision="fp64")
+    out = m.step(_grads(torch, wl), 200)
+    torch.cuda.synchronize()
+    s, c, h, step = m.get_state()
+    ob = _oracle_boxes(orc, wl)[0]
+    mean, parts, _ = orc.run_box(p, p["seed"], 10, ob, wl.boxes[0].L, 200)
+    assert step == ob.step == 200
+    assert np.allclose(h[0], ob.h, rtol=0, atol=1e-10)
+    assert _min_image_dr(s, ob.s, ob.h) <= 1e-4
+    assert np.abs(c - ob.c).max() <= 1e-4
+    g = out.cpu().numpy()[0]
+    assert np.abs(g - mean).max() <= 1e-6 * np.abs(mean).max()
+    gp = m.stress_parts()[0]
+    assert np.abs(gp[0] - parts[0]).max() <= 1e-6 * np.abs(mean).max()           # kinetic
+    assert np.abs(gp[1] - parts[1:4].sum(axis=0)).max() <= 1e-6 * np.abs(mean).max()  # DPD pairs
+    assert np.abs(gp[2] - parts[4]).max() <= 1e-6 * np.abs(mean).max()           # FENE
+    assert m.flags().tolist() == [0]
+    m.close()
+
+
+def test_fp64_trajectory_200_steps_ragged_batch(torch_gpu, orc):
+    """Five boxes of 267-750 particles (ragged work blocks), five different
+    gradients, one launch sequence; each box against its own oracle run."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(5)
+    p = wl.params
+    m = micro.from_workload(wl, precision="fp64", graphs=False)
+    out = m.step(_grads(torch, wl), 200)
+    torch.cuda.synchronize()
+    s, c, h, _ = m.get_state()
+    obs = _oracle_boxes(orc, wl)
+    means, _ = orc.run_batch(p, p["seed"], 10, obs, [b.L for b in wl.boxes], 200)
+    off = _offsets(wl)
+    g = out.cpu().numpy()
+    for k, ob in enumerate(obs):
+        assert _min_image_dr(s[off[k]:off[k + 1]], ob.s, ob.h) <= 1e-4, k
+        assert np.abs(c[off[k]:off[k + 1]] - ob.c).max() <= 1e-4, k
+        assert np.abs(g[k] - means[k]).max() <= 1e-6 * np.abs(means[k]).max(), k
+    m.close()
+
+
+def test_pair_counts_exact_fp64(torch_gpu, orc):
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(3, seed_k=11)
+    p = wl.params
+    m = micro.from_workload(wl, precision="fp64")
+    nsteps = 10
+    m.step(_grads(torch, wl), nsteps)
+    counts = m.pair_counts()
+    obs = _oracle_boxes(orc, wl)
+    for k, ob in enumerate(obs):
+        total = 0
+        for _ in range(nsteps):
+            orc.run_box(p, p["seed"], 10, ob, wl.boxes[k].L, 1)
+            ij, _ = orc.pairs(ob.s, ob.h, p["rc"], 0)
+            total += len(ij)
+        assert int(counts[k]) == total
+    m.close()
+
+
+def test_fp32_short_trajectory_and_stress_statistics(torch_gpu, orc):
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.single_box()
+    p = wl.params
+    m = micro.from_workload(wl, precision="fp32")
+    G = _grads(torch, wl)
+    m.step(G, 20)
+    s, c, h, _ = m.get_state()
+    ob = _oracle_boxes(orc, wl)[0]
+    orc.run_box(p, p["seed"], 10, ob, wl.boxes[0].L, 20)
+    assert _min_image_dr(s, ob.s, ob.h) <= 1e-3
+    assert np.abs(c - ob.c).max() <= 1e-3
+    gb, ob_means = [], []
+    for _ in range(10):
+        gb.append(m.step(G, 50).cpu().numpy()[0])
+        ob_means.append(orc.run_box(p, p["seed"], 10, ob, wl.boxes[0].L, 50)[0])
+    gb, ob_means = np.array(gb), np.array(ob_means)
+    se = np.sqrt(gb.var(axis=0, ddof=1) / len(gb) + ob_means.var(axis=0, ddof=1) / len(ob_means))
+    diff = np.abs(gb.mean(axis=0) - ob_means.mean(axis=0))
+    assert np.all(diff <= 2 * se), (diff, se)
+    m.close()
+
+
+def test_graph_replay_equals_eager_bitwise(torch_gpu):
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(4, seed_k=21)
+    G = _grads(torch, wl)
+    res = []
+    for graphs in (True, False):
+        m = micro.from_workload(wl, precision="fp32", graphs=graphs)
+        outs = [m.step(G, 37).cpu().numpy() for _ in range(3)]  # 37 steps: one chunk shape, replayed
+        s, c, h, st = m.get_state()
+        res.append((outs, s, c, h, st))
+        m.close()
+    (o1, s1, c1, h1, t1), (o2, s2, c2, h2, t2) = res
+    assert t1 == t2 == 111
+    assert np.array_equal(s1, s2) and np.array_equal(c1, c2) and np.array_equal(h1, h2)
+    for a, b in zip(o1, o2):
+        assert np.array_equal(a, b)
+
+
+def test_box_in_batch_equals_box_alone(torch_gpu):
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(4, seed_k=23)
+    mb = micro.from_workload(wl, precision="fp32")
+    ob = mb.step(_grads(torch, wl), 60).cpu().numpy()
+    sb, cb, _, _ = mb.get_state()
+    off = _offsets(wl)
+    k = 2
+    one = inputs.Workload("one", wl.params, [wl.boxes[k]], 0)
+    ms = micro.from_workload(one, precision="fp32", rng_ids=[k])
+    os_ = ms.step(_grads(torch, one), 60).cpu().numpy()
+    ss, cs, _, _ = ms.get_state()
+    assert np.array_equal(ss, sb[off[k]:off[k + 1]])
+    assert np.array_equal(cs, cb[off[k]:off[k + 1]])
+    assert np.array_equal(os_[0], ob[k])
+    mb.close()
+    ms.close()
+
+
+def test_state_roundtrip_resume_is_exact(torch_gpu):
+    """get_state -> set_state (with the carried forces) -> continue equals an
+    uninterrupted run bitwise (the random stream is counter-based, so the
+    state is (s, c, F, h, step))."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(2, seed_k=29)
+    G = _grads(torch, wl)
+    for prec in ("fp32", "fp64"):
+        a = micro.from_workload(wl, precision=prec)
+        a.step(G, 30)
+        a.step(G, 30)
+        sa, ca, ha, ta = a.get_state()
+        b = micro.from_workload(wl, precision=prec)
+        b.step(G, 30)
+        s, c, h, t, f = b.get_state(with_forces=True)
+        b2 = micro.from_workload(wl, precision=prec)
+        b2.set_state(s, c, h.reshape(-1, 9), t, f=f)
+        b2.step(G, 30)
+        sb, cb, hb, tb = b2.get_state()
+        assert ta == tb == 60
+        assert np.array_equal(ha, hb)
+        assert np.array_equal(sa, sb) and np.array_equal(ca, cb)
+        for e in (a, b, b2):
+            e.close()
+
+
+def test_flags_and_errors(torch_gpu):
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(3, seed_k=31)
+    m = micro.from_workload(wl, precision="fp32")
+    G = _grads(torch, wl)
+    with pytest.raises(_lib.LhmmError) as ei:
+        m.step(G, 0)
+    assert ei.value.code == _lib.LHMM_ERR_ARG
+    # a non-traceless gradient on box 1 flags that box only
+    bad = G.clone()
+    bad[1, 1, 1] = 0.3
+    m.step(bad, 5)
+    fl = m.flags(clear=True)
+    assert fl[1] & _lib.FLAG_ARG and not fl[0] & _lib.FLAG_ARG and not fl[2] & _lib.FLAG_ARG
+    # a bond stretched past R0 flags BOND
+    s = np.concatenate([b.s for b in wl.boxes])
+    c = np.concatenate([b.c for b in wl.boxes])
+    h0 = wl.boxes[0].h
+    s[1] = s[0] + np.linalg.inv(h0) @ np.array([1.01 * wl.params["R0"], 0, 0])
+    s[1] -= np.floor(s[1])
+    s = np.asarray(s, dtype=np.float32).astype(np.float64)
+    s[s >= 1.0] = 0.0
+    m.set_state(s, c, None, 0)
+    m.step(G, 1)
+    assert m.flags()[0] & _lib.FLAG_BOND
+    with pytest.raises(_lib.LhmmError):
+        m.set_state(s * 2.0 + 1.0, c)  # s outside [0, 1)
+    m.close()
+    # stepping before any state is loaded
+    m2 = micro.Micro(wl.params, [(b.N, b.n_chains, b.h) for b in wl.boxes])
+    with pytest.raises(_lib.LhmmError) as ei:
+        m2.step(G, 1)
+    assert ei.value.code == _lib.LHMM_ERR_STATE
+    m2.close()
+
+
+def test_cell_guard_flags_collapsing_box(torch_gpu):
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.single_box(edge=4.2, polymer_fraction=0.0, shear_rate=0.0)
+    wl.boxes[0].L = inputs.planar_gradient(0.5, 0.0, 0.0)
+    m = micro.from_workload(wl, precision="fp32")
+    m.step(_grads(torch, wl), 200)
+    assert m.flags()[0] & _lib.FLAG_CELL
+    m.close()
+
+
+def test_full_batch_sampled_parity(torch_gpu, orc):
+    """The 256-box batch (1.5k-12k particles per box, KR-aligned cells) in
+    the launch configuration the benchmark times: forces of sampled boxes
+    at the initial state, then 200 FP64 steps of the whole batch against
+    the oracle on the sampled boxes."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.batch()
+    p = wl.params
+    sizes = np.array([b.N for b in wl.boxes])
+    sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 100, 201})
+    off = _offsets(wl)
+    m = micro.from_workload(wl, precision="fp32")
+    f, _ = m.forces(np.stack([b.L.reshape(9) for b in wl.boxes]))
+    for k in sample:
+        b = wl.boxes[k]
+        Fr, _, _ = orc.forces(p, p["seed"], 10, k, b.n_chains, b.s, b.c, b.h, b.L, 0)
+        assert np.linalg.norm(f[off[k]:off[k + 1]] - Fr) / np.linalg.norm(Fr) <= 1e-5, k
+    m.close()
+    m = micro.from_workload(wl, precision="fp64")
+    out = m.step(_grads(torch, wl), 200).cpu().numpy()
+    s, c, h, _ = m.get_state()
+    obs = [orc.OracleBox(s=wl.boxes[k].s, c=wl.boxes[k].c, h=wl.boxes[k].h, n_chains=wl.boxes[k].n_chains,
+                         box_id=k) for k in sample]
+    means, _ = orc.run_batch(p, p["seed"], 10, obs, [wl.boxes[k].L for k in sample], 200)
+    for q, k in enumerate(sample):
+        assert _min_image_dr(s[off[k]:off[k + 1]], obs[q].s, obs[q].h) <= 1e-4, k
+        assert np.abs(c[off[k]:off[k + 1]] - obs[q].c).max() <= 1e-4, k
+        assert np.abs(out[k] - means[q]).max() <= 1e-6 * np.abs(means[q]).max(), k
+    assert not np.any(m.flags() & (_lib.FLAG_CELL | _lib.FLAG_BOND | _lib.FLAG_NONFINITE))
+    m.close()
