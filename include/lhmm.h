@@ -69,7 +69,10 @@ extern "C" {
 #define LHMM_FP32 0 /* single-precision particle state and pair forces     */
 #define LHMM_FP64 1 /* double-precision particle state and pair forces     */
 
-#define LHMM_OPT_NO_GRAPH 1 /* launch every kernel eagerly (no HIP graphs) */
+#define LHMM_OPT_NO_GRAPH 1      /* launch every kernel eagerly (no HIP graphs) */
+#define LHMM_OPT_DETERMINISTIC 2 /* evaluate every ordered pair in its own     */
+                                 /* particle's work block, no float atomics:    */
+                                 /* bitwise reproducible, about 2x the pair work */
 
 typedef struct lhmm_micro lhmm_micro;
 

@@ -101,8 +101,9 @@ struct Ctx {
     void* f;
     int* pcell;
     int* cell_start;
-    int* cell_list;
-    double* part_vir;   // n_blocks x 12: pair virial (ordered pairs), FENE virial
+    void* cell_pos;     // per box, cell-sorted (s0, s1, s2, local index) as 4 reals
+    double* part_vir;   // n_blocks x 12: pair virial, FENE virial
+    double vir_scale;   // 1 when each pair is evaluated once, 1/2 when twice
     double* part_kin;   // n_blocks x 6
     unsigned* part_pairs;  // n_blocks: ordered pairs within the cutoff
     double* acc;        // n_boxes x 18: kinetic, pair, FENE stress sums
@@ -161,6 +162,25 @@ __device__ __forceinline__ real pair_theta(unsigned id_i, unsigned id_j, unsigne
     philox4x32_10(x0, x1, x2, x3, k0, k1);
     return box_muller<real>(x0, x1);
 }
+
+// ---------------------------------------------------------------------------
+// Cell-sorted particle records: (s0, s1, s2, local index) in one 4-vector
+// ---------------------------------------------------------------------------
+
+template <typename real>
+struct Rec;
+template <>
+struct Rec<float> {
+    using T = float4;
+    __device__ static T make(float x, float y, float z, int id) { return make_float4(x, y, z, __int_as_float(id)); }
+    __device__ static int id(T v) { return __float_as_int(v.w); }
+};
+template <>
+struct Rec<double> {
+    using T = double4;
+    __device__ static T make(double x, double y, double z, int id) { return make_double4(x, y, z, (double)id); }
+    __device__ static int id(T v) { return (int)v.w; }
+};
 
 // ---------------------------------------------------------------------------
 // FP64 cell algebra (row-major 3x3; columns are lattice vectors)
@@ -417,11 +437,17 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
         s[i] = s0; s[N + i] = s1; s[2 * N + i] = s2;
     }
     C.pcell[i] = cell_of(s0, s1, s2, D.nc);
+    // forces of the new positions are accumulated from zero by k_forces
+    real* fw = (real*)C.f;
+    fw[i] = 0; fw[N + i] = 0; fw[2 * N + i] = 0;
 }
 
-// One workgroup per box: counting sort by cell in LDS, then every cell's
-// list sorted by particle index.
+// One workgroup per box: counting sort by cell in LDS, writing each
+// particle's record (position, local index) in cell order; every cell's
+// records are then sorted by index so all later sums have a fixed order.
+template <typename real>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
+    using R = Rec<real>;
     __shared__ int cnt[MAX_CELLS_PER_BOX];
     __shared__ int wsum[BIN_THREADS / 64];
     const int b = blockIdx.x;
@@ -462,112 +488,241 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
     }
     if (threadIdx.x == 0) start[ncell] = carry;
     __syncthreads();
-    int* list = C.cell_list + B.off;
+    typename R::T* rec = (typename R::T*)C.cell_pos + B.off;
+    const real* s = (const real*)C.s;
+    const int N = C.n_total;
     for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) {
         const int pos = atomicAdd(&cnt[pc[k]], 1);
-        list[pos] = B.off + k;
+        const int g = B.off + k;
+        rec[pos] = R::make(s[g], s[N + g], s[2 * N + g], k);
     }
     __threadfence_block();
     __syncthreads();
     for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) {
         const int q0 = start[k], q1 = start[k + 1];
-        for (int q = q0 + 1; q < q1; ++q) {  // insertion sort, a few entries
-            const int v = list[q];
+        for (int q = q0 + 1; q < q1; ++q) {  // insertion sort by index, a few entries
+            const typename R::T v = rec[q];
+            const int key = R::id(v);
             int r = q - 1;
-            while (r >= q0 && list[r] > v) {
-                list[r + 1] = list[r];
+            while (r >= q0 && R::id(rec[r]) > key) {
+                rec[r + 1] = rec[r];
                 --r;
             }
-            list[r + 1] = v;
+            rec[r + 1] = v;
         }
     }
 }
 
-template <typename real>
+// Stencil of neighbour cells: index 0 is the particle's own cell; with
+// HALF only the 13 cells after it in (d0, d1, d2) order follow, otherwise
+// all 26 others.
+__device__ __forceinline__ void stencil_offset(int k, bool half, int& d0, int& d1, int& d2) {
+    if (k == 0) {
+        d0 = d1 = d2 = 0;
+        return;
+    }
+    // full: the 26 non-zero offsets; half: the 13 lexicographically positive ones
+    int e = half ? k + 13 : (k <= 13 ? k - 1 : k);
+    d0 = e / 9 - 1;
+    d1 = (e / 3) % 3 - 1;
+    d2 = e % 3 - 1;
+}
+
+constexpr int QCAP = 128;  // per-wave ring of accepted pairs (power of two, >= 127)
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pair forces (Eqs. conservative, dissipative, random) and FENE bonds (Eq.
+// fene_force).  Each lane owns one particle in cell order and walks its
+// candidate neighbours (cell-sorted records, 27 or 14 cells); accepted pairs
+// (0 < r < rc) are compacted into a per-wave LDS ring, and whenever 64 are
+// waiting all lanes evaluate one pair each: relative velocity including the
+// streaming difference L d, Philox normal, force, virial.  Forces on the
+// block's own particles accumulate in LDS.  With HALF each unordered pair is
+// evaluated once and the reaction on a particle outside the block goes to
+// global memory atomically; without HALF every ordered pair is evaluated by
+// its first particle's block and no global atomics are used (deterministic).
+template <typename real, bool HALF>
 __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
-    __shared__ double sh[13 * (BS / 64)];
+    using R = Rec<real>;
+    constexpr int NW = BS / 64;
+    __shared__ real f_l[3][BS];
+    __shared__ real c_l[3][BS];
+    __shared__ int pid_l[BS];
+    __shared__ real q_d[3][NW][QCAP];
+    __shared__ int q_i[NW][QCAP];
+    __shared__ int q_j[NW][QCAP];
+    __shared__ int q_js[NW][QCAP];
+    __shared__ double red[13 * NW];
+
     const int blk = blockIdx.x;
     const int b = C.blk_box[blk];
     const BoxInfo B = C.box[b];
     const BoxDyn& D = C.dyn[b];
-    const int i = C.blk_first[blk] + (int)threadIdx.x;
-    const bool act = i < B.off + B.n;
     const int N = C.n_total;
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    const int p0 = C.blk_first[blk] - B.off;  // first cell-order position of the block
+    const int pos = p0 + t;
+    const bool act = pos < B.n;
+    const typename R::T* rec = (const typename R::T*)C.cell_pos + B.off;
     const real* s = (const real*)C.s;
     const real* c = (const real*)C.c;
     real* f = (real*)C.f;
-    real h[9], L[4];
-    for (int k = 0; k < 9; ++k) h[k] = (real)D.h[k];
-    L[0] = (real)D.L[0]; L[1] = (real)D.L[1]; L[2] = (real)D.L[3]; L[3] = (real)D.L[4];
+
+    real si0 = 0, si1 = 0, si2 = 0;
+    int i = -1;
+    if (act) {
+        const typename R::T v = rec[pos];
+        si0 = v.x; si1 = v.y; si2 = v.z;
+        i = B.off + R::id(v);
+    }
+    pid_l[t] = i;
+    for (int k = 0; k < 3; ++k) {
+        c_l[k][t] = act ? c[k * N + i] : (real)0;
+        f_l[k][t] = 0;
+    }
+    __syncthreads();
+
+    // in-plane cell and gradient
+    const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
+    const real h22 = (real)D.h[8];
+    const real L00 = (real)D.L[0], L01 = (real)D.L[1], L10 = (real)D.L[3], L11 = (real)D.L[4];
     const int n0 = D.nc[0], n1 = D.nc[1], n2 = D.nc[2];
     const unsigned stepc = (unsigned)(*C.step + (unsigned long long)step_offset);
-    const real a = (real)C.a, gam = (real)C.gamma, sig = (real)(C.sigma * C.rdt), rc = (real)C.rc;
+    const real a = (real)C.a, gam = (real)C.gamma, sig = (real)(C.sigma * C.rdt);
     const real rc2 = (real)C.rc2, irc = (real)(1.0 / C.rc);
+    const int* start = C.cell_start + B.cell_off;
+    const int own_id = i - B.off;
 
-    real fx = 0, fy = 0, fz = 0;
-    real w[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    unsigned npairs = 0;
+    int k0 = 0, k1 = 0, k2 = 0;
     if (act) {
-        const unsigned id_i = (unsigned)(i - B.off);
-        const real si0 = s[i], si1 = s[N + i], si2 = s[2 * N + i];
-        const real ci0 = c[i], ci1 = c[N + i], ci2 = c[2 * N + i];
-        const int pc = C.pcell[i];
-        const int k2 = pc % n2, k1 = (pc / n2) % n1, k0 = pc / (n1 * n2);
-        const int* start = C.cell_start + B.cell_off;
-        const int* list = C.cell_list + B.off;
-        for (int d0 = -1; d0 <= 1; ++d0) {
-            int m0 = k0 + d0;
-            real sh0 = 0;
-            if (m0 < 0) { m0 += n0; sh0 = -1; }
-            if (m0 >= n0) { m0 -= n0; sh0 = 1; }
-            for (int d1 = -1; d1 <= 1; ++d1) {
-                int m1 = k1 + d1;
-                real sh1 = 0;
-                if (m1 < 0) { m1 += n1; sh1 = -1; }
-                if (m1 >= n1) { m1 -= n1; sh1 = 1; }
-                for (int d2 = -1; d2 <= 1; ++d2) {
-                    int m2 = k2 + d2;
-                    real sh2 = 0;
-                    if (m2 < 0) { m2 += n2; sh2 = -1; }
-                    if (m2 >= n2) { m2 -= n2; sh2 = 1; }
-                    const int cc = (m0 * n1 + m1) * n2 + m2;
-                    const int q1 = start[cc + 1];
-                    for (int q = start[cc]; q < q1; ++q) {
-                        const int j = list[q];
-                        if (j == i) continue;
-                        const real ds0 = si0 - (s[j] + sh0);
-                        const real ds1 = si1 - (s[N + j] + sh1);
-                        const real ds2 = si2 - (s[2 * N + j] + sh2);
-                        const real dx = h[0] * ds0 + h[1] * ds1 + h[2] * ds2;
-                        const real dy = h[3] * ds0 + h[4] * ds1 + h[5] * ds2;
-                        const real dz = h[6] * ds0 + h[7] * ds1 + h[8] * ds2;
-                        const real r2 = dx * dx + dy * dy + dz * dz;
-                        if (r2 < rc2 && r2 > (real)0) {
-                            const real r = sqrt(r2);
-                            const real ir = (real)1 / r;
-                            const real ex = dx * ir, ey = dy * ir, ez = dz * ir;
-                            const real wR = (real)1 - r * irc;
-                            // relative velocity of i and the image of j
-                            const real vx = ci0 - c[j] + L[0] * dx + L[1] * dy;
-                            const real vy = ci1 - c[N + j] + L[2] * dx + L[3] * dy;
-                            const real vz = ci2 - c[2 * N + j];
-                            const real ev = ex * vx + ey * vy + ez * vz;
-                            const real th = pair_theta<real>(id_i, (unsigned)(j - B.off), stepc, B.rng_id,
-                                                             C.key0, C.key1);
-                            const real mag = wR * (a - gam * wR * ev + sig * th);
-                            const real gx = mag * ex, gy = mag * ey, gz = mag * ez;
-                            fx += gx; fy += gy; fz += gz;
-                            w[0] += dx * gx; w[1] += dy * gy; w[2] += dz * gz;
-                            w[3] += dx * gy; w[4] += dx * gz; w[5] += dy * gz;
-                            ++npairs;
-                        }
-                    }
+        const int pc = cell_of(si0, si1, si2, D.nc);
+        k2 = pc % n2;
+        k1 = (pc / n2) % n1;
+        k0 = pc / (n1 * n2);
+    }
+    constexpr int NSTEN = HALF ? 14 : 27;
+    int dc = 0, q = 0, qe = 0;
+    real sh0 = 0, sh1 = 0, sh2 = 0;
+    bool live = act;
+    int head = 0, tail = 0;
+    real w[6] = {0, 0, 0, 0, 0, 0};
+    unsigned npairs = 0;
+
+    // evaluate ring entries head .. head + n - 1 (one per lane)
+    auto process = [&](int n) {
+        wave_sync_lds();
+        if (lane < n) {
+            const int e = (head + lane) & (QCAP - 1);
+            const real dx = q_d[0][wv][e], dy = q_d[1][wv][e], dz = q_d[2][wv][e];
+            const int is = q_i[wv][e], jg = q_j[wv][e], js = q_js[wv][e];
+            real cj0, cj1, cj2;
+            if (js >= 0) {
+                cj0 = c_l[0][js]; cj1 = c_l[1][js]; cj2 = c_l[2][js];
+            } else {
+                cj0 = c[jg]; cj1 = c[N + jg]; cj2 = c[2 * N + jg];
+            }
+            const real r2 = dx * dx + dy * dy + dz * dz;
+            const real r = sqrt(r2);
+            const real ir = (real)1 / r;
+            const real ex = dx * ir, ey = dy * ir, ez = dz * ir;
+            const real wR = (real)1 - r * irc;
+            const real vx = c_l[0][is] - cj0 + L00 * dx + L01 * dy;
+            const real vy = c_l[1][is] - cj1 + L10 * dx + L11 * dy;
+            const real vz = c_l[2][is] - cj2;
+            const real ev = ex * vx + ey * vy + ez * vz;
+            const real th = pair_theta<real>((unsigned)(pid_l[is] - B.off), (unsigned)(jg - B.off), stepc, B.rng_id,
+                                             C.key0, C.key1);
+            const real mag = wR * (a - gam * wR * ev + sig * th);
+            const real gx = mag * ex, gy = mag * ey, gz = mag * ez;
+            atomicAdd(&f_l[0][is], gx);
+            atomicAdd(&f_l[1][is], gy);
+            atomicAdd(&f_l[2][is], gz);
+            if (HALF) {
+                if (js >= 0) {
+                    atomicAdd(&f_l[0][js], -gx);
+                    atomicAdd(&f_l[1][js], -gy);
+                    atomicAdd(&f_l[2][js], -gz);
+                } else {
+                    atomicAdd(&f[jg], -gx);
+                    atomicAdd(&f[N + jg], -gy);
+                    atomicAdd(&f[2 * N + jg], -gz);
                 }
             }
+            w[0] += dx * gx; w[1] += dy * gy; w[2] += dz * gz;
+            w[3] += dx * gy; w[4] += dx * gz; w[5] += dy * gz;
+            ++npairs;
         }
+        head += n;
+        wave_sync_lds();
+    };
+
+    while (__ballot(live) != 0ull) {
+        bool acc = false;
+        real dx = 0, dy = 0, dz = 0;
+        int jg = 0, jq = 0;
+        if (live) {
+            while (q >= qe && dc < NSTEN) {
+                int d0, d1, d2;
+                stencil_offset(dc, HALF, d0, d1, d2);
+                int m0 = k0 + d0, m1 = k1 + d1, m2 = k2 + d2;
+                sh0 = 0; sh1 = 0; sh2 = 0;
+                if (m0 < 0) { m0 += n0; sh0 = -1; } else if (m0 >= n0) { m0 -= n0; sh0 = 1; }
+                if (m1 < 0) { m1 += n1; sh1 = -1; } else if (m1 >= n1) { m1 -= n1; sh1 = 1; }
+                if (m2 < 0) { m2 += n2; sh2 = -1; } else if (m2 >= n2) { m2 -= n2; sh2 = 1; }
+                const int cc = (m0 * n1 + m1) * n2 + m2;
+                q = start[cc];
+                qe = start[cc + 1];
+                if (HALF && dc == 0) q = pos + 1;  // own cell: later records only
+                ++dc;
+            }
+            if (q < qe) {
+                const typename R::T v = rec[q];
+                const int jl = R::id(v);
+                if (HALF || jl != own_id) {
+                    const real ds0 = si0 - (v.x + sh0), ds1 = si1 - (v.y + sh1), ds2 = si2 - (v.z + sh2);
+                    dx = h00 * ds0 + h01 * ds1;
+                    dy = h10 * ds0 + h11 * ds1;
+                    dz = h22 * ds2;
+                    const real r2 = dx * dx + dy * dy + dz * dz;
+                    acc = r2 < rc2 && r2 > (real)0;
+                    jg = B.off + jl;
+                    jq = q;
+                }
+                ++q;
+            } else {
+                live = false;
+            }
+        }
+        const unsigned long long mask = __ballot(acc);
+        if (acc) {
+            const unsigned lo = (unsigned)mask, hi = (unsigned)(mask >> 32);
+            const int below = (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+            const int e = (tail + below) & (QCAP - 1);
+            q_d[0][wv][e] = dx;
+            q_d[1][wv][e] = dy;
+            q_d[2][wv][e] = dz;
+            q_i[wv][e] = t;
+            q_j[wv][e] = jg;
+            q_js[wv][e] = (jq >= p0 && jq < p0 + BS) ? jq - p0 : -1;
+        }
+        tail += __popcll(mask);
+        if (tail - head >= 64) process(64);
+    }
+    while (tail - head > 0) process(min(64, tail - head));
+    __syncthreads();
+
+    real fx = 0, fy = 0, fz = 0;
+    real wf[6] = {0, 0, 0, 0, 0, 0};
+    if (act) {
+        fx = f_l[0][t]; fy = f_l[1][t]; fz = f_l[2][t];
         // FENE springs to the chain neighbours
-        if ((int)id_i < B.n_beads) {
-            const int bead = (int)id_i % C.chain_len;
+        if (own_id < B.n_beads) {
+            const int bead = own_id % C.chain_len;
             const real Hf = (real)C.H, iR02 = (real)C.inv_R02;
             for (int side = 0; side < 2; ++side) {
                 if (side == 0 && bead == 0) continue;
@@ -575,9 +730,7 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
                 const int j = side == 0 ? i - 1 : i + 1;
                 real ds0 = si0 - s[j], ds1 = si1 - s[N + j], ds2 = si2 - s[2 * N + j];
                 ds0 -= rint(ds0); ds1 -= rint(ds1); ds2 -= rint(ds2);
-                const real dx = h[0] * ds0 + h[1] * ds1 + h[2] * ds2;
-                const real dy = h[3] * ds0 + h[4] * ds1 + h[5] * ds2;
-                const real dz = h[6] * ds0 + h[7] * ds1 + h[8] * ds2;
+                const real dx = h00 * ds0 + h01 * ds1, dy = h10 * ds0 + h11 * ds1, dz = h22 * ds2;
                 real den = (real)1 - (dx * dx + dy * dy + dz * dz) * iR02;
                 if (den <= (real)0) atomicOr(&C.flags[b], LHMM_FLAG_BOND);
                 if (den < (real)0.01) den = (real)0.01;
@@ -585,17 +738,26 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
                 const real gx = k * dx, gy = k * dy, gz = k * dz;
                 fx += gx; fy += gy; fz += gz;
                 if (side == 1) {  // each bond's virial once, by its lower bead
-                    w[6] += dx * gx; w[7] += dy * gy; w[8] += dz * gz;
-                    w[9] += dx * gy; w[10] += dx * gz; w[11] += dy * gz;
+                    wf[0] += dx * gx; wf[1] += dy * gy; wf[2] += dz * gz;
+                    wf[3] += dx * gy; wf[4] += dx * gz; wf[5] += dy * gz;
                 }
             }
         }
-        f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
+        if (HALF) {
+            atomicAdd(&f[i], fx);
+            atomicAdd(&f[N + i], fy);
+            atomicAdd(&f[2 * N + i], fz);
+        } else {
+            f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
+        }
     }
     double v[13];
-    for (int k = 0; k < 12; ++k) v[k] = (double)w[k];
+    for (int k = 0; k < 6; ++k) {
+        v[k] = (double)w[k];
+        v[6 + k] = (double)wf[k];
+    }
     v[12] = (double)npairs;
-    block_sum<13>(v, sh);
+    block_sum<13>(v, red);
     if (threadIdx.x == 0) {
         for (int k = 0; k < 12; ++k) C.part_vir[12 * blk + k] = v[k];
         C.part_pairs[blk] = (unsigned)v[12];
@@ -649,14 +811,14 @@ __global__ void k_box_stress(Ctx C) {
         double* acc = C.acc + 18 * b;
         bool finite = true;
         for (int q = 0; q < 6; ++q) {
-            const double sk = -K[q] * iv, sp = -0.5 * W[q] * iv, sf = -W[6 + q] * iv;
+            const double sk = -K[q] * iv, sp = -C.vir_scale * W[q] * iv, sf = -W[6 + q] * iv;
             acc[q] += sk;
             acc[6 + q] += sp;
             acc[12 + q] += sf;
             if (!(fabs(sk + sp + sf) <= 1e300)) finite = false;
         }
         if (!finite) C.flags[b] |= LHMM_FLAG_NONFINITE;
-        C.acc_pairs[b] += np / 2;
+        C.acc_pairs[b] += C.vir_scale < 1.0 ? np / 2 : np;
     }
     if (b == 0) *C.step += 1ull;
 }
@@ -691,7 +853,9 @@ struct lhmm_micro {
     unsigned* d_flags = nullptr;
     int *d_blk_box = nullptr, *d_blk_first = nullptr;
     void *d_s = nullptr, *d_c = nullptr, *d_f = nullptr;
-    int *d_pcell = nullptr, *d_cell_start = nullptr, *d_cell_list = nullptr;
+    int *d_pcell = nullptr, *d_cell_start = nullptr;
+    void* d_cell_pos = nullptr;
+    bool deterministic = false;
     double *d_part_vir = nullptr, *d_part_kin = nullptr;
     unsigned* d_part_pairs = nullptr;
     double *d_acc = nullptr, *d_parts = nullptr, *d_gradL = nullptr;
@@ -709,8 +873,11 @@ void launch_step_kernels(lhmm_micro* m, int step_offset, bool advance, bool full
     const int bt = 256, bg = (m->n_boxes + bt - 1) / bt;
     k_cell_step<<<bg, bt, 0, m->stream>>>(C, advance ? 1 : 0);
     k_kick_drift<real><<<m->n_blocks, BS, 0, m->stream>>>(C, advance ? 1 : 0);
-    k_bin_box<<<m->n_boxes, BIN_THREADS, 0, m->stream>>>(C);
-    k_forces<real><<<m->n_blocks, BS, 0, m->stream>>>(C, step_offset);
+    k_bin_box<real><<<m->n_boxes, BIN_THREADS, 0, m->stream>>>(C);
+    if (m->deterministic)
+        k_forces<real, false><<<m->n_blocks, BS, 0, m->stream>>>(C, step_offset);
+    else
+        k_forces<real, true><<<m->n_blocks, BS, 0, m->stream>>>(C, step_offset);
     if (full_step) {
         k_kick2<real><<<m->n_blocks, BS, 0, m->stream>>>(C);
         k_box_stress<<<bg, bt, 0, m->stream>>>(C);
@@ -730,10 +897,13 @@ void launch_step_timed(lhmm_micro* m, hipEvent_t* ev) {
     k_kick_drift<real><<<m->n_blocks, BS, 0, st>>>(C, 1);
     (void)hipEventRecord(ev[3], st);
     (void)hipEventRecord(ev[4], st);
-    k_bin_box<<<m->n_boxes, BIN_THREADS, 0, st>>>(C);
+    k_bin_box<real><<<m->n_boxes, BIN_THREADS, 0, st>>>(C);
     (void)hipEventRecord(ev[5], st);
     (void)hipEventRecord(ev[6], st);
-    k_forces<real><<<m->n_blocks, BS, 0, st>>>(C, 1);
+    if (m->deterministic)
+        k_forces<real, false><<<m->n_blocks, BS, 0, st>>>(C, 1);
+    else
+        k_forces<real, true><<<m->n_blocks, BS, 0, st>>>(C, 1);
     (void)hipEventRecord(ev[7], st);
     (void)hipEventRecord(ev[8], st);
     k_kick2<real><<<m->n_blocks, BS, 0, st>>>(C);
@@ -797,7 +967,7 @@ void release(lhmm_micro* m) {
     for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
     m->graphs.clear();
     void* bufs[] = {m->d_box, m->d_dyn, m->d_flags, m->d_blk_box, m->d_blk_first, m->d_s, m->d_c, m->d_f,
-                    m->d_pcell, m->d_cell_start, m->d_cell_list, m->d_part_vir, m->d_part_kin,
+                    m->d_pcell, m->d_cell_start, m->d_cell_pos, m->d_part_vir, m->d_part_kin,
                     m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_step};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -839,6 +1009,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->precision = p->precision;
     m->real_size = p->precision == LHMM_FP64 ? sizeof(double) : sizeof(float);
     m->user_stream = (hipStream_t)stream;
+    m->deterministic = (p->flags & LHMM_OPT_DETERMINISTIC) != 0;
 
     long long off = 0;
     int cell_off = 0, blk_off = 0;
@@ -900,7 +1071,6 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     ALLOC(m->d_blk_first, (size_t)m->n_blocks);
     ALLOC(m->d_pcell, N);
     ALLOC(m->d_cell_start, (size_t)cell_off);
-    ALLOC(m->d_cell_list, N);
     ALLOC(m->d_part_vir, (size_t)m->n_blocks * 12);
     ALLOC(m->d_part_kin, (size_t)m->n_blocks * 6);
     ALLOC(m->d_part_pairs, (size_t)m->n_blocks);
@@ -912,8 +1082,9 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
 #undef ALLOC
     if (rc == LHMM_OK) {
         const size_t bytes = 3 * N * m->real_size;
-        for (void** pp : {&m->d_s, &m->d_c, &m->d_f}) {
-            if (hipMalloc(pp, bytes ? bytes : 1) != hipSuccess) {
+        for (void** pp : {&m->d_s, &m->d_c, &m->d_f, &m->d_cell_pos}) {
+            const size_t nb = pp == &m->d_cell_pos ? 4 * N * m->real_size : bytes;
+            if (hipMalloc(pp, nb ? nb : 1) != hipSuccess) {
                 rc = fail(LHMM_ERR_OOM, "hipMalloc of particle arrays failed");
                 break;
             }
@@ -966,7 +1137,8 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     C.f = m->d_f;
     C.pcell = m->d_pcell;
     C.cell_start = m->d_cell_start;
-    C.cell_list = m->d_cell_list;
+    C.cell_pos = m->d_cell_pos;
+    C.vir_scale = m->deterministic ? 0.5 : 1.0;
     C.part_vir = m->d_part_vir;
     C.part_kin = m->d_part_kin;
     C.part_pairs = m->d_part_pairs;
