@@ -1310,7 +1310,7 @@ int lhmm_micro_forces(lhmm_micro* m, const double* gradL, double* f_out, double*
             for (int q = 0; q < 12; ++q) o[q] = 0.0;
             for (int k = 0; k < m->box[b].nblk; ++k)
                 for (int q = 0; q < 12; ++q) o[q] += pv[12 * (size_t)(m->box[b].blk_off + k) + q];
-            for (int q = 0; q < 6; ++q) o[q] *= 0.5;  // ordered pairs count each pair twice
+            for (int q = 0; q < 6; ++q) o[q] *= m->ctx.vir_scale;  // ordered pairs count each pair twice
         }
     }
     return LHMM_OK;
