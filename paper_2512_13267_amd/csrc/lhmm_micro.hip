@@ -513,20 +513,11 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
     }
 }
 
-// Stencil of neighbour cells: index 0 is the particle's own cell; with
-// HALF only the 13 cells after it in (d0, d1, d2) order follow, otherwise
-// all 26 others.
-__device__ __forceinline__ void stencil_offset(int k, bool half, int& d0, int& d1, int& d2) {
-    if (k == 0) {
-        d0 = d1 = d2 = 0;
-        return;
-    }
-    // full: the 26 non-zero offsets; half: the 13 lexicographically positive ones
-    int e = half ? k + 13 : (k <= 13 ? k - 1 : k);
-    d0 = e / 9 - 1;
-    d1 = (e / 3) % 3 - 1;
-    d2 = e % 3 - 1;
-}
+// Neighbour-cell stencil: entry 0 is the particle's own cell; then the 13
+// offsets that follow (0, 0, 0) in (d0, d1, d2) order (half stencil), then
+// the 13 that precede it.  Packed as (d0 + 1) * 9 + (d1 + 1) * 3 + (d2 + 1).
+__constant__ int c_stencil[27] = {13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26,
+                                  0,  1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12};
 
 constexpr int QCAP = 128;  // per-wave ring of accepted pairs (power of two, >= 127)
 
@@ -536,9 +527,18 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <typename real>
+__device__ __forceinline__ real inv_sqrt(real x);
+template <>
+__device__ __forceinline__ float inv_sqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <>
+__device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt(x); }
+
 // Pair forces (Eqs. conservative, dissipative, random) and FENE bonds (Eq.
-// fene_force).  Each lane owns one particle in cell order and walks its
-// candidate neighbours (cell-sorted records, 27 or 14 cells); accepted pairs
+// fene_force).  Each lane owns one particle in cell order.  The wave walks
+// the neighbour-cell stencil in step (27 cells, or the own cell plus the 13
+// after it), each lane scanning its own neighbour cell two records at a
+// time; lanes of one home cell read the same records.  Accepted pairs
 // (0 < r < rc) are compacted into a per-wave LDS ring, and whenever 64 are
 // waiting all lanes evaluate one pair each: relative velocity including the
 // streaming difference L d, Philox normal, force, virial.  Forces on the
@@ -549,14 +549,14 @@ __device__ __forceinline__ void wave_sync_lds() {
 template <typename real, bool HALF>
 __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
     using R = Rec<real>;
+    using V4 = typename R::T;
     constexpr int NW = BS / 64;
     __shared__ real f_l[3][BS];
     __shared__ real c_l[3][BS];
     __shared__ int pid_l[BS];
     __shared__ real q_d[3][NW][QCAP];
-    __shared__ int q_i[NW][QCAP];
+    __shared__ int q_ij[NW][QCAP];  // (slot of i) | (slot of j + 1) << 16, slot of j = -1 outside the block
     __shared__ int q_j[NW][QCAP];
-    __shared__ int q_js[NW][QCAP];
     __shared__ double red[13 * NW];
 
     const int blk = blockIdx.x;
@@ -568,7 +568,7 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
     const int p0 = C.blk_first[blk] - B.off;  // first cell-order position of the block
     const int pos = p0 + t;
     const bool act = pos < B.n;
-    const typename R::T* rec = (const typename R::T*)C.cell_pos + B.off;
+    const V4* rec = (const V4*)C.cell_pos + B.off;
     const real* s = (const real*)C.s;
     const real* c = (const real*)C.c;
     real* f = (real*)C.f;
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
     real si0 = 0, si1 = 0, si2 = 0;
     int i = -1;
     if (act) {
-        const typename R::T v = rec[pos];
+        const V4 v = rec[pos];
         si0 = v.x; si1 = v.y; si2 = v.z;
         i = B.off + R::id(v);
     }
@@ -605,10 +605,6 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
         k1 = (pc / n2) % n1;
         k0 = pc / (n1 * n2);
     }
-    constexpr int NSTEN = HALF ? 14 : 27;
-    int dc = 0, q = 0, qe = 0;
-    real sh0 = 0, sh1 = 0, sh2 = 0;
-    bool live = act;
     int head = 0, tail = 0;
     real w[6] = {0, 0, 0, 0, 0, 0};
     unsigned npairs = 0;
@@ -619,7 +615,8 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
         if (lane < n) {
             const int e = (head + lane) & (QCAP - 1);
             const real dx = q_d[0][wv][e], dy = q_d[1][wv][e], dz = q_d[2][wv][e];
-            const int is = q_i[wv][e], jg = q_j[wv][e], js = q_js[wv][e];
+            const int ij = q_ij[wv][e], jg = q_j[wv][e];
+            const int is = ij & 0xFFFF, js = (ij >> 16) - 1;
             real cj0, cj1, cj2;
             if (js >= 0) {
                 cj0 = c_l[0][js]; cj1 = c_l[1][js]; cj2 = c_l[2][js];
@@ -627,8 +624,8 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
                 cj0 = c[jg]; cj1 = c[N + jg]; cj2 = c[2 * N + jg];
             }
             const real r2 = dx * dx + dy * dy + dz * dz;
-            const real r = sqrt(r2);
-            const real ir = (real)1 / r;
+            const real ir = inv_sqrt(r2);
+            const real r = r2 * ir;
             const real ex = dx * ir, ey = dy * ir, ez = dz * ir;
             const real wR = (real)1 - r * irc;
             const real vx = c_l[0][is] - cj0 + L00 * dx + L01 * dy;
@@ -660,58 +657,61 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
         head += n;
         wave_sync_lds();
     };
-
-    while (__ballot(live) != 0ull) {
+    // test one candidate record at cell-order position q and queue it if accepted
+    auto push = [&](bool valid, const V4& v, int q, real sh0, real sh1, real sh2) {
         bool acc = false;
         real dx = 0, dy = 0, dz = 0;
-        int jg = 0, jq = 0;
-        if (live) {
-            while (q >= qe && dc < NSTEN) {
-                int d0, d1, d2;
-                stencil_offset(dc, HALF, d0, d1, d2);
-                int m0 = k0 + d0, m1 = k1 + d1, m2 = k2 + d2;
-                sh0 = 0; sh1 = 0; sh2 = 0;
-                if (m0 < 0) { m0 += n0; sh0 = -1; } else if (m0 >= n0) { m0 -= n0; sh0 = 1; }
-                if (m1 < 0) { m1 += n1; sh1 = -1; } else if (m1 >= n1) { m1 -= n1; sh1 = 1; }
-                if (m2 < 0) { m2 += n2; sh2 = -1; } else if (m2 >= n2) { m2 -= n2; sh2 = 1; }
-                const int cc = (m0 * n1 + m1) * n2 + m2;
-                q = start[cc];
-                qe = start[cc + 1];
-                if (HALF && dc == 0) q = pos + 1;  // own cell: later records only
-                ++dc;
-            }
-            if (q < qe) {
-                const typename R::T v = rec[q];
-                const int jl = R::id(v);
-                if (HALF || jl != own_id) {
-                    const real ds0 = si0 - (v.x + sh0), ds1 = si1 - (v.y + sh1), ds2 = si2 - (v.z + sh2);
-                    dx = h00 * ds0 + h01 * ds1;
-                    dy = h10 * ds0 + h11 * ds1;
-                    dz = h22 * ds2;
-                    const real r2 = dx * dx + dy * dy + dz * dz;
-                    acc = r2 < rc2 && r2 > (real)0;
-                    jg = B.off + jl;
-                    jq = q;
-                }
-                ++q;
-            } else {
-                live = false;
-            }
+        const int jl = R::id(v);
+        if (valid && (HALF || jl != own_id)) {
+            const real ds0 = si0 - (v.x + sh0), ds1 = si1 - (v.y + sh1), ds2 = si2 - (v.z + sh2);
+            dx = h00 * ds0 + h01 * ds1;
+            dy = h10 * ds0 + h11 * ds1;
+            dz = h22 * ds2;
+            const real r2 = dx * dx + dy * dy + dz * dz;
+            acc = r2 < rc2 && r2 > (real)0;
         }
         const unsigned long long mask = __ballot(acc);
         if (acc) {
             const unsigned lo = (unsigned)mask, hi = (unsigned)(mask >> 32);
             const int below = (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
             const int e = (tail + below) & (QCAP - 1);
+            const int js = (q >= p0 && q < p0 + BS) ? q - p0 : -1;
             q_d[0][wv][e] = dx;
             q_d[1][wv][e] = dy;
             q_d[2][wv][e] = dz;
-            q_i[wv][e] = t;
-            q_j[wv][e] = jg;
-            q_js[wv][e] = (jq >= p0 && jq < p0 + BS) ? jq - p0 : -1;
+            q_ij[wv][e] = t | ((js + 1) << 16);
+            q_j[wv][e] = B.off + jl;
         }
         tail += __popcll(mask);
         if (tail - head >= 64) process(64);
+    };
+
+    constexpr int NSTEN = HALF ? 14 : 27;
+    for (int ds = 0; ds < NSTEN; ++ds) {
+        const int code = c_stencil[ds];
+        int m0 = k0 + code / 9 - 1, m1 = k1 + (code / 3) % 3 - 1, m2 = k2 + code % 3 - 1;
+        const real sh0 = m0 < 0 ? (real)-1 : (m0 >= n0 ? (real)1 : (real)0);
+        const real sh1 = m1 < 0 ? (real)-1 : (m1 >= n1 ? (real)1 : (real)0);
+        const real sh2 = m2 < 0 ? (real)-1 : (m2 >= n2 ? (real)1 : (real)0);
+        m0 -= (int)sh0 * n0;
+        m1 -= (int)sh1 * n1;
+        m2 -= (int)sh2 * n2;
+        const int cc = (m0 * n1 + m1) * n2 + m2;
+        int q = 0, qe = 0;
+        if (act) {
+            q = start[cc];
+            qe = start[cc + 1];
+            if (HALF && ds == 0) q = pos + 1;  // own cell: later records only
+        }
+        while (__ballot(q < qe) != 0ull) {
+            const bool v0ok = q < qe, v1ok = q + 1 < qe;
+            // out-of-range lanes read record 0 (always present) and discard it
+            const V4 v0 = rec[v0ok ? q : 0];
+            const V4 v1 = rec[v1ok ? q + 1 : 0];
+            push(v0ok, v0, q, sh0, sh1, sh2);
+            push(v1ok, v1, q + 1, sh0, sh1, sh2);
+            q += 2;
+        }
     }
     while (tail - head > 0) process(min(64, tail - head));
     __syncthreads();
