@@ -32,8 +32,22 @@ VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 # Algorithmic VALU lane-cycles of one unordered pair (derivation in the
 # design notes): Philox4x32-10 (10 rounds x (2 quarter-rate 32x32->64-bit
 # multiplies + 2 three-input xors) = 100), Box-Muller (3 quarter-rate
-# transcendentals + 4 = 16), force, scatter and virial arithmetic (50).
-PAIR_LANE_CYCLES = 166.0
+# transcendentals + 8 = 20), geometry (15), relative velocity (10), force and
+# its two updates (13), virial (6).
+PAIR_LANE_CYCLES = 164.0
+
+
+def measured_traffic(kernel_file: str, record: str):
+    """HBM bytes per launch from a committed profiler record, or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", record)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(os.path.join(ROOT, kernel_file), "rb").read()).hexdigest()
+    return rec["hbm_bytes_per_launch"] if rec.get("source_sha256") == sha else None
 
 
 def cpu_baseline(wl, budget_s: float = 12.0):
@@ -64,7 +78,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=100)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 2^27 floats (512 MiB read, 512 MiB written) five "
+                         "times, to scale the HBM byte counters of a profiler run")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        x = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": x.numel() * 4, "copy_calibration_bytes_written": y.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the micro-boxes are independent and "
               "would shard by box across GPUs, which this build does not do.", file=sys.stderr)
@@ -101,9 +128,12 @@ def main():
     pairs_timing = int(m.pair_counts().sum()) / args.timing_steps
     f_ms = kt["forces"]
     achieved = PAIR_LANE_CYCLES * pairs_timing / (f_ms * 1e-3)
+    traffic = measured_traffic("paper_2512_13267_amd/csrc/lhmm_micro.hip", "k_forces_batch256_traffic.json")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                "unit": "T VALU lane-ops/s", "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None,
-                "kernel": "k_forces", "kernel_ms": f_ms, "kernel_ms_all": kt}
+                "unit": "T VALU lane-ops/s", "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch", "kernel": "k_forces", "kernel_ms": f_ms,
+                "kernel_ms_all": kt, "pairs_per_launch": pairs_timing,
+                "hbm_GBps": (traffic / (f_ms * 1e-3) / 1e9) if traffic else None}
 
     rec = {
         "metric": "micro-DPD pair-force updates/s",
@@ -122,7 +152,9 @@ def main():
                                "U(0.1,0.3) in 10-bead chains, constant planar gradients U(-0.5,0.5), "
                                "FP32 forces / FP64 stress",
                    "n_boxes": len(wl.boxes), "n_particles": n_particles,
-                   "pairs_per_step": pairs / args.steps, "flagged_boxes": int(np.count_nonzero(flags))},
+                   "pairs_per_step": pairs / args.steps,
+                   "flagged_boxes": {"bond": int(np.count_nonzero(flags & 1)), "cell": int(np.count_nonzero(flags & 2)),
+                                     "nonfinite": int(np.count_nonzero(flags & 4))}},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

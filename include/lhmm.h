@@ -26,6 +26,9 @@
  *   - micro boxes persist between calls (continuous-intermittent coupling,
  *     Sec. "Temporal Coupling Scheme").
  *
+ * Results are reproducible bit for bit: every sum has a fixed order (no
+ * floating-point atomics to global memory).
+ *
  * Conventions
  *   - Matrices are 3x3 row-major doubles.  A cell h has the lattice vectors
  *     as columns (r = h s, s in [0,1)^3).  A velocity gradient L maps
@@ -69,10 +72,7 @@ extern "C" {
 #define LHMM_FP32 0 /* single-precision particle state and pair forces     */
 #define LHMM_FP64 1 /* double-precision particle state and pair forces     */
 
-#define LHMM_OPT_NO_GRAPH 1      /* launch every kernel eagerly (no HIP graphs) */
-#define LHMM_OPT_DETERMINISTIC 2 /* evaluate every ordered pair in its own     */
-                                 /* particle's work block, no float atomics:    */
-                                 /* bitwise reproducible, about 2x the pair work */
+#define LHMM_OPT_NO_GRAPH 1 /* launch every kernel eagerly (no HIP graphs) */
 
 typedef struct lhmm_micro lhmm_micro;
 

@@ -26,7 +26,6 @@ FLAG_ARG = 8
 FP32 = 0
 FP64 = 1
 OPT_NO_GRAPH = 1
-OPT_DETERMINISTIC = 2
 
 # every symbol include/lhmm.h declares
 EXPORTS = (

@@ -101,7 +101,8 @@ struct Ctx {
     void* f;
     int* pcell;
     int* cell_start;
-    void* cell_pos;     // per box, cell-sorted (s0, s1, s2, local index) as 4 reals
+    void* cell_pos;     // per box, cell-sorted (x, y, z, local index) as 4 reals, r = h s
+    void* cell_vel;     // per box, cell-sorted (cx, cy, cz, local index) as 4 reals
     double* part_vir;   // n_blocks x 12: pair virial, FENE virial
     double vir_scale;   // 1 when each pair is evaluated once, 1/2 when twice
     double* part_kin;   // n_blocks x 6
@@ -164,7 +165,7 @@ __device__ __forceinline__ real pair_theta(unsigned id_i, unsigned id_j, unsigne
 }
 
 // ---------------------------------------------------------------------------
-// Cell-sorted particle records: (s0, s1, s2, local index) in one 4-vector
+// Cell-sorted particle records: (x, y, z, local index) in one 4-vector
 // ---------------------------------------------------------------------------
 
 template <typename real>
@@ -321,6 +322,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh /* NV * (B
 // Kernels
 // ---------------------------------------------------------------------------
 
+constexpr int N_XCD = 8;  // MI355X: workgroups are dealt to the 8 XCDs round robin
+
+// Work item of workgroup b out of n, chosen so that each XCD (b mod 8) gets
+// one contiguous run of work items: the blocks of a box then share one L2.
+__device__ __forceinline__ int xcd_local_work(int b, int n) {
+    const int x = b % N_XCD, l = b / N_XCD;
+    const int per = n / N_XCD, rem = n % N_XCD;
+    return x * per + min(x, rem) + l;
+}
+
 // Per call: take each box's gradient (device array n_boxes x 9), validate,
 // and form exp(L dt), exp(L dt/2).
 __global__ void k_setup_call(Ctx C, const double* __restrict__ gradL) {
@@ -437,9 +448,6 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
         s[i] = s0; s[N + i] = s1; s[2 * N + i] = s2;
     }
     C.pcell[i] = cell_of(s0, s1, s2, D.nc);
-    // forces of the new positions are accumulated from zero by k_forces
-    real* fw = (real*)C.f;
-    fw[i] = 0; fw[N + i] = 0; fw[2 * N + i] = 0;
 }
 
 // One workgroup per box: counting sort by cell in LDS, writing each
@@ -491,10 +499,13 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
     typename R::T* rec = (typename R::T*)C.cell_pos + B.off;
     const real* s = (const real*)C.s;
     const int N = C.n_total;
+    const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
+    const real h22 = (real)D.h[8];
     for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) {
         const int pos = atomicAdd(&cnt[pc[k]], 1);
         const int g = B.off + k;
-        rec[pos] = R::make(s[g], s[N + g], s[2 * N + g], k);
+        const real s0 = s[g], s1 = s[N + g], s2 = s[2 * N + g];
+        rec[pos] = R::make(h00 * s0 + h01 * s1, h10 * s0 + h11 * s1, h22 * s2, k);
     }
     __threadfence_block();
     __syncthreads();
@@ -511,20 +522,14 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
             rec[r + 1] = v;
         }
     }
-}
-
-// Neighbour-cell stencil: entry 0 is the particle's own cell; then the 13
-// offsets that follow (0, 0, 0) in (d0, d1, d2) order (half stencil), then
-// the 13 that precede it.  Packed as (d0 + 1) * 9 + (d1 + 1) * 3 + (d2 + 1).
-__constant__ int c_stencil[27] = {13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26,
-                                  0,  1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 11, 12};
-
-constexpr int QCAP = 128;  // per-wave ring of accepted pairs (power of two, >= 127)
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __threadfence_block();
+    __syncthreads();
+    typename R::T* vel = (typename R::T*)C.cell_vel + B.off;
+    const real* c = (const real*)C.c;
+    for (int q = threadIdx.x; q < B.n; q += BIN_THREADS) {
+        const int g = B.off + R::id(rec[q]);
+        vel[q] = R::make(c[g], c[N + g], c[2 * N + g], g - B.off);
+    }
 }
 
 template <typename real>
@@ -535,31 +540,29 @@ template <>
 __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt(x); }
 
 // Pair forces (Eqs. conservative, dissipative, random) and FENE bonds (Eq.
-// fene_force).  Each lane owns one particle in cell order.  The wave walks
-// the neighbour-cell stencil in step (27 cells, or the own cell plus the 13
-// after it), each lane scanning its own neighbour cell two records at a
-// time; lanes of one home cell read the same records.  Accepted pairs
-// (0 < r < rc) are compacted into a per-wave LDS ring, and whenever 64 are
-// waiting all lanes evaluate one pair each: relative velocity including the
-// streaming difference L d, Philox normal, force, virial.  Forces on the
-// block's own particles accumulate in LDS.  With HALF each unordered pair is
-// evaluated once and the reaction on a particle outside the block goes to
-// global memory atomically; without HALF every ordered pair is evaluated by
-// its first particle's block and no global atomics are used (deterministic).
-template <typename real, bool HALF>
+// fene_force).  Each lane owns one particle in cell order and sums that
+// particle's force in registers, so every ordered pair is evaluated by its
+// first particle's lane: no atomics, and a fixed summation order.
+//   Search: the wave walks the nine stencil rows in step (cells k2-1 .. k2+1
+//   of a row are contiguous in cell order, except across the periodic end of
+//   the row); each lane scans its own row range two records at a time
+//   (lanes of one home cell read the same records) and appends accepted
+//   neighbours (0 < r < rc; the particle itself has r = 0) to its own LDS
+//   queue of QD entries.
+//   Evaluation: a round pops one queued neighbour per lane and evaluates the
+//   pair (relative velocity including the streaming difference L d, Philox
+//   normal, force, virial).  A round runs whenever 56 or more lanes have work
+//   or a queue could overflow, and the queues are drained at the end.
+template <typename real>
 __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
     using R = Rec<real>;
     using V4 = typename R::T;
     constexpr int NW = BS / 64;
-    __shared__ real f_l[3][BS];
-    __shared__ real c_l[3][BS];
-    __shared__ int pid_l[BS];
-    __shared__ real q_d[3][NW][QCAP];
-    __shared__ int q_ij[NW][QCAP];  // (slot of i) | (slot of j + 1) << 16, slot of j = -1 outside the block
-    __shared__ int q_j[NW][QCAP];
+    constexpr int QD = sizeof(real) == 4 ? 8 : 4;  // queue depth per lane (power of two)
+    __shared__ V4 qbuf[QD][NW][64];                 // (dx, dy, dz, cell-order position of j)
     __shared__ double red[13 * NW];
 
-    const int blk = blockIdx.x;
+    const int blk = xcd_local_work(blockIdx.x, gridDim.x);
     const int b = C.blk_box[blk];
     const BoxInfo B = C.box[b];
     const BoxDyn& D = C.dyn[b];
@@ -569,23 +572,19 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
     const int pos = p0 + t;
     const bool act = pos < B.n;
     const V4* rec = (const V4*)C.cell_pos + B.off;
+    const V4* vel = (const V4*)C.cell_vel + B.off;
     const real* s = (const real*)C.s;
-    const real* c = (const real*)C.c;
     real* f = (real*)C.f;
 
-    real si0 = 0, si1 = 0, si2 = 0;
-    int i = -1;
+    real ri0 = 0, ri1 = 0, ri2 = 0, ci0 = 0, ci1 = 0, ci2 = 0;
+    int own_id = 0;
     if (act) {
         const V4 v = rec[pos];
-        si0 = v.x; si1 = v.y; si2 = v.z;
-        i = B.off + R::id(v);
+        ri0 = v.x; ri1 = v.y; ri2 = v.z;
+        own_id = R::id(v);
+        const V4 u = vel[pos];
+        ci0 = u.x; ci1 = u.y; ci2 = u.z;
     }
-    pid_l[t] = i;
-    for (int k = 0; k < 3; ++k) {
-        c_l[k][t] = act ? c[k * N + i] : (real)0;
-        f_l[k][t] = 0;
-    }
-    __syncthreads();
 
     // in-plane cell and gradient
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
@@ -596,132 +595,133 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
     const real a = (real)C.a, gam = (real)C.gamma, sig = (real)(C.sigma * C.rdt);
     const real rc2 = (real)C.rc2, irc = (real)(1.0 / C.rc);
     const int* start = C.cell_start + B.cell_off;
-    const int own_id = i - B.off;
 
     int k0 = 0, k1 = 0, k2 = 0;
     if (act) {
-        const int pc = cell_of(si0, si1, si2, D.nc);
+        const int pc = C.pcell[B.off + own_id];
         k2 = pc % n2;
         k1 = (pc / n2) % n1;
         k0 = pc / (n1 * n2);
     }
-    int head = 0, tail = 0;
+    int qh = 0, qt = 0;  // this lane's queue: popped, pushed
+    real fx = 0, fy = 0, fz = 0;
     real w[6] = {0, 0, 0, 0, 0, 0};
     unsigned npairs = 0;
 
-    // evaluate ring entries head .. head + n - 1 (one per lane)
-    auto process = [&](int n) {
-        wave_sync_lds();
-        if (lane < n) {
-            const int e = (head + lane) & (QCAP - 1);
-            const real dx = q_d[0][wv][e], dy = q_d[1][wv][e], dz = q_d[2][wv][e];
-            const int ij = q_ij[wv][e], jg = q_j[wv][e];
-            const int is = ij & 0xFFFF, js = (ij >> 16) - 1;
-            real cj0, cj1, cj2;
-            if (js >= 0) {
-                cj0 = c_l[0][js]; cj1 = c_l[1][js]; cj2 = c_l[2][js];
-            } else {
-                cj0 = c[jg]; cj1 = c[N + jg]; cj2 = c[2 * N + jg];
-            }
+    // one evaluation round: each lane with a queued neighbour takes the oldest
+    auto round = [&]() {
+        if (qt > qh) {
+            const V4 e = qbuf[qh & (QD - 1)][wv][lane];
+            ++qh;
+            const real dx = e.x, dy = e.y, dz = e.z;
+            const V4 cj = vel[R::id(e)];
             const real r2 = dx * dx + dy * dy + dz * dz;
             const real ir = inv_sqrt(r2);
             const real r = r2 * ir;
             const real ex = dx * ir, ey = dy * ir, ez = dz * ir;
             const real wR = (real)1 - r * irc;
-            const real vx = c_l[0][is] - cj0 + L00 * dx + L01 * dy;
-            const real vy = c_l[1][is] - cj1 + L10 * dx + L11 * dy;
-            const real vz = c_l[2][is] - cj2;
+            const real vx = ci0 - cj.x + L00 * dx + L01 * dy;
+            const real vy = ci1 - cj.y + L10 * dx + L11 * dy;
+            const real vz = ci2 - cj.z;
             const real ev = ex * vx + ey * vy + ez * vz;
-            const real th = pair_theta<real>((unsigned)(pid_l[is] - B.off), (unsigned)(jg - B.off), stepc, B.rng_id,
-                                             C.key0, C.key1);
+            const real th = pair_theta<real>((unsigned)own_id, (unsigned)R::id(cj), stepc, B.rng_id, C.key0, C.key1);
             const real mag = wR * (a - gam * wR * ev + sig * th);
             const real gx = mag * ex, gy = mag * ey, gz = mag * ez;
-            atomicAdd(&f_l[0][is], gx);
-            atomicAdd(&f_l[1][is], gy);
-            atomicAdd(&f_l[2][is], gz);
-            if (HALF) {
-                if (js >= 0) {
-                    atomicAdd(&f_l[0][js], -gx);
-                    atomicAdd(&f_l[1][js], -gy);
-                    atomicAdd(&f_l[2][js], -gz);
-                } else {
-                    atomicAdd(&f[jg], -gx);
-                    atomicAdd(&f[N + jg], -gy);
-                    atomicAdd(&f[2 * N + jg], -gz);
-                }
-            }
+            fx += gx; fy += gy; fz += gz;
             w[0] += dx * gx; w[1] += dy * gy; w[2] += dz * gz;
             w[3] += dx * gy; w[4] += dx * gz; w[5] += dy * gz;
             ++npairs;
         }
-        head += n;
-        wave_sync_lds();
     };
-    // test one candidate record at cell-order position q and queue it if accepted
-    auto push = [&](bool valid, const V4& v, int q, real sh0, real sh1, real sh2) {
-        bool acc = false;
-        real dx = 0, dy = 0, dz = 0;
-        const int jl = R::id(v);
-        if (valid && (HALF || jl != own_id)) {
-            const real ds0 = si0 - (v.x + sh0), ds1 = si1 - (v.y + sh1), ds2 = si2 - (v.z + sh2);
-            dx = h00 * ds0 + h01 * ds1;
-            dy = h10 * ds0 + h11 * ds1;
-            dz = h22 * ds2;
-            const real r2 = dx * dx + dy * dy + dz * dz;
-            acc = r2 < rc2 && r2 > (real)0;
+    // test one candidate record (position q) against (px, py, pz), the lane's
+    // position minus the image shift of the range scanned; queue it if accepted
+    auto push = [&](bool valid, const V4& v, int q, real px, real py, real pz) {
+        const real dx = px - v.x, dy = py - v.y, dz = pz - v.z;
+        const real r2 = dx * dx + dy * dy + dz * dz;
+        if (valid && r2 < rc2 && r2 > (real)0) {
+            qbuf[qt & (QD - 1)][wv][lane] = R::make(dx, dy, dz, q);
+            ++qt;
         }
-        const unsigned long long mask = __ballot(acc);
-        if (acc) {
-            const unsigned lo = (unsigned)mask, hi = (unsigned)(mask >> 32);
-            const int below = (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-            const int e = (tail + below) & (QCAP - 1);
-            const int js = (q >= p0 && q < p0 + BS) ? q - p0 : -1;
-            q_d[0][wv][e] = dx;
-            q_d[1][wv][e] = dy;
-            q_d[2][wv][e] = dz;
-            q_ij[wv][e] = t | ((js + 1) << 16);
-            q_j[wv][e] = B.off + jl;
-        }
-        tail += __popcll(mask);
-        if (tail - head >= 64) process(64);
     };
 
-    constexpr int NSTEN = HALF ? 14 : 27;
-    for (int ds = 0; ds < NSTEN; ++ds) {
-        const int code = c_stencil[ds];
-        int m0 = k0 + code / 9 - 1, m1 = k1 + (code / 3) % 3 - 1, m2 = k2 + code % 3 - 1;
-        const real sh0 = m0 < 0 ? (real)-1 : (m0 >= n0 ? (real)1 : (real)0);
-        const real sh1 = m1 < 0 ? (real)-1 : (m1 >= n1 ? (real)1 : (real)0);
-        const real sh2 = m2 < 0 ? (real)-1 : (m2 >= n2 ? (real)1 : (real)0);
-        m0 -= (int)sh0 * n0;
-        m1 -= (int)sh1 * n1;
-        m2 -= (int)sh2 * n2;
-        const int cc = (m0 * n1 + m1) * n2 + m2;
-        int q = 0, qe = 0;
+    // Scan state: the wave is at stencil row `row` (d0, d1) and range `piece`
+    // of it (0: cells max(k2-1,0) .. min(k2+1,n2-1) unshifted in z; 1: the
+    // cell across the periodic end of the row, if any); each lane scans its
+    // records q .. qe-1 against (bx, by, pz), its position minus the image
+    // shift of that range.
+    int row = 0, piece = 0;
+    int q = 0, qe = 0;
+    real bx = 0, by = 0, pz = 0;
+    auto set_range = [&]() {
+        const int d0 = row / 3 - 1, d1 = row % 3 - 1;
+        int m0 = k0 + d0, m1 = k1 + d1;
+        const int sh0 = m0 < 0 ? -1 : (m0 >= n0 ? 1 : 0);
+        const int sh1 = m1 < 0 ? -1 : (m1 >= n1 ? 1 : 0);
+        m0 -= sh0 * n0;
+        m1 -= sh1 * n1;
+        const int rb = (m0 * n1 + m1) * n2;
+        bx = ri0 - (h00 * (real)sh0 + h01 * (real)sh1);
+        by = ri1 - (h10 * (real)sh0 + h11 * (real)sh1);
+        pz = ri2;
+        q = 0;
+        qe = 0;
         if (act) {
-            q = start[cc];
-            qe = start[cc + 1];
-            if (HALF && ds == 0) q = pos + 1;  // own cell: later records only
+            const int lo = k2 - 1, hi = k2 + 1;
+            if (piece == 0) {
+                q = start[rb + max(lo, 0)];
+                qe = start[rb + min(hi, n2 - 1) + 1];
+            } else if (lo < 0) {
+                q = start[rb + n2 - 1];
+                qe = start[rb + n2];
+                pz = ri2 + h22;
+            } else if (hi >= n2) {
+                q = start[rb];
+                qe = start[rb + 1];
+                pz = ri2 - h22;
+            }
         }
-        while (__ballot(q < qe) != 0ull) {
+    };
+    set_range();
+    bool scanning = true;  // wave-uniform
+    while (true) {
+        // search until the stencil is done or some queue might not take two more
+        while (scanning) {
+            if (__ballot(q < qe) == 0ull) {
+                if (++piece == 2) {
+                    piece = 0;
+                    if (++row == 9) {
+                        scanning = false;
+                        break;
+                    }
+                }
+                set_range();
+                continue;
+            }
             const bool v0ok = q < qe, v1ok = q + 1 < qe;
             // out-of-range lanes read record 0 (always present) and discard it
             const V4 v0 = rec[v0ok ? q : 0];
             const V4 v1 = rec[v1ok ? q + 1 : 0];
-            push(v0ok, v0, q, sh0, sh1, sh2);
-            push(v1ok, v1, q + 1, sh0, sh1, sh2);
+            push(v0ok, v0, q, bx, by, pz);
+            push(v1ok, v1, q + 1, bx, by, pz);
             q += 2;
+            if (__ballot(qt - qh > QD - 2) != 0ull) break;
         }
+        if (!scanning) {
+            while (__ballot(qt > qh) != 0ull) round();
+            break;
+        }
+        // evaluate until every queue is at most half full
+        do {
+            round();
+        } while (__ballot(qt - qh > QD / 2) != 0ull);
     }
-    while (tail - head > 0) process(min(64, tail - head));
-    __syncthreads();
 
-    real fx = 0, fy = 0, fz = 0;
     real wf[6] = {0, 0, 0, 0, 0, 0};
     if (act) {
-        fx = f_l[0][t]; fy = f_l[1][t]; fz = f_l[2][t];
+        const int i = B.off + own_id;
         // FENE springs to the chain neighbours
         if (own_id < B.n_beads) {
+            const real si0 = s[i], si1 = s[N + i], si2 = s[2 * N + i];
             const int bead = own_id % C.chain_len;
             const real Hf = (real)C.H, iR02 = (real)C.inv_R02;
             for (int side = 0; side < 2; ++side) {
@@ -743,13 +743,7 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
                 }
             }
         }
-        if (HALF) {
-            atomicAdd(&f[i], fx);
-            atomicAdd(&f[N + i], fy);
-            atomicAdd(&f[2 * N + i], fz);
-        } else {
-            f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
-        }
+        f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
     }
     double v[13];
     for (int k = 0; k < 6; ++k) {
@@ -794,33 +788,41 @@ __global__ __launch_bounds__(BS) void k_kick2(Ctx C) {
         for (int k = 0; k < 6; ++k) C.part_kin[6 * blk + k] = k6[k];
 }
 
-// One thread per box: the step's stress, sigma = -(K + W)/V, by part.
-__global__ void k_box_stress(Ctx C) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < C.n_boxes) {
-        const BoxInfo B = C.box[b];
-        double K[6] = {0, 0, 0, 0, 0, 0}, W[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        unsigned long long np = 0;
-        for (int k = 0; k < B.nblk; ++k) {
-            const int blk = B.blk_off + k;
-            for (int q = 0; q < 6; ++q) K[q] += C.part_kin[6 * blk + q];
-            for (int q = 0; q < 12; ++q) W[q] += C.part_vir[12 * blk + q];
-            np += C.part_pairs[blk];
-        }
+// One wave per box: the step's stress, sigma = -(K + W)/V, by part.  Lane l
+// sums the partials of blocks l, l+64, ...; a fixed shuffle tree combines
+// the lanes, so the order of every sum is fixed.
+__global__ __launch_bounds__(64) void k_box_stress(Ctx C) {
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const BoxInfo B = C.box[b];
+    double v[19];
+    for (int q = 0; q < 19; ++q) v[q] = 0.0;
+    for (int k = lane; k < B.nblk; k += 64) {
+        const int blk = B.blk_off + k;
+        for (int q = 0; q < 6; ++q) v[q] += C.part_kin[6 * blk + q];
+        for (int q = 0; q < 12; ++q) v[6 + q] += C.part_vir[12 * blk + q];
+        v[18] += (double)C.part_pairs[blk];
+    }
+#pragma unroll
+    for (int q = 0; q < 19; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    if (lane == 0) {
         const double iv = 1.0 / C.dyn[b].vol;
         double* acc = C.acc + 18 * b;
         bool finite = true;
         for (int q = 0; q < 6; ++q) {
-            const double sk = -K[q] * iv, sp = -C.vir_scale * W[q] * iv, sf = -W[6 + q] * iv;
+            const double sk = -v[q] * iv, sp = -C.vir_scale * v[6 + q] * iv, sf = -v[12 + q] * iv;
             acc[q] += sk;
             acc[6 + q] += sp;
             acc[12 + q] += sf;
             if (!(fabs(sk + sp + sf) <= 1e300)) finite = false;
         }
         if (!finite) C.flags[b] |= LHMM_FLAG_NONFINITE;
+        const unsigned long long np = (unsigned long long)v[18];
         C.acc_pairs[b] += C.vir_scale < 1.0 ? np / 2 : np;
+        if (b == 0) *C.step += 1ull;
     }
-    if (b == 0) *C.step += 1ull;
 }
 
 __global__ void k_finalize(Ctx C, double* __restrict__ stress_out, double* __restrict__ parts_out,
@@ -855,7 +857,7 @@ struct lhmm_micro {
     void *d_s = nullptr, *d_c = nullptr, *d_f = nullptr;
     int *d_pcell = nullptr, *d_cell_start = nullptr;
     void* d_cell_pos = nullptr;
-    bool deterministic = false;
+    void* d_cell_vel = nullptr;
     double *d_part_vir = nullptr, *d_part_kin = nullptr;
     unsigned* d_part_pairs = nullptr;
     double *d_acc = nullptr, *d_parts = nullptr, *d_gradL = nullptr;
@@ -874,13 +876,10 @@ void launch_step_kernels(lhmm_micro* m, int step_offset, bool advance, bool full
     k_cell_step<<<bg, bt, 0, m->stream>>>(C, advance ? 1 : 0);
     k_kick_drift<real><<<m->n_blocks, BS, 0, m->stream>>>(C, advance ? 1 : 0);
     k_bin_box<real><<<m->n_boxes, BIN_THREADS, 0, m->stream>>>(C);
-    if (m->deterministic)
-        k_forces<real, false><<<m->n_blocks, BS, 0, m->stream>>>(C, step_offset);
-    else
-        k_forces<real, true><<<m->n_blocks, BS, 0, m->stream>>>(C, step_offset);
+    k_forces<real><<<m->n_blocks, BS, 0, m->stream>>>(C, step_offset);
     if (full_step) {
         k_kick2<real><<<m->n_blocks, BS, 0, m->stream>>>(C);
-        k_box_stress<<<bg, bt, 0, m->stream>>>(C);
+        k_box_stress<<<m->n_boxes, 64, 0, m->stream>>>(C);
     }
 }
 
@@ -900,16 +899,13 @@ void launch_step_timed(lhmm_micro* m, hipEvent_t* ev) {
     k_bin_box<real><<<m->n_boxes, BIN_THREADS, 0, st>>>(C);
     (void)hipEventRecord(ev[5], st);
     (void)hipEventRecord(ev[6], st);
-    if (m->deterministic)
-        k_forces<real, false><<<m->n_blocks, BS, 0, st>>>(C, 1);
-    else
-        k_forces<real, true><<<m->n_blocks, BS, 0, st>>>(C, 1);
+    k_forces<real><<<m->n_blocks, BS, 0, st>>>(C, 1);
     (void)hipEventRecord(ev[7], st);
     (void)hipEventRecord(ev[8], st);
     k_kick2<real><<<m->n_blocks, BS, 0, st>>>(C);
     (void)hipEventRecord(ev[9], st);
     (void)hipEventRecord(ev[10], st);
-    k_box_stress<<<bg, bt, 0, st>>>(C);
+    k_box_stress<<<m->n_boxes, 64, 0, st>>>(C);
     (void)hipEventRecord(ev[11], st);
 }
 
@@ -967,7 +963,7 @@ void release(lhmm_micro* m) {
     for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
     m->graphs.clear();
     void* bufs[] = {m->d_box, m->d_dyn, m->d_flags, m->d_blk_box, m->d_blk_first, m->d_s, m->d_c, m->d_f,
-                    m->d_pcell, m->d_cell_start, m->d_cell_pos, m->d_part_vir, m->d_part_kin,
+                    m->d_pcell, m->d_cell_start, m->d_cell_pos, m->d_cell_vel, m->d_part_vir, m->d_part_kin,
                     m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_step};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -1009,7 +1005,6 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->precision = p->precision;
     m->real_size = p->precision == LHMM_FP64 ? sizeof(double) : sizeof(float);
     m->user_stream = (hipStream_t)stream;
-    m->deterministic = (p->flags & LHMM_OPT_DETERMINISTIC) != 0;
 
     long long off = 0;
     int cell_off = 0, blk_off = 0;
@@ -1082,8 +1077,8 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
 #undef ALLOC
     if (rc == LHMM_OK) {
         const size_t bytes = 3 * N * m->real_size;
-        for (void** pp : {&m->d_s, &m->d_c, &m->d_f, &m->d_cell_pos}) {
-            const size_t nb = pp == &m->d_cell_pos ? 4 * N * m->real_size : bytes;
+        for (void** pp : {&m->d_s, &m->d_c, &m->d_f, &m->d_cell_pos, &m->d_cell_vel}) {
+            const size_t nb = (pp == &m->d_cell_pos || pp == &m->d_cell_vel) ? 4 * N * m->real_size : bytes;
             if (hipMalloc(pp, nb ? nb : 1) != hipSuccess) {
                 rc = fail(LHMM_ERR_OOM, "hipMalloc of particle arrays failed");
                 break;
@@ -1138,7 +1133,8 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     C.pcell = m->d_pcell;
     C.cell_start = m->d_cell_start;
     C.cell_pos = m->d_cell_pos;
-    C.vir_scale = m->deterministic ? 0.5 : 1.0;
+    C.cell_vel = m->d_cell_vel;
+    C.vir_scale = 0.5;  // every unordered pair is evaluated from both ends
     C.part_vir = m->d_part_vir;
     C.part_kin = m->d_part_kin;
     C.part_pairs = m->d_part_pairs;

@@ -171,8 +171,10 @@ def kr_cell(L: np.ndarray, edge: float, t_run: float, min_width: float = 3.5,
             ratios: Optional[np.ndarray] = None) -> tuple:
     """Initial in-plane lattice for a constant in-plane gradient L.
 
-    Returns (h0, kind) with kind "cubic" or "kr".  A cubic cell is kept when
-    its reduced lattice stays at least ``min_width`` wide over ``t_run``.
+    Returns (h0, kind) with kind "cubic", "kr" or "rotated".  A cubic cell is
+    kept when its reduced lattice stays at least ``min_width`` wide over
+    ``t_run``; a rotational or shear-like gradient (a^2 + bc <= 0) otherwise
+    gets the best rotated square lattice.
     Otherwise, for a hyperbolic L (a^2 + bc > 0), the lattice is aligned in
     the manner of Kraynik and Reinelt: its basis P satisfies
     exp(L T) P = P M with M = [[2, 1], [1, 1]], so the flow maps the lattice
@@ -188,7 +190,7 @@ def kr_cell(L: np.ndarray, edge: float, t_run: float, min_width: float = 3.5,
     a, b, c = L2[0, 0], L2[0, 1], L2[1, 0]
     k2 = a * a + b * c
     if k2 <= 0.0:
-        return cubic_cell(edge), "cubic"
+        return _rotated_square_cell(L2, edge, t_run), "rotated"
     k = math.sqrt(k2)
     evals, V = np.linalg.eig(L2)
     V = np.real(V[:, np.argsort(-np.real(evals))])  # columns: +k, -k
@@ -219,6 +221,24 @@ def kr_cell(L: np.ndarray, edge: float, t_run: float, min_width: float = 3.5,
     h[:2, :2] = _short_basis(bestP)
     h[2, 2] = edge
     return h, "kr"
+
+
+def _rotated_square_cell(L2: np.ndarray, edge: float, t_run: float, angles: int = 46) -> np.ndarray:
+    """For a rotational or shear-like (a^2 + bc <= 0) gradient whose cubic
+    cell narrows: the square lattice of side ``edge`` rotated to the angle
+    whose minimum width over ``t_run`` is largest (these flows stretch a
+    lattice at most linearly in time, so a wide enumeration suffices)."""
+    E = _flow_maps(L2, np.linspace(0.0, t_run, 81))
+    best, bestB = -1.0, None
+    for th in np.linspace(0.0, 0.5 * math.pi, angles, endpoint=False):
+        R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]]) * edge
+        w = float(_lattice_min_widths(E @ R, K=24).min())
+        if w > best:
+            best, bestB = w, R
+    h = np.zeros((3, 3))
+    h[:2, :2] = _short_basis(bestB)
+    h[2, 2] = edge
+    return h
 
 
 def _short_basis(B: np.ndarray, K: int = 12) -> np.ndarray:

@@ -28,7 +28,7 @@ class Micro:
     """
 
     def __init__(self, params: dict, boxes: Sequence, precision: str = "fp32", graphs: bool = True,
-                 stream=None, deterministic: bool = False):
+                 stream=None):
         import torch
 
         if not torch.cuda.is_available():
@@ -40,7 +40,7 @@ class Micro:
         p.seed = int(params["seed"]) & ((1 << 64) - 1)
         p.chain_len = int(params["chain_len"])
         p.precision = {"fp32": _lib.FP32, "fp64": _lib.FP64}[precision]
-        p.flags = (0 if graphs else _lib.OPT_NO_GRAPH) | (_lib.OPT_DETERMINISTIC if deterministic else 0)
+        p.flags = 0 if graphs else _lib.OPT_NO_GRAPH
         arr = (LhmmBox * len(boxes))()
         for k, spec in enumerate(boxes):
             n, nch, h0 = spec[0], spec[1], spec[2]
@@ -150,12 +150,11 @@ class Micro:
             pass
 
 
-def from_workload(wl, precision: str = "fp32", graphs: bool = True, rng_ids=None,
-                  deterministic: bool = False) -> Micro:
+def from_workload(wl, precision: str = "fp32", graphs: bool = True, rng_ids=None) -> Micro:
     """Engine holding every box of an ``inputs.Workload`` with its initial state loaded."""
     ids = range(len(wl.boxes)) if rng_ids is None else rng_ids
     boxes = [(b.N, b.n_chains, b.h, k) for b, k in zip(wl.boxes, ids)]
-    m = Micro(wl.params, boxes, precision=precision, graphs=graphs, deterministic=deterministic)
+    m = Micro(wl.params, boxes, precision=precision, graphs=graphs)
     s = np.concatenate([b.s for b in wl.boxes])
     c = np.concatenate([b.c for b in wl.boxes])
     h = np.stack([b.h.reshape(9) for b in wl.boxes])

@@ -58,13 +58,12 @@ def _min_image_dr(s1, s2, h):
     return np.abs(ds @ np.asarray(h).reshape(3, 3).T).max()
 
 
-@pytest.mark.parametrize("deterministic", [False, True])
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-12)])
-def test_forces_match_oracle_ragged_boxes(torch_gpu, orc, precision, tol, deterministic):
+def test_forces_match_oracle_ragged_boxes(torch_gpu, orc, precision, tol):
     _lib, inputs, micro = _mod()
     wl = inputs.tiny_boxes(5)
     p = wl.params
-    m = micro.from_workload(wl, precision=precision, deterministic=deterministic)
+    m = micro.from_workload(wl, precision=precision)
     Ls = np.stack([b.L for b in wl.boxes])
     f, vir = m.forces(Ls)
     off = _offsets(wl)
@@ -97,13 +96,12 @@ def test_forces_match_oracle_large_box_and_rng_id(torch_gpu, orc):
     m.close()
 
 
-@pytest.mark.parametrize("deterministic", [False, True])
-def test_fp64_trajectory_200_steps_single_box(torch_gpu, orc, deterministic):
+def test_fp64_trajectory_200_steps_single_box(torch_gpu, orc):
     torch = torch_gpu
     _lib, inputs, micro = _mod()
     wl = inputs.single_box()  # 3000 particles, 30 chains, shear rate 0.1
     p = wl.params
-    m = micro.from_workload(wl, precision="fp64", deterministic=deterministic)
+    m = micro.from_workload(wl, precision="fp64")
     out = m.step(_grads(torch, wl), 200)
     torch.cuda.synchronize()
     s, c, h, step = m.get_state()
@@ -145,13 +143,12 @@ def test_fp64_trajectory_200_steps_ragged_batch(torch_gpu, orc):
     m.close()
 
 
-@pytest.mark.parametrize("deterministic", [False, True])
-def test_pair_counts_exact_fp64(torch_gpu, orc, deterministic):
+def test_pair_counts_exact_fp64(torch_gpu, orc):
     torch = torch_gpu
     _lib, inputs, micro = _mod()
     wl = inputs.tiny_boxes(3, seed_k=11)
     p = wl.params
-    m = micro.from_workload(wl, precision="fp64", deterministic=deterministic)
+    m = micro.from_workload(wl, precision="fp64")
     nsteps = 10
     m.step(_grads(torch, wl), nsteps)
     counts = m.pair_counts()
@@ -197,7 +194,7 @@ def test_graph_replay_equals_eager_bitwise(torch_gpu):
     G = _grads(torch, wl)
     res = []
     for graphs in (True, False):
-        m = micro.from_workload(wl, precision="fp32", graphs=graphs, deterministic=True)
+        m = micro.from_workload(wl, precision="fp32", graphs=graphs)
         outs = [m.step(G, 37).cpu().numpy() for _ in range(3)]  # 37 steps: one chunk shape, replayed
         s, c, h, st = m.get_state()
         res.append((outs, s, c, h, st))
@@ -213,13 +210,13 @@ def test_box_in_batch_equals_box_alone(torch_gpu):
     torch = torch_gpu
     _lib, inputs, micro = _mod()
     wl = inputs.tiny_boxes(4, seed_k=23)
-    mb = micro.from_workload(wl, precision="fp32", deterministic=True)
+    mb = micro.from_workload(wl, precision="fp32")
     ob = mb.step(_grads(torch, wl), 60).cpu().numpy()
     sb, cb, _, _ = mb.get_state()
     off = _offsets(wl)
     k = 2
     one = inputs.Workload("one", wl.params, [wl.boxes[k]], 0)
-    ms = micro.from_workload(one, precision="fp32", rng_ids=[k], deterministic=True)
+    ms = micro.from_workload(one, precision="fp32", rng_ids=[k])
     os_ = ms.step(_grads(torch, one), 60).cpu().numpy()
     ss, cs, _, _ = ms.get_state()
     assert np.array_equal(ss, sb[off[k]:off[k + 1]])
@@ -238,14 +235,14 @@ def test_state_roundtrip_resume_is_exact(torch_gpu):
     wl = inputs.tiny_boxes(2, seed_k=29)
     G = _grads(torch, wl)
     for prec in ("fp32", "fp64"):
-        a = micro.from_workload(wl, precision=prec, deterministic=True)
+        a = micro.from_workload(wl, precision=prec)
         a.step(G, 30)
         a.step(G, 30)
         sa, ca, ha, ta = a.get_state()
-        b = micro.from_workload(wl, precision=prec, deterministic=True)
+        b = micro.from_workload(wl, precision=prec)
         b.step(G, 30)
         s, c, h, t, f = b.get_state(with_forces=True)
-        b2 = micro.from_workload(wl, precision=prec, deterministic=True)
+        b2 = micro.from_workload(wl, precision=prec)
         b2.set_state(s, c, h.reshape(-1, 9), t, f=f)
         b2.step(G, 30)
         sb, cb, hb, tb = b2.get_state()
@@ -254,18 +251,6 @@ def test_state_roundtrip_resume_is_exact(torch_gpu):
         assert np.array_equal(sa, sb) and np.array_equal(ca, cb)
         for e in (a, b, b2):
             e.close()
-
-
-def test_default_mode_matches_deterministic_mode(torch_gpu):
-    """The half-stencil (atomic) and full-stencil (deterministic) force paths
-    agree to single-precision rounding from the same state."""
-    _lib, inputs, micro = _mod()
-    wl = inputs.tiny_boxes(4, seed_k=27)
-    Ls = np.stack([b.L for b in wl.boxes])
-    fa, va = micro.from_workload(wl, precision="fp32").forces(Ls)
-    fb, vb = micro.from_workload(wl, precision="fp32", deterministic=True).forces(Ls)
-    assert np.linalg.norm(fa - fb) / np.linalg.norm(fb) < 2e-6
-    assert np.abs(va - vb).max() < 1e-5 * np.abs(vb).max()
 
 
 def test_flags_and_errors(torch_gpu):
