@@ -29,8 +29,8 @@ if ROOT not in sys.path:
 # MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz; one full-rate
 # VALU lane-operation per lane per cycle (FMA counted once).
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
-# Algorithmic VALU lane-cycles of one unordered pair (derivation in the
-# design notes): Philox4x32-10 (10 rounds x (2 quarter-rate 32x32->64-bit
+# Algorithmic VALU lane-cycles of one unordered pair:
+# Philox4x32-10 (10 rounds x (2 quarter-rate 32x32->64-bit
 # multiplies + 2 three-input xors) = 100), Box-Muller (3 quarter-rate
 # transcendentals + 8 = 20), geometry (15), relative velocity (10), force and
 # its two updates (13), virial (6).

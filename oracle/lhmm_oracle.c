@@ -24,8 +24,7 @@
  *     v = L r.  Here it is imposed homogeneously: the periodic cell deforms
  *     with dh/dt = L h and particles carry peculiar velocities c = v - L r.
  *
- * Readings taken where the paper is silent or garbled (each is listed in
- * the design notes):
+ * Readings taken where the paper is silent or garbled:
  *   - the discrete random force carries 1/sqrt(dt);
  *   - w^R(r) = 1 - r/rc and w^D = (w^R)^2; sigma = sqrt(2 gamma kBT);
  *   - bonded pairs also feel the DPD pair forces (the sum in Eq. F_DPD runs
