@@ -180,6 +180,74 @@ int lhmm_micro_sizes(const lhmm_micro* m, int64_t* n_total, int32_t* n_boxes);
 /* Release every resource of the engine (waits for its stream).  NULL ok. */
 int lhmm_micro_destroy(lhmm_micro* m);
 
+/* ------------------------------------------------------------------------
+ * Macro side: 2-D SPH in a periodic box and the coupled exchange interval.
+ *   - number density d_I = sum_J W(r_IJ), rho_I = m d_I, Tait pressure
+ *     p = c^2 rho0/7 ((rho/rho0)^7 - 1) + theta c^2 rho0/7 (Eq. tait);
+ *   - momentum, Eq. (sph_continuity): pressure, viscous (a = 2 eta - zeta,
+ *     b = 4 zeta + 2 eta) and micro-to-macro polymer terms, plus a body
+ *     force per unit mass of +F x-hat where y >= Ly/2 and -F x-hat below;
+ *   - quintic kernel of support radius h: W = 63/(478 pi h^2)
+ *     [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5]_+, q = 3 r / h;
+ *   - velocity-Verlet steps (Appendix "Detailed Coupling Protocol");
+ *   - velocity gradient for the micro-domains, Eq. (macro_micro) with the
+ *     volume factor 1/d_J; the micro-domain of particle I is driven by
+ *     L_I = lambda* x the traceless part of (grad v_I)^T (the isochoric part
+ *     of the weakly compressible flow);
+ *   - the polymer stress fed back is alpha/lambda* x the in-plane part of
+ *     the micro-domain's deviatoric mean stress (Eq. pip).
+ * ------------------------------------------------------------------------ */
+typedef struct lhmm_sph lhmm_sph;
+
+typedef struct {
+    double rho0;        /* reference density                                 */
+    double eta;         /* solvent shear viscosity eta_s                     */
+    double zeta;        /* solvent bulk viscosity                            */
+    double c;           /* artificial sound speed                            */
+    double theta;       /* background-pressure factor (< 1)                  */
+    double F;           /* body force magnitude per unit mass                */
+    double h;           /* kernel support radius                             */
+    double dt;          /* macro time step                                   */
+    double mass;        /* particle mass                                     */
+    double Lx, Ly;      /* periodic box                                      */
+    double lambda_star; /* time-scale ratio lambda*                          */
+    double alpha;       /* viscosity ratio alpha                             */
+} lhmm_sph_params;
+
+/* Allocate an SPH engine of n particles.  r0, v0: host n x 2.  stream: the
+ * caller's hipStream_t (all SPH work is launched on it).  Errors: ARG, HIP,
+ * OOM. */
+int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const double* v0, void* stream,
+                    lhmm_sph** out);
+
+/* One velocity-Verlet step with the polymer stress of the given micro
+ * stresses held fixed, then the micro-domain gradients at the new state.
+ *   sigma: DEVICE n x 6 (micro mean stresses xx,yy,zz,xy,xz,yz) or NULL for
+ *          no polymer stress;
+ *   gradL_out: DEVICE n x 9 (may be NULL).
+ * Asynchronous on the engine's stream.  Errors: ARG, HIP. */
+int lhmm_sph_step(lhmm_sph* s, const double* sigma, double* gradL_out);
+
+/* State to host: r, v n x 2, d n (any may be NULL).  Synchronous. */
+int lhmm_sph_get_state(lhmm_sph* s, double* r, double* v, double* d);
+
+/* Host copies of the coupling state kept by the engine for
+ * lhmm_couple_step: the micro stresses of the last interval (n x 6) and the
+ * micro gradients of the last SPH step (n x 9); either may be NULL.
+ * Synchronous. */
+int lhmm_sph_coupling_state(lhmm_sph* s, double* sigma, double* gradL);
+
+/* One exchange interval of the coupling protocol (Appendix "Detailed
+ * Coupling Protocol", Steps 1-4, with one SPH step per interval): SPH step
+ * with the stored micro stresses, gradients to the micro-domains, k_micro
+ * micro steps of every box, their mean stresses stored for the next
+ * interval.  The micro engine must hold one box per SPH particle, in order,
+ * and both engines must have been created on the same stream.  No host
+ * synchronisation.  Errors: ARG, STATE, HIP. */
+int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t k_micro);
+
+int lhmm_sph_destroy(lhmm_sph* s);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* lhmm_last_error(void);
 

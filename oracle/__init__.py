@@ -21,6 +21,14 @@ from .oracle import (  # noqa: F401
     reduce_cell,
     run_batch,
     run_box,
+    sph_accel,
+    sph_density,
+    sph_F,
+    sph_gradv,
+    sph_params_vector,
+    sph_polymer_stress,
+    sph_step,
+    sph_W,
     theta,
     uniform23,
     widths,

@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lhmm_oracle.c")
+SOURCES = [SRC, os.path.join(HERE, "sph_oracle.c")]
 LIB = os.path.join(HERE, "liblhmm_oracle.so")
 
 ERR_BOND = 1
@@ -26,10 +27,10 @@ ERR_ARG = 8
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (double precision, no fast-math, no FMA
     contraction, OpenMP over boxes)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if force or _stale():
         tmp = LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
-               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", tmp, SRC, "-lm"]
+               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", tmp, *SOURCES, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, LIB)
     return LIB
@@ -38,10 +39,14 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def _stale() -> bool:
+    return not os.path.exists(LIB) or any(os.path.getmtime(LIB) < os.path.getmtime(s) for s in SOURCES)
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if _stale():
             build(force=True)
         L = C.CDLL(LIB)
         dp = C.POINTER(C.c_double)
@@ -72,6 +77,15 @@ def lib():
                                        u64p, dp, C.c_int, dp, dp, up, C.c_int, C.POINTER(C.c_longlong)]
         L.oracle_run_batch.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
+        L.oracle_sph_W.argtypes = [C.c_double, C.c_double]
+        L.oracle_sph_W.restype = C.c_double
+        L.oracle_sph_F.argtypes = [C.c_double, C.c_double]
+        L.oracle_sph_F.restype = C.c_double
+        L.oracle_sph_density.argtypes = [dp, C.c_int, dp, dp, dp]
+        L.oracle_sph_gradv.argtypes = [dp, C.c_int, dp, dp, dp, dp]
+        L.oracle_sph_accel.argtypes = [dp, C.c_int, dp, dp, dp, dp, dp, dp]
+        L.oracle_sph_step.argtypes = [dp, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.oracle_sph_polymer_stress.argtypes = [dp, C.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -262,3 +276,63 @@ def run_batch(p, seed, chain_len, boxes, Ls, nsteps, mode=1, count_pairs=False):
 
 def max_threads() -> int:
     return int(lib().oracle_max_threads())
+
+
+# ---------------------------------------------------------------------------
+# SPH macro side
+# ---------------------------------------------------------------------------
+
+def sph_params_vector(q) -> np.ndarray:
+    keys = ["rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly", "lambda_star", "alpha"]
+    return np.array([float(q[k]) for k in keys], dtype=np.float64)
+
+
+def sph_W(r, h):
+    return lib().oracle_sph_W(float(r), float(h))
+
+
+def sph_F(r, h):
+    return lib().oracle_sph_F(float(r), float(h))
+
+
+def sph_density(q, r):
+    P = sph_params_vector(q)
+    r = _f64(r)
+    n = r.shape[0]
+    d = np.zeros(n)
+    p = np.zeros(n)
+    lib().oracle_sph_density(_d(P), n, _d(r), _d(d), _d(p))
+    return d, p
+
+
+def sph_gradv(q, r, v, d):
+    P = sph_params_vector(q)
+    r, v, d = _f64(r), _f64(v), _f64(d)
+    G = np.zeros((r.shape[0], 4))
+    lib().oracle_sph_gradv(_d(P), r.shape[0], _d(r), _d(v), _d(d), _d(G))
+    return G.reshape(-1, 2, 2)
+
+
+def sph_accel(q, r, v, d, p, pi):
+    P = sph_params_vector(q)
+    r, v, d, p, pi = _f64(r), _f64(v), _f64(d), _f64(p), _f64(pi)
+    a = np.zeros((r.shape[0], 2))
+    lib().oracle_sph_accel(_d(P), r.shape[0], _d(r), _d(v), _d(d), _d(p), _d(pi), _d(a))
+    return a
+
+
+def sph_step(q, r, v, pi):
+    """One macro velocity-Verlet step in place; returns the micro gradients (n, 3, 3)."""
+    P = sph_params_vector(q)
+    n = r.shape[0]
+    d, p, acc, G, L = np.zeros(n), np.zeros(n), np.zeros(2 * n), np.zeros(4 * n), np.zeros(9 * n)
+    lib().oracle_sph_step(_d(P), n, _d(r), _d(v), _d(_f64(pi)), _d(d), _d(p), _d(acc), _d(G), _d(L))
+    return L.reshape(n, 3, 3)
+
+
+def sph_polymer_stress(q, sig):
+    P = sph_params_vector(q)
+    sig = _f64(sig).reshape(-1, 6)
+    pi = np.zeros((sig.shape[0], 3))
+    lib().oracle_sph_polymer_stress(_d(P), sig.shape[0], _d(sig), _d(pi))
+    return pi

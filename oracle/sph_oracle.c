@@ -1,0 +1,196 @@
+/*
+ * sph_oracle.c -- double-precision CPU oracle of the SPH macro side of the
+ * Lagrangian Heterogeneous Multiscale Method (2-D, periodic box).
+ *
+ * TEST INFRASTRUCTURE ONLY (see lhmm_oracle.c).  Plain C, all-pairs loops,
+ * each quantity computed as the paper writes it:
+ *   - number density d_I = sum_J W(r_IJ) (self included) and rho_I = m d_I
+ *     (Sec. "Macroscale: Smoothed Particle Hydrodynamics");
+ *   - Tait equation of state, Eq. (tait), background pressure
+ *     p_b = theta c^2 rho0 / 7;
+ *   - momentum equation, Eq. (sph_continuity): pressure, viscous (friction
+ *     coefficients a = 2 eta - zeta, b = 4 zeta + 2 eta) and the
+ *     micro-to-macro polymer term with <pi>_IJ = pi_I/d_I^2 + pi_J/d_J^2,
+ *     plus a body force per unit mass;
+ *   - velocity gradient for the micro-domains, Eq. (macro_micro), read with
+ *     the volume factor 1/d_J: (grad v)_I = sum_J F_IJ r_IJ (x) v_IJ / d_J;
+ *   - velocity-Verlet time stepping (Appendix "Detailed Coupling Protocol",
+ *     Step 1).
+ * Kernel: the quintic spline with support radius h (q = 3 r / h),
+ * W = 63/(478 pi h^2) [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5] (terms where the
+ * bracket is positive); F_IJ = -W'(r_IJ)/r_IJ.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+/* parameter vector layout (double[14]) */
+enum {
+    S_RHO0 = 0, S_ETA, S_ZETA, S_C, S_THETA, S_F, S_H, S_DT, S_MASS, S_LX, S_LY, S_LAMBDA, S_ALPHA, S_COUNT
+};
+
+double oracle_sph_W(double r, double h)
+{
+    double q = 3.0 * r / h;
+    if (q >= 3.0) return 0.0;
+    double w = pow(3.0 - q, 5);
+    if (q < 2.0) w -= 6.0 * pow(2.0 - q, 5);
+    if (q < 1.0) w += 15.0 * pow(1.0 - q, 5);
+    return 63.0 / (478.0 * M_PI * h * h) * w;
+}
+
+/* F = -W'(r)/r, r > 0 */
+double oracle_sph_F(double r, double h)
+{
+    double q = 3.0 * r / h;
+    if (q >= 3.0) return 0.0;
+    double dw = -5.0 * pow(3.0 - q, 4);
+    if (q < 2.0) dw += 30.0 * pow(2.0 - q, 4);
+    if (q < 1.0) dw -= 75.0 * pow(1.0 - q, 4);
+    double dWdr = 63.0 / (478.0 * M_PI * h * h) * dw * 3.0 / h;
+    return -dWdr / r;
+}
+
+static void min_image(const double *P, double *dx, double *dy)
+{
+    *dx -= P[S_LX] * round(*dx / P[S_LX]);
+    *dy -= P[S_LY] * round(*dy / P[S_LY]);
+}
+
+/* d (n) and p (n) */
+void oracle_sph_density(const double *P, int n, const double *r, double *d, double *p)
+{
+    const double rho0 = P[S_RHO0], c = P[S_C], h = P[S_H], m = P[S_MASS];
+    const double B = c * c * rho0 / 7.0;
+    for (int I = 0; I < n; ++I) {
+        double s = 0.0;
+        for (int J = 0; J < n; ++J) {
+            double dx = r[2 * I] - r[2 * J], dy = r[2 * I + 1] - r[2 * J + 1];
+            min_image(P, &dx, &dy);
+            s += oracle_sph_W(sqrt(dx * dx + dy * dy), h);
+        }
+        d[I] = s;
+        double rho = m * s;
+        p[I] = B * (pow(rho / rho0, 7) - 1.0) + P[S_THETA] * B;
+    }
+}
+
+/* G (n x 4): G_ab = (grad v)_ab = d_a v_b = sum_J F r_a v_b / d_J, row-major */
+void oracle_sph_gradv(const double *P, int n, const double *r, const double *v, const double *d, double *G)
+{
+    const double h = P[S_H];
+    for (int I = 0; I < n; ++I) {
+        double g[4] = {0, 0, 0, 0};
+        for (int J = 0; J < n; ++J) {
+            if (J == I) continue;
+            double dx = r[2 * I] - r[2 * J], dy = r[2 * I + 1] - r[2 * J + 1];
+            min_image(P, &dx, &dy);
+            double rr = sqrt(dx * dx + dy * dy);
+            if (rr >= h || rr == 0.0) continue;
+            double F = oracle_sph_F(rr, h) / d[J];
+            double vx = v[2 * I] - v[2 * J], vy = v[2 * I + 1] - v[2 * J + 1];
+            g[0] += F * dx * vx;
+            g[1] += F * dx * vy;
+            g[2] += F * dy * vx;
+            g[3] += F * dy * vy;
+        }
+        memcpy(&G[4 * I], g, sizeof g);
+    }
+}
+
+/* acceleration (n x 2) from Eq. (sph_continuity); pi (n x 3: xx, xy, yy) is
+ * the polymer stress already multiplied by alpha / lambda*; body force:
+ * +F x-hat for y >= Ly/2 and -F x-hat below. */
+void oracle_sph_accel(const double *P, int n, const double *r, const double *v, const double *d,
+                      const double *p, const double *pi, double *acc)
+{
+    const double h = P[S_H], m = P[S_MASS];
+    const double av = 2.0 * P[S_ETA] - P[S_ZETA], bv = 4.0 * P[S_ZETA] + 2.0 * P[S_ETA];
+    for (int I = 0; I < n; ++I) {
+        double fx = 0.0, fy = 0.0;
+        for (int J = 0; J < n; ++J) {
+            if (J == I) continue;
+            double dx = r[2 * I] - r[2 * J], dy = r[2 * I + 1] - r[2 * J + 1];
+            min_image(P, &dx, &dy);
+            double rr = sqrt(dx * dx + dy * dy);
+            if (rr >= h || rr == 0.0) continue;
+            double F = oracle_sph_F(rr, h);
+            double ex = dx / rr, ey = dy / rr;
+            double vx = v[2 * I] - v[2 * J], vy = v[2 * I + 1] - v[2 * J + 1];
+            /* pressure */
+            double pp = p[I] / (d[I] * d[I]) + p[J] / (d[J] * d[J]);
+            fx += pp * F * dx;
+            fy += pp * F * dy;
+            /* viscous */
+            double ve = vx * ex + vy * ey;
+            double vis = F / (d[I] * d[J]);
+            fx -= (av * vx + bv * ve * ex) * vis;
+            fy -= (av * vy + bv * ve * ey) * vis;
+            /* polymer stress <pi>_IJ . r_IJ F_IJ */
+            double i2 = 1.0 / (d[I] * d[I]), j2 = 1.0 / (d[J] * d[J]);
+            double sxx = pi[3 * I] * i2 + pi[3 * J] * j2;
+            double sxy = pi[3 * I + 1] * i2 + pi[3 * J + 1] * j2;
+            double syy = pi[3 * I + 2] * i2 + pi[3 * J + 2] * j2;
+            fx -= (sxx * dx + sxy * dy) * F;
+            fy -= (sxy * dx + syy * dy) * F;
+        }
+        double body = r[2 * I + 1] >= 0.5 * P[S_LY] ? P[S_F] : -P[S_F];
+        acc[2 * I] = fx / m + body;
+        acc[2 * I + 1] = fy / m;
+    }
+}
+
+static double wrapL(double x, double L)
+{
+    x -= L * floor(x / L);
+    if (x >= L) x = 0.0;
+    return x;
+}
+
+/* One velocity-Verlet step with the polymer stress held fixed; then the
+ * velocity gradient at the new state and the micro-domain gradient
+ * L_I = lambda* x traceless part of (grad v)^T, as a 3x3 row-major matrix
+ * (zero z row and column).  Work arrays: d, p (n), acc (2n). */
+void oracle_sph_step(const double *P, int n, double *r, double *v, const double *pi, double *d, double *p,
+                     double *acc, double *G, double *Lout)
+{
+    const double dt = P[S_DT];
+    oracle_sph_density(P, n, r, d, p);
+    oracle_sph_accel(P, n, r, v, d, p, pi, acc);
+    for (int k = 0; k < 2 * n; ++k) v[k] += 0.5 * dt * acc[k];
+    for (int I = 0; I < n; ++I) {
+        r[2 * I] = wrapL(r[2 * I] + dt * v[2 * I], P[S_LX]);
+        r[2 * I + 1] = wrapL(r[2 * I + 1] + dt * v[2 * I + 1], P[S_LY]);
+    }
+    oracle_sph_density(P, n, r, d, p);
+    oracle_sph_accel(P, n, r, v, d, p, pi, acc);
+    for (int k = 0; k < 2 * n; ++k) v[k] += 0.5 * dt * acc[k];
+    oracle_sph_gradv(P, n, r, v, d, G);
+    for (int I = 0; I < n; ++I) {
+        const double *g = &G[4 * I];
+        /* u = L r with L = (grad v)^T: L = [[g0, g2], [g1, g3]] */
+        double L00 = g[0], L01 = g[2], L10 = g[1], L11 = g[3];
+        double half_tr = 0.5 * (L00 + L11);
+        double *o = &Lout[9 * I];
+        for (int k = 0; k < 9; ++k) o[k] = 0.0;
+        o[0] = P[S_LAMBDA] * (L00 - half_tr);
+        o[1] = P[S_LAMBDA] * L01;
+        o[3] = P[S_LAMBDA] * L10;
+        o[4] = P[S_LAMBDA] * (L11 - half_tr);
+    }
+}
+
+/* polymer stress for the macro side from the micro-domains' mean stress
+ * (n x 6: xx, yy, zz, xy, xz, yz): alpha / lambda* x in-plane part of the
+ * deviatoric stress, as (xx, xy, yy). */
+void oracle_sph_polymer_stress(const double *P, int n, const double *sig, double *pi)
+{
+    const double s = P[S_ALPHA] / P[S_LAMBDA];
+    for (int I = 0; I < n; ++I) {
+        const double *g = &sig[6 * I];
+        double tr3 = (g[0] + g[1] + g[2]) / 3.0;
+        pi[3 * I] = s * (g[0] - tr3);
+        pi[3 * I + 1] = s * g[3];
+        pi[3 * I + 2] = s * (g[1] - tr3);
+    }
+}

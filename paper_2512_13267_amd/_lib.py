@@ -32,6 +32,8 @@ EXPORTS = (
     "lhmm_micro_create", "lhmm_micro_set_state", "lhmm_micro_get_state", "lhmm_micro_step",
     "lhmm_micro_forces", "lhmm_micro_stress_parts", "lhmm_micro_pair_counts", "lhmm_micro_flags",
     "lhmm_micro_sizes", "lhmm_micro_destroy", "lhmm_last_error", "lhmm_micro_time",
+    "lhmm_sph_create", "lhmm_sph_step", "lhmm_sph_get_state", "lhmm_sph_coupling_state", "lhmm_couple_step",
+    "lhmm_sph_destroy",
 )
 KERNEL_NAMES = ("cell_step", "kick_drift", "bin_box", "forces", "kick2", "box_stress")
 
@@ -46,6 +48,11 @@ class LhmmParams(C.Structure):
 class LhmmBox(C.Structure):
     _fields_ = [("n_particles", C.c_int32), ("n_chains", C.c_int32), ("rng_id", C.c_uint32),
                 ("reserved", C.c_int32), ("h0", C.c_double * 9)]
+
+
+class LhmmSphParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly",
+                                            "lambda_star", "alpha")]
 
 
 class LhmmError(RuntimeError):
@@ -76,6 +83,12 @@ def lib():
         L.lhmm_micro_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.lhmm_micro_destroy.argtypes = [vp]
         L.lhmm_micro_time.argtypes = [vp, vp, C.c_int32, dp, vp]
+        L.lhmm_sph_create.argtypes = [C.POINTER(LhmmSphParams), C.c_int32, dp, dp, vp, C.POINTER(vp)]
+        L.lhmm_sph_step.argtypes = [vp, vp, vp]
+        L.lhmm_sph_get_state.argtypes = [vp, dp, dp, dp]
+        L.lhmm_sph_coupling_state.argtypes = [vp, dp, dp]
+        L.lhmm_couple_step.argtypes = [vp, vp, C.c_int32]
+        L.lhmm_sph_destroy.argtypes = [vp]
         L.lhmm_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "lhmm_last_error":

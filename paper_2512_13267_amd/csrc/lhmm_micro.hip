@@ -40,6 +40,7 @@
 #include <vector>
 
 #include "lhmm.h"
+#include "lhmm_internal.h"
 
 namespace {
 
@@ -979,6 +980,20 @@ int sync_engine(lhmm_micro* m) {
 }
 
 }  // namespace
+
+int lhmm_fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+void lhmm_clear_error() { g_err.clear(); }
+
+hipStream_t lhmm_micro_caller_stream(const lhmm_micro* m) { return m->user_stream; }
 
 extern "C" {
 

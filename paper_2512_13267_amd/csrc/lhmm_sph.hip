@@ -1,0 +1,341 @@
+// lhmm_sph.hip -- gfx950 kernels and runtime of the SPH macro side and of the
+// coupled exchange interval (include/lhmm.h, lhmm_sph_* and
+// lhmm_couple_step).
+//
+// The macro problem is small (10^3-10^4 particles) and double precision:
+// each kernel gives one thread per particle I and loops over all J with the
+// minimum image of the periodic box, which for these sizes costs a few
+// microseconds and keeps every sum in a fixed order.  A step is
+//   k_density -> k_accel -> k_kick_drift -> k_density -> k_accel -> k_kick
+//   -> k_gradL
+// (velocity-Verlet, then the micro-domain gradients at the new state).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "lhmm.h"
+#include "lhmm_internal.h"
+
+namespace {
+
+constexpr int TPB = 128;
+
+struct SphCtx {
+    int n;
+    double rho0, eta, zeta, c, theta, F, h, dt, mass, Lx, Ly, lambda_star, alpha;
+    double* r;    // n x 2
+    double* v;    // n x 2
+    double* d;    // n
+    double* p;    // n
+    double* acc;  // n x 2
+};
+
+// quintic kernel of support radius h, q = 3 r / h
+__device__ __forceinline__ double kernel_W(double r, double h) {
+    const double q = 3.0 * r / h;
+    if (q >= 3.0) return 0.0;
+    double w = pow(3.0 - q, 5);
+    if (q < 2.0) w -= 6.0 * pow(2.0 - q, 5);
+    if (q < 1.0) w += 15.0 * pow(1.0 - q, 5);
+    return 63.0 / (478.0 * M_PI * h * h) * w;
+}
+
+// F = -W'(r) / r
+__device__ __forceinline__ double kernel_F(double r, double h) {
+    const double q = 3.0 * r / h;
+    if (q >= 3.0) return 0.0;
+    double dw = -5.0 * pow(3.0 - q, 4);
+    if (q < 2.0) dw += 30.0 * pow(2.0 - q, 4);
+    if (q < 1.0) dw -= 75.0 * pow(1.0 - q, 4);
+    return -(63.0 / (478.0 * M_PI * h * h) * dw * 3.0 / h) / r;
+}
+
+__device__ __forceinline__ void min_image(const SphCtx& S, double& dx, double& dy) {
+    dx -= S.Lx * rint(dx / S.Lx);
+    dy -= S.Ly * rint(dy / S.Ly);
+}
+
+__global__ void k_density(SphCtx S) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= S.n) return;
+    const double xi = S.r[2 * I], yi = S.r[2 * I + 1];
+    double s = 0.0;
+    for (int J = 0; J < S.n; ++J) {
+        double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
+        min_image(S, dx, dy);
+        s += kernel_W(sqrt(dx * dx + dy * dy), S.h);
+    }
+    S.d[I] = s;
+    const double B = S.c * S.c * S.rho0 / 7.0;
+    S.p[I] = B * (pow(S.mass * s / S.rho0, 7) - 1.0) + S.theta * B;
+}
+
+// polymer stress of particle I: alpha/lambda* x in-plane deviatoric part of
+// its micro-domain's mean stress (xx, yy, zz, xy, xz, yz)
+__device__ __forceinline__ void polymer_stress(const SphCtx& S, const double* sigma, int I, double& xx, double& xy,
+                                               double& yy) {
+    if (!sigma) {
+        xx = xy = yy = 0.0;
+        return;
+    }
+    const double* g = sigma + 6 * I;
+    const double s = S.alpha / S.lambda_star;
+    const double tr3 = (g[0] + g[1] + g[2]) / 3.0;
+    xx = s * (g[0] - tr3);
+    xy = s * g[3];
+    yy = s * (g[1] - tr3);
+}
+
+// Eq. (sph_continuity) divided by the mass, plus the body force
+__global__ void k_accel(SphCtx S, const double* __restrict__ sigma) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= S.n) return;
+    const double av = 2.0 * S.eta - S.zeta, bv = 4.0 * S.zeta + 2.0 * S.eta;
+    const double xi = S.r[2 * I], yi = S.r[2 * I + 1], vxi = S.v[2 * I], vyi = S.v[2 * I + 1];
+    const double di = S.d[I], pi_ = S.p[I];
+    double pxx, pxy, pyy;
+    polymer_stress(S, sigma, I, pxx, pxy, pyy);
+    const double i2 = 1.0 / (di * di);
+    double fx = 0.0, fy = 0.0;
+    for (int J = 0; J < S.n; ++J) {
+        if (J == I) continue;
+        double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
+        min_image(S, dx, dy);
+        const double rr = sqrt(dx * dx + dy * dy);
+        if (rr >= S.h || rr == 0.0) continue;
+        const double F = kernel_F(rr, S.h);
+        const double ex = dx / rr, ey = dy / rr;
+        const double vx = vxi - S.v[2 * J], vy = vyi - S.v[2 * J + 1];
+        const double dj = S.d[J];
+        const double j2 = 1.0 / (dj * dj);
+        const double pp = pi_ * i2 + S.p[J] * j2;
+        fx += pp * F * dx;
+        fy += pp * F * dy;
+        const double ve = vx * ex + vy * ey;
+        const double vis = F / (di * dj);
+        fx -= (av * vx + bv * ve * ex) * vis;
+        fy -= (av * vy + bv * ve * ey) * vis;
+        double qxx, qxy, qyy;
+        polymer_stress(S, sigma, J, qxx, qxy, qyy);
+        const double sxx = pxx * i2 + qxx * j2, sxy = pxy * i2 + qxy * j2, syy = pyy * i2 + qyy * j2;
+        fx -= (sxx * dx + sxy * dy) * F;
+        fy -= (sxy * dx + syy * dy) * F;
+    }
+    const double body = yi >= 0.5 * S.Ly ? S.F : -S.F;
+    S.acc[2 * I] = fx / S.mass + body;
+    S.acc[2 * I + 1] = fy / S.mass;
+}
+
+__device__ __forceinline__ double wrap_len(double x, double L) {
+    x -= L * floor(x / L);
+    return x >= L ? 0.0 : x;
+}
+
+__global__ void k_kick_drift(SphCtx S) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= S.n) return;
+    const double hdt = 0.5 * S.dt;
+    const double vx = S.v[2 * I] + hdt * S.acc[2 * I], vy = S.v[2 * I + 1] + hdt * S.acc[2 * I + 1];
+    S.v[2 * I] = vx;
+    S.v[2 * I + 1] = vy;
+    S.r[2 * I] = wrap_len(S.r[2 * I] + S.dt * vx, S.Lx);
+    S.r[2 * I + 1] = wrap_len(S.r[2 * I + 1] + S.dt * vy, S.Ly);
+}
+
+__global__ void k_kick(SphCtx S) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= S.n) return;
+    const double hdt = 0.5 * S.dt;
+    S.v[2 * I] += hdt * S.acc[2 * I];
+    S.v[2 * I + 1] += hdt * S.acc[2 * I + 1];
+}
+
+// Eq. (macro_micro) with 1/d_J: G_ab = d_a v_b; micro gradient
+// L = lambda* x traceless part of G^T (u = L r), 3x3 row-major, zero z.
+__global__ void k_gradL(SphCtx S, double* __restrict__ gradL) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= S.n) return;
+    const double xi = S.r[2 * I], yi = S.r[2 * I + 1], vxi = S.v[2 * I], vyi = S.v[2 * I + 1];
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+    for (int J = 0; J < S.n; ++J) {
+        if (J == I) continue;
+        double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
+        min_image(S, dx, dy);
+        const double rr = sqrt(dx * dx + dy * dy);
+        if (rr >= S.h || rr == 0.0) continue;
+        const double F = kernel_F(rr, S.h) / S.d[J];
+        const double vx = vxi - S.v[2 * J], vy = vyi - S.v[2 * J + 1];
+        g0 += F * dx * vx;
+        g1 += F * dx * vy;
+        g2 += F * dy * vx;
+        g3 += F * dy * vy;
+    }
+    const double half_tr = 0.5 * (g0 + g3);
+    double* o = gradL + 9 * I;
+    o[0] = S.lambda_star * (g0 - half_tr);
+    o[1] = S.lambda_star * g2;
+    o[2] = 0.0;
+    o[3] = S.lambda_star * g1;
+    o[4] = S.lambda_star * (g3 - half_tr);
+    o[5] = 0.0;
+    o[6] = 0.0;
+    o[7] = 0.0;
+    o[8] = 0.0;
+}
+
+}  // namespace
+
+struct lhmm_sph {
+    SphCtx S{};
+    hipStream_t stream = nullptr;
+    double* d_sigma = nullptr;  // n x 6, micro stresses of the last interval (zero at start)
+    double* d_gradL = nullptr;  // n x 9
+    void* bufs[7] = {};
+};
+
+namespace {
+
+void sph_release(lhmm_sph* s) {
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (void* b : s->bufs)
+        if (b) (void)hipFree(b);
+}
+
+void launch_sph_step(lhmm_sph* s, const double* sigma, double* gradL) {
+    const int g = (s->S.n + TPB - 1) / TPB;
+    hipStream_t st = s->stream;
+    k_density<<<g, TPB, 0, st>>>(s->S);
+    k_accel<<<g, TPB, 0, st>>>(s->S, sigma);
+    k_kick_drift<<<g, TPB, 0, st>>>(s->S);
+    k_density<<<g, TPB, 0, st>>>(s->S);
+    k_accel<<<g, TPB, 0, st>>>(s->S, sigma);
+    k_kick<<<g, TPB, 0, st>>>(s->S);
+    if (gradL) k_gradL<<<g, TPB, 0, st>>>(s->S, gradL);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const double* v0, void* stream,
+                    lhmm_sph** out) {
+    lhmm_clear_error();
+    if (!p || !r0 || !v0 || !out) return lhmm_fail(LHMM_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (n <= 0) return lhmm_fail(LHMM_ERR_ARG, "n must be positive (got %d)", n);
+    const double vals[] = {p->rho0, p->eta, p->zeta, p->c, p->theta, p->F, p->h, p->dt, p->mass, p->Lx, p->Ly,
+                           p->lambda_star, p->alpha};
+    for (double x : vals)
+        if (!std::isfinite(x)) return lhmm_fail(LHMM_ERR_ARG, "non-finite SPH parameter");
+    if (!(p->rho0 > 0) || !(p->c > 0) || !(p->h > 0) || !(p->dt > 0) || !(p->mass > 0) || !(p->lambda_star > 0) ||
+        p->eta < 0 || p->zeta < 0)
+        return lhmm_fail(LHMM_ERR_ARG, "SPH parameters out of range");
+    if (!(p->Lx > 2 * p->h) || !(p->Ly > 2 * p->h))
+        return lhmm_fail(LHMM_ERR_ARG, "the periodic box must be wider than twice the kernel support");
+    for (int k = 0; k < 2 * n; ++k) {
+        if (!std::isfinite(r0[k]) || !std::isfinite(v0[k])) return lhmm_fail(LHMM_ERR_ARG, "non-finite state");
+        const double L = (k % 2 == 0) ? p->Lx : p->Ly;
+        if (!(r0[k] >= 0.0 && r0[k] < L)) return lhmm_fail(LHMM_ERR_ARG, "position %d outside the box", k / 2);
+    }
+    lhmm_sph* s = new (std::nothrow) lhmm_sph();
+    if (!s) return lhmm_fail(LHMM_ERR_OOM, "host allocation failed");
+    s->stream = (hipStream_t)stream;
+    SphCtx& S = s->S;
+    S.n = n;
+    S.rho0 = p->rho0; S.eta = p->eta; S.zeta = p->zeta; S.c = p->c; S.theta = p->theta; S.F = p->F; S.h = p->h;
+    S.dt = p->dt; S.mass = p->mass; S.Lx = p->Lx; S.Ly = p->Ly; S.lambda_star = p->lambda_star; S.alpha = p->alpha;
+    const size_t sizes[7] = {2 * (size_t)n, 2 * (size_t)n, (size_t)n, (size_t)n, 2 * (size_t)n, 6 * (size_t)n,
+                             9 * (size_t)n};
+    for (int k = 0; k < 7; ++k) {
+        if (hipMalloc(&s->bufs[k], sizes[k] * sizeof(double)) != hipSuccess) {
+            sph_release(s);
+            delete s;
+            return lhmm_fail(LHMM_ERR_OOM, "hipMalloc failed");
+        }
+    }
+    S.r = (double*)s->bufs[0];
+    S.v = (double*)s->bufs[1];
+    S.d = (double*)s->bufs[2];
+    S.p = (double*)s->bufs[3];
+    S.acc = (double*)s->bufs[4];
+    s->d_sigma = (double*)s->bufs[5];
+    s->d_gradL = (double*)s->bufs[6];
+    auto init = [&]() -> int {
+        LHMM_HIPCHK(hipMemcpy(S.r, r0, 2 * (size_t)n * sizeof(double), hipMemcpyHostToDevice));
+        LHMM_HIPCHK(hipMemcpy(S.v, v0, 2 * (size_t)n * sizeof(double), hipMemcpyHostToDevice));
+        LHMM_HIPCHK(hipMemset(s->d_sigma, 0, 6 * (size_t)n * sizeof(double)));
+        LHMM_HIPCHK(hipMemset(s->d_gradL, 0, 9 * (size_t)n * sizeof(double)));
+        return LHMM_OK;
+    };
+    int rc = init();
+    if (rc != LHMM_OK) {
+        sph_release(s);
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return LHMM_OK;
+}
+
+int lhmm_sph_step(lhmm_sph* s, const double* sigma, double* gradL_out) {
+    lhmm_clear_error();
+    if (!s) return lhmm_fail(LHMM_ERR_ARG, "null engine");
+    launch_sph_step(s, sigma, gradL_out);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sph_get_state(lhmm_sph* s, double* r, double* v, double* d) {
+    lhmm_clear_error();
+    if (!s) return lhmm_fail(LHMM_ERR_ARG, "null engine");
+    LHMM_HIPCHK(hipStreamSynchronize(s->stream));
+    const size_t n = (size_t)s->S.n;
+    if (r) LHMM_HIPCHK(hipMemcpy(r, s->S.r, 2 * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (v) LHMM_HIPCHK(hipMemcpy(v, s->S.v, 2 * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (d) {
+        // density at the current positions
+        const int g = (s->S.n + TPB - 1) / TPB;
+        k_density<<<g, TPB, 0, s->stream>>>(s->S);
+        LHMM_HIPCHK(hipGetLastError());
+        LHMM_HIPCHK(hipStreamSynchronize(s->stream));
+        LHMM_HIPCHK(hipMemcpy(d, s->S.d, n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return LHMM_OK;
+}
+
+int lhmm_sph_coupling_state(lhmm_sph* s, double* sigma, double* gradL) {
+    lhmm_clear_error();
+    if (!s) return lhmm_fail(LHMM_ERR_ARG, "null engine");
+    LHMM_HIPCHK(hipStreamSynchronize(s->stream));
+    const size_t n = (size_t)s->S.n;
+    if (sigma) LHMM_HIPCHK(hipMemcpy(sigma, s->d_sigma, 6 * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (gradL) LHMM_HIPCHK(hipMemcpy(gradL, s->d_gradL, 9 * n * sizeof(double), hipMemcpyDeviceToHost));
+    return LHMM_OK;
+}
+
+int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t k_micro) {
+    lhmm_clear_error();
+    if (!s || !m) return lhmm_fail(LHMM_ERR_ARG, "null engine");
+    if (k_micro <= 0) return lhmm_fail(LHMM_ERR_ARG, "k_micro must be positive (got %d)", k_micro);
+    int32_t nb = 0;
+    int rc = lhmm_micro_sizes(m, nullptr, &nb);
+    if (rc != LHMM_OK) return rc;
+    if (nb != s->S.n) return lhmm_fail(LHMM_ERR_ARG, "micro engine holds %d boxes for %d SPH particles", nb, s->S.n);
+    if (lhmm_micro_caller_stream(m) != s->stream)
+        return lhmm_fail(LHMM_ERR_ARG, "the SPH and micro engines must share one stream");
+    launch_sph_step(s, s->d_sigma, s->d_gradL);
+    LHMM_HIPCHK(hipGetLastError());
+    return lhmm_micro_step(m, s->d_gradL, k_micro, s->d_sigma);
+}
+
+int lhmm_sph_destroy(lhmm_sph* s) {
+    lhmm_clear_error();
+    if (!s) return LHMM_OK;
+    sph_release(s);
+    delete s;
+    return LHMM_OK;
+}
+
+}  // extern "C"

@@ -323,3 +323,60 @@ def tiny_boxes(n_boxes: int, seed_k: int = 7, edges=(4.2, 5.0, 6.3), density: fl
         s, cc = random_box(rng, h, N, n_chains, p["chain_len"], p["kBT"], p["mass"])
         boxes.append(BoxInit(s=s, c=cc, h=h, n_chains=n_chains, L=L, edge=edge, phi=phi))
     return Workload("tiny_boxes", p, boxes, 0)
+
+
+# ---------------------------------------------------------------------------
+# Macro (SPH) workloads
+# ---------------------------------------------------------------------------
+
+@dataclass
+class MacroInit:
+    """Initial SPH state and parameters of a 2-D periodic macro problem."""
+    r: np.ndarray           # n x 2 positions
+    v: np.ndarray           # n x 2 velocities
+    params: dict
+    n_steps: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.r.shape[0])
+
+
+def reverse_poiseuille(nx: int = 16, ny: int = 64, width: float = 1.0, force: float = 0.2, eta_s: float = 0.1,
+                       beta: float = 0.5, rho0: float = 1.0, dt: float = 1e-3, lambda_star: float = 0.2,
+                       alpha: float = 0.07, theta: float = 0.5, n_steps: int = 200) -> MacroInit:
+    """Reverse Poiseuille flow: a periodic channel of two counter-flowing
+    halves of the given width (Ly = 2 width), body force +force along x for
+    y >= width and -force below, SPH particles on an nx x ny lattice of
+    spacing dh = 2 width / ny, quintic kernel of support h = 3 dh.  The sound
+    speed follows Eq. (sound_speed) with delta = 0.1, the characteristic
+    length = width and the expected peak velocity of the Newtonian profile
+    force width^2 / (8 nu_tot), nu_tot = eta_s / ((1 - beta) rho0)."""
+    dh = 2.0 * width / ny
+    Lx, Ly = nx * dh, ny * dh
+    eta_tot = eta_s / (1.0 - beta)
+    vmax = force * width * width / (8.0 * eta_tot / rho0)
+    delta = 0.1
+    c = max(vmax / delta, math.sqrt(eta_tot * vmax / (delta * width)), math.sqrt(force * width / delta))
+    xs, ys = np.meshgrid((np.arange(nx) + 0.5) * dh, (np.arange(ny) + 0.5) * dh, indexing="ij")
+    r = np.stack([xs.ravel(), ys.ravel()], axis=1)
+    params = dict(rho0=rho0, eta=eta_s, zeta=0.0, c=c, theta=theta, F=force, h=3.0 * dh, dt=dt,
+                  mass=rho0 * dh * dh, Lx=Lx, Ly=Ly, lambda_star=lambda_star, alpha=alpha)
+    return MacroInit(r=r, v=np.zeros_like(r), params=params, n_steps=n_steps)
+
+
+def lhmm_boxes(n_boxes: int, n_particles: int = 4000, density: float = 3.0, polymer_fraction: float = 0.1,
+               seed_k: int = 2, **param_over) -> Workload:
+    """One cubic micro-box per SPH particle, each of n_particles at the given
+    density (edge (n/density)^(1/3)), 10-bead chains holding the polymer
+    fraction, random start, no gradient (the macro side supplies it)."""
+    p = default_params(seed=SEED_BASE + seed_k, **param_over)
+    rng = np.random.default_rng(SEED_BASE + seed_k)
+    edge = (n_particles / density) ** (1.0 / 3.0)
+    n_chains = int(round(polymer_fraction * n_particles / p["chain_len"]))
+    h = cubic_cell(edge)
+    boxes = []
+    for _ in range(n_boxes):
+        s, c = random_box(rng, h, n_particles, n_chains, p["chain_len"], p["kBT"], p["mass"])
+        boxes.append(BoxInit(s=s, c=c, h=h, n_chains=n_chains, L=np.zeros((3, 3)), edge=edge, phi=polymer_fraction))
+    return Workload("lhmm_boxes", p, boxes, 0)

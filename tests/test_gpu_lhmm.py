@@ -1,0 +1,82 @@
+"""GPU parity of the SPH macro engine and of the coupled exchange interval
+against the oracle (FP64 on both sides, through the C ABI).
+
+Tolerances: the SPH side is double precision all-pairs on both sides, so
+states agree to rounding (1e-11 relative after 50 steps).  The coupled run
+adds the micro boxes in FP64 for 3 x 10 micro steps; the chaos growth over
+30 steps is ~10^2, so micro stresses agree to 1e-8 relative.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_sph_matches_oracle(torch_gpu, orc):
+    from paper_2512_13267_amd import inputs, lhmm
+
+    m = inputs.reverse_poiseuille(nx=8, ny=32)
+    q = m.params
+    torch = torch_gpu
+    rng = np.random.default_rng(5)
+    sig = rng.normal(scale=0.3, size=(m.n, 6))
+    sig_dev = torch.tensor(sig, dtype=torch.float64, device="cuda")
+    L_dev = torch.zeros((m.n, 9), dtype=torch.float64, device="cuda")
+    s = lhmm.Sph(q, m.r, m.v)
+    r, v = m.r.copy(), m.v.copy()
+    pi = orc.sph_polymer_stress(q, sig)
+    for _ in range(50):
+        s.step(sig_dev, L_dev)
+        Lo = orc.sph_step(q, r, v, pi)
+    rg, vg, dg = s.get_state()
+    dr = rg - r
+    dr[:, 0] -= q["Lx"] * np.round(dr[:, 0] / q["Lx"])
+    dr[:, 1] -= q["Ly"] * np.round(dr[:, 1] / q["Ly"])
+    assert np.abs(dr).max() < 1e-11
+    assert np.abs(vg - v).max() < 1e-11 * max(1.0, np.abs(v).max())
+    Lg = L_dev.cpu().numpy().reshape(-1, 3, 3)
+    assert np.abs(Lg - Lo).max() < 1e-9 * np.abs(Lo).max()
+    # the micro gradients are traceless and in-plane
+    assert np.abs(Lg[:, 0, 0] + Lg[:, 1, 1]).max() < 1e-14
+    assert np.abs(Lg[:, 2, :]).max() == 0.0 and np.abs(Lg[:, :, 2]).max() == 0.0
+    d_o, _ = orc.sph_density(q, r)
+    assert np.abs(dg - d_o).max() < 1e-10 * d_o.max()
+    s.close()
+
+
+def test_coupled_interval_matches_oracle(torch_gpu, orc):
+    from paper_2512_13267_amd import inputs, lhmm, micro
+
+    mac = inputs.reverse_poiseuille(nx=4, ny=16, force=2.0)
+    q = mac.params
+    wl = inputs.lhmm_boxes(mac.n, n_particles=300, polymer_fraction=0.2, seed_k=9)
+    p = wl.params
+    m = micro.from_workload(wl, precision="fp64")
+    s = lhmm.Sph(q, mac.r, mac.v)
+    cp = lhmm.Coupled(s, m)
+    k = 10
+    r, v = mac.r.copy(), mac.v.copy()
+    boxes = [orc.OracleBox(s=b.s, c=b.c, h=b.h, n_chains=b.n_chains, box_id=i) for i, b in enumerate(wl.boxes)]
+    pi = np.zeros((mac.n, 3))
+    for _ in range(3):
+        cp.step(k)
+        L = orc.sph_step(q, r, v, pi)
+        means, _ = orc.run_batch(p, p["seed"], p["chain_len"], boxes, list(L), k)
+        pi = orc.sph_polymer_stress(q, means)
+    sig, grad = cp.coupling_state()
+    assert np.abs(grad - L).max() <= 1e-10 * max(1e-3, np.abs(L).max())
+    assert np.abs(sig - means).max() <= 1e-8 * np.abs(means).max()
+    rg, vg, _ = s.get_state()
+    assert np.abs(vg - v).max() < 1e-9 * max(1.0, np.abs(v).max())
+    assert not np.any(m.flags())
+    m.close()
+    s.close()

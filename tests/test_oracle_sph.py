@@ -1,0 +1,96 @@
+"""Pins of the SPH oracle (Sec. "Macroscale: Smoothed Particle Hydrodynamics",
+Eqs. tait, sph_continuity, macro_micro).
+
+* the quintic kernel integrates to one; F = -W'/r against finite
+  differences of W;
+* number density on the uniform lattice is 1/dh^2 (kernel consistency);
+* the velocity gradient of a smooth periodic field approaches the analytic
+  derivative;
+* pair forces conserve momentum: sum m a = sum of body forces;
+* Newtonian start-up of reverse Poiseuille flow follows the Fourier-series
+  solution of v_t = nu v_yy + f(y).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_2512_13267_amd import inputs
+
+
+@pytest.mark.parametrize("h", [0.05, 0.1875, 1.0])
+def test_kernel_normalised_and_derivative(orc, h):
+    I, _ = integrate.quad(lambda r: 2 * math.pi * r * orc.sph_W(r, h), 0, h, points=[h / 3, 2 * h / 3])
+    assert abs(I - 1.0) < 1e-10
+    for r in np.linspace(0.03 * h, 0.98 * h, 25):
+        eps = 1e-6 * h
+        dW = (orc.sph_W(r + eps, h) - orc.sph_W(r - eps, h)) / (2 * eps)
+        assert abs(orc.sph_F(r, h) - (-dW / r)) < 1e-6 * abs(dW / r) + 1e-8 / h ** 3
+    assert orc.sph_W(h, h) == 0.0 and orc.sph_F(1.01 * h, h) == 0.0
+
+
+def test_lattice_density(orc):
+    m = inputs.reverse_poiseuille(nx=8, ny=32)
+    d, p = orc.sph_density(m.params, m.r)
+    dh = m.params["Lx"] / 8
+    assert np.allclose(d, 1.0 / dh ** 2, rtol=2e-3)
+    assert np.ptp(d) < 1e-9 * d.mean()
+    # background pressure at the reference density
+    B = m.params["c"] ** 2 * m.params["rho0"] / 7
+    assert np.allclose(p, B * ((m.params["mass"] * d / m.params["rho0"]) ** 7 - 1) + m.params["theta"] * B)
+
+
+def test_velocity_gradient_of_smooth_field(orc):
+    m = inputs.reverse_poiseuille(nx=32, ny=32)  # square box, k h = 0.59 in both directions
+    q = m.params
+    k = 2 * math.pi / q["Ly"]
+    A, B = 0.3, -0.2
+    v = np.stack([A * np.sin(k * m.r[:, 1]), B * np.cos(k * m.r[:, 0] * q["Ly"] / q["Lx"])], axis=1)
+    d, _ = orc.sph_density(q, m.r)
+    G = orc.sph_gradv(q, m.r, v, d)
+    exact_yx = A * k * np.cos(k * m.r[:, 1])                      # d_y v_x
+    kx = k * q["Ly"] / q["Lx"]
+    exact_xy = -B * kx * np.sin(kx * m.r[:, 0])                    # d_x v_y
+    assert np.abs(G[:, 1, 0] - exact_yx).max() < 0.04 * abs(A * k)
+    assert np.abs(G[:, 0, 1] - exact_xy).max() < 0.04 * abs(B * kx)
+    assert np.abs(G[:, 0, 0]).max() < 1e-10 and np.abs(G[:, 1, 1]).max() < 1e-10
+
+
+def test_momentum_balance(orc):
+    rng = np.random.default_rng(3)
+    m = inputs.reverse_poiseuille(nx=8, ny=32)
+    q = dict(m.params)
+    r = m.r + rng.normal(scale=0.01, size=m.r.shape)
+    r[:, 0] %= q["Lx"]
+    r[:, 1] %= q["Ly"]
+    v = rng.normal(scale=0.1, size=r.shape)
+    pi = rng.normal(scale=0.5, size=(m.n, 3))
+    d, p = orc.sph_density(q, r)
+    a = orc.sph_accel(q, r, v, d, p, pi)
+    body = np.where(r[:, 1] >= 0.5 * q["Ly"], q["F"], -q["F"])
+    total = q["mass"] * a.sum(axis=0)
+    assert abs(total[0] - q["mass"] * body.sum()) < 1e-10 * q["mass"] * m.n
+    assert abs(total[1]) < 1e-10 * q["mass"] * m.n
+
+
+def test_newtonian_startup_matches_fourier_series(orc):
+    m = inputs.reverse_poiseuille(nx=8, ny=32, alpha=0.0, beta=0.0)
+    q = m.params
+    r, v = m.r.copy(), m.v.copy()
+    pi = np.zeros((m.n, 3))
+    nsteps = 200
+    for _ in range(nsteps):
+        orc.sph_step(q, r, v, pi)
+    t = nsteps * q["dt"]
+    nu = q["eta"] / q["rho0"]
+    # v_t = nu v_yy + f(y), f = -F on (0, 1), +F on (1, 2), period 2:
+    # f = -(4F/pi) sum_odd sin(k pi y)/k
+    y = r[:, 1]
+    series = np.zeros_like(y)
+    for kk in range(1, 400, 2):
+        lam = nu * (kk * math.pi) ** 2
+        series += -(4 * q["F"] / math.pi) * np.sin(kk * math.pi * y) / kk * (1 - math.exp(-lam * t)) / lam
+    err = np.abs(v[:, 0] - series).max()
+    assert err < 0.05 * np.abs(series).max()
+    assert np.abs(v[:, 1]).max() < 0.02 * np.abs(series).max()
