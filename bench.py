@@ -71,6 +71,44 @@ def cpu_baseline(wl, budget_s: float = 12.0):
                       f"{steps} FP64 steps, {dt:.1f} s"}
 
 
+def bench_lhmm(macro_steps: int, k_micro: int = 50, equil_steps: int = 500, warmup: int = 5):
+    """Reverse-Poiseuille LHMM: 1024 SPH particles (16 x 64, quintic kernel of
+    support 3 dh, dt 1e-3), one 4000-particle FP32 micro-box per particle
+    (40 chains of 10 beads), k_micro micro steps per macro step.  The micro
+    boxes first equilibrate equil_steps at zero gradient (untimed)."""
+    import torch
+
+    from paper_2512_13267_amd import inputs, lhmm, micro
+
+    mac = inputs.reverse_poiseuille(n_steps=macro_steps)
+    wl = inputs.lhmm_boxes(mac.n, n_particles=4000, seed_k=2)
+    m = micro.from_workload(wl, precision="fp32")
+    zero = torch.zeros((mac.n, 9), dtype=torch.float64, device="cuda")
+    m.step(zero, equil_steps)
+    s = lhmm.Sph(mac.params, mac.r, mac.v)
+    cp = lhmm.Coupled(s, m)
+    for _ in range(warmup):
+        cp.step(k_micro)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(macro_steps):
+        cp.step(k_micro)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pairs = float(m.pair_counts().sum()) * macro_steps  # counts of the last interval x intervals
+    flags = m.flags()
+    r, v, d = s.get_state()
+    out = {"metric": "LHMM macro steps/s (plain batched DPD)", "value": macro_steps / el,
+           "ms_per_macro_step": el / macro_steps * 1e3, "macro_steps": macro_steps, "warmup": warmup,
+           "workload": "reverse Poiseuille, 1024 SPH particles, 1024 micro-boxes x 4000 particles, "
+                       f"{k_micro} micro steps per macro step", "micro_pair_updates_per_s": pairs / el,
+           "max_vx": float(np.abs(v[:, 0]).max()),
+           "flagged_boxes": {"bond": int(np.count_nonzero(flags & 1)), "cell": int(np.count_nonzero(flags & 2))}}
+    m.close()
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +116,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=100)
+    ap.add_argument("--lhmm-steps", type=int, default=200,
+                    help="macro steps of the coupled reverse-Poiseuille run (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2^27 floats (512 MiB read, 512 MiB written) five "
                          "times, to scale the HBM byte counters of a profiler run")
@@ -157,10 +197,14 @@ def main():
                                      "nonfinite": int(np.count_nonzero(flags & 4))}},
         "roofline": roofline,
     }
+    m.close()
+    if args.lhmm_steps > 0:
+        print("[bench] coupled LHMM run", file=sys.stderr, flush=True)
+        rec["lhmm"] = bench_lhmm(args.lhmm_steps)
+        print(f"[bench] {rec['lhmm']['value']:.2f} macro steps/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(wl)
-    m.close()
     print(json.dumps(rec))
 
 
