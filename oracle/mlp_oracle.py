@@ -1,0 +1,99 @@
+"""Double-precision oracle of the stress surrogate: an ensemble of MLPs
+(inputs -> hidden -> hidden -> outputs, GELU), mean-squared-error loss and
+Adam, with the mixed-precision dataflow of the device path written out.
+
+TEST INFRASTRUCTURE ONLY.  Plain numpy in float64.  The device multiplies
+BF16 operands with FP32 accumulation; the points where its operands are
+rounded to BF16 are part of the method's definition, so this oracle rounds at
+the same points (``bf16``, round to nearest even) and computes everything
+else in float64:
+
+forward   Z1 = bf(X) bf(W1) + b1,  H1 = gelu(Z1)
+          Z2 = bf(H1) bf(W2) + b2, H2 = gelu(Z2)
+          Y  = bf(H2) bf(W3) + b3
+loss      (1 / (B n_out)) sum (Y - T)^2              (per member)
+backward  dY  = 2 (Y - T) / (B n_out)
+          dW3 = bf(H2)^T bf(dY),  db3 = sum_b dY
+          dZ2 = (bf(dY) bf(W3)^T) * gelu'(Z2),  dW2 = bf(H1)^T bf(dZ2), db2
+          dZ1 = (bf(dZ2) bf(W2)^T) * gelu'(Z1), dW1 = bf(X)^T bf(dZ1),  db1
+Adam      m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+          w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+with gelu(z) = z Phi(z) (erf form) and gelu'(z) = Phi(z) + z phi(z).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erf
+
+ADAM_B1, ADAM_B2, ADAM_EPS = 0.9, 0.999, 1e-8
+
+
+def bf16(x: np.ndarray) -> np.ndarray:
+    """Round float values to bfloat16 (8-bit mantissa), to nearest, ties to
+    even, via the float32 bit pattern; returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    nan = np.isnan(f)
+    out = (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out
+
+
+def gelu(z):
+    return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
+
+
+def gelu_grad(z):
+    return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+
+
+def forward(params, X):
+    """params: dict W1 (nin x nh), b1, W2 (nh x nh), b2, W3 (nh x nout), b3.
+    Returns Y and the cache for backward."""
+    Z1 = bf16(X) @ bf16(params["W1"]) + params["b1"]
+    H1 = gelu(Z1)
+    Z2 = bf16(H1) @ bf16(params["W2"]) + params["b2"]
+    H2 = gelu(Z2)
+    Y = bf16(H2) @ bf16(params["W3"]) + params["b3"]
+    return Y, (X, Z1, H1, Z2, H2)
+
+
+def loss_and_grads(params, X, T):
+    Y, (X, Z1, H1, Z2, H2) = forward(params, X)
+    B, nout = T.shape
+    loss = float(np.mean((Y - T) ** 2))
+    dY = 2.0 * (Y - T) / (B * nout)
+    g = {}
+    g["W3"] = bf16(H2).T @ bf16(dY)
+    g["b3"] = dY.sum(axis=0)
+    dZ2 = (bf16(dY) @ bf16(params["W3"]).T) * gelu_grad(Z2)
+    g["W2"] = bf16(H1).T @ bf16(dZ2)
+    g["b2"] = dZ2.sum(axis=0)
+    dZ1 = (bf16(dZ2) @ bf16(params["W2"]).T) * gelu_grad(Z1)
+    g["W1"] = bf16(X).T @ bf16(dZ1)
+    g["b1"] = dZ1.sum(axis=0)
+    return loss, g, Y
+
+
+def adam_step(params, grads, state, lr, t):
+    """In-place Adam (step number t >= 1) on float64 params; state holds m, v."""
+    for k in params:
+        m = state.setdefault("m_" + k, np.zeros_like(params[k]))
+        v = state.setdefault("v_" + k, np.zeros_like(params[k]))
+        m[...] = ADAM_B1 * m + (1.0 - ADAM_B1) * grads[k]
+        v[...] = ADAM_B2 * v + (1.0 - ADAM_B2) * grads[k] ** 2
+        mh = m / (1.0 - ADAM_B1 ** t)
+        vh = v / (1.0 - ADAM_B2 ** t)
+        params[k] -= lr * mh / (np.sqrt(vh) + ADAM_EPS)
+    return params
+
+
+def forward_exact(params, X):
+    """The same network without any BF16 rounding (float64 throughout)."""
+    H1 = gelu(X @ params["W1"] + params["b1"])
+    H2 = gelu(H1 @ params["W2"] + params["b2"])
+    return H2 @ params["W3"] + params["b3"]
