@@ -248,6 +248,94 @@ int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t k_micro);
 
 int lhmm_sph_destroy(lhmm_sph* s);
 
+/* ------------------------------------------------------------------------
+ * Stress surrogate: an ensemble of n_members independent MLPs
+ *   x -> GELU(x W1 + b1) -> GELU(. W2 + b2) -> . W3 + b3
+ * (GELU in the erf form) mapping a particle's recent history of micro
+ * velocity gradients to the deviatoric micro stress, trained with mean
+ * squared error and Adam (beta1 0.9, beta2 0.999, eps 1e-8).  The paper
+ * drives every SPH particle's micro-domain with its own history of
+ * gradients (Sec. "Temporal Coupling Scheme", continuous-intermittent
+ * coupling); the surrogate replaces that micro-domain where the members
+ * agree, and the plain micro-DPD engine stays the fallback elsewhere.
+ *
+ * Arithmetic: every product is a BF16 x BF16 matrix product with FP32
+ * accumulation on the matrix cores; the operands rounded to BF16 (round to
+ * nearest even) are x, the weights, both hidden activations and the
+ * gradients flowing into each product.  Pre-activations, biases, losses,
+ * bias gradients and the Adam state are FP32.  Results are deterministic.
+ *
+ * Weights cross the ABI as FP32 host arrays, member after member, each
+ * member packed as W1 (n_in x n_hidden, row-major), b1 (n_hidden),
+ * W2 (n_hidden x n_hidden), b2, W3 (n_hidden x n_out), b3 (n_out).
+ * ------------------------------------------------------------------------ */
+typedef struct lhmm_sur lhmm_sur;
+
+typedef struct {
+    int32_t n_members; /* 1 .. 64                                            */
+    int32_t n_in;      /* >= 1 (padded internally to a multiple of 32)       */
+    int32_t n_hidden;  /* positive multiple of 32                            */
+    int32_t n_out;     /* 1 .. 32                                            */
+    int32_t max_batch; /* largest B of any later call                        */
+} lhmm_sur_params;
+
+/* Number of history samples of the surrogate features and the feature count
+ * (4 gradient components per sample plus the polymer fraction). */
+#define LHMM_SUR_HIST 32
+#define LHMM_SUR_FEATURES (4 * LHMM_SUR_HIST + 1)
+
+/* Allocate the ensemble and load weights (host, packed as above).  stream:
+ * the caller's hipStream_t; all work of the engine runs on it.  Errors:
+ * ARG, HIP, OOM. */
+int lhmm_sur_create(const lhmm_sur_params* p, const float* weights, void* stream, lhmm_sur** out);
+
+/* Replace the weights (host, packed) and reset the Adam state and step
+ * count.  Synchronous.  Errors: ARG (non-finite weight), HIP. */
+int lhmm_sur_set_weights(lhmm_sur* s, const float* weights);
+
+/* Copy the FP32 master weights to host (packed).  Synchronous. */
+int lhmm_sur_get_weights(lhmm_sur* s, float* weights);
+
+/* Copy the gradients of the mean squared error computed by the last
+ * lhmm_sur_train_step (before its update) to host, packed like the weights
+ * (zeros before the first step).  A data-parallel trainer sums these across
+ * replicas.  Synchronous. */
+int lhmm_sur_get_grads(lhmm_sur* s, float* grads);
+
+/* One Adam step of every member on the same minibatch.
+ *   X: DEVICE B x n_in FP32 features; T: DEVICE B x n_out FP32 targets;
+ *   lr: learning rate >= 0;
+ *   loss: DEVICE n_members FP32, the mean squared error of each member on
+ *         the minibatch before the step (NULL: not written).
+ * Asynchronous.  Errors: ARG (B outside 1..max_batch), HIP. */
+int lhmm_sur_train_step(lhmm_sur* s, const float* X, const float* T, int32_t B, float lr, float* loss);
+
+/* Predictions of every member.  X: DEVICE B x n_in; Y: DEVICE
+ * n_members x B x n_out.  Asynchronous.  Errors: ARG, HIP. */
+int lhmm_sur_forward(lhmm_sur* s, const float* X, int32_t B, float* Y);
+
+/* Record sample t (t = 0, 1, ...) of the micro gradients of n particles:
+ * ring is DEVICE n x LHMM_SUR_HIST x 4 FP32 (caller-owned), slot t mod
+ * LHMM_SUR_HIST of particle b receives (L_xx, L_xy, L_yx, L_yy) of
+ * gradL (DEVICE n x 9 doubles).  stream: hipStream_t to launch on. */
+int lhmm_sur_push_history(float* ring, int32_t n, const double* gradL, int64_t t, void* stream);
+
+/* Feature rows after sample t: X (DEVICE n x LHMM_SUR_FEATURES FP32) row b
+ * holds samples t-LHMM_SUR_HIST+1 .. t of particle b, oldest first, then
+ * phi[b] (DEVICE n FP32, the polymer fraction of its micro-domain).  Slots
+ * never written hold whatever the caller initialised the ring with. */
+int lhmm_sur_features(const float* ring, int32_t n, int64_t t, const float* phi, float* X, void* stream);
+
+/* Ensemble gate.  Y: DEVICE n_members x B x n_out (as lhmm_sur_forward
+ * writes it); mean: DEVICE B x n_out, the member mean; flag: DEVICE B,
+ * 1 where the spread sqrt(mean over outputs of the member variance)
+ * exceeds threshold x max(|mean|_2, floor), else 0. */
+int lhmm_sur_gate(const float* Y, int32_t n_members, int32_t B, int32_t n_out, float threshold, float floor,
+                  float* mean, uint32_t* flag, void* stream);
+
+/* Release every resource (waits for the stream).  NULL ok. */
+int lhmm_sur_destroy(lhmm_sur* s);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* lhmm_last_error(void);
 

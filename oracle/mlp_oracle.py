@@ -97,3 +97,27 @@ def forward_exact(params, X):
     H1 = gelu(X @ params["W1"] + params["b1"])
     H2 = gelu(H1 @ params["W2"] + params["b2"])
     return H2 @ params["W3"] + params["b3"]
+
+
+def features(history, phi):
+    """Feature rows of the surrogate: history (n, T, 4) holds each particle's
+    gradient samples (L_xx, L_xy, L_yx, L_yy) in time order; the row is the
+    last 32 samples, oldest first, flattened, then the polymer fraction."""
+    h = np.asarray(history, dtype=np.float64)
+    last = h[:, -32:, :].reshape(h.shape[0], -1)
+    return np.concatenate([last, np.asarray(phi, dtype=np.float64)[:, None]], axis=1)
+
+
+def gate(Y, threshold, floor):
+    """Ensemble mean and disagreement flag of member predictions Y
+    (members, B, n_out): spread = sqrt(mean over outputs of the population
+    variance across members); flagged where spread > threshold x
+    max(|mean|_2, floor).  Returns (mean, flag, ratio) with ratio = spread /
+    (threshold x max(|mean|_2, floor))."""
+    Y = np.asarray(Y, dtype=np.float64)
+    mu = Y.mean(axis=0)
+    var = ((Y - mu) ** 2).mean(axis=0)
+    spread = np.sqrt(var.mean(axis=1))
+    denom = threshold * np.maximum(np.sqrt((mu ** 2).sum(axis=1)), floor)
+    ratio = spread / denom
+    return mu, ratio > 1.0, ratio

@@ -34,7 +34,11 @@ EXPORTS = (
     "lhmm_micro_sizes", "lhmm_micro_destroy", "lhmm_last_error", "lhmm_micro_time",
     "lhmm_sph_create", "lhmm_sph_step", "lhmm_sph_get_state", "lhmm_sph_coupling_state", "lhmm_couple_step",
     "lhmm_sph_destroy",
+    "lhmm_sur_create", "lhmm_sur_set_weights", "lhmm_sur_get_weights", "lhmm_sur_get_grads", "lhmm_sur_train_step", "lhmm_sur_forward",
+    "lhmm_sur_push_history", "lhmm_sur_features", "lhmm_sur_gate", "lhmm_sur_destroy",
 )
+SUR_HIST = 32
+SUR_FEATURES = 4 * SUR_HIST + 1
 KERNEL_NAMES = ("cell_step", "kick_drift", "bin_box", "forces", "kick2", "box_stress")
 
 
@@ -53,6 +57,10 @@ class LhmmBox(C.Structure):
 class LhmmSphParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly",
                                             "lambda_star", "alpha")]
+
+
+class LhmmSurParams(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("n_members", "n_in", "n_hidden", "n_out", "max_batch")]
 
 
 class LhmmError(RuntimeError):
@@ -89,6 +97,17 @@ def lib():
         L.lhmm_sph_coupling_state.argtypes = [vp, dp, dp]
         L.lhmm_couple_step.argtypes = [vp, vp, C.c_int32]
         L.lhmm_sph_destroy.argtypes = [vp]
+        fp = C.POINTER(C.c_float)
+        L.lhmm_sur_create.argtypes = [C.POINTER(LhmmSurParams), fp, vp, C.POINTER(vp)]
+        L.lhmm_sur_set_weights.argtypes = [vp, fp]
+        L.lhmm_sur_get_weights.argtypes = [vp, fp]
+        L.lhmm_sur_get_grads.argtypes = [vp, fp]
+        L.lhmm_sur_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp]
+        L.lhmm_sur_forward.argtypes = [vp, vp, C.c_int32, vp]
+        L.lhmm_sur_push_history.argtypes = [vp, C.c_int32, vp, C.c_int64, vp]
+        L.lhmm_sur_features.argtypes = [vp, C.c_int32, C.c_int64, vp, vp, vp]
+        L.lhmm_sur_gate.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float, vp, vp, vp]
+        L.lhmm_sur_destroy.argtypes = [vp]
         L.lhmm_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "lhmm_last_error":

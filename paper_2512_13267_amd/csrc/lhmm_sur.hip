@@ -1,0 +1,637 @@
+// lhmm_sur.hip -- gfx950 kernels and runtime of the stress surrogate: an
+// ensemble of MLPs (n_in -> n_hidden -> n_hidden -> n_out, GELU) trained with
+// mean-squared error and Adam, evaluated in the LHMM loop with an ensemble
+// spread gate (include/lhmm.h, lhmm_sur_*).
+//
+// Every product is one NT GEMM  C[M x N] = A[M x K] * B[N x K]^T  on BF16
+// operands with FP32 accumulation (v_mfma_f32_32x32x16_bf16), one wave per
+// 32 x 32 output tile, batched over the ensemble members (grid z).  Operand
+// fragments are loaded straight from global memory as 16-byte vectors (lane
+// l takes row l%32 and k-slice 8*(l/32) .. +7 of A and of B), so every
+// operand is kept in the layout whose reduction index is contiguous:
+//   forward  Z = X W:  A = X [B x nin],  B = W^T [nh x nin]
+//   backward dH = dZ W^T: A = dZ [B x nout], B = W [nin x nout]
+//   weights  dW = X^T dZ: A = X^T [nin x B], B = dZ^T [nout x B]
+// Epilogues add the bias, apply GELU (keeping the FP32 pre-activation) or
+// multiply by GELU'(Z), and write BF16 results in both layouts as needed.
+// Dimensions are padded: inputs to a multiple of 32, outputs to 32, batch
+// rows to a multiple of 32 (padded rows carry zero gradient).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "lhmm.h"
+#include "lhmm_internal.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int HIST = LHMM_SUR_HIST;  // gradient samples per feature vector
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+enum Epi {
+    EPI_F32 = 0,      // C -> f32 [M x N]
+    EPI_BIAS_F32,     // C + bias -> f32 [M x N]
+    EPI_BIAS_GELU,    // Z = C + bias -> f32; H = gelu(Z) -> bf16 [M x N] and [N x M]
+    EPI_GELU_GRAD,    // dZ = C * gelu'(Z) -> f32 [M x N], bf16 [M x N] and [N x M]
+};
+
+struct Gemm {
+    const bf16* A;
+    const bf16* B;
+    int M, N, K, lda, ldb;
+    long sA, sB;       // member strides (elements)
+    const float* bias;  // [N] per member
+    long sBias;
+    const float* Zin;   // EPI_GELU_GRAD: pre-activation [M x N]
+    float* Cf;          // f32 output [M x N]
+    bf16* Cb;           // bf16 output [M x N] (ld = N)
+    bf16* Ct;           // bf16 transposed output [N x M] (ld = ldt)
+    int ldt;
+    long sC, sCt;       // member strides of the M x N and N x M outputs
+};
+
+template <int EPI>
+__global__ __launch_bounds__(64) void k_gemm_nt(Gemm g) {
+    const int e = blockIdx.z;
+    const int n0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
+    const int l = threadIdx.x;
+    const bf16* A = g.A + e * g.sA + (long)(m0 + (l & 31)) * g.lda + 8 * (l >> 5);
+    const bf16* B = g.B + e * g.sB + (long)(n0 + (l & 31)) * g.ldb + 8 * (l >> 5);
+    floatx16 acc = {};
+    for (int k = 0; k < g.K; k += 16) {
+        const bf16x8 a = *(const bf16x8*)(A + k);
+        const bf16x8 b = *(const bf16x8*)(B + k);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    const int col = n0 + (l & 31);
+    const long cbase = e * g.sC, tbase = e * g.sCt;
+    float bias = 0.0f;
+    if (EPI == EPI_BIAS_F32 || EPI == EPI_BIAS_GELU) bias = g.bias[e * g.sBias + col];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = m0 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+        const long idx = cbase + (long)row * g.N + col;
+        const float c = acc[v];
+        if (EPI == EPI_F32) {
+            g.Cf[idx] = c;
+        } else if (EPI == EPI_BIAS_F32) {
+            g.Cf[idx] = c + bias;
+        } else if (EPI == EPI_BIAS_GELU) {
+            const float z = c + bias;
+            g.Cf[idx] = z;
+            const bf16 h = (bf16)gelu_f(z);
+            g.Cb[idx] = h;
+            g.Ct[tbase + (long)col * g.ldt + row] = h;
+        } else {  // EPI_GELU_GRAD
+            const float dz = c * gelu_grad_f(g.Zin[idx]);
+            g.Cf[idx] = dz;
+            const bf16 hb = (bf16)dz;
+            g.Cb[idx] = hb;
+            g.Ct[tbase + (long)col * g.ldt + row] = hb;
+        }
+    }
+}
+
+// caller features (B x n_in, f32) -> padded BF16 inputs X [Bp x nin_p] and
+// X^T [nin_p x Bp]; padding rows and columns are zero
+__global__ void k_inputs(const float* __restrict__ x, int B, int nin, int Bp, int nin_p, bf16* __restrict__ X,
+                         bf16* __restrict__ Xt) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)Bp * nin_p) return;
+    const int r = (int)(t / nin_p), c = (int)(t % nin_p);
+    const bf16 v = (bf16)((r < B && c < nin) ? x[(long)r * nin + c] : 0.0f);
+    X[t] = v;
+    Xt[(long)c * Bp + r] = v;
+}
+
+// MSE gradient and per-block loss partials for every member:
+// dY = 2 (Y - T) / (B n_out) on real rows and columns, 0 on padding.
+__global__ void k_loss_grad(const float* __restrict__ Y, long ystride, const float* __restrict__ T, int B, int Bp,
+                            int n_out, int nout_p, bf16* __restrict__ dY, bf16* __restrict__ dYt,
+                            float* __restrict__ dYf, float* __restrict__ part) {
+    __shared__ float sh[256];
+    const int e = blockIdx.y;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    float sq = 0.0f;
+    if (t < (long)Bp * nout_p) {
+        const int b = (int)(t / nout_p), j = (int)(t % nout_p);
+        float d = 0.0f;
+        if (b < B && j < n_out) {
+            const float diff = Y[(long)e * ystride + t] - T[(long)b * n_out + j];
+            sq = diff * diff;
+            d = 2.0f * diff / (float)(B * n_out);
+        }
+        dYf[(long)e * Bp * nout_p + t] = d;
+        dY[(long)e * Bp * nout_p + t] = (bf16)d;
+        dYt[(long)e * nout_p * Bp + (long)j * Bp + b] = (bf16)d;
+    }
+    sh[threadIdx.x] = sq;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long)e * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void k_loss_final(const float* __restrict__ part, int nparts, int B, int n_out, float* __restrict__ loss) {
+    const int e = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += part[(long)e * nparts + k];
+    loss[e] = (float)(s / (double)(B * n_out));
+}
+
+// column sums of f32 [rows x cols] per member (bias gradients): 64 columns
+// x 16 row groups per block, row group y sums rows y, y+16, ...; the 16
+// partials are added in a fixed order
+__global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ x, int rows, int cols, long stride,
+                                                float* __restrict__ out, long ostride) {
+    __shared__ float sh[16][64];
+    const int e = blockIdx.y;
+    const int c = blockIdx.x * 64 + threadIdx.x;
+    float s = 0.0f;
+    if (c < cols) {
+        const float* p = x + e * stride + c;
+        for (int r = threadIdx.y; r < rows; r += 16) s += p[(long)r * cols];
+    }
+    sh[threadIdx.y][threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.y == 0 && c < cols) {
+        float t = 0.0f;
+        for (int y = 0; y < 16; ++y) t += sh[y][threadIdx.x];
+        out[e * ostride + c] = t;
+    }
+}
+
+// Adam on FP32 masters of one weight matrix [rows x cols] per member, then
+// BF16 copies W [rows x cols] and W^T [cols x rows]
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int rows, int cols, long stride, int n_members, float lr, float c1,
+                       float c2, bf16* __restrict__ wb, bf16* __restrict__ wt) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per = (long)rows * cols;
+    if (t >= per * n_members) return;
+    const int e = (int)(t / per);
+    const long q = t % per;
+    const long idx = e * stride + q;
+    const float gg = g[idx];
+    const float mm = 0.9f * m[idx] + 0.1f * gg;
+    const float vv = 0.999f * v[idx] + 0.001f * gg * gg;
+    m[idx] = mm;
+    v[idx] = vv;
+    const float wn = w[idx] - lr * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
+    w[idx] = wn;
+    if (wb) {
+        const int r = (int)(q / cols), c = (int)(q % cols);
+        const bf16 h = (bf16)wn;
+        wb[e * stride + q] = h;
+        wt[e * stride + (long)c * rows + r] = h;
+    }
+}
+
+// member outputs (stride Bmax x nout_p) -> n_members x B x n_out
+__global__ void k_outputs(const float* __restrict__ Ysrc, long stride, int nout_p, int E, int B, int nout,
+                          float* __restrict__ Y) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)E * B * nout) return;
+    const int e = (int)(t / ((long)B * nout));
+    const long r = t % ((long)B * nout);
+    const int b = (int)(r / nout), j = (int)(r % nout);
+    Y[t] = Ysrc[e * stride + (long)b * nout_p + j];
+}
+
+// history ring of the in-plane gradient components: sample t of particle b
+// goes to slot t mod HIST as (L_xx, L_xy, L_yx, L_yy)
+__global__ void k_push_history(float* __restrict__ ring, int n, const double* __restrict__ gradL, long t) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const double* L = gradL + 9 * (long)b;
+    float* o = ring + ((long)b * HIST + (int)(t % HIST)) * 4;
+    o[0] = (float)L[0];
+    o[1] = (float)L[1];
+    o[2] = (float)L[3];
+    o[3] = (float)L[4];
+}
+
+// features of particle b after sample t: samples t-HIST+1 .. t (oldest
+// first, 4 components each) and the polymer fraction
+__global__ void k_features(const float* __restrict__ ring, int n, long t, const float* __restrict__ phi,
+                           float* __restrict__ X) {
+    constexpr int NF = 4 * HIST + 1;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)n * NF) return;
+    const int b = (int)(i / NF), f = (int)(i % NF);
+    float x;
+    if (f < 4 * HIST) {
+        const int s = f / 4, c = f % 4;
+        const int slot = (int)((t + 1 + s) % HIST);  // t + 1 - HIST + s, mod HIST
+        x = ring[((long)b * HIST + slot) * 4 + c];
+    } else {
+        x = phi[b];
+    }
+    X[i] = x;
+}
+
+// ensemble mean and spread gate: spread = sqrt(mean_j var_members(Y_j)),
+// flag if spread > threshold x max(|mean|_2, floor)
+__global__ void k_gate(const float* __restrict__ Y, int n_members, int B, int Bp, int n_out, int nout_p,
+                       float threshold, float floor_, float* __restrict__ mean, unsigned* __restrict__ flag) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float var_sum = 0.0f, norm2 = 0.0f;
+    for (int j = 0; j < n_out; ++j) {
+        float s = 0.0f, s2 = 0.0f;
+        for (int e = 0; e < n_members; ++e) {
+            const float y = Y[((long)e * Bp + b) * nout_p + j];
+            s += y;
+            s2 += y * y;
+        }
+        const float mu = s / n_members;
+        var_sum += fmaxf(s2 / n_members - mu * mu, 0.0f);
+        norm2 += mu * mu;
+        mean[(long)b * n_out + j] = mu;
+    }
+    const float spread = sqrtf(var_sum / n_out);
+    flag[b] = spread > threshold * fmaxf(sqrtf(norm2), floor_) ? 1u : 0u;
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct lhmm_sur {
+    int E = 0, nin = 0, nin_p = 0, nh = 0, nout = 0, nout_p = 32, Bmax = 0, step = 0;
+    hipStream_t stream = nullptr;
+    std::vector<void*> bufs;
+    // FP32 masters, grads, Adam moments, per member (stride = size of one member's tensor)
+    float *W1 = nullptr, *b1 = nullptr, *W2 = nullptr, *b2 = nullptr, *W3 = nullptr, *b3 = nullptr;
+    float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;
+    float *mW1, *mb1, *mW2, *mb2, *mW3, *mb3, *vW1, *vb1, *vW2, *vb2, *vW3, *vb3;
+    // BF16 weights in both layouts
+    bf16 *W1b, *W1t, *W2b, *W2t, *W3b, *W3t;
+    // activations
+    bf16 *X, *Xt, *H1, *H1t, *H2, *H2t, *dY, *dYt, *dZ2, *dZ2t, *dZ1, *dZ1t;
+    float *Z1, *Z2, *Y, *dYf, *dZ1f, *dZ2f, *part;
+};
+
+namespace {
+
+template <typename T>
+int sur_alloc(lhmm_sur* s, T** p, size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, (count ? count : 1) * sizeof(T)) != hipSuccess)
+        return lhmm_fail(LHMM_ERR_OOM, "hipMalloc(%zu) failed", count * sizeof(T));
+    s->bufs.push_back(q);
+    *p = (T*)q;
+    return LHMM_OK;
+}
+
+void sur_release(lhmm_sur* s) {
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (void* b : s->bufs) (void)hipFree(b);
+    s->bufs.clear();
+}
+
+template <int EPI>
+void gemm(lhmm_sur* s, const Gemm& g) {
+    dim3 grid(g.N / 32, g.M / 32, s->E);
+    k_gemm_nt<EPI><<<grid, 64, 0, s->stream>>>(g);
+}
+
+long szW1(const lhmm_sur* s) { return (long)s->nin_p * s->nh; }
+long szW2(const lhmm_sur* s) { return (long)s->nh * s->nh; }
+long szW3(const lhmm_sur* s) { return (long)s->nh * s->nout_p; }
+
+// forward of every member on the first Bp rows of s->X / s->Xt
+void forward(lhmm_sur* s, int Bp) {
+    Gemm g{};
+    // layer 1: Z1 = X W1 + b1
+    g.A = s->X; g.lda = s->nin_p; g.sA = 0;
+    g.B = s->W1t; g.ldb = s->nin_p; g.sB = szW1(s);
+    g.M = Bp; g.N = s->nh; g.K = s->nin_p;
+    g.bias = s->b1; g.sBias = s->nh;
+    g.Cf = s->Z1; g.Cb = s->H1; g.Ct = s->H1t; g.ldt = Bp; g.sC = (long)s->Bmax * s->nh; g.sCt = g.sC;
+    gemm<EPI_BIAS_GELU>(s, g);
+    // layer 2
+    g.A = s->H1; g.lda = s->nh; g.sA = (long)s->Bmax * s->nh;
+    g.B = s->W2t; g.ldb = s->nh; g.sB = szW2(s);
+    g.M = Bp; g.N = s->nh; g.K = s->nh;
+    g.bias = s->b2; g.sBias = s->nh;
+    g.Cf = s->Z2; g.Cb = s->H2; g.Ct = s->H2t; g.ldt = Bp;
+    gemm<EPI_BIAS_GELU>(s, g);
+    // layer 3: Y = H2 W3 + b3
+    g.A = s->H2; g.lda = s->nh; g.sA = (long)s->Bmax * s->nh;
+    g.B = s->W3t; g.ldb = s->nh; g.sB = szW3(s);
+    g.M = Bp; g.N = s->nout_p; g.K = s->nh;
+    g.bias = s->b3; g.sBias = s->nout_p;
+    g.Cf = s->Y; g.sC = (long)s->Bmax * s->nout_p; g.Cb = nullptr; g.Ct = nullptr;
+    gemm<EPI_BIAS_F32>(s, g);
+}
+
+int check_dims(const lhmm_sur_params* p) {
+    if (p->n_members < 1 || p->n_members > 64) return lhmm_fail(LHMM_ERR_ARG, "n_members must be 1..64");
+    if (p->n_in < 1 || p->n_out < 1 || p->n_out > 32) return lhmm_fail(LHMM_ERR_ARG, "need n_in >= 1, 1 <= n_out <= 32");
+    if (p->n_hidden < 32 || p->n_hidden % 32) return lhmm_fail(LHMM_ERR_ARG, "n_hidden must be a positive multiple of 32");
+    if (p->max_batch < 1) return lhmm_fail(LHMM_ERR_ARG, "max_batch must be positive");
+    return LHMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lhmm_sur_create(const lhmm_sur_params* p, const float* weights, void* stream, lhmm_sur** out) {
+    lhmm_clear_error();
+    if (!p || !weights || !out) return lhmm_fail(LHMM_ERR_ARG, "null argument");
+    *out = nullptr;
+    int rc = check_dims(p);
+    if (rc != LHMM_OK) return rc;
+    lhmm_sur* s = new (std::nothrow) lhmm_sur();
+    if (!s) return lhmm_fail(LHMM_ERR_OOM, "host allocation failed");
+    s->E = p->n_members;
+    s->nin = p->n_in;
+    s->nin_p = round_up(p->n_in, 32);
+    s->nh = p->n_hidden;
+    s->nout = p->n_out;
+    s->Bmax = round_up(p->max_batch, 32);
+    s->stream = (hipStream_t)stream;
+    const long E = s->E, w1 = szW1(s), w2 = szW2(s), w3 = szW3(s), nh = s->nh, no = s->nout_p;
+    const long Bm = s->Bmax;
+    float** f32s[] = {&s->W1, &s->gW1, &s->mW1, &s->vW1};
+    for (float** q : f32s) rc = rc ? rc : sur_alloc(s, q, E * w1);
+    float** f32h[] = {&s->b1, &s->gb1, &s->mb1, &s->vb1, &s->b2, &s->gb2, &s->mb2, &s->vb2};
+    for (float** q : f32h) rc = rc ? rc : sur_alloc(s, q, E * nh);
+    float** f32w2[] = {&s->W2, &s->gW2, &s->mW2, &s->vW2};
+    for (float** q : f32w2) rc = rc ? rc : sur_alloc(s, q, E * w2);
+    float** f32w3[] = {&s->W3, &s->gW3, &s->mW3, &s->vW3};
+    for (float** q : f32w3) rc = rc ? rc : sur_alloc(s, q, E * w3);
+    float** f32b3[] = {&s->b3, &s->gb3, &s->mb3, &s->vb3};
+    for (float** q : f32b3) rc = rc ? rc : sur_alloc(s, q, E * no);
+    bf16** wb[] = {&s->W1b, &s->W1t};
+    for (bf16** q : wb) rc = rc ? rc : sur_alloc(s, q, E * w1);
+    bf16** wb2[] = {&s->W2b, &s->W2t};
+    for (bf16** q : wb2) rc = rc ? rc : sur_alloc(s, q, E * w2);
+    bf16** wb3[] = {&s->W3b, &s->W3t};
+    for (bf16** q : wb3) rc = rc ? rc : sur_alloc(s, q, E * w3);
+    rc = rc ? rc : sur_alloc(s, &s->X, Bm * s->nin_p);
+    rc = rc ? rc : sur_alloc(s, &s->Xt, Bm * s->nin_p);
+    bf16** acts[] = {&s->H1, &s->H1t, &s->H2, &s->H2t, &s->dZ2, &s->dZ2t, &s->dZ1, &s->dZ1t};
+    for (bf16** q : acts) rc = rc ? rc : sur_alloc(s, q, E * Bm * nh);
+    float** actf[] = {&s->Z1, &s->Z2, &s->dZ1f, &s->dZ2f};
+    for (float** q : actf) rc = rc ? rc : sur_alloc(s, q, E * Bm * nh);
+    rc = rc ? rc : sur_alloc(s, &s->Y, E * Bm * no);
+    rc = rc ? rc : sur_alloc(s, &s->dYf, E * Bm * no);
+    rc = rc ? rc : sur_alloc(s, &s->dY, E * Bm * no);
+    rc = rc ? rc : sur_alloc(s, &s->dYt, E * Bm * no);
+    rc = rc ? rc : sur_alloc(s, &s->part, E * (Bm * no / 256 + 1));
+    if (rc == LHMM_OK) rc = lhmm_sur_set_weights(s, weights);
+    if (rc != LHMM_OK) {
+        sur_release(s);
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return LHMM_OK;
+}
+
+int lhmm_sur_set_weights(lhmm_sur* s, const float* weights) {
+    lhmm_clear_error();
+    if (!s || !weights) return lhmm_fail(LHMM_ERR_ARG, "null argument");
+    const int E = s->E, nin = s->nin, nin_p = s->nin_p, nh = s->nh, nout = s->nout, no = s->nout_p;
+    const long w1 = szW1(s), w2 = szW2(s), w3 = szW3(s);
+    std::vector<float> W1((size_t)E * w1, 0.f), W2((size_t)E * w2, 0.f), W3((size_t)E * w3, 0.f);
+    std::vector<float> B1((size_t)E * nh, 0.f), B2((size_t)E * nh, 0.f), B3((size_t)E * no, 0.f);
+    const float* q = weights;
+    for (int e = 0; e < E; ++e) {
+        for (int i = 0; i < nin; ++i)
+            for (int j = 0; j < nh; ++j) W1[e * w1 + (long)i * nh + j] = *q++;
+        for (int j = 0; j < nh; ++j) B1[(size_t)e * nh + j] = *q++;
+        for (int i = 0; i < nh; ++i)
+            for (int j = 0; j < nh; ++j) W2[e * w2 + (long)i * nh + j] = *q++;
+        for (int j = 0; j < nh; ++j) B2[(size_t)e * nh + j] = *q++;
+        for (int i = 0; i < nh; ++i)
+            for (int j = 0; j < nout; ++j) W3[e * w3 + (long)i * no + j] = *q++;
+        for (int j = 0; j < nout; ++j) B3[(size_t)e * no + j] = *q++;
+    }
+    const long total = (long)E * ((long)nin * nh + nh + (long)nh * nh + nh + (long)nh * nout + nout);
+    for (long i = 0; i < total; ++i)
+        if (!std::isfinite(weights[i])) return lhmm_fail(LHMM_ERR_ARG, "non-finite weight %ld", i);
+    LHMM_HIPCHK(hipStreamSynchronize(s->stream));
+    LHMM_HIPCHK(hipMemcpy(s->W1, W1.data(), W1.size() * 4, hipMemcpyHostToDevice));
+    LHMM_HIPCHK(hipMemcpy(s->W2, W2.data(), W2.size() * 4, hipMemcpyHostToDevice));
+    LHMM_HIPCHK(hipMemcpy(s->W3, W3.data(), W3.size() * 4, hipMemcpyHostToDevice));
+    LHMM_HIPCHK(hipMemcpy(s->b1, B1.data(), B1.size() * 4, hipMemcpyHostToDevice));
+    LHMM_HIPCHK(hipMemcpy(s->b2, B2.data(), B2.size() * 4, hipMemcpyHostToDevice));
+    LHMM_HIPCHK(hipMemcpy(s->b3, B3.data(), B3.size() * 4, hipMemcpyHostToDevice));
+    float* zero[] = {s->mW1, s->vW1, s->mW2, s->vW2, s->mW3, s->vW3, s->mb1, s->vb1, s->mb2, s->vb2, s->mb3, s->vb3,
+                     s->gW1, s->gW2, s->gW3, s->gb1, s->gb2, s->gb3};
+    const long zs[] = {w1, w1, w2, w2, w3, w3, nh, nh, nh, nh, no, no, w1, w2, w3, nh, nh, no};
+    for (int k = 0; k < 18; ++k) LHMM_HIPCHK(hipMemset(zero[k], 0, (size_t)E * zs[k] * 4));
+    // BF16 copies: an Adam step with zero learning rate and zero gradient
+    // leaves the masters unchanged and writes both layouts
+    const int t = 256;
+    k_adam<<<(E * w1 + t - 1) / t, t, 0, s->stream>>>(s->W1, s->gW1, s->mW1, s->vW1, nin_p, nh, w1, E, 0.f, 1.f, 1.f,
+                                                     s->W1b, s->W1t);
+    k_adam<<<(E * w2 + t - 1) / t, t, 0, s->stream>>>(s->W2, s->gW2, s->mW2, s->vW2, nh, nh, w2, E, 0.f, 1.f, 1.f,
+                                                     s->W2b, s->W2t);
+    k_adam<<<(E * w3 + t - 1) / t, t, 0, s->stream>>>(s->W3, s->gW3, s->mW3, s->vW3, nh, no, w3, E, 0.f, 1.f, 1.f,
+                                                     s->W3b, s->W3t);
+    LHMM_HIPCHK(hipGetLastError());
+    LHMM_HIPCHK(hipStreamSynchronize(s->stream));
+    s->step = 0;
+    return LHMM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// device FP32 tensors of one kind (masters or gradients) -> packed host layout
+int copy_packed(lhmm_sur* s, bool grads, float* out) {
+    const int E = s->E, nin = s->nin, nh = s->nh, nout = s->nout, no = s->nout_p;
+    const long w1 = szW1(s), w2 = szW2(s), w3 = szW3(s);
+    std::vector<float> W1((size_t)E * w1), W2((size_t)E * w2), W3((size_t)E * w3), B1((size_t)E * nh),
+        B2((size_t)E * nh), B3((size_t)E * no);
+    const float* src[6] = {grads ? s->gW1 : s->W1, grads ? s->gb1 : s->b1, grads ? s->gW2 : s->W2,
+                           grads ? s->gb2 : s->b2, grads ? s->gW3 : s->W3, grads ? s->gb3 : s->b3};
+    std::vector<float>* dst[6] = {&W1, &B1, &W2, &B2, &W3, &B3};
+    LHMM_HIPCHK(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < 6; ++k)
+        LHMM_HIPCHK(hipMemcpy(dst[k]->data(), src[k], dst[k]->size() * 4, hipMemcpyDeviceToHost));
+    float* q = out;
+    for (int e = 0; e < E; ++e) {
+        for (int i = 0; i < nin; ++i)
+            for (int j = 0; j < nh; ++j) *q++ = W1[e * w1 + (long)i * nh + j];
+        for (int j = 0; j < nh; ++j) *q++ = B1[(size_t)e * nh + j];
+        for (int i = 0; i < nh; ++i)
+            for (int j = 0; j < nh; ++j) *q++ = W2[e * w2 + (long)i * nh + j];
+        for (int j = 0; j < nh; ++j) *q++ = B2[(size_t)e * nh + j];
+        for (int i = 0; i < nh; ++i)
+            for (int j = 0; j < nout; ++j) *q++ = W3[e * w3 + (long)i * no + j];
+        for (int j = 0; j < nout; ++j) *q++ = B3[(size_t)e * no + j];
+    }
+    return LHMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lhmm_sur_get_weights(lhmm_sur* s, float* weights) {
+    lhmm_clear_error();
+    if (!s || !weights) return lhmm_fail(LHMM_ERR_ARG, "null argument");
+    return copy_packed(s, false, weights);
+}
+
+int lhmm_sur_get_grads(lhmm_sur* s, float* grads) {
+    lhmm_clear_error();
+    if (!s || !grads) return lhmm_fail(LHMM_ERR_ARG, "null argument");
+    return copy_packed(s, true, grads);
+}
+
+// B rows of f32 features (device, B x n_in) into the padded BF16 inputs
+static int load_inputs(lhmm_sur* s, const float* X, int B, int Bp) {
+    const long n = (long)Bp * s->nin_p;
+    k_inputs<<<(n + 255) / 256, 256, 0, s->stream>>>(X, B, s->nin, Bp, s->nin_p, s->X, s->Xt);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_train_step(lhmm_sur* s, const float* X, const float* T, int32_t B, float lr, float* loss) {
+    lhmm_clear_error();
+    if (!s || !X || !T) return lhmm_fail(LHMM_ERR_ARG, "null argument");
+    if (B < 1 || B > s->Bmax) return lhmm_fail(LHMM_ERR_ARG, "batch %d outside 1..%d", B, s->Bmax);
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return lhmm_fail(LHMM_ERR_ARG, "bad learning rate");
+    const int Bp = round_up(B, 32), E = s->E, nh = s->nh, no = s->nout_p;
+    const long Bm = s->Bmax;
+    int rc = load_inputs(s, X, B, Bp);
+    if (rc != LHMM_OK) return rc;
+    forward(s, Bp);
+    // dY and loss
+    const long nY = (long)Bp * no;
+    const int nparts = (int)((nY + 255) / 256);
+    // dY, dY^T and the f32 dY use member stride Bp x n_out_p
+    k_loss_grad<<<dim3(nparts, E), 256, 0, s->stream>>>(s->Y, Bm * no, T, B, Bp, s->nout, no, s->dY, s->dYt, s->dYf,
+                                                        s->part);
+    Gemm g{};
+    // dW3 = H2^T dY : A = H2t [nh x Bp], B = dYt [no x Bp]
+    g.A = s->H2t; g.lda = Bp; g.sA = Bm * nh;
+    g.B = s->dYt; g.ldb = Bp; g.sB = (long)no * Bp;
+    g.M = nh; g.N = no; g.K = Bp;
+    g.Cf = s->gW3; g.sC = szW3(s);
+    gemm<EPI_F32>(s, g);
+    // dZ2 = (dY W3^T) * gelu'(Z2): A = dY [Bp x no], B = W3b [nh x no]
+    g = Gemm{};
+    g.A = s->dY; g.lda = no; g.sA = (long)Bp * no;
+    g.B = s->W3b; g.ldb = no; g.sB = szW3(s);
+    g.M = Bp; g.N = nh; g.K = no;
+    g.Zin = s->Z2; g.Cf = s->dZ2f; g.Cb = s->dZ2; g.Ct = s->dZ2t; g.ldt = Bp; g.sC = Bm * nh; g.sCt = Bm * nh;
+    gemm<EPI_GELU_GRAD>(s, g);
+    // dW2 = H1^T dZ2 : A = H1t [nh x Bp], B = dZ2t [nh x Bp]
+    g = Gemm{};
+    g.A = s->H1t; g.lda = Bp; g.sA = Bm * nh;
+    g.B = s->dZ2t; g.ldb = Bp; g.sB = Bm * nh;
+    g.M = nh; g.N = nh; g.K = Bp;
+    g.Cf = s->gW2; g.sC = szW2(s);
+    gemm<EPI_F32>(s, g);
+    // dZ1 = (dZ2 W2^T) * gelu'(Z1): A = dZ2 [Bp x nh], B = W2b [nh x nh]
+    g = Gemm{};
+    g.A = s->dZ2; g.lda = nh; g.sA = Bm * nh;
+    g.B = s->W2b; g.ldb = nh; g.sB = szW2(s);
+    g.M = Bp; g.N = nh; g.K = nh;
+    g.Zin = s->Z1; g.Cf = s->dZ1f; g.Cb = s->dZ1; g.Ct = s->dZ1t; g.ldt = Bp; g.sC = Bm * nh; g.sCt = Bm * nh;
+    gemm<EPI_GELU_GRAD>(s, g);
+    // dW1 = X^T dZ1 : A = Xt [nin_p x Bp], B = dZ1t [nh x Bp]
+    g = Gemm{};
+    g.A = s->Xt; g.lda = Bp; g.sA = 0;
+    g.B = s->dZ1t; g.ldb = Bp; g.sB = Bm * nh;
+    g.M = s->nin_p; g.N = nh; g.K = Bp;
+    g.Cf = s->gW1; g.sC = szW1(s);
+    gemm<EPI_F32>(s, g);
+    // bias gradients
+    k_colsum<<<dim3((no + 63) / 64, E), dim3(64, 16), 0, s->stream>>>(s->dYf, Bp, no, (long)Bp * no, s->gb3, no);
+    k_colsum<<<dim3((nh + 63) / 64, E), dim3(64, 16), 0, s->stream>>>(s->dZ2f, Bp, nh, Bm * nh, s->gb2, nh);
+    k_colsum<<<dim3((nh + 63) / 64, E), dim3(64, 16), 0, s->stream>>>(s->dZ1f, Bp, nh, Bm * nh, s->gb1, nh);
+    // Adam
+    s->step += 1;
+    const float c1 = 1.0f - powf(0.9f, (float)s->step), c2 = 1.0f - powf(0.999f, (float)s->step);
+    const int t = 256;
+    const long w1 = szW1(s), w2 = szW2(s), w3 = szW3(s);
+    k_adam<<<(E * w1 + t - 1) / t, t, 0, s->stream>>>(s->W1, s->gW1, s->mW1, s->vW1, s->nin_p, nh, w1, E, lr, c1, c2,
+                                                     s->W1b, s->W1t);
+    k_adam<<<(E * w2 + t - 1) / t, t, 0, s->stream>>>(s->W2, s->gW2, s->mW2, s->vW2, nh, nh, w2, E, lr, c1, c2,
+                                                     s->W2b, s->W2t);
+    k_adam<<<(E * w3 + t - 1) / t, t, 0, s->stream>>>(s->W3, s->gW3, s->mW3, s->vW3, nh, no, w3, E, lr, c1, c2,
+                                                     s->W3b, s->W3t);
+    k_adam<<<(E * nh + t - 1) / t, t, 0, s->stream>>>(s->b1, s->gb1, s->mb1, s->vb1, 1, nh, nh, E, lr, c1, c2,
+                                                     nullptr, nullptr);
+    k_adam<<<(E * nh + t - 1) / t, t, 0, s->stream>>>(s->b2, s->gb2, s->mb2, s->vb2, 1, nh, nh, E, lr, c1, c2,
+                                                     nullptr, nullptr);
+    k_adam<<<(E * no + t - 1) / t, t, 0, s->stream>>>(s->b3, s->gb3, s->mb3, s->vb3, 1, no, no, E, lr, c1, c2,
+                                                     nullptr, nullptr);
+    if (loss) k_loss_final<<<E, 64, 0, s->stream>>>(s->part, nparts, B, s->nout, loss);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_forward(lhmm_sur* s, const float* X, int32_t B, float* Y) {
+    lhmm_clear_error();
+    if (!s || !X || !Y) return lhmm_fail(LHMM_ERR_ARG, "null argument");
+    if (B < 1 || B > s->Bmax) return lhmm_fail(LHMM_ERR_ARG, "batch %d outside 1..%d", B, s->Bmax);
+    const int Bp = round_up(B, 32);
+    int rc = load_inputs(s, X, B, Bp);
+    if (rc != LHMM_OK) return rc;
+    forward(s, Bp);
+    const long n = (long)s->E * B * s->nout;
+    k_outputs<<<(n + 255) / 256, 256, 0, s->stream>>>(s->Y, (long)s->Bmax * s->nout_p, s->nout_p, s->E, B, s->nout, Y);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_push_history(float* ring, int32_t n, const double* gradL, int64_t t, void* stream) {
+    lhmm_clear_error();
+    if (!ring || !gradL || n < 1 || t < 0) return lhmm_fail(LHMM_ERR_ARG, "bad history arguments");
+    k_push_history<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(ring, n, gradL, t);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_features(const float* ring, int32_t n, int64_t t, const float* phi, float* X, void* stream) {
+    lhmm_clear_error();
+    if (!ring || !phi || !X || n < 1 || t < 0) return lhmm_fail(LHMM_ERR_ARG, "bad feature arguments");
+    const long total = (long)n * (4 * HIST + 1);
+    k_features<<<(total + 255) / 256, 256, 0, (hipStream_t)stream>>>(ring, n, t, phi, X);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_gate(const float* Y, int32_t n_members, int32_t B, int32_t n_out, float threshold, float floor_,
+                  float* mean, uint32_t* flag, void* stream) {
+    lhmm_clear_error();
+    if (!Y || !mean || !flag || n_members < 1 || B < 1 || n_out < 1) return lhmm_fail(LHMM_ERR_ARG, "bad gate arguments");
+    k_gate<<<(B + 255) / 256, 256, 0, (hipStream_t)stream>>>(Y, n_members, B, B, n_out, n_out, threshold, floor_,
+                                                           mean, flag);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_destroy(lhmm_sur* s) {
+    lhmm_clear_error();
+    if (!s) return LHMM_OK;
+    sur_release(s);
+    delete s;
+    return LHMM_OK;
+}
+
+}  // extern "C"

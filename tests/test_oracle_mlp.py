@@ -106,3 +106,31 @@ def test_gelu_derivative():
     assert np.allclose(mo.gelu_grad(z), fd, atol=1e-8)
     assert mo.gelu(np.array([0.0]))[0] == 0.0
     assert abs(mo.gelu(np.array([10.0]))[0] - 10.0) < 1e-12
+
+
+def test_gate_special_cases():
+    # identical members: zero spread, never flagged, mean = the member
+    Y1 = np.tile(np.array([[[1.0, -2.0, 0.5], [0.0, 0.0, 0.0]]]), (5, 1, 1))
+    mu, flag, ratio = mo.gate(Y1, 0.05, 0.1)
+    assert np.array_equal(mu, Y1[0]) and not flag.any() and np.all(ratio == 0)
+    # two members at +-d around m: spread = d exactly (population variance)
+    m = np.array([3.0, 4.0, 0.0])
+    d = 0.2
+    Y2 = np.stack([m + d, m - d])[:, None, :]
+    mu, flag, ratio = mo.gate(Y2, 0.05, 0.1)
+    assert np.allclose(mu[0], m) and abs(ratio[0] - d / (0.05 * 5.0)) < 1e-12 and not flag[0]
+    _, flag, _ = mo.gate(np.stack([m + 0.3, m - 0.3])[:, None, :], 0.05, 0.1)
+    assert flag[0]
+    # below the floor the denominator is the floor
+    Y3 = np.stack([np.full(3, 1e-3), np.full(3, -1e-3)])[:, None, :]
+    _, _, ratio = mo.gate(Y3, 0.05, 0.1)
+    assert abs(ratio[0] - 1e-3 / (0.05 * 0.1)) < 1e-12
+
+
+def test_features_order():
+    n, T = 3, 40
+    hist = np.arange(n * T * 4, dtype=np.float64).reshape(n, T, 4)
+    X = mo.features(hist, np.array([0.1, 0.2, 0.3]))
+    assert X.shape == (3, 129)
+    # first feature = oldest kept sample (index T-32), component xx
+    assert X[1, 0] == hist[1, T - 32, 0] and X[1, 127] == hist[1, T - 1, 3] and X[2, 128] == 0.3
