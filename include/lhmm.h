@@ -68,6 +68,12 @@ extern "C" {
 #define LHMM_FLAG_CELL 2u      /* a cell width fell below 3 rc              */
 #define LHMM_FLAG_NONFINITE 4u /* a stress sample was not finite            */
 #define LHMM_FLAG_ARG 8u       /* the box's gradient was rejected (L := 0)  */
+/* the reduced cell's smallest width fell below LHMM_THIN_WIDTH rc: the box
+ * is still exact, but a flow that keeps stretching it will reach the
+ * LHMM_FLAG_CELL guard; long runs under time-varying gradients restore or
+ * re-initialise such boxes */
+#define LHMM_FLAG_THIN 16u
+#define LHMM_THIN_WIDTH 3.3
 
 #define LHMM_FP32 0 /* single-precision particle state and pair forces     */
 #define LHMM_FP64 1 /* double-precision particle state and pair forces     */
@@ -137,6 +143,28 @@ int lhmm_micro_get_state(lhmm_micro* m, double* s, double* c, double* f, double*
  * the host; ordered on the caller's stream.  Errors: ARG (n_steps <= 0),
  * STATE (no state loaded), HIP. */
 int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double* stress_out);
+
+/* As lhmm_micro_step, for the listed boxes only: boxes is a HOST array of
+ * n_sel strictly increasing box indices; the launches cover just their
+ * particles and cells.  The other boxes keep their state; their rows of
+ * stress_out are written as zero.  Every step advances the shared random-
+ * force counter once, so a selected box follows exactly the trajectory a
+ * full lhmm_micro_step would give it from the same state and counter.
+ * Used where only some micro-domains must run (the surrogate's fallback
+ * boxes).  Waits for the upload of the previous call's list.  Errors: ARG
+ * (empty, unsorted or out-of-range list), STATE, HIP. */
+int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, double* stress_out,
+                           const int32_t* boxes, int32_t n_sel);
+
+/* Keep a device copy of the current state of every box (positions,
+ * velocities, forces, cell).  Ordered on the caller's stream.  Errors:
+ * STATE (no state loaded), OOM, HIP. */
+int lhmm_micro_snapshot(lhmm_micro* m);
+
+/* Return the listed boxes (HOST, strictly increasing) to their snapshot
+ * state and clear their flags; the random-force counter is not rewound.
+ * Ordered on the caller's stream.  Errors: ARG, STATE (no snapshot), HIP. */
+int lhmm_micro_restore(lhmm_micro* m, const int32_t* boxes, int32_t n_sel);
 
 /* Forces at the current state with random-force counter = current step,
  * without advancing: f_out host n_total x 3; virial_out host n_boxes x 12
@@ -316,9 +344,15 @@ int lhmm_sur_forward(lhmm_sur* s, const float* X, int32_t B, float* Y);
 
 /* Record sample t (t = 0, 1, ...) of the micro gradients of n particles:
  * ring is DEVICE n x LHMM_SUR_HIST x 4 FP32 (caller-owned), slot t mod
- * LHMM_SUR_HIST of particle b receives (L_xx, L_xy, L_yx, L_yy) of
+ * LHMM_SUR_HIST of particle b receives scale x (L_xx, L_xy, L_yx, L_yy) of
  * gradL (DEVICE n x 9 doubles).  stream: hipStream_t to launch on. */
-int lhmm_sur_push_history(float* ring, int32_t n, const double* gradL, int64_t t, void* stream);
+int lhmm_sur_push_history(float* ring, int32_t n, const double* gradL, int64_t t, float scale, void* stream);
+
+/* Sample t of the ring (still held: at most LHMM_SUR_HIST - 1 samples old)
+ * back to traceless in-plane gradients: gradL DEVICE n x 9 doubles,
+ * components / scale (inv_scale = 1 / scale).  Used to replay a particle's
+ * recent history on a micro-domain. */
+int lhmm_sur_history_gradient(const float* ring, int32_t n, int64_t t, float inv_scale, double* gradL, void* stream);
 
 /* Feature rows after sample t: X (DEVICE n x LHMM_SUR_FEATURES FP32) row b
  * holds samples t-LHMM_SUR_HIST+1 .. t of particle b, oldest first, then
@@ -332,6 +366,19 @@ int lhmm_sur_features(const float* ring, int32_t n, int64_t t, const float* phi,
  * exceeds threshold x max(|mean|_2, floor), else 0. */
 int lhmm_sur_gate(const float* Y, int32_t n_members, int32_t B, int32_t n_out, float threshold, float floor,
                   float* mean, uint32_t* flag, void* stream);
+
+/* Training targets from micro stresses: sigma DEVICE n x 6 doubles (xx, yy,
+ * zz, xy, xz, yz); T DEVICE n x 3 FP32 = inv_scale x (sigma_xx - tr/3,
+ * sigma_xy, sigma_yy - tr/3), the in-plane deviatoric stress the macro
+ * momentum equation takes from the micro-domain (Eq. pip). */
+int lhmm_sur_targets(const double* sigma, int32_t n, float inv_scale, float* T, void* stream);
+
+/* Stress handed to the macro solver, DEVICE n x 6: row b is sigma_dpd[b]
+ * where use_dpd[b] != 0 (DEVICE n uint32, NULL: none), else the traceless
+ * tensor with in-plane deviatoric part scale x mean[b] (DEVICE n x 3 FP32,
+ * the surrogate's (xx, xy, yy)). */
+int lhmm_sur_blend(const float* mean, const uint32_t* use_dpd, const double* sigma_dpd, int32_t n, float scale,
+                   double* sigma_out, void* stream);
 
 /* Release every resource (waits for the stream).  NULL ok. */
 int lhmm_sur_destroy(lhmm_sur* s);

@@ -121,3 +121,25 @@ def gate(Y, threshold, floor):
     denom = threshold * np.maximum(np.sqrt((mu ** 2).sum(axis=1)), floor)
     ratio = spread / denom
     return mu, ratio > 1.0, ratio
+
+
+def targets(sigma, inv_scale=1.0):
+    """In-plane deviatoric part (xx - tr/3, xy, yy - tr/3) of micro stresses
+    sigma (n, 6) = (xx, yy, zz, xy, xz, yz), times inv_scale: what the
+    macro momentum equation takes from a micro-domain (Eq. pip, before the
+    factor alpha/lambda*)."""
+    s = np.asarray(sigma, dtype=np.float64)
+    tr3 = s[:, :3].sum(axis=1) / 3.0
+    return np.stack([s[:, 0] - tr3, s[:, 3], s[:, 1] - tr3], axis=1) * inv_scale
+
+
+def blend(mean, use_dpd, sigma_dpd, scale=1.0):
+    """Stress rows for the macro solver: the micro stress where use_dpd,
+    else the traceless tensor whose in-plane deviatoric part is scale x mean."""
+    m = np.asarray(mean, dtype=np.float64) * scale
+    out = np.zeros((m.shape[0], 6))
+    out[:, 0], out[:, 1], out[:, 2], out[:, 3] = m[:, 0], m[:, 2], -(m[:, 0] + m[:, 2]), m[:, 1]
+    if use_dpd is not None:
+        u = np.asarray(use_dpd).astype(bool)
+        out[u] = np.asarray(sigma_dpd)[u]
+    return out

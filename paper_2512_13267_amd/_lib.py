@@ -22,6 +22,8 @@ FLAG_BOND = 1
 FLAG_CELL = 2
 FLAG_NONFINITE = 4
 FLAG_ARG = 8
+FLAG_THIN = 16
+THIN_WIDTH = 3.3
 
 FP32 = 0
 FP64 = 1
@@ -32,10 +34,12 @@ EXPORTS = (
     "lhmm_micro_create", "lhmm_micro_set_state", "lhmm_micro_get_state", "lhmm_micro_step",
     "lhmm_micro_forces", "lhmm_micro_stress_parts", "lhmm_micro_pair_counts", "lhmm_micro_flags",
     "lhmm_micro_sizes", "lhmm_micro_destroy", "lhmm_last_error", "lhmm_micro_time",
+    "lhmm_micro_step_subset", "lhmm_micro_snapshot", "lhmm_micro_restore",
     "lhmm_sph_create", "lhmm_sph_step", "lhmm_sph_get_state", "lhmm_sph_coupling_state", "lhmm_couple_step",
     "lhmm_sph_destroy",
     "lhmm_sur_create", "lhmm_sur_set_weights", "lhmm_sur_get_weights", "lhmm_sur_get_grads", "lhmm_sur_train_step", "lhmm_sur_forward",
-    "lhmm_sur_push_history", "lhmm_sur_features", "lhmm_sur_gate", "lhmm_sur_destroy",
+    "lhmm_sur_push_history", "lhmm_sur_features", "lhmm_sur_gate", "lhmm_sur_destroy", "lhmm_sur_targets",
+    "lhmm_sur_blend", "lhmm_sur_history_gradient",
 )
 SUR_HIST = 32
 SUR_FEATURES = 4 * SUR_HIST + 1
@@ -84,6 +88,10 @@ def lib():
         L.lhmm_micro_set_state.argtypes = [vp, dp, dp, dp, dp, C.c_uint64]
         L.lhmm_micro_get_state.argtypes = [vp, dp, dp, dp, dp, u64p]
         L.lhmm_micro_step.argtypes = [vp, vp, C.c_int32, vp]
+        i32p = C.POINTER(C.c_int32)
+        L.lhmm_micro_step_subset.argtypes = [vp, vp, C.c_int32, vp, i32p, C.c_int32]
+        L.lhmm_micro_snapshot.argtypes = [vp]
+        L.lhmm_micro_restore.argtypes = [vp, i32p, C.c_int32]
         L.lhmm_micro_forces.argtypes = [vp, dp, dp, dp]
         L.lhmm_micro_stress_parts.argtypes = [vp, dp]
         L.lhmm_micro_pair_counts.argtypes = [vp, u64p]
@@ -104,7 +112,10 @@ def lib():
         L.lhmm_sur_get_grads.argtypes = [vp, fp]
         L.lhmm_sur_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp]
         L.lhmm_sur_forward.argtypes = [vp, vp, C.c_int32, vp]
-        L.lhmm_sur_push_history.argtypes = [vp, C.c_int32, vp, C.c_int64, vp]
+        L.lhmm_sur_push_history.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_float, vp]
+        L.lhmm_sur_targets.argtypes = [vp, C.c_int32, C.c_float, vp, vp]
+        L.lhmm_sur_blend.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp, vp]
+        L.lhmm_sur_history_gradient.argtypes = [vp, C.c_int32, C.c_int64, C.c_float, vp, vp]
         L.lhmm_sur_features.argtypes = [vp, C.c_int32, C.c_int64, vp, vp, vp]
         L.lhmm_sur_gate.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float, vp, vp, vp]
         L.lhmm_sur_destroy.argtypes = [vp]

@@ -97,6 +97,11 @@ struct Ctx {
     unsigned* flags;
     const int* blk_box;
     const int* blk_first;
+    // selection: when sel is set, per-box kernels run over the n_sel boxes
+    // sel[0..n_sel) and per-block kernels over the work blocks blk_list[..]
+    const int* sel;
+    const int* blk_list;
+    int n_sel;
     void* s;  // SoA: component k of particle i at [k * n_total + i]
     void* c;
     void* f;
@@ -359,8 +364,9 @@ __global__ void k_zero_acc(Ctx C) {
 // One thread per box.  advance = 1: mid-step inverse, deformation and
 // reduction of this step; advance = 0: grid for the current cell only.
 __global__ void k_cell_step(Ctx C, int advance) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= C.n_boxes) return;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (C.sel ? C.n_sel : C.n_boxes)) return;
+    const int b = C.sel ? C.sel[q] : q;
     BoxDyn& D = C.dyn[b];
     double h[9];
     for (int k = 0; k < 9; ++k) h[k] = D.h[k];
@@ -395,6 +401,7 @@ __global__ void k_cell_step(Ctx C, int advance) {
         nc[a] -= 1;
     }
     if (narrow) C.flags[b] |= LHMM_FLAG_CELL;
+    if (!(fmin(fmin(w[0], w[1]), w[2]) >= LHMM_THIN_WIDTH * C.rc)) C.flags[b] |= LHMM_FLAG_THIN;
     D.nc[0] = nc[0]; D.nc[1] = nc[1]; D.nc[2] = nc[2];
 }
 
@@ -415,7 +422,7 @@ __device__ __forceinline__ real wrap01(real x) {
 
 template <typename real>
 __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
-    const int blk = blockIdx.x;
+    const int blk = C.blk_list ? C.blk_list[blockIdx.x] : (int)blockIdx.x;
     const int b = C.blk_box[blk];
     const BoxInfo B = C.box[b];
     const int i = C.blk_first[blk] + (int)threadIdx.x;
@@ -459,7 +466,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
     using R = Rec<real>;
     __shared__ int cnt[MAX_CELLS_PER_BOX];
     __shared__ int wsum[BIN_THREADS / 64];
-    const int b = blockIdx.x;
+    const int b = C.sel ? C.sel[blockIdx.x] : (int)blockIdx.x;
     const BoxInfo B = C.box[b];
     const BoxDyn& D = C.dyn[b];
     const int ncell = D.nc[0] * D.nc[1] * D.nc[2];
@@ -563,7 +570,8 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
     __shared__ V4 qbuf[QD][NW][64];                 // (dx, dy, dz, cell-order position of j)
     __shared__ double red[13 * NW];
 
-    const int blk = xcd_local_work(blockIdx.x, gridDim.x);
+    int blk = xcd_local_work(blockIdx.x, gridDim.x);
+    if (C.blk_list) blk = C.blk_list[blk];
     const int b = C.blk_box[blk];
     const BoxInfo B = C.box[b];
     const BoxDyn& D = C.dyn[b];
@@ -762,7 +770,7 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
 template <typename real>
 __global__ __launch_bounds__(BS) void k_kick2(Ctx C) {
     __shared__ double sh[6 * (BS / 64)];
-    const int blk = blockIdx.x;
+    const int blk = C.blk_list ? C.blk_list[blockIdx.x] : (int)blockIdx.x;
     const int b = C.blk_box[blk];
     const BoxInfo B = C.box[b];
     const BoxDyn& D = C.dyn[b];
@@ -793,7 +801,7 @@ __global__ __launch_bounds__(BS) void k_kick2(Ctx C) {
 // sums the partials of blocks l, l+64, ...; a fixed shuffle tree combines
 // the lanes, so the order of every sum is fixed.
 __global__ __launch_bounds__(64) void k_box_stress(Ctx C) {
-    const int b = blockIdx.x;
+    const int b = C.sel ? C.sel[blockIdx.x] : (int)blockIdx.x;
     const int lane = threadIdx.x;
     const BoxInfo B = C.box[b];
     double v[19];
@@ -822,7 +830,31 @@ __global__ __launch_bounds__(64) void k_box_stress(Ctx C) {
         if (!finite) C.flags[b] |= LHMM_FLAG_NONFINITE;
         const unsigned long long np = (unsigned long long)v[18];
         C.acc_pairs[b] += C.vir_scale < 1.0 ? np / 2 : np;
-        if (b == 0) *C.step += 1ull;
+        if (blockIdx.x == 0) *C.step += 1ull;
+    }
+}
+
+// Copy the snapshot state of the selected boxes back (one workgroup per box)
+// and clear their flags.
+template <typename real>
+__global__ __launch_bounds__(256) void k_restore(Ctx C, const real* __restrict__ ss, const real* __restrict__ sc,
+                                                 const real* __restrict__ sf, const BoxDyn* __restrict__ sdyn) {
+    const int b = C.sel[blockIdx.x];
+    const BoxInfo B = C.box[b];
+    const int N = C.n_total;
+    real* s = (real*)C.s;
+    real* c = (real*)C.c;
+    real* f = (real*)C.f;
+    for (int k = 0; k < 3; ++k)
+        for (int i = threadIdx.x; i < B.n; i += blockDim.x) {
+            const long q = (long)k * N + B.off + i;
+            s[q] = ss[q];
+            c[q] = sc[q];
+            f[q] = sf[q];
+        }
+    if (threadIdx.x == 0) {
+        C.dyn[b] = sdyn[b];
+        C.flags[b] = 0u;
     }
 }
 
@@ -863,6 +895,13 @@ struct lhmm_micro {
     unsigned* d_part_pairs = nullptr;
     double *d_acc = nullptr, *d_parts = nullptr, *d_gradL = nullptr;
     unsigned long long *d_acc_pairs = nullptr, *d_step = nullptr;
+    // selection lists (device) and their pinned staging, reused once ev_sel completes
+    int *d_sel = nullptr, *d_blk_list = nullptr, *h_sel = nullptr;
+    hipEvent_t ev_sel = nullptr;
+    // snapshot of the particle state and per-box cells
+    void *d_snap_s = nullptr, *d_snap_c = nullptr, *d_snap_f = nullptr;
+    BoxDyn* d_snap_dyn = nullptr;
+    bool have_snapshot = false;
     bool have_state = false, forces_valid = false;
     std::map<int, hipGraphExec_t> graphs;
     Ctx ctx{};
@@ -870,17 +909,19 @@ struct lhmm_micro {
 
 namespace {
 
+// One step (or a force evaluation) of the boxes C selects: all n_boxes boxes
+// and n_blocks work blocks, or the n_sel selected boxes and their nblk blocks.
 template <typename real>
-void launch_step_kernels(lhmm_micro* m, int step_offset, bool advance, bool full_step) {
-    const Ctx& C = m->ctx;
-    const int bt = 256, bg = (m->n_boxes + bt - 1) / bt;
+void launch_step_kernels(lhmm_micro* m, const Ctx& C, int nbox, int nblk, int step_offset, bool advance,
+                         bool full_step) {
+    const int bt = 256, bg = (nbox + bt - 1) / bt;
     k_cell_step<<<bg, bt, 0, m->stream>>>(C, advance ? 1 : 0);
-    k_kick_drift<real><<<m->n_blocks, BS, 0, m->stream>>>(C, advance ? 1 : 0);
-    k_bin_box<real><<<m->n_boxes, BIN_THREADS, 0, m->stream>>>(C);
-    k_forces<real><<<m->n_blocks, BS, 0, m->stream>>>(C, step_offset);
+    k_kick_drift<real><<<nblk, BS, 0, m->stream>>>(C, advance ? 1 : 0);
+    k_bin_box<real><<<nbox, BIN_THREADS, 0, m->stream>>>(C);
+    k_forces<real><<<nblk, BS, 0, m->stream>>>(C, step_offset);
     if (full_step) {
-        k_kick2<real><<<m->n_blocks, BS, 0, m->stream>>>(C);
-        k_box_stress<<<m->n_boxes, 64, 0, m->stream>>>(C);
+        k_kick2<real><<<nblk, BS, 0, m->stream>>>(C);
+        k_box_stress<<<nbox, 64, 0, m->stream>>>(C);
     }
 }
 
@@ -912,16 +953,23 @@ void launch_step_timed(lhmm_micro* m, hipEvent_t* ev) {
 
 void launch_one_step(lhmm_micro* m) {
     if (m->precision == LHMM_FP64)
-        launch_step_kernels<double>(m, 1, true, true);
+        launch_step_kernels<double>(m, m->ctx, m->n_boxes, m->n_blocks, 1, true, true);
     else
-        launch_step_kernels<float>(m, 1, true, true);
+        launch_step_kernels<float>(m, m->ctx, m->n_boxes, m->n_blocks, 1, true, true);
+}
+
+void launch_one_step_sel(lhmm_micro* m, const Ctx& C, int nbox, int nblk) {
+    if (m->precision == LHMM_FP64)
+        launch_step_kernels<double>(m, C, nbox, nblk, 1, true, true);
+    else
+        launch_step_kernels<float>(m, C, nbox, nblk, 1, true, true);
 }
 
 void launch_force_eval(lhmm_micro* m) {
     if (m->precision == LHMM_FP64)
-        launch_step_kernels<double>(m, 0, false, false);
+        launch_step_kernels<double>(m, m->ctx, m->n_boxes, m->n_blocks, 0, false, false);
     else
-        launch_step_kernels<float>(m, 0, false, false);
+        launch_step_kernels<float>(m, m->ctx, m->n_boxes, m->n_blocks, 0, false, false);
 }
 
 int get_graph(lhmm_micro* m, int nsteps, hipGraphExec_t* out) {
@@ -965,9 +1013,12 @@ void release(lhmm_micro* m) {
     m->graphs.clear();
     void* bufs[] = {m->d_box, m->d_dyn, m->d_flags, m->d_blk_box, m->d_blk_first, m->d_s, m->d_c, m->d_f,
                     m->d_pcell, m->d_cell_start, m->d_cell_pos, m->d_cell_vel, m->d_part_vir, m->d_part_kin,
-                    m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_step};
+                    m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_step,
+                    m->d_sel, m->d_blk_list, m->d_snap_s, m->d_snap_c, m->d_snap_f, m->d_snap_dyn};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    if (m->h_sel) (void)hipHostFree(m->h_sel);
+    if (m->ev_sel) (void)hipEventDestroy(m->ev_sel);
     if (m->ev_in) (void)hipEventDestroy(m->ev_in);
     if (m->ev_out) (void)hipEventDestroy(m->ev_out);
     if (m->stream) (void)hipStreamDestroy(m->stream);
@@ -976,6 +1027,42 @@ void release(lhmm_micro* m) {
 int sync_engine(lhmm_micro* m) {
     HIPCHK(hipStreamSynchronize(m->stream));
     HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+// Validate a host list of boxes (strictly increasing, in range), upload it
+// and the list of their work blocks on the engine stream, and return a
+// context that selects them.
+int select_boxes(lhmm_micro* m, const int32_t* boxes, int32_t n_sel, Ctx* out, int* nblk) {
+    if (!boxes || n_sel < 1 || n_sel > m->n_boxes) return fail(LHMM_ERR_ARG, "need 1..%d boxes (got %d)", m->n_boxes, n_sel);
+    for (int q = 0; q < n_sel; ++q) {
+        if (boxes[q] < 0 || boxes[q] >= m->n_boxes) return fail(LHMM_ERR_ARG, "box %d out of range", boxes[q]);
+        if (q && boxes[q] <= boxes[q - 1]) return fail(LHMM_ERR_ARG, "boxes must be strictly increasing");
+    }
+    if (!m->d_sel) {
+        int rc = dalloc(&m->d_sel, m->n_boxes);
+        if (rc == LHMM_OK) rc = dalloc(&m->d_blk_list, m->n_blocks);
+        if (rc != LHMM_OK) return rc;
+        HIPCHK(hipHostMalloc((void**)&m->h_sel, sizeof(int) * (m->n_boxes + m->n_blocks)));
+        HIPCHK(hipEventCreateWithFlags(&m->ev_sel, hipEventDisableTiming));
+    } else {
+        HIPCHK(hipEventSynchronize(m->ev_sel));  // the previous upload has left the staging buffer
+    }
+    int nb = 0;
+    int* hb = m->h_sel + m->n_boxes;
+    for (int q = 0; q < n_sel; ++q) {
+        const BoxInfo& B = m->box[boxes[q]];
+        m->h_sel[q] = boxes[q];
+        for (int k = 0; k < B.nblk; ++k) hb[nb++] = B.blk_off + k;
+    }
+    HIPCHK(hipMemcpyAsync(m->d_sel, m->h_sel, sizeof(int) * n_sel, hipMemcpyHostToDevice, m->stream));
+    HIPCHK(hipMemcpyAsync(m->d_blk_list, hb, sizeof(int) * nb, hipMemcpyHostToDevice, m->stream));
+    HIPCHK(hipEventRecord(m->ev_sel, m->stream));
+    *out = m->ctx;
+    out->sel = m->d_sel;
+    out->blk_list = m->d_blk_list;
+    out->n_sel = n_sel;
+    *nblk = nb;
     return LHMM_OK;
 }
 
@@ -1284,6 +1371,83 @@ int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double*
         }
     }
     k_finalize<<<bg, bt, 0, m->stream>>>(m->ctx, stress_out, m->d_parts, 1.0 / n_steps);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(m->ev_out, m->stream));
+    HIPCHK(hipStreamWaitEvent(m->user_stream, m->ev_out, 0));
+    return LHMM_OK;
+}
+
+int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, double* stress_out,
+                           const int32_t* boxes, int32_t n_sel) {
+    g_err.clear();
+    if (!m || !gradL || !stress_out) return fail(LHMM_ERR_ARG, "null argument");
+    if (n_steps <= 0) return fail(LHMM_ERR_ARG, "n_steps must be positive (got %d)", n_steps);
+    if (!m->have_state) return fail(LHMM_ERR_STATE, "no particle state loaded");
+    const int bt = 256, bg = (m->n_boxes + bt - 1) / bt;
+    HIPCHK(hipEventRecord(m->ev_in, m->user_stream));
+    HIPCHK(hipStreamWaitEvent(m->stream, m->ev_in, 0));
+    Ctx C{};
+    int nblk = 0;
+    int rc = select_boxes(m, boxes, n_sel, &C, &nblk);
+    if (rc != LHMM_OK) return rc;
+    k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, gradL);
+    k_zero_acc<<<(18 * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
+    if (!m->forces_valid) {
+        launch_force_eval(m);
+        m->forces_valid = true;
+    }
+    for (int k = 0; k < n_steps; ++k) launch_one_step_sel(m, C, n_sel, nblk);
+    k_finalize<<<bg, bt, 0, m->stream>>>(m->ctx, stress_out, m->d_parts, 1.0 / n_steps);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(m->ev_out, m->stream));
+    HIPCHK(hipStreamWaitEvent(m->user_stream, m->ev_out, 0));
+    return LHMM_OK;
+}
+
+int lhmm_micro_snapshot(lhmm_micro* m) {
+    g_err.clear();
+    if (!m) return fail(LHMM_ERR_ARG, "null argument");
+    if (!m->have_state) return fail(LHMM_ERR_STATE, "no particle state loaded");
+    const size_t bytes = 3 * (size_t)m->n_total * m->real_size;
+    if (!m->d_snap_s) {
+        int rc = dalloc((char**)&m->d_snap_s, bytes);
+        if (rc == LHMM_OK) rc = dalloc((char**)&m->d_snap_c, bytes);
+        if (rc == LHMM_OK) rc = dalloc((char**)&m->d_snap_f, bytes);
+        if (rc == LHMM_OK) rc = dalloc(&m->d_snap_dyn, m->n_boxes);
+        if (rc != LHMM_OK) return rc;
+    }
+    HIPCHK(hipEventRecord(m->ev_in, m->user_stream));
+    HIPCHK(hipStreamWaitEvent(m->stream, m->ev_in, 0));
+    if (!m->forces_valid) {
+        launch_force_eval(m);
+        m->forces_valid = true;
+    }
+    HIPCHK(hipMemcpyAsync(m->d_snap_s, m->d_s, bytes, hipMemcpyDeviceToDevice, m->stream));
+    HIPCHK(hipMemcpyAsync(m->d_snap_c, m->d_c, bytes, hipMemcpyDeviceToDevice, m->stream));
+    HIPCHK(hipMemcpyAsync(m->d_snap_f, m->d_f, bytes, hipMemcpyDeviceToDevice, m->stream));
+    HIPCHK(hipMemcpyAsync(m->d_snap_dyn, m->d_dyn, sizeof(BoxDyn) * m->n_boxes, hipMemcpyDeviceToDevice, m->stream));
+    HIPCHK(hipEventRecord(m->ev_out, m->stream));
+    HIPCHK(hipStreamWaitEvent(m->user_stream, m->ev_out, 0));
+    m->have_snapshot = true;
+    return LHMM_OK;
+}
+
+int lhmm_micro_restore(lhmm_micro* m, const int32_t* boxes, int32_t n_sel) {
+    g_err.clear();
+    if (!m) return fail(LHMM_ERR_ARG, "null argument");
+    if (!m->have_snapshot) return fail(LHMM_ERR_STATE, "no snapshot taken");
+    HIPCHK(hipEventRecord(m->ev_in, m->user_stream));
+    HIPCHK(hipStreamWaitEvent(m->stream, m->ev_in, 0));
+    Ctx C{};
+    int nblk = 0;
+    int rc = select_boxes(m, boxes, n_sel, &C, &nblk);
+    if (rc != LHMM_OK) return rc;
+    if (m->precision == LHMM_FP64)
+        k_restore<double><<<n_sel, 256, 0, m->stream>>>(C, (const double*)m->d_snap_s, (const double*)m->d_snap_c,
+                                                        (const double*)m->d_snap_f, m->d_snap_dyn);
+    else
+        k_restore<float><<<n_sel, 256, 0, m->stream>>>(C, (const float*)m->d_snap_s, (const float*)m->d_snap_c,
+                                                       (const float*)m->d_snap_f, m->d_snap_dyn);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(m->ev_out, m->stream));
     HIPCHK(hipStreamWaitEvent(m->user_stream, m->ev_out, 0));

@@ -213,15 +213,16 @@ __global__ void k_outputs(const float* __restrict__ Ysrc, long stride, int nout_
 
 // history ring of the in-plane gradient components: sample t of particle b
 // goes to slot t mod HIST as (L_xx, L_xy, L_yx, L_yy)
-__global__ void k_push_history(float* __restrict__ ring, int n, const double* __restrict__ gradL, long t) {
+__global__ void k_push_history(float* __restrict__ ring, int n, const double* __restrict__ gradL, long t,
+                               float scale) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
     const double* L = gradL + 9 * (long)b;
     float* o = ring + ((long)b * HIST + (int)(t % HIST)) * 4;
-    o[0] = (float)L[0];
-    o[1] = (float)L[1];
-    o[2] = (float)L[3];
-    o[3] = (float)L[4];
+    o[0] = (float)(L[0] * scale);
+    o[1] = (float)(L[1] * scale);
+    o[2] = (float)(L[3] * scale);
+    o[3] = (float)(L[4] * scale);
 }
 
 // features of particle b after sample t: samples t-HIST+1 .. t (oldest
@@ -264,6 +265,52 @@ __global__ void k_gate(const float* __restrict__ Y, int n_members, int B, int Bp
     }
     const float spread = sqrtf(var_sum / n_out);
     flag[b] = spread > threshold * fmaxf(sqrtf(norm2), floor_) ? 1u : 0u;
+}
+
+// micro stresses (xx, yy, zz, xy, xz, yz) -> deviatoric in-plane targets
+// (xx - tr/3, xy, yy - tr/3) x inv_scale
+__global__ void k_targets(const double* __restrict__ sigma, int n, float inv_scale, float* __restrict__ T) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const double* s = sigma + 6 * (long)b;
+    const double tr3 = (s[0] + s[1] + s[2]) / 3.0;
+    T[3 * (long)b + 0] = (float)((s[0] - tr3) * inv_scale);
+    T[3 * (long)b + 1] = (float)(s[3] * inv_scale);
+    T[3 * (long)b + 2] = (float)((s[1] - tr3) * inv_scale);
+}
+
+// stress for the macro solver: the micro stress where use_dpd[b], else the
+// traceless tensor built from the surrogate mean
+__global__ void k_blend(const float* __restrict__ mean, const unsigned* __restrict__ use_dpd,
+                        const double* __restrict__ sigma_dpd, int n, float scale, double* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    double* o = out + 6 * (long)b;
+    if (use_dpd && use_dpd[b]) {
+        for (int q = 0; q < 6; ++q) o[q] = sigma_dpd[6 * (long)b + q];
+    } else {
+        const double dxx = (double)mean[3 * (long)b] * scale, dxy = (double)mean[3 * (long)b + 1] * scale,
+                     dyy = (double)mean[3 * (long)b + 2] * scale;
+        o[0] = dxx;
+        o[1] = dyy;
+        o[2] = -(dxx + dyy);
+        o[3] = dxy;
+        o[4] = 0.0;
+        o[5] = 0.0;
+    }
+}
+
+// gradient sample s of the history ring back to micro gradients (n x 9)
+__global__ void k_ring_to_grad(const float* __restrict__ ring, int n, long s, float inv_scale,
+                               double* __restrict__ gradL) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const float* r = ring + ((long)b * HIST + (int)(s % HIST)) * 4;
+    double* L = gradL + 9 * (long)b;
+    const double xx = (double)r[0] * inv_scale, xy = (double)r[1] * inv_scale, yx = (double)r[2] * inv_scale;
+    L[0] = xx; L[1] = xy; L[2] = 0.0;
+    L[3] = yx; L[4] = -xx; L[5] = 0.0;
+    L[6] = 0.0; L[7] = 0.0; L[8] = 0.0;
 }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -599,10 +646,10 @@ int lhmm_sur_forward(lhmm_sur* s, const float* X, int32_t B, float* Y) {
     return LHMM_OK;
 }
 
-int lhmm_sur_push_history(float* ring, int32_t n, const double* gradL, int64_t t, void* stream) {
+int lhmm_sur_push_history(float* ring, int32_t n, const double* gradL, int64_t t, float scale, void* stream) {
     lhmm_clear_error();
-    if (!ring || !gradL || n < 1 || t < 0) return lhmm_fail(LHMM_ERR_ARG, "bad history arguments");
-    k_push_history<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(ring, n, gradL, t);
+    if (!ring || !gradL || n < 1 || t < 0 || !std::isfinite(scale)) return lhmm_fail(LHMM_ERR_ARG, "bad history arguments");
+    k_push_history<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(ring, n, gradL, t, scale);
     LHMM_HIPCHK(hipGetLastError());
     return LHMM_OK;
 }
@@ -622,6 +669,31 @@ int lhmm_sur_gate(const float* Y, int32_t n_members, int32_t B, int32_t n_out, f
     if (!Y || !mean || !flag || n_members < 1 || B < 1 || n_out < 1) return lhmm_fail(LHMM_ERR_ARG, "bad gate arguments");
     k_gate<<<(B + 255) / 256, 256, 0, (hipStream_t)stream>>>(Y, n_members, B, B, n_out, n_out, threshold, floor_,
                                                            mean, flag);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_targets(const double* sigma, int32_t n, float inv_scale, float* T, void* stream) {
+    lhmm_clear_error();
+    if (!sigma || !T || n < 1) return lhmm_fail(LHMM_ERR_ARG, "bad target arguments");
+    k_targets<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(sigma, n, inv_scale, T);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_blend(const float* mean, const uint32_t* use_dpd, const double* sigma_dpd, int32_t n, float scale,
+                   double* sigma_out, void* stream) {
+    lhmm_clear_error();
+    if (!mean || !sigma_out || n < 1 || (use_dpd && !sigma_dpd)) return lhmm_fail(LHMM_ERR_ARG, "bad blend arguments");
+    k_blend<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(mean, use_dpd, sigma_dpd, n, scale, sigma_out);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_history_gradient(const float* ring, int32_t n, int64_t t, float inv_scale, double* gradL, void* stream) {
+    lhmm_clear_error();
+    if (!ring || !gradL || n < 1 || t < 0) return lhmm_fail(LHMM_ERR_ARG, "bad history arguments");
+    k_ring_to_grad<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(ring, n, t, inv_scale, gradL);
     LHMM_HIPCHK(hipGetLastError());
     return LHMM_OK;
 }

@@ -365,18 +365,20 @@ def reverse_poiseuille(nx: int = 16, ny: int = 64, width: float = 1.0, force: fl
     return MacroInit(r=r, v=np.zeros_like(r), params=params, n_steps=n_steps)
 
 
-def lhmm_boxes(n_boxes: int, n_particles: int = 4000, density: float = 3.0, polymer_fraction: float = 0.1,
+def lhmm_boxes(n_boxes: int, n_particles: int = 4000, density: float = 3.0, polymer_fraction=0.1,
                seed_k: int = 2, **param_over) -> Workload:
     """One cubic micro-box per SPH particle, each of n_particles at the given
     density (edge (n/density)^(1/3)), 10-bead chains holding the polymer
-    fraction, random start, no gradient (the macro side supplies it)."""
+    fraction (a number, or one value per box), random start, no gradient
+    (the macro side supplies it)."""
     p = default_params(seed=SEED_BASE + seed_k, **param_over)
     rng = np.random.default_rng(SEED_BASE + seed_k)
     edge = (n_particles / density) ** (1.0 / 3.0)
-    n_chains = int(round(polymer_fraction * n_particles / p["chain_len"]))
+    phis = np.broadcast_to(np.asarray(polymer_fraction, dtype=np.float64), (n_boxes,))
     h = cubic_cell(edge)
     boxes = []
-    for _ in range(n_boxes):
+    for b in range(n_boxes):
+        n_chains = int(round(phis[b] * n_particles / p["chain_len"]))
         s, c = random_box(rng, h, n_particles, n_chains, p["chain_len"], p["kBT"], p["mass"])
-        boxes.append(BoxInit(s=s, c=c, h=h, n_chains=n_chains, L=np.zeros((3, 3)), edge=edge, phi=polymer_fraction))
+        boxes.append(BoxInit(s=s, c=c, h=h, n_chains=n_chains, L=np.zeros((3, 3)), edge=edge, phi=float(phis[b])))
     return Workload("lhmm_boxes", p, boxes, 0)

@@ -104,6 +104,33 @@ class Micro:
                                         C.c_void_p(out.data_ptr())))
         return out
 
+    def step_subset(self, gradL, n_steps: int, boxes, out=None):
+        """Advance only the listed boxes (strictly increasing indices); rows of
+        the other boxes in the returned stress are zero."""
+        torch = self._torch
+        g = gradL.reshape(self.n_boxes, 9)
+        if g.dtype != torch.float64 or not g.is_cuda or not g.is_contiguous():
+            raise ValueError("gradL must be a contiguous cuda float64 tensor")
+        sel = np.ascontiguousarray(boxes, dtype=np.int32)
+        if out is None:
+            out = torch.empty((self.n_boxes, 6), dtype=torch.float64, device=g.device)
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() != 6 * self.n_boxes:
+            raise ValueError("out must be a contiguous cuda float64 tensor of n_boxes x 6")
+        with torch.cuda.stream(self.stream):
+            check(lib().lhmm_micro_step_subset(self._h, C.c_void_p(g.data_ptr()), int(n_steps),
+                                               C.c_void_p(out.data_ptr()),
+                                               sel.ctypes.data_as(C.POINTER(C.c_int32)), int(sel.size)))
+        return out
+
+    def snapshot(self):
+        with self._torch.cuda.stream(self.stream):
+            check(lib().lhmm_micro_snapshot(self._h))
+
+    def restore(self, boxes):
+        sel = np.ascontiguousarray(boxes, dtype=np.int32)
+        with self._torch.cuda.stream(self.stream):
+            check(lib().lhmm_micro_restore(self._h, sel.ctypes.data_as(C.POINTER(C.c_int32)), int(sel.size)))
+
     def time_kernels(self, gradL, n_steps: int) -> dict:
         """Advance n_steps eagerly with HIP events around every kernel on the
         engine's stream; returns {kernel name: mean ms per launch}."""

@@ -136,13 +136,38 @@ class Surrogate:
             pass
 
 
-def push_history(ring, gradL, t, stream):
-    """ring: cuda float32 (n, SUR_HIST, 4); gradL: cuda float64 (n, 9)."""
+def push_history(ring, gradL, t, stream, scale=1.0):
+    """ring: cuda float32 (n, SUR_HIST, 4); gradL: cuda float64 (>= n rows of 9)."""
     n = ring.shape[0]
-    if ring.shape[1:] != (SUR_HIST, 4) or gradL.numel() != 9 * n:
+    if ring.shape[1:] != (SUR_HIST, 4) or gradL.numel() < 9 * n:
         raise ValueError("ring must be (n, 32, 4) and gradL (n, 9)")
     check(lib().lhmm_sur_push_history(C.c_void_p(ring.data_ptr()), n, C.c_void_p(gradL.data_ptr()), int(t),
-                                      C.c_void_p(stream.cuda_stream)))
+                                      float(scale), C.c_void_p(stream.cuda_stream)))
+
+
+def history_gradient(ring, t, gradL, stream, inv_scale=1.0):
+    n = ring.shape[0]
+    if gradL.numel() < 9 * n or gradL.dtype.itemsize != 8:
+        raise ValueError("gradL must hold n x 9 float64")
+    check(lib().lhmm_sur_history_gradient(C.c_void_p(ring.data_ptr()), n, int(t), float(inv_scale),
+                                          C.c_void_p(gradL.data_ptr()), C.c_void_p(stream.cuda_stream)))
+
+
+def targets(sigma, inv_scale, T, stream):
+    """sigma: cuda float64 (n, 6) -> T cuda float32 (n, 3)."""
+    n = T.shape[0]
+    if sigma.numel() < 6 * n or T.shape != (n, 3):
+        raise ValueError("sigma must hold n x 6 and T be (n, 3)")
+    check(lib().lhmm_sur_targets(C.c_void_p(sigma.data_ptr()), n, float(inv_scale), C.c_void_p(T.data_ptr()),
+                                 C.c_void_p(stream.cuda_stream)))
+
+
+def blend(mean, use_dpd, sigma_dpd, scale, out, stream):
+    n = mean.shape[0]
+    check(lib().lhmm_sur_blend(C.c_void_p(mean.data_ptr()),
+                               C.c_void_p(0 if use_dpd is None else use_dpd.data_ptr()),
+                               C.c_void_p(0 if sigma_dpd is None else sigma_dpd.data_ptr()), n, float(scale),
+                               C.c_void_p(out.data_ptr()), C.c_void_p(stream.cuda_stream)))
 
 
 def features(ring, t, phi, X, stream):

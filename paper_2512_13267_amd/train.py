@@ -1,0 +1,266 @@
+"""Training pipeline of the stress surrogate.
+
+Data: a batch of micro-domains (4000 particles, polymer fraction uniform in
+[0.1, 0.3]) advanced by the batched micro-DPD engine under random
+gradient histories: each box follows piecewise-constant traceless in-plane
+gradients, one per macro step, whose three free entries are independent
+Ornstein-Uhlenbeck sequences (standard deviation GRAD_SD, correlation
+CORR_STEPS macro steps).  A sample is (the box's last LHMM_SUR_HIST
+gradients and its polymer fraction) -> (the in-plane deviatoric micro
+stress averaged over the macro step's micro steps), the quantity the
+macro momentum equation takes from a micro-domain (Eq. pip).  Every step of
+the data path runs in the library: micro steps, history ring, features and
+targets.  PyTorch only holds the buffers and shuffles the rows.
+
+A periodic cell under a generic time-varying flow is eventually stretched
+until its reduced cell becomes too thin for the cutoff.  Boxes that reach
+the LHMM_FLAG_THIN width are returned to their equilibrated snapshot; their
+samples count again once LHMM_SUR_HIST macro steps have passed since the
+restart, so every kept sample's history window was lived by its box.
+
+Training: every member takes the same minibatches (members differ by their
+random initialisation), Adam with a cosine-decayed learning rate, mean
+squared error on targets divided by STRESS_SCALE.  10 % of the boxes are
+held out.  A group of boxes can be run as replicas (same start, same
+gradients, different random-force streams) to measure the DPD noise of a
+target.
+
+Command line: ``python -m paper_2512_13267_amd.train --out DIR`` writes
+``surrogate.npz`` (weights and scales) and ``train_metrics.json``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import _lib, inputs, surrogate
+from .micro import from_workload
+
+HIST = _lib.SUR_HIST
+N_FEATURES = _lib.SUR_FEATURES
+GRAD_SD = 0.05
+CORR_STEPS = 10.0
+GRAD_SCALE = 1.0 / GRAD_SD     # features hold L / GRAD_SD
+STRESS_SCALE = 0.1             # the network predicts deviatoric stress / STRESS_SCALE
+K_MICRO = 50
+PHI_RANGE = (0.1, 0.3)
+RESET_FLAGS = _lib.FLAG_THIN | _lib.FLAG_CELL | _lib.FLAG_BOND | _lib.FLAG_NONFINITE
+BAD_FLAGS = _lib.FLAG_CELL | _lib.FLAG_BOND | _lib.FLAG_NONFINITE
+
+
+def phi_feature(phi):
+    """Polymer fraction as fed to the network (centred, unit range)."""
+    return (np.asarray(phi, dtype=np.float32) - 0.2) * 10.0
+
+
+def ou_gradients(n_boxes, n_macro, sd=GRAD_SD, corr=CORR_STEPS, seed=0):
+    """(n_macro, n_boxes, 9) piecewise-constant gradients [[a, b, 0], [c, -a, 0], 0]
+    with (a, b, c) stationary OU sequences."""
+    rng = np.random.default_rng(seed)
+    rho = math.exp(-1.0 / corr)
+    x = rng.normal(size=(n_boxes, 3)) * sd
+    out = np.zeros((n_macro, n_boxes, 9))
+    for t in range(n_macro):
+        out[t, :, 0], out[t, :, 1], out[t, :, 3], out[t, :, 4] = x[:, 0], x[:, 1], x[:, 2], -x[:, 0]
+        x = rho * x + math.sqrt(1.0 - rho * rho) * sd * rng.normal(size=(n_boxes, 3))
+    return out
+
+
+def generate(n_boxes, n_macro, k_micro=K_MICRO, equil=500, seed_k=3, replicas=1, log=print):
+    """Run the micro engine and return device tensors X (n, 129), T (n, 3),
+    box (n,) int32, step (n,) int32 and a summary dict.  With replicas = R,
+    boxes come in groups of R sharing start and gradients."""
+    import torch
+
+    n_unique = n_boxes // replicas
+    rng = np.random.default_rng(inputs.SEED_BASE + seed_k)
+    phis_u = rng.uniform(*PHI_RANGE, size=n_unique)
+    wl_u = inputs.lhmm_boxes(n_unique, polymer_fraction=phis_u, seed_k=seed_k)
+    boxes = [b for b in wl_u.boxes for _ in range(replicas)]
+    wl = inputs.Workload("surrogate_data", wl_u.params, boxes, 0)
+    phis = np.repeat(phis_u, replicas)
+    G_u = ou_gradients(n_unique, n_macro, seed=inputs.SEED_BASE + seed_k + 1)
+    G_host = np.repeat(G_u, replicas, axis=1)
+    t0 = time.time()
+    m = from_workload(wl, precision="fp32", rng_ids=list(range(n_boxes)))
+    st = m.stream
+    dev = torch.device("cuda")
+    zero = torch.zeros((n_boxes, 9), dtype=torch.float64, device=dev)
+    m.step(zero, equil)
+    m.snapshot()
+    m.flags(clear=True)
+    G = torch.from_numpy(G_host).to(dev)
+    ring = torch.zeros((n_boxes, HIST, 4), dtype=torch.float32, device=dev)
+    phi_d = torch.from_numpy(phi_feature(phis)).to(dev)
+    Xt = torch.empty((n_boxes, N_FEATURES), dtype=torch.float32, device=dev)
+    Tt = torch.empty((n_boxes, 3), dtype=torch.float32, device=dev)
+    sig = torch.empty((n_boxes, 6), dtype=torch.float64, device=dev)
+    cap = n_boxes * max(n_macro - HIST + 1, 1)
+    X = torch.empty((cap, N_FEATURES), dtype=torch.float32, device=dev)
+    T = torch.empty((cap, 3), dtype=torch.float32, device=dev)
+    box_id = torch.empty(cap, dtype=torch.int32, device=dev)
+    step_id = torch.empty(cap, dtype=torch.int32, device=dev)
+    ids_all = torch.arange(n_boxes, dtype=torch.int32, device=dev)
+    age = np.zeros(n_boxes, dtype=np.int64)
+    n = 0
+    resets = 0
+    bad = 0
+    with torch.cuda.stream(st):
+        for t in range(n_macro):
+            g = G[t].contiguous()
+            surrogate.push_history(ring, g, t, st, scale=GRAD_SCALE)
+            m.step(g, k_micro, out=sig)
+            surrogate.features(ring, t, phi_d, Xt, st)
+            surrogate.targets(sig, 1.0 / STRESS_SCALE, Tt, st)
+            fl = m.flags(clear=True)
+            age += 1
+            keep = (age >= HIST) & ((fl & BAD_FLAGS) == 0)
+            bad += int(((fl & BAD_FLAGS) != 0).sum())
+            if keep.any():
+                idx = torch.from_numpy(np.nonzero(keep)[0]).to(dev)
+                k = idx.numel()
+                X[n:n + k] = Xt[idx]
+                T[n:n + k] = Tt[idx]
+                box_id[n:n + k] = ids_all[idx]
+                step_id[n:n + k] = t
+                n += k
+            reset = np.nonzero(fl & RESET_FLAGS)[0]
+            if reset.size:
+                m.restore(reset.astype(np.int32))
+                age[reset] = 0
+                resets += int(reset.size)
+            if (t + 1) % 50 == 0:
+                torch.cuda.synchronize()
+                log(f"  macro step {t + 1}/{n_macro}: {n} samples, {resets} resets, "
+                    f"{time.time() - t0:.1f} s", flush=True)
+    torch.cuda.synchronize()
+    info = {"n_boxes": n_boxes, "replicas": replicas, "n_macro": n_macro, "k_micro": k_micro, "equil": equil,
+            "samples": n, "resets": resets, "bad_samples": bad, "seconds": time.time() - t0,
+            "grad_sd": GRAD_SD, "corr_steps": CORR_STEPS}
+    m.close()
+    return X[:n], T[:n], box_id[:n], step_id[:n], info
+
+
+def evaluate(sur, X, T, batch):
+    """Ensemble mean predictions and relative errors on (X, T)."""
+    import torch
+
+    means = []
+    spreads = []
+    for k in range(0, X.shape[0], batch):
+        Y = sur.forward(X[k:k + batch].contiguous())
+        means.append(Y.mean(dim=0))
+        spreads.append(Y.std(dim=0, unbiased=False).pow(2).mean(dim=1).sqrt())
+    M = torch.cat(means)
+    err = (M - T).double()
+    rel = float(err.norm() / T.double().norm())
+    comp = [float(err[:, j].norm() / T[:, j].double().norm()) for j in range(3)]
+    return M, {"rel_l2": rel, "rel_l2_xx_xy_yy": comp, "rmse_scaled": float(err.pow(2).mean().sqrt()),
+               "mean_spread_scaled": float(torch.cat(spreads).mean())}
+
+
+def train(X, T, box_id, n_members=5, hidden=256, epochs=30, batch=4096, lr=1e-3, seed=0, held_mod=10,
+          log=print):
+    import torch
+
+    dev = X.device
+    held = (box_id % held_mod) == 0
+    tr = torch.nonzero(~held).flatten()
+    te = torch.nonzero(held).flatten()
+    members = surrogate.init_members(n_members, N_FEATURES, hidden, 3, seed=inputs.SEED_BASE + 100 + seed)
+    sur = surrogate.Surrogate(members, N_FEATURES, hidden, 3, max_batch=batch)
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(inputs.SEED_BASE + 200 + seed)
+    steps_per_epoch = max(tr.numel() // batch, 1)
+    total = steps_per_epoch * epochs
+    loss = torch.zeros(n_members, dtype=torch.float32, device=dev)
+    acc = torch.zeros(n_members, dtype=torch.float64, device=dev)
+    t0 = time.time()
+    history = []
+    k = 0
+    with torch.cuda.stream(sur.stream):
+        for ep in range(epochs):
+            perm = tr[torch.randperm(tr.numel(), generator=gen).to(dev)]
+            acc.zero_()
+            for j in range(steps_per_epoch):
+                idx = perm[j * batch:(j + 1) * batch]
+                rate = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * k / total)))
+                sur.train_step(X[idx].contiguous(), T[idx].contiguous(), rate, loss)
+                acc += loss
+                k += 1
+            torch.cuda.synchronize()
+            ep_loss = (acc / steps_per_epoch).cpu().numpy().tolist()
+            history.append(ep_loss)
+            log(f"  epoch {ep + 1}/{epochs}: train mse (scaled) {np.mean(ep_loss):.4f}, {time.time() - t0:.1f} s",
+                flush=True)
+    train_s = time.time() - t0
+    _, m_te = evaluate(sur, X[te], T[te], batch)
+    _, m_tr = evaluate(sur, X[tr[:te.numel()]], T[tr[:te.numel()]], batch)
+    # the method without the learned part: a linear (Newtonian-like) map from
+    # the current gradient alone, fitted by least squares on the training rows
+    cur = X[:, 4 * (HIST - 1):4 * HIST].double()
+    A = torch.cat([cur, torch.ones_like(cur[:, :1])], dim=1)
+    coef = torch.linalg.lstsq(A[tr].cpu(), T[tr].double().cpu()).solution.to(dev)
+    lin = (A[te] @ coef)
+    lin_rel = float((lin - T[te].double()).norm() / T[te].double().norm())
+    metrics = {"train_seconds": train_s, "steps": k, "epochs": epochs, "batch": batch, "lr": lr,
+               "train_rows": int(tr.numel()), "held_out_rows": int(te.numel()), "held_out": m_te,
+               "train_subset": m_tr, "linear_current_gradient_rel_l2": lin_rel, "epoch_loss": history}
+    return sur, metrics
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--boxes", type=int, default=4096)
+    ap.add_argument("--macro", type=int, default=520)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--replica-groups", type=int, default=32)
+    ap.add_argument("--replicas", type=int, default=8)
+    args = ap.parse_args(argv)
+    import torch
+
+    if not torch.cuda.is_available():
+        raise SystemExit("the training pipeline runs on the GPU")
+    os.makedirs(args.out, exist_ok=True)
+    print(f"generating: {args.boxes} boxes x {args.macro} macro steps", flush=True)
+    X, T, box_id, step_id, info = generate(args.boxes, args.macro)
+    print(json.dumps(info), flush=True)
+    sur, metrics = train(X, T, box_id, epochs=args.epochs)
+    metrics["data"] = info
+    print(json.dumps({k: v for k, v in metrics.items() if k != "epoch_loss"}), flush=True)
+    del X, T
+    if args.replica_groups > 0:
+        nb = args.replica_groups * args.replicas
+        print(f"replicas: {args.replica_groups} groups x {args.replicas}", flush=True)
+        Xr, Tr, br, sr, rinfo = generate(nb, min(args.macro, 200), seed_k=5, replicas=args.replicas)
+        M, _ = evaluate(sur, Xr, Tr, 4096)
+        grp = (br // args.replicas).long() * 1000000 + sr.long()
+        uniq, inv, counts = torch.unique(grp, return_inverse=True, return_counts=True)
+        full = counts[inv] == args.replicas
+        Tm = torch.zeros((uniq.numel(), 3), dtype=torch.float64, device=Tr.device).index_add_(0, inv, Tr.double())
+        Tm = Tm / counts[:, None].double()
+        dev_single = (Tr.double() - Tm[inv])[full]
+        noise = float(dev_single.norm() / Tm[inv][full].norm()) * math.sqrt(args.replicas / (args.replicas - 1.0))
+        model_vs_mean = float((M.double() - Tm[inv])[full].norm() / Tm[inv][full].norm())
+        model_vs_single = float((M.double() - Tr.double())[full].norm() / Tr.double()[full].norm())
+        metrics["replicas"] = {"info": rinfo, "dpd_single_noise_rel_l2": noise,
+                               "model_vs_replica_mean_rel_l2": model_vs_mean,
+                               "model_vs_single_rel_l2": model_vs_single}
+        print(json.dumps(metrics["replicas"]), flush=True)
+    W = sur.get_weights()
+    arrays = {f"m{e}_{k}": W[e][k] for e in range(len(W)) for k in surrogate.LAYERS}
+    np.savez(os.path.join(args.out, "surrogate.npz"), grad_scale=GRAD_SCALE, stress_scale=STRESS_SCALE,
+             n_hidden=256, n_members=len(W), **arrays)
+    with open(os.path.join(args.out, "train_metrics.json"), "w") as f:
+        json.dump(metrics, f, indent=1)
+    print("done", flush=True)
+
+
+if __name__ == "__main__":
+    main()

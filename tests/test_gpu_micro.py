@@ -332,3 +332,70 @@ def test_full_batch_sampled_parity(torch_gpu, orc):
         assert np.abs(out[k] - means[q]).max() <= 1e-6 * np.abs(means[q]).max(), k
     assert not np.any(m.flags() & (_lib.FLAG_CELL | _lib.FLAG_BOND | _lib.FLAG_NONFINITE))
     m.close()
+
+
+def test_subset_step_equals_full_step_for_selected_boxes(torch_gpu):
+    """Stepping a subset of boxes gives those boxes exactly the trajectory and
+    stress of a full step from the same state and counter; the other boxes
+    do not move and report zero stress."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(5, seed_k=31)
+    G = _grads(torch, wl)
+    off = _offsets(wl)
+    sel = [0, 2, 3]
+    for prec in ("fp32", "fp64"):
+        print(f"subset step {prec}", flush=True)
+        a = micro.from_workload(wl, precision=prec, graphs=False)
+        b = micro.from_workload(wl, precision=prec)
+        s0, c0, h0, _ = b.get_state()
+        oa = a.step(G, 25).cpu().numpy()
+        ob = b.step_subset(G, 25, sel).cpu().numpy()
+        sa, ca, ha, ta = a.get_state()
+        sb, cb, hb, tb = b.get_state()
+        assert ta == tb == 25
+        for k in range(5):
+            r = slice(off[k], off[k + 1])
+            if k in sel:
+                assert np.array_equal(sa[r], sb[r]) and np.array_equal(ca[r], cb[r]), (prec, k)
+                assert np.array_equal(ha[k], hb[k]) and np.array_equal(oa[k], ob[k]), (prec, k)
+            else:
+                assert np.array_equal(s0[r], sb[r]) and np.array_equal(c0[r], cb[r]), (prec, k)
+                assert np.array_equal(h0[k], hb[k]) and not ob[k].any(), (prec, k)
+        a.close()
+        b.close()
+
+
+def test_snapshot_restore_returns_boxes_to_saved_state(torch_gpu):
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(3, seed_k=37)
+    G = _grads(torch, wl)
+    off = _offsets(wl)
+    m = micro.from_workload(wl, precision="fp32")
+    m.step(G, 10)
+    m.snapshot()
+    s1, c1, h1, t1, f1 = m.get_state(with_forces=True)
+    m.step(G, 15)
+    s2, c2, h2, t2, f2 = m.get_state(with_forces=True)
+    m.restore([1])
+    s3, c3, h3, t3, f3 = m.get_state(with_forces=True)
+    assert t3 == t2 == t1 + 15
+    for k in range(3):
+        r = slice(off[k], off[k + 1])
+        ref = (s1, c1, f1, h1) if k == 1 else (s2, c2, f2, h2)
+        got = (s3[r], c3[r], f3[r], h3[k])
+        for x, y in zip(got, (ref[0][r], ref[1][r], ref[2][r], ref[3][k])):
+            assert np.array_equal(x, y), k
+    # the restored box continues like an engine resumed from the saved state
+    # at the same counter
+    m.step_subset(G, 20, [1])
+    s4, c4, _, t4 = m.get_state()
+    e = micro.from_workload(wl, precision="fp32")
+    e.set_state(s1, c1, h1.reshape(-1, 9), t3, f=f1)
+    e.step(G, 20)
+    s5, c5, _, t5 = e.get_state()
+    r = slice(off[1], off[2])
+    assert t4 == t5 and np.array_equal(s4[r], s5[r]) and np.array_equal(c4[r], c5[r])
+    m.close()
+    e.close()

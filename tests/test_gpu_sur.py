@@ -203,3 +203,29 @@ def test_history_features_and_gate_match_oracle():
     decided = np.abs(ratio - 1.0) > 1e-4
     assert np.array_equal(got[decided], fl[decided])
     assert 0.1 < fl.mean() < 0.9
+
+
+def test_targets_blend_and_history_gradient_match_oracle():
+    sur = _cuda()
+    st = torch.cuda.current_stream()
+    rng = np.random.default_rng(15)
+    n = 300
+    sigma = rng.normal(size=(n, 6))
+    T = torch.zeros((n, 3), dtype=torch.float32, device="cuda")
+    sur.targets(torch.from_numpy(sigma).cuda(), 0.5, T, st)
+    assert np.allclose(T.cpu().numpy(), mo.targets(sigma, 0.5), rtol=1e-6, atol=1e-6)
+    mean = rng.normal(size=(n, 3)).astype(np.float32)
+    use = (rng.uniform(size=n) < 0.3).astype(np.uint32)
+    out = torch.zeros((n, 6), dtype=torch.float64, device="cuda")
+    sur.blend(torch.from_numpy(mean).cuda(), torch.from_numpy(use.astype(np.int32)).cuda(),
+              torch.from_numpy(sigma).cuda(), 1.5, out, st)
+    assert np.allclose(out.cpu().numpy(), mo.blend(mean.astype(np.float64), use, sigma, 1.5), rtol=1e-12, atol=1e-12)
+    # the ring gives back the traceless in-plane gradient it was fed
+    ring = torch.zeros((n, 32, 4), dtype=torch.float32, device="cuda")
+    a, b, c = (rng.normal(size=n) * 0.1 for _ in range(3))
+    L = np.zeros((n, 9))
+    L[:, 0], L[:, 1], L[:, 3], L[:, 4] = a, b, c, -a
+    sur.push_history(ring, torch.from_numpy(L).cuda(), 40, st, scale=20.0)
+    back = torch.zeros((n, 9), dtype=torch.float64, device="cuda")
+    sur.history_gradient(ring, 40, back, st, inv_scale=1.0 / 20.0)
+    assert np.allclose(back.cpu().numpy(), L, rtol=1e-6, atol=1e-9)

@@ -134,3 +134,23 @@ def test_features_order():
     assert X.shape == (3, 129)
     # first feature = oldest kept sample (index T-32), component xx
     assert X[1, 0] == hist[1, T - 32, 0] and X[1, 127] == hist[1, T - 1, 3] and X[2, 128] == 0.3
+
+
+def test_targets_and_blend_pins():
+    rng = np.random.default_rng(14)
+    # an isotropic stress has no deviatoric part
+    iso = np.tile(np.array([[2.5, 2.5, 2.5, 0.0, 0.0, 0.0]]), (3, 1))
+    assert np.abs(mo.targets(iso)).max() == 0.0
+    # simple shear stress: only xy survives
+    sh = np.array([[0.0, 0.0, 0.0, 0.7, 0.0, 0.0]])
+    assert np.allclose(mo.targets(sh, 2.0), [[0.0, 1.4, 0.0]])
+    # a blended surrogate row is traceless and its targets give back the mean
+    mean = rng.normal(size=(6, 3))
+    out = mo.blend(mean, None, None, 1.7)
+    assert np.allclose(out[:, :3].sum(axis=1), 0.0)
+    assert np.allclose(mo.targets(out, 1.0 / 1.7), mean)
+    # rows flagged for DPD are the micro stress unchanged
+    sd = rng.normal(size=(6, 6))
+    use = np.array([1, 0, 0, 1, 0, 1])
+    out = mo.blend(mean, use, sd, 1.0)
+    assert np.array_equal(out[use == 1], sd[use == 1])
