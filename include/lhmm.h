@@ -214,7 +214,14 @@ int lhmm_micro_destroy(lhmm_micro* m);
  *     p = c^2 rho0/7 ((rho/rho0)^7 - 1) + theta c^2 rho0/7 (Eq. tait);
  *   - momentum, Eq. (sph_continuity): pressure, viscous (a = 2 eta - zeta,
  *     b = 4 zeta + 2 eta) and micro-to-macro polymer terms, plus a body
- *     force per unit mass of +F x-hat where y >= Ly/2 and -F x-hat below;
+ *     force per unit mass (force_mode: reversing at mid-height for the
+ *     reverse Poiseuille flow, or uniform);
+ *   - obstacles: the last n_fixed particles are frozen wall particles (the
+ *     paper does not say how its cylinders are represented).  They enter
+ *     every sum as neighbours (density, pressure from their own density,
+ *     the viscous term with their velocity) but never move, carry no
+ *     micro-domain and no polymer stress (their rows of sigma are ignored),
+ *     and get zero gradient rows;
  *   - quintic kernel of support radius h: W = 63/(478 pi h^2)
  *     [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5]_+, q = 3 r / h;
  *   - velocity-Verlet steps (Appendix "Detailed Coupling Protocol");
@@ -240,7 +247,12 @@ typedef struct {
     double Lx, Ly;      /* periodic box                                      */
     double lambda_star; /* time-scale ratio lambda*                          */
     double alpha;       /* viscosity ratio alpha                             */
+    int32_t n_fixed;    /* trailing wall particles (see below)               */
+    int32_t force_mode; /* LHMM_FORCE_REVERSE or LHMM_FORCE_UNIFORM          */
 } lhmm_sph_params;
+
+#define LHMM_FORCE_REVERSE 0 /* +F x-hat where y >= Ly/2, -F below            */
+#define LHMM_FORCE_UNIFORM 1 /* +F x-hat everywhere                          */
 
 /* Allocate an SPH engine of n particles.  r0, v0: host n x 2.  stream: the
  * caller's hipStream_t (all SPH work is launched on it).  Errors: ARG, HIP,
@@ -269,7 +281,7 @@ int lhmm_sph_coupling_state(lhmm_sph* s, double* sigma, double* gradL);
  * Coupling Protocol", Steps 1-4, with one SPH step per interval): SPH step
  * with the stored micro stresses, gradients to the micro-domains, k_micro
  * micro steps of every box, their mean stresses stored for the next
- * interval.  The micro engine must hold one box per SPH particle, in order,
+ * interval.  The micro engine must hold one box per mobile SPH particle, in order,
  * and both engines must have been created on the same stream.  No host
  * synchronisation.  Errors: ARG, STATE, HIP. */
 int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t k_micro);
@@ -382,6 +394,72 @@ int lhmm_sur_blend(const float* mean, const uint32_t* use_dpd, const double* sig
 
 /* Release every resource (waits for the stream).  NULL ok. */
 int lhmm_sur_destroy(lhmm_sur* s);
+
+/* ------------------------------------------------------------------------
+ * The LHMM macro step with the surrogate in the loop (exchange interval of
+ * the coupling protocol, one SPH step per interval, continuous-intermittent
+ * micro-domains).  Per step: SPH step with the stresses of the last
+ * interval; each mobile particle's micro gradient enters its history ring;
+ * in LHMM_HYBRID_SURROGATE mode the ensemble predicts the deviatoric stress
+ * and the gate flags particles whose members disagree; a flagged particle
+ * runs plain micro-DPD for the next `hold` steps.  A particle entering DPD
+ * gets its micro-domain back from the equilibrated snapshot taken at
+ * create time and replays its last `replay` gradient samples (k_micro micro
+ * steps each) before the interval, so the polymer memory of its box matches
+ * its history.  Boxes on DPD advance k_micro steps and their mean stress is
+ * used for their particles; the others take the surrogate's mean.  In
+ * LHMM_HYBRID_DPD mode every box runs every step (the reference run).  In
+ * both modes a box whose cell became thin (LHMM_FLAG_THIN) is restored and
+ * replayed the same way after its stress has been used.
+ *
+ * The SPH, micro and surrogate engines must share one stream; the micro
+ * engine holds one box per mobile SPH particle and must already be
+ * equilibrated (create takes its snapshot).  The surrogate must map
+ * LHMM_SUR_FEATURES features to 3 outputs with max_batch >= the mobile
+ * count.  The hybrid borrows the engines; destroy it before them.
+ * ------------------------------------------------------------------------ */
+typedef struct lhmm_hybrid lhmm_hybrid;
+
+#define LHMM_HYBRID_SURROGATE 0
+#define LHMM_HYBRID_DPD 1
+
+typedef struct {
+    int32_t mode;       /* LHMM_HYBRID_SURROGATE or LHMM_HYBRID_DPD          */
+    int32_t k_micro;    /* micro steps per macro step (>= 1)                  */
+    int32_t hold;       /* steps a flagged particle stays on DPD (>= 1)       */
+    int32_t replay;     /* history samples replayed on entry or reset
+                           (0 .. LHMM_SUR_HIST - 1)                           */
+    float threshold;    /* gate threshold on the relative ensemble spread     */
+    float floor;        /* gate floor on |mean| (surrogate output units)      */
+    float grad_scale;   /* history holds L x grad_scale                      */
+    float stress_scale; /* deviatoric stress = surrogate output x this       */
+} lhmm_hybrid_params;
+
+typedef struct {
+    int64_t macro_step;      /* steps done                                    */
+    int64_t micro_box_steps; /* micro steps x boxes run so far, with replays  */
+    int32_t n_dpd;           /* particles on DPD in the last step             */
+    int32_t n_entered;       /* of which entered DPD in it                    */
+    int32_t n_flagged;       /* gate flags in it                              */
+    int32_t n_reset;         /* thin boxes restored after it                  */
+} lhmm_hybrid_stats;
+
+/* phi: HOST n_mobile FP32, the polymer-fraction feature of each
+ * particle's micro-domain.  sur may be NULL in LHMM_HYBRID_DPD mode.
+ * Synchronous.  Errors: ARG, OOM, HIP, STATE (micro state not loaded). */
+int lhmm_hybrid_create(const lhmm_hybrid_params* p, lhmm_sph* sph, lhmm_micro* micro, lhmm_sur* sur,
+                       const float* phi, lhmm_hybrid** out);
+
+/* One macro step; stats (HOST, may be NULL) receives its counters.  Waits
+ * for the gate flags and the micro flags (two host synchronisations). */
+int lhmm_hybrid_step(lhmm_hybrid* h, lhmm_hybrid_stats* stats);
+
+/* HOST copies of the stress handed to the SPH step of the next interval
+ * (n x 6; wall rows zero) and of the DPD mask of the last step (n_mobile);
+ * either may be NULL.  Synchronous. */
+int lhmm_hybrid_state(lhmm_hybrid* h, double* sigma, uint32_t* on_dpd);
+
+int lhmm_hybrid_destroy(lhmm_hybrid* h);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* lhmm_last_error(void);

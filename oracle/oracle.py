@@ -284,7 +284,8 @@ def max_threads() -> int:
 
 def sph_params_vector(q) -> np.ndarray:
     keys = ["rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly", "lambda_star", "alpha"]
-    return np.array([float(q[k]) for k in keys], dtype=np.float64)
+    vals = [float(q[k]) for k in keys] + [float(q.get("n_fixed", 0)), float(q.get("force_mode", 0))]
+    return np.array(vals, dtype=np.float64)
 
 
 def sph_W(r, h):

@@ -15,7 +15,13 @@
  *   - velocity gradient for the micro-domains, Eq. (macro_micro), read with
  *     the volume factor 1/d_J: (grad v)_I = sum_J F_IJ r_IJ (x) v_IJ / d_J;
  *   - velocity-Verlet time stepping (Appendix "Detailed Coupling Protocol",
- *     Step 1).
+ *     Step 1);
+ *   - solid obstacles (the cylinders of the flow past a periodic array,
+ *     Sec. "Flow Past a Periodic Array of Cylinders"), on which the paper
+ *     gives no treatment: here the last n_fixed particles are frozen wall
+ *     particles that take part in every sum as neighbours (density,
+ *     pressure, viscous term with their zero velocity) but never move,
+ *     carry no micro-domain and no polymer stress, and get no gradient.
  * Kernel: the quintic spline with support radius h (q = 3 r / h),
  * W = 63/(478 pi h^2) [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5] (terms where the
  * bracket is positive); F_IJ = -W'(r_IJ)/r_IJ.
@@ -24,10 +30,15 @@
 #include <stdint.h>
 #include <string.h>
 
-/* parameter vector layout (double[14]) */
+/* parameter vector layout (double[S_COUNT]); S_NFIXED: number of trailing
+ * wall particles; S_FMODE: 0 = body force +F for y >= Ly/2, -F below
+ * (reverse Poiseuille), 1 = +F everywhere */
 enum {
-    S_RHO0 = 0, S_ETA, S_ZETA, S_C, S_THETA, S_F, S_H, S_DT, S_MASS, S_LX, S_LY, S_LAMBDA, S_ALPHA, S_COUNT
+    S_RHO0 = 0, S_ETA, S_ZETA, S_C, S_THETA, S_F, S_H, S_DT, S_MASS, S_LX, S_LY, S_LAMBDA, S_ALPHA, S_NFIXED,
+    S_FMODE, S_COUNT
 };
+
+static int n_mobile(const double *P, int n) { return n - (int)P[S_NFIXED]; }
 
 double oracle_sph_W(double r, double h)
 {
@@ -99,14 +110,20 @@ void oracle_sph_gradv(const double *P, int n, const double *r, const double *v, 
 }
 
 /* acceleration (n x 2) from Eq. (sph_continuity); pi (n x 3: xx, xy, yy) is
- * the polymer stress already multiplied by alpha / lambda*; body force:
- * +F x-hat for y >= Ly/2 and -F x-hat below. */
+ * the polymer stress already multiplied by alpha / lambda* (rows of wall
+ * particles are ignored: walls carry none); body force per S_FMODE.  Wall
+ * particles get zero acceleration. */
 void oracle_sph_accel(const double *P, int n, const double *r, const double *v, const double *d,
                       const double *p, const double *pi, double *acc)
 {
     const double h = P[S_H], m = P[S_MASS];
     const double av = 2.0 * P[S_ETA] - P[S_ZETA], bv = 4.0 * P[S_ZETA] + 2.0 * P[S_ETA];
+    const int nm = n_mobile(P, n);
     for (int I = 0; I < n; ++I) {
+        if (I >= nm) {
+            acc[2 * I] = acc[2 * I + 1] = 0.0;
+            continue;
+        }
         double fx = 0.0, fy = 0.0;
         for (int J = 0; J < n; ++J) {
             if (J == I) continue;
@@ -127,14 +144,15 @@ void oracle_sph_accel(const double *P, int n, const double *r, const double *v, 
             fx -= (av * vx + bv * ve * ex) * vis;
             fy -= (av * vy + bv * ve * ey) * vis;
             /* polymer stress <pi>_IJ . r_IJ F_IJ */
-            double i2 = 1.0 / (d[I] * d[I]), j2 = 1.0 / (d[J] * d[J]);
-            double sxx = pi[3 * I] * i2 + pi[3 * J] * j2;
-            double sxy = pi[3 * I + 1] * i2 + pi[3 * J + 1] * j2;
-            double syy = pi[3 * I + 2] * i2 + pi[3 * J + 2] * j2;
+            double i2 = 1.0 / (d[I] * d[I]), j2 = J < nm ? 1.0 / (d[J] * d[J]) : 0.0;
+            int Jp = J < nm ? J : I; /* a wall contributes no polymer stress */
+            double sxx = pi[3 * I] * i2 + pi[3 * Jp] * j2;
+            double sxy = pi[3 * I + 1] * i2 + pi[3 * Jp + 1] * j2;
+            double syy = pi[3 * I + 2] * i2 + pi[3 * Jp + 2] * j2;
             fx -= (sxx * dx + sxy * dy) * F;
             fy -= (sxy * dx + syy * dy) * F;
         }
-        double body = r[2 * I + 1] >= 0.5 * P[S_LY] ? P[S_F] : -P[S_F];
+        double body = (P[S_FMODE] != 0.0 || r[2 * I + 1] >= 0.5 * P[S_LY]) ? P[S_F] : -P[S_F];
         acc[2 * I] = fx / m + body;
         acc[2 * I + 1] = fy / m;
     }
@@ -155,18 +173,23 @@ void oracle_sph_step(const double *P, int n, double *r, double *v, const double 
                      double *acc, double *G, double *Lout)
 {
     const double dt = P[S_DT];
+    const int nm = n_mobile(P, n);
     oracle_sph_density(P, n, r, d, p);
     oracle_sph_accel(P, n, r, v, d, p, pi, acc);
-    for (int k = 0; k < 2 * n; ++k) v[k] += 0.5 * dt * acc[k];
-    for (int I = 0; I < n; ++I) {
+    for (int k = 0; k < 2 * nm; ++k) v[k] += 0.5 * dt * acc[k];
+    for (int I = 0; I < nm; ++I) {
         r[2 * I] = wrapL(r[2 * I] + dt * v[2 * I], P[S_LX]);
         r[2 * I + 1] = wrapL(r[2 * I + 1] + dt * v[2 * I + 1], P[S_LY]);
     }
     oracle_sph_density(P, n, r, d, p);
     oracle_sph_accel(P, n, r, v, d, p, pi, acc);
-    for (int k = 0; k < 2 * n; ++k) v[k] += 0.5 * dt * acc[k];
+    for (int k = 0; k < 2 * nm; ++k) v[k] += 0.5 * dt * acc[k];
     oracle_sph_gradv(P, n, r, v, d, G);
     for (int I = 0; I < n; ++I) {
+        if (I >= nm) {
+            for (int k = 0; k < 9; ++k) Lout[9 * I + k] = 0.0;
+            continue;
+        }
         const double *g = &G[4 * I];
         /* u = L r with L = (grad v)^T: L = [[g0, g2], [g1, g3]] */
         double L00 = g[0], L01 = g[2], L10 = g[1], L11 = g[3];

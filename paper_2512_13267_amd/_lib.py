@@ -40,6 +40,7 @@ EXPORTS = (
     "lhmm_sur_create", "lhmm_sur_set_weights", "lhmm_sur_get_weights", "lhmm_sur_get_grads", "lhmm_sur_train_step", "lhmm_sur_forward",
     "lhmm_sur_push_history", "lhmm_sur_features", "lhmm_sur_gate", "lhmm_sur_destroy", "lhmm_sur_targets",
     "lhmm_sur_blend", "lhmm_sur_history_gradient",
+    "lhmm_hybrid_create", "lhmm_hybrid_step", "lhmm_hybrid_state", "lhmm_hybrid_destroy",
 )
 SUR_HIST = 32
 SUR_FEATURES = 4 * SUR_HIST + 1
@@ -60,11 +61,27 @@ class LhmmBox(C.Structure):
 
 class LhmmSphParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly",
-                                            "lambda_star", "alpha")]
+                                            "lambda_star", "alpha")] + [("n_fixed", C.c_int32),
+                                                                        ("force_mode", C.c_int32)]
 
 
 class LhmmSurParams(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("n_members", "n_in", "n_hidden", "n_out", "max_batch")]
+
+
+class LhmmHybridParams(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("k_micro", C.c_int32), ("hold", C.c_int32), ("replay", C.c_int32),
+                ("threshold", C.c_float), ("floor", C.c_float), ("grad_scale", C.c_float),
+                ("stress_scale", C.c_float)]
+
+
+class LhmmHybridStats(C.Structure):
+    _fields_ = [("macro_step", C.c_int64), ("micro_box_steps", C.c_int64), ("n_dpd", C.c_int32),
+                ("n_entered", C.c_int32), ("n_flagged", C.c_int32), ("n_reset", C.c_int32)]
+
+
+HYBRID_SURROGATE = 0
+HYBRID_DPD = 1
 
 
 class LhmmError(RuntimeError):
@@ -119,6 +136,10 @@ def lib():
         L.lhmm_sur_features.argtypes = [vp, C.c_int32, C.c_int64, vp, vp, vp]
         L.lhmm_sur_gate.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float, vp, vp, vp]
         L.lhmm_sur_destroy.argtypes = [vp]
+        L.lhmm_hybrid_create.argtypes = [C.POINTER(LhmmHybridParams), vp, vp, vp, fp, C.POINTER(vp)]
+        L.lhmm_hybrid_step.argtypes = [vp, C.POINTER(LhmmHybridStats)]
+        L.lhmm_hybrid_state.argtypes = [vp, dp, C.POINTER(C.c_uint32)]
+        L.lhmm_hybrid_destroy.argtypes = [vp]
         L.lhmm_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "lhmm_last_error":

@@ -12,6 +12,12 @@ int lhmm_fail(int code, const char* fmt, ...);
 void lhmm_clear_error();
 // The caller stream a micro engine was created with.
 hipStream_t lhmm_micro_caller_stream(const lhmm_micro* m);
+// The stream an SPH engine launches on, its particle count and mobile count.
+hipStream_t lhmm_sph_caller_stream(const lhmm_sph* s);
+void lhmm_sph_counts(const lhmm_sph* s, int* n, int* n_mobile);
+// The stream of a surrogate engine and its dimensions.
+hipStream_t lhmm_sur_caller_stream(const lhmm_sur* s);
+void lhmm_sur_dims(const lhmm_sur* s, int* n_members, int* n_in, int* n_out, int* max_batch);
 
 #define LHMM_HIPCHK(expr)                                                                        \
     do {                                                                                         \

@@ -23,7 +23,7 @@ namespace {
 constexpr int TPB = 128;
 
 struct SphCtx {
-    int n;
+    int n, n_mobile, force_mode;  // particles n_mobile .. n-1 are frozen walls
     double rho0, eta, zeta, c, theta, F, h, dt, mass, Lx, Ly, lambda_star, alpha;
     double* r;    // n x 2
     double* v;    // n x 2
@@ -91,7 +91,7 @@ __device__ __forceinline__ void polymer_stress(const SphCtx& S, const double* si
 // Eq. (sph_continuity) divided by the mass, plus the body force
 __global__ void k_accel(SphCtx S, const double* __restrict__ sigma) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= S.n) return;
+    if (I >= S.n_mobile) return;
     const double av = 2.0 * S.eta - S.zeta, bv = 4.0 * S.zeta + 2.0 * S.eta;
     const double xi = S.r[2 * I], yi = S.r[2 * I + 1], vxi = S.v[2 * I], vyi = S.v[2 * I + 1];
     const double di = S.d[I], pi_ = S.p[I];
@@ -110,6 +110,7 @@ __global__ void k_accel(SphCtx S, const double* __restrict__ sigma) {
         const double vx = vxi - S.v[2 * J], vy = vyi - S.v[2 * J + 1];
         const double dj = S.d[J];
         const double j2 = 1.0 / (dj * dj);
+        const bool wall = J >= S.n_mobile;
         const double pp = pi_ * i2 + S.p[J] * j2;
         fx += pp * F * dx;
         fy += pp * F * dy;
@@ -117,13 +118,13 @@ __global__ void k_accel(SphCtx S, const double* __restrict__ sigma) {
         const double vis = F / (di * dj);
         fx -= (av * vx + bv * ve * ex) * vis;
         fy -= (av * vy + bv * ve * ey) * vis;
-        double qxx, qxy, qyy;
-        polymer_stress(S, sigma, J, qxx, qxy, qyy);
+        double qxx = 0.0, qxy = 0.0, qyy = 0.0;
+        if (!wall) polymer_stress(S, sigma, J, qxx, qxy, qyy);
         const double sxx = pxx * i2 + qxx * j2, sxy = pxy * i2 + qxy * j2, syy = pyy * i2 + qyy * j2;
         fx -= (sxx * dx + sxy * dy) * F;
         fy -= (sxy * dx + syy * dy) * F;
     }
-    const double body = yi >= 0.5 * S.Ly ? S.F : -S.F;
+    const double body = (S.force_mode == LHMM_FORCE_UNIFORM || yi >= 0.5 * S.Ly) ? S.F : -S.F;
     S.acc[2 * I] = fx / S.mass + body;
     S.acc[2 * I + 1] = fy / S.mass;
 }
@@ -135,7 +136,7 @@ __device__ __forceinline__ double wrap_len(double x, double L) {
 
 __global__ void k_kick_drift(SphCtx S) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= S.n) return;
+    if (I >= S.n_mobile) return;
     const double hdt = 0.5 * S.dt;
     const double vx = S.v[2 * I] + hdt * S.acc[2 * I], vy = S.v[2 * I + 1] + hdt * S.acc[2 * I + 1];
     S.v[2 * I] = vx;
@@ -146,7 +147,7 @@ __global__ void k_kick_drift(SphCtx S) {
 
 __global__ void k_kick(SphCtx S) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= S.n) return;
+    if (I >= S.n_mobile) return;
     const double hdt = 0.5 * S.dt;
     S.v[2 * I] += hdt * S.acc[2 * I];
     S.v[2 * I + 1] += hdt * S.acc[2 * I + 1];
@@ -157,6 +158,10 @@ __global__ void k_kick(SphCtx S) {
 __global__ void k_gradL(SphCtx S, double* __restrict__ gradL) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= S.n) return;
+    if (I >= S.n_mobile) {
+        for (int k = 0; k < 9; ++k) gradL[9 * I + k] = 0.0;
+        return;
+    }
     const double xi = S.r[2 * I], yi = S.r[2 * I + 1], vxi = S.v[2 * I], vyi = S.v[2 * I + 1];
     double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
     for (int J = 0; J < S.n; ++J) {
@@ -217,6 +222,13 @@ void launch_sph_step(lhmm_sph* s, const double* sigma, double* gradL) {
 
 }  // namespace
 
+hipStream_t lhmm_sph_caller_stream(const lhmm_sph* s) { return s->stream; }
+
+void lhmm_sph_counts(const lhmm_sph* s, int* n, int* n_mobile) {
+    *n = s->S.n;
+    *n_mobile = s->S.n_mobile;
+}
+
 extern "C" {
 
 int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const double* v0, void* stream,
@@ -225,6 +237,9 @@ int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const
     if (!p || !r0 || !v0 || !out) return lhmm_fail(LHMM_ERR_ARG, "null argument");
     *out = nullptr;
     if (n <= 0) return lhmm_fail(LHMM_ERR_ARG, "n must be positive (got %d)", n);
+    if (p->n_fixed < 0 || p->n_fixed >= n) return lhmm_fail(LHMM_ERR_ARG, "n_fixed must be in 0..n-1 (got %d)", p->n_fixed);
+    if (p->force_mode != LHMM_FORCE_REVERSE && p->force_mode != LHMM_FORCE_UNIFORM)
+        return lhmm_fail(LHMM_ERR_ARG, "unknown force_mode %d", p->force_mode);
     const double vals[] = {p->rho0, p->eta, p->zeta, p->c, p->theta, p->F, p->h, p->dt, p->mass, p->Lx, p->Ly,
                            p->lambda_star, p->alpha};
     for (double x : vals)
@@ -244,6 +259,8 @@ int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const
     s->stream = (hipStream_t)stream;
     SphCtx& S = s->S;
     S.n = n;
+    S.n_mobile = n - p->n_fixed;
+    S.force_mode = p->force_mode;
     S.rho0 = p->rho0; S.eta = p->eta; S.zeta = p->zeta; S.c = p->c; S.theta = p->theta; S.F = p->F; S.h = p->h;
     S.dt = p->dt; S.mass = p->mass; S.Lx = p->Lx; S.Ly = p->Ly; S.lambda_star = p->lambda_star; S.alpha = p->alpha;
     const size_t sizes[7] = {2 * (size_t)n, 2 * (size_t)n, (size_t)n, (size_t)n, 2 * (size_t)n, 6 * (size_t)n,
@@ -322,7 +339,8 @@ int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t k_micro) {
     int32_t nb = 0;
     int rc = lhmm_micro_sizes(m, nullptr, &nb);
     if (rc != LHMM_OK) return rc;
-    if (nb != s->S.n) return lhmm_fail(LHMM_ERR_ARG, "micro engine holds %d boxes for %d SPH particles", nb, s->S.n);
+    if (nb != s->S.n_mobile)
+        return lhmm_fail(LHMM_ERR_ARG, "micro engine holds %d boxes for %d mobile SPH particles", nb, s->S.n_mobile);
     if (lhmm_micro_caller_stream(m) != s->stream)
         return lhmm_fail(LHMM_ERR_ARG, "the SPH and micro engines must share one stream");
     launch_sph_step(s, s->d_sigma, s->d_gradL);

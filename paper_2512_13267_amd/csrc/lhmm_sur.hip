@@ -396,6 +396,15 @@ int check_dims(const lhmm_sur_params* p) {
 
 }  // namespace
 
+hipStream_t lhmm_sur_caller_stream(const lhmm_sur* s) { return s->stream; }
+
+void lhmm_sur_dims(const lhmm_sur* s, int* n_members, int* n_in, int* n_out, int* max_batch) {
+    *n_members = s->E;
+    *n_in = s->nin;
+    *n_out = s->nout;
+    *max_batch = s->Bmax;
+}
+
 extern "C" {
 
 int lhmm_sur_create(const lhmm_sur_params* p, const float* weights, void* stream, lhmm_sur** out) {

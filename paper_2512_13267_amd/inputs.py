@@ -361,7 +361,33 @@ def reverse_poiseuille(nx: int = 16, ny: int = 64, width: float = 1.0, force: fl
     xs, ys = np.meshgrid((np.arange(nx) + 0.5) * dh, (np.arange(ny) + 0.5) * dh, indexing="ij")
     r = np.stack([xs.ravel(), ys.ravel()], axis=1)
     params = dict(rho0=rho0, eta=eta_s, zeta=0.0, c=c, theta=theta, F=force, h=3.0 * dh, dt=dt,
-                  mass=rho0 * dh * dh, Lx=Lx, Ly=Ly, lambda_star=lambda_star, alpha=alpha)
+                  mass=rho0 * dh * dh, Lx=Lx, Ly=Ly, lambda_star=lambda_star, alpha=alpha, n_fixed=0, force_mode=0)
+    return MacroInit(r=r, v=np.zeros_like(r), params=params, n_steps=n_steps)
+
+
+def cylinder_array(n: int = 64, radius: float = 0.2, force: float = 1.0, eta_s: float = 0.1, beta: float = 0.5,
+                   rho0: float = 1.0, dt: float = 1e-3, lambda_star: float = 0.2, alpha: float = 0.07,
+                   theta: float = 0.5, n_steps: int = 500) -> MacroInit:
+    """Flow past a periodic square array of cylinders: the unit cell [0, 1)^2
+    with one cylinder of the given radius at its centre, SPH particles on an
+    n x n lattice of spacing dh = 1/n (support h = 3 dh); lattice sites inside
+    the cylinder become frozen wall particles, stored after the fluid ones
+    (params["n_fixed"] of them).  A uniform body force +force x-hat drives
+    the flow (params["force_mode"] = 1).  The sound speed follows
+    Eq. (sound_speed) with delta = 0.1 and the radius as length scale."""
+    dh = 1.0 / n
+    xs, ys = np.meshgrid((np.arange(n) + 0.5) * dh, (np.arange(n) + 0.5) * dh, indexing="ij")
+    r = np.stack([xs.ravel(), ys.ravel()], axis=1)
+    inside = np.hypot(r[:, 0] - 0.5, r[:, 1] - 0.5) < radius
+    r = np.concatenate([r[~inside], r[inside]])
+    eta_tot = eta_s / (1.0 - beta)
+    gap = 1.0 - 2.0 * radius
+    vmax = force * gap * gap / (8.0 * eta_tot / rho0)
+    delta = 0.1
+    c = max(vmax / delta, math.sqrt(eta_tot * vmax / (delta * radius)), math.sqrt(force * radius / delta))
+    params = dict(rho0=rho0, eta=eta_s, zeta=0.0, c=c, theta=theta, F=force, h=3.0 * dh, dt=dt,
+                  mass=rho0 * dh * dh, Lx=1.0, Ly=1.0, lambda_star=lambda_star, alpha=alpha,
+                  n_fixed=int(inside.sum()), force_mode=1)
     return MacroInit(r=r, v=np.zeros_like(r), params=params, n_steps=n_steps)
 
 

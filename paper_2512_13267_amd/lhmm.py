@@ -26,7 +26,9 @@ class Sph:
         if not torch.cuda.is_available():
             raise RuntimeError("the SPH engine needs a ROCm GPU")
         self._torch = torch
-        p = LhmmSphParams(**{k: float(params[k]) for k in SPH_KEYS})
+        p = LhmmSphParams(**{k: float(params[k]) for k in SPH_KEYS}, n_fixed=int(params.get("n_fixed", 0)),
+                          force_mode=int(params.get("force_mode", 0)))
+        self.n_fixed = int(params.get("n_fixed", 0))
         r0 = np.ascontiguousarray(r0, dtype=np.float64).reshape(-1, 2)
         v0 = np.ascontiguousarray(v0, dtype=np.float64).reshape(-1, 2)
         self.n = r0.shape[0]
@@ -70,8 +72,8 @@ class Coupled:
     """One micro-box per SPH particle; step() is one exchange interval."""
 
     def __init__(self, sph: Sph, micro: Micro):
-        if micro.n_boxes != sph.n:
-            raise ValueError("one micro-box per SPH particle is required")
+        if micro.n_boxes != sph.n - sph.n_fixed:
+            raise ValueError("one micro-box per mobile SPH particle is required")
         self.sph, self.micro = sph, micro
 
     def step(self, k_micro: int):
@@ -84,3 +86,45 @@ class Coupled:
         grad = np.zeros((self.sph.n, 9))
         check(lib().lhmm_sph_coupling_state(self.sph._h, _dptr(sig), _dptr(grad)))
         return sig, grad.reshape(-1, 3, 3)
+
+
+class Hybrid:
+    """The LHMM macro step with the surrogate in the loop (lhmm_hybrid_*).
+    mode: "surrogate" or "dpd"; the engines must share one stream and the
+    micro engine must be equilibrated."""
+
+    def __init__(self, sph: Sph, micro: Micro, sur=None, phi=None, mode="surrogate", k_micro=50, hold=10,
+                 replay=31, threshold=0.05, floor=0.05, grad_scale=1.0, stress_scale=1.0):
+        from ._lib import HYBRID_DPD, HYBRID_SURROGATE, LhmmHybridParams
+
+        p = LhmmHybridParams(mode={"surrogate": HYBRID_SURROGATE, "dpd": HYBRID_DPD}[mode], k_micro=int(k_micro),
+                             hold=int(hold), replay=int(replay), threshold=float(threshold), floor=float(floor),
+                             grad_scale=float(grad_scale), stress_scale=float(stress_scale))
+        n_mobile = micro.n_boxes
+        phi = np.ascontiguousarray(np.zeros(n_mobile) if phi is None else phi, dtype=np.float32)
+        if phi.size != n_mobile:
+            raise ValueError("phi needs one value per micro-domain")
+        h = C.c_void_p()
+        check(lib().lhmm_hybrid_create(C.byref(p), sph._h, micro._h, None if sur is None else sur._h,
+                                       phi.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)))
+        self._h = h
+        self.n, self.n_mobile = sph.n, n_mobile
+        self._keep = (sph, micro, sur)
+
+    def step(self) -> dict:
+        from ._lib import LhmmHybridStats
+
+        st = LhmmHybridStats()
+        check(lib().lhmm_hybrid_step(self._h, C.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in LhmmHybridStats._fields_}
+
+    def state(self):
+        sig = np.zeros((self.n, 6))
+        on = np.zeros(self.n_mobile, dtype=np.uint32)
+        check(lib().lhmm_hybrid_state(self._h, _dptr(sig), on.ctypes.data_as(C.POINTER(C.c_uint32))))
+        return sig, on
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(lib().lhmm_hybrid_destroy(self._h))
+            self._h = C.c_void_p()

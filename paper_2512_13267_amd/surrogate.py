@@ -187,3 +187,15 @@ def gate(Y, threshold, floor, mean, flag, stream):
     check(lib().lhmm_sur_gate(C.c_void_p(Y.data_ptr()), E, B, n_out, float(threshold), float(floor),
                               C.c_void_p(mean.data_ptr()), C.c_void_p(flag.data_ptr()),
                               C.c_void_p(stream.cuda_stream)))
+
+
+TRAINED = __import__("os").path.join(__import__("os").path.dirname(__file__), "weights", "surrogate_e5_h256.npz")
+
+
+def load_trained(path: str = TRAINED):
+    """Members (list of dicts), hidden width, grad_scale, stress_scale of a
+    weights file written by the training pipeline."""
+    z = np.load(path, allow_pickle=False)
+    E = int(z["n_members"])
+    members = [{k: z[f"m{e}_{k}"].astype(np.float64) for k in LAYERS} for e in range(E)]
+    return members, int(z["n_hidden"]), float(z["grad_scale"]), float(z["stress_scale"])

@@ -53,6 +53,37 @@ def test_sph_matches_oracle(torch_gpu, orc):
     s.close()
 
 
+def test_sph_with_walls_and_uniform_force_matches_oracle(torch_gpu, orc):
+    """Cylinder-array geometry (frozen wall particles, uniform force)."""
+    from paper_2512_13267_amd import inputs, lhmm
+
+    m = inputs.cylinder_array(n=32)
+    q = m.params
+    n, nw = m.r.shape[0], q["n_fixed"]
+    assert nw > 0
+    torch = torch_gpu
+    rng = np.random.default_rng(6)
+    sig = rng.normal(scale=0.3, size=(n, 6))
+    sig_dev = torch.tensor(sig, dtype=torch.float64, device="cuda")
+    L_dev = torch.zeros((n, 9), dtype=torch.float64, device="cuda")
+    s = lhmm.Sph(q, m.r, m.v)
+    r, v = m.r.copy(), m.v.copy()
+    pi = orc.sph_polymer_stress(q, sig)
+    for _ in range(40):
+        s.step(sig_dev, L_dev)
+        Lo = orc.sph_step(q, r, v, pi)
+    rg, vg, dg = s.get_state()
+    dr = rg - r
+    dr -= np.round(dr)
+    assert np.abs(dr).max() < 1e-11
+    assert np.abs(vg - v).max() < 1e-11 * max(1.0, np.abs(v).max())
+    assert np.array_equal(rg[n - nw:], m.r[n - nw:]) and not vg[n - nw:].any()
+    Lg = L_dev.cpu().numpy().reshape(-1, 3, 3)
+    assert np.abs(Lg - Lo).max() < 1e-9 * np.abs(Lo).max()
+    assert not Lg[n - nw:].any()
+    s.close()
+
+
 def test_coupled_interval_matches_oracle(torch_gpu, orc):
     from paper_2512_13267_amd import inputs, lhmm, micro
 

@@ -94,3 +94,86 @@ def test_newtonian_startup_matches_fourier_series(orc):
     err = np.abs(v[:, 0] - series).max()
     assert err < 0.05 * np.abs(series).max()
     assert np.abs(v[:, 1]).max() < 0.02 * np.abs(series).max()
+
+
+def _channel(nx=8, n_fluid_rows=32, n_wall_rows=4, force=1.0, eta=0.1):
+    """Plane channel of width 1 between two slabs of frozen wall particles
+    (uniform body force along x), fluid rows first."""
+    dh = 1.0 / n_fluid_rows
+    ny = n_fluid_rows + 2 * n_wall_rows
+    xs, ys = np.meshgrid((np.arange(nx) + 0.5) * dh, (np.arange(ny) + 0.5) * dh, indexing="ij")
+    r = np.stack([xs.ravel(), ys.ravel()], axis=1)
+    row = np.floor(r[:, 1] / dh).astype(int)
+    wall = (row < n_wall_rows) | (row >= n_wall_rows + n_fluid_rows)
+    r = np.concatenate([r[~wall], r[wall]])
+    c = 2.0
+    q = dict(rho0=1.0, eta=eta, zeta=0.0, c=c, theta=0.5, F=force, h=3.0 * dh, dt=1e-3, mass=dh * dh,
+             Lx=nx * dh, Ly=ny * dh, lambda_star=0.2, alpha=0.0, n_fixed=int(wall.sum()), force_mode=1)
+    return r, q, n_wall_rows * dh
+
+
+def test_walls_do_not_change_fluid_forces_and_never_move(orc):
+    """A wall particle acts on the fluid exactly as a particle at rest with no
+    polymer stress would; walls get no acceleration and keep their place."""
+    rng = np.random.default_rng(8)
+    r, q, _ = _channel()
+    n, nw = r.shape[0], q["n_fixed"]
+    r = r + rng.normal(scale=0.002, size=r.shape)
+    r[:, 0] %= q["Lx"]
+    r[:, 1] %= q["Ly"]
+    v = rng.normal(scale=0.1, size=r.shape)
+    v[n - nw:] = 0.0
+    pi = rng.normal(scale=0.3, size=(n, 3))
+    pi[n - nw:] = 0.0
+    d, p = orc.sph_density(q, r)
+    a_fixed = orc.sph_accel(q, r, v, d, p, pi)
+    q_free = dict(q, n_fixed=0)
+    a_free = orc.sph_accel(q_free, r, v, d, p, pi)
+    assert np.array_equal(a_fixed[:n - nw], a_free[:n - nw])
+    assert not a_fixed[n - nw:].any()
+    # momentum: with every particle free, pair forces cancel
+    total = q["mass"] * a_free.sum(axis=0)
+    assert abs(total[0] - q["mass"] * q["F"] * n) < 1e-10 * q["mass"] * n
+    assert abs(total[1]) < 1e-10 * q["mass"] * n
+    r1, v1 = r.copy(), v.copy()
+    L = orc.sph_step(q, r1, v1, pi)
+    assert np.array_equal(r1[n - nw:], r[n - nw:]) and not v1[n - nw:].any()
+    assert not L[n - nw:].any()
+
+
+def test_uniform_force_on_a_lattice_accelerates_every_particle_alike(orc):
+    m = inputs.reverse_poiseuille(nx=8, ny=16)
+    q = dict(m.params, force_mode=1)
+    r, v = m.r.copy(), m.v.copy()
+    orc.sph_step(q, r, v, np.zeros((m.n, 3)))
+    assert np.abs(v[:, 0] - q["F"] * q["dt"]).max() < 1e-12
+    assert np.abs(v[:, 1]).max() < 1e-12
+
+
+def test_channel_between_wall_particles_matches_startup_series(orc):
+    """Plane Poiseuille start-up between frozen wall particles versus the
+    Fourier series of u_t = nu u_yy + F with u = 0 on the no-slip planes.
+    Frozen wall particles put the no-slip plane on their outermost row (one
+    lattice spacing outside the last fluid row; placing it half a spacing
+    out instead gives an 8 % error, a full spacing inward 18 %)."""
+    r, q, y_surf = _channel()
+    dh = 1.0 / 32
+    y0 = y_surf - 0.5 * dh
+    n, nw = r.shape[0], q["n_fixed"]
+    v = np.zeros_like(r)
+    pi = np.zeros((n, 3))
+    nsteps = 300
+    for _ in range(nsteps):
+        orc.sph_step(q, r, v, pi)
+    t = nsteps * q["dt"]
+    nu = q["eta"] / q["rho0"]
+    W = 1.0 + dh
+    xi = r[:n - nw, 1] - y0
+    u = q["F"] / (2 * nu) * xi * (W - xi)
+    for kk in range(1, 400, 2):
+        u -= 4 * q["F"] * W * W / (nu * math.pi ** 3 * kk ** 3) * np.sin(kk * math.pi * xi / W) * \
+            math.exp(-nu * (kk * math.pi / W) ** 2 * t)
+    err = np.abs(v[:n - nw, 0] - u).max()
+    print("channel start-up: max error / max u", err / np.abs(u).max())
+    assert err < 0.05 * np.abs(u).max()
+    assert np.abs(v[:n - nw, 1]).max() < 0.02 * np.abs(u).max()
