@@ -10,6 +10,13 @@ stress).  The timed region is one engine call of K steps (HIP-graph
 replays) on device-resident state; the metric is unordered DPD pairs within
 the cutoff evaluated per second (counted by the engine itself).
 
+Secondary legs (same JSON line): the coupled reverse-Poiseuille LHMM run
+(plain batched DPD, macro steps/s) and the flow past a periodic array of
+cylinders run twice, with all-DPD micro-domains and with the surrogate in
+the loop (gate and DPD fallback): macro steps/s of each, the speed-up, the
+fallback rate and the relative L2 error of the time-averaged deviatoric
+stress of the surrogate run against the all-DPD run.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -109,15 +116,46 @@ def bench_lhmm(macro_steps: int, k_micro: int = 50, equil_steps: int = 500, warm
     return out
 
 
+def bench_pac(macro_steps: int, avg: int):
+    """Cylinder-array LHMM (64 x 64 SPH lattice, ~3.6k micro-domains of 4000
+    particles): all-DPD versus surrogate in the loop, same seeds."""
+    import torch
+
+    from paper_2512_13267_amd import pac
+
+    out = {"workload": "flow past a periodic square array of cylinders (radius 0.2), 64 x 64 SPH lattice, "
+                       "one 4000-particle micro-domain per mobile particle, 50 micro steps per macro step",
+           "macro_steps": macro_steps, "avg_last": avg, "gate_threshold": pac.GATE_THRESHOLD,
+           "gate_floor": pac.GATE_FLOOR, "hold": pac.HOLD, "replay": pac.REPLAY}
+    means = {}
+    for mode in ("dpd", "surrogate"):
+        ctx = pac.build(mode)
+        r, means[mode] = pac.run(ctx, macro_steps, avg, log=lambda *a, **k: print(*a, file=sys.stderr, **k),
+                                 label=mode)
+        out["n_mobile"] = ctx["nm"]
+        pac.close(ctx)
+        torch.cuda.synchronize()
+        out[mode] = {"macro_steps_per_s": r["macro_steps_per_s"], "fallback_rate": r["fallback_rate"],
+                     "micro_box_steps": r["micro_box_steps"], "resets": r["resets"], "entered": r["entered"]}
+    out["speedup"] = out["surrogate"]["macro_steps_per_s"] / out["dpd"]["macro_steps_per_s"]
+    out["stress_rel_l2_vs_dpd"] = pac.compare(means["surrogate"], means["dpd"], out["n_mobile"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the engine's default launch parameters instead of the tuned (cached) ones")
     ap.add_argument("--timing-steps", type=int, default=100)
     ap.add_argument("--lhmm-steps", type=int, default=200,
                     help="macro steps of the coupled reverse-Poiseuille run (0 skips it)")
+    ap.add_argument("--pac-steps", type=int, default=500,
+                    help="macro steps of each cylinder-array run (all-DPD and surrogate; 0 skips them)")
+    ap.add_argument("--pac-avg", type=int, default=100, help="macro steps of the stress average")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2^27 floats (512 MiB read, 512 MiB written) five "
                          "times, to scale the HBM byte counters of a profiler run")
@@ -150,6 +188,13 @@ def main():
     m = micro.from_workload(wl, precision="fp32")
     G = torch.tensor(np.stack([b.L for b in wl.boxes]), dtype=torch.float64, device="cuda").contiguous()
 
+    tuning = None
+    if not args.no_autotune:
+        from paper_2512_13267_amd import autotune
+
+        tuning = autotune.tune(m, G, [b.N for b in wl.boxes], "fp32")
+        print(f"[bench] launch parameters {tuning['config']} (cached: {tuning['cached']})", file=sys.stderr,
+              flush=True)
     if args.warmup > 0:
         m.step(G, args.warmup)
     torch.cuda.synchronize()
@@ -193,6 +238,7 @@ def main():
                                "FP32 forces / FP64 stress",
                    "n_boxes": len(wl.boxes), "n_particles": n_particles,
                    "pairs_per_step": pairs / args.steps,
+                   "launch": m.config(), "tuned": tuning is not None,
                    "flagged_boxes": {"bond": int(np.count_nonzero(flags & 1)), "cell": int(np.count_nonzero(flags & 2)),
                                      "nonfinite": int(np.count_nonzero(flags & 4))}},
         "roofline": roofline,
@@ -202,6 +248,11 @@ def main():
         print("[bench] coupled LHMM run", file=sys.stderr, flush=True)
         rec["lhmm"] = bench_lhmm(args.lhmm_steps)
         print(f"[bench] {rec['lhmm']['value']:.2f} macro steps/s", file=sys.stderr, flush=True)
+    if args.pac_steps > 0:
+        print("[bench] cylinder-array LHMM: all-DPD and surrogate", file=sys.stderr, flush=True)
+        rec["lhmm_pac"] = bench_pac(args.pac_steps, min(args.pac_avg, args.pac_steps))
+        print(f"[bench] surrogate {rec['lhmm_pac']['surrogate']['macro_steps_per_s']:.2f} vs DPD "
+              f"{rec['lhmm_pac']['dpd']['macro_steps_per_s']:.2f} macro steps/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(wl)

@@ -156,6 +156,41 @@ int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double*
 int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, double* stress_out,
                            const int32_t* boxes, int32_t n_sel);
 
+/* Launch parameters of the step kernels.  None of them changes a result:
+ * every sum keeps its order, so all configurations give bit-identical
+ * trajectories.
+ *   queue_depth: per-lane neighbour queue of the pair-force kernel
+ *                (2, 4, 8 in FP32; 2, 4 in FP64);
+ *   drain:       evaluation rounds run until every queue holds at most this
+ *                many neighbours (0 .. queue_depth - 2: a search iteration
+ *                adds up to two before the queues are checked again);
+ *   bin_threads: threads of the per-box binning workgroup (256, 512, 1024);
+ *   graph_chunk: micro steps per captured HIP graph (1 .. 1000). */
+typedef struct {
+    int32_t queue_depth;
+    int32_t drain;
+    int32_t bin_threads;
+    int32_t graph_chunk;
+} lhmm_micro_config;
+
+/* Set / read the launch parameters (defaults: depth 8 in FP32, 4 in FP64;
+ * drain depth/2; 1024 binning threads; 50-step graphs).  Set waits for the
+ * engine and drops its captured graphs.  Errors: ARG. */
+int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg);
+int lhmm_micro_get_config(lhmm_micro* m, lhmm_micro_config* cfg);
+
+/* Choose the launch parameters for the loaded boxes by timing: a coordinate
+ * search over (queue_depth, drain), then bin_threads, then graph_chunk,
+ * each candidate timed over trial_steps steps (after trial_steps warm-up
+ * steps) under gradL (DEVICE n_boxes x 9) with HIP events.  The particle
+ * state, cells, flags and random-force counter are put back after every
+ * trial, so tuning does not change the trajectory.  The best configuration
+ * is set and returned in best (HOST, may be NULL) with its time per step in
+ * best_ms (HOST, may be NULL).  Synchronous; allocates a temporary copy of
+ * the state.  Errors: ARG, STATE, OOM, HIP. */
+int lhmm_micro_autotune(lhmm_micro* m, const double* gradL, int32_t trial_steps, lhmm_micro_config* best,
+                        double* best_ms);
+
 /* Keep a device copy of the current state of every box (positions,
  * velocities, forces, cell).  Ordered on the caller's stream.  Errors:
  * STATE (no state loaded), OOM, HIP. */
@@ -392,6 +427,15 @@ int lhmm_sur_targets(const double* sigma, int32_t n, float inv_scale, float* T, 
 int lhmm_sur_blend(const float* mean, const uint32_t* use_dpd, const double* sigma_dpd, int32_t n, float scale,
                    double* sigma_out, void* stream);
 
+/* Symmetry images of training samples, in place: X DEVICE n x
+ * LHMM_SUR_FEATURES, T DEVICE n x 3 (xx, xy, yy).  Row b is mapped by the
+ * in-plane orthogonal matrix Q = Rot(theta[b]) M, M = diag(1, -1) where
+ * mirror[b] != 0 else the identity: each gradient sample L -> Q L Q^T and
+ * the stress S -> Q S Q^T (the micro model is isotropic).  theta (FP32) and
+ * mirror (uint32) are DEVICE n arrays of random draws supplied by the
+ * caller. */
+int lhmm_sur_augment(float* X, float* T, int32_t n, const float* theta, const uint32_t* mirror, void* stream);
+
 /* Release every resource (waits for the stream).  NULL ok. */
 int lhmm_sur_destroy(lhmm_sur* s);
 
@@ -458,6 +502,11 @@ int lhmm_hybrid_step(lhmm_hybrid* h, lhmm_hybrid_stats* stats);
  * (n x 6; wall rows zero) and of the DPD mask of the last step (n_mobile);
  * either may be NULL.  Synchronous. */
 int lhmm_hybrid_state(lhmm_hybrid* h, double* sigma, uint32_t* on_dpd);
+
+/* HOST n x 6: the mean of the stresses handed to the SPH steps since
+ * create or the last reset (may be NULL); reset != 0 restarts the mean.
+ * Synchronous. */
+int lhmm_hybrid_mean_stress(lhmm_hybrid* h, double* sigma_mean, int32_t reset);
 
 int lhmm_hybrid_destroy(lhmm_hybrid* h);
 

@@ -143,3 +143,24 @@ def blend(mean, use_dpd, sigma_dpd, scale=1.0):
         u = np.asarray(use_dpd).astype(bool)
         out[u] = np.asarray(sigma_dpd)[u]
     return out
+
+
+def augment(X, T, theta, mirror, hist=32):
+    """Symmetry images of surrogate samples under the in-plane orthogonal
+    group: each row b is reflected (y -> -y) when mirror[b], then rotated
+    by theta[b].  Gradient samples transform as L' = Q L Q^T and the stress
+    targets as S' = Q S Q^T with S = [[s_xx, s_xy], [s_xy, s_yy]]
+    (the micro model is isotropic, so these are samples of the same
+    conditional law).  The polymer-fraction column is unchanged."""
+    X = np.asarray(X, dtype=np.float64).copy()
+    T = np.asarray(T, dtype=np.float64).copy()
+    for b in range(X.shape[0]):
+        c, s = math.cos(theta[b]), math.sin(theta[b])
+        Q = np.array([[c, -s], [s, c]]) @ (np.diag([1.0, -1.0]) if mirror[b] else np.eye(2))
+        for k in range(hist):
+            L = X[b, 4 * k:4 * k + 4].reshape(2, 2)
+            X[b, 4 * k:4 * k + 4] = (Q @ L @ Q.T).reshape(4)
+        S = np.array([[T[b, 0], T[b, 1]], [T[b, 1], T[b, 2]]])
+        S = Q @ S @ Q.T
+        T[b] = [S[0, 0], S[0, 1], S[1, 1]]
+    return X, T

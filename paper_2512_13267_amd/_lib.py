@@ -35,12 +35,13 @@ EXPORTS = (
     "lhmm_micro_forces", "lhmm_micro_stress_parts", "lhmm_micro_pair_counts", "lhmm_micro_flags",
     "lhmm_micro_sizes", "lhmm_micro_destroy", "lhmm_last_error", "lhmm_micro_time",
     "lhmm_micro_step_subset", "lhmm_micro_snapshot", "lhmm_micro_restore",
+    "lhmm_micro_set_config", "lhmm_micro_get_config", "lhmm_micro_autotune",
     "lhmm_sph_create", "lhmm_sph_step", "lhmm_sph_get_state", "lhmm_sph_coupling_state", "lhmm_couple_step",
     "lhmm_sph_destroy",
     "lhmm_sur_create", "lhmm_sur_set_weights", "lhmm_sur_get_weights", "lhmm_sur_get_grads", "lhmm_sur_train_step", "lhmm_sur_forward",
     "lhmm_sur_push_history", "lhmm_sur_features", "lhmm_sur_gate", "lhmm_sur_destroy", "lhmm_sur_targets",
-    "lhmm_sur_blend", "lhmm_sur_history_gradient",
-    "lhmm_hybrid_create", "lhmm_hybrid_step", "lhmm_hybrid_state", "lhmm_hybrid_destroy",
+    "lhmm_sur_blend", "lhmm_sur_history_gradient", "lhmm_sur_augment",
+    "lhmm_hybrid_create", "lhmm_hybrid_step", "lhmm_hybrid_state", "lhmm_hybrid_destroy", "lhmm_hybrid_mean_stress",
 )
 SUR_HIST = 32
 SUR_FEATURES = 4 * SUR_HIST + 1
@@ -63,6 +64,10 @@ class LhmmSphParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly",
                                             "lambda_star", "alpha")] + [("n_fixed", C.c_int32),
                                                                         ("force_mode", C.c_int32)]
+
+
+class LhmmMicroConfig(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("queue_depth", "drain", "bin_threads", "graph_chunk")]
 
 
 class LhmmSurParams(C.Structure):
@@ -108,6 +113,9 @@ def lib():
         i32p = C.POINTER(C.c_int32)
         L.lhmm_micro_step_subset.argtypes = [vp, vp, C.c_int32, vp, i32p, C.c_int32]
         L.lhmm_micro_snapshot.argtypes = [vp]
+        L.lhmm_micro_set_config.argtypes = [vp, C.POINTER(LhmmMicroConfig)]
+        L.lhmm_micro_get_config.argtypes = [vp, C.POINTER(LhmmMicroConfig)]
+        L.lhmm_micro_autotune.argtypes = [vp, vp, C.c_int32, C.POINTER(LhmmMicroConfig), dp]
         L.lhmm_micro_restore.argtypes = [vp, i32p, C.c_int32]
         L.lhmm_micro_forces.argtypes = [vp, dp, dp, dp]
         L.lhmm_micro_stress_parts.argtypes = [vp, dp]
@@ -130,6 +138,7 @@ def lib():
         L.lhmm_sur_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp]
         L.lhmm_sur_forward.argtypes = [vp, vp, C.c_int32, vp]
         L.lhmm_sur_push_history.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_float, vp]
+        L.lhmm_sur_augment.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
         L.lhmm_sur_targets.argtypes = [vp, C.c_int32, C.c_float, vp, vp]
         L.lhmm_sur_blend.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp, vp]
         L.lhmm_sur_history_gradient.argtypes = [vp, C.c_int32, C.c_int64, C.c_float, vp, vp]
@@ -140,6 +149,7 @@ def lib():
         L.lhmm_hybrid_step.argtypes = [vp, C.POINTER(LhmmHybridStats)]
         L.lhmm_hybrid_state.argtypes = [vp, dp, C.POINTER(C.c_uint32)]
         L.lhmm_hybrid_destroy.argtypes = [vp]
+        L.lhmm_hybrid_mean_stress.argtypes = [vp, dp, C.c_int32]
         L.lhmm_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "lhmm_last_error":

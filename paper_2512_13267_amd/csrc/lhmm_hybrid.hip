@@ -41,6 +41,8 @@ struct lhmm_hybrid {
     float *ring = nullptr, *phi = nullptr, *X = nullptr, *Y = nullptr, *mean = nullptr;
     unsigned *gflag = nullptr, *on_d = nullptr;
     double *sigma = nullptr, *sigma_dpd = nullptr, *gradL = nullptr, *gradL_r = nullptr, *scratch = nullptr;
+    double* sigma_sum = nullptr;  // running sum of the stresses handed to SPH
+    long long n_sum = 0;
     std::vector<void*> bufs;
     // host (pinned)
     unsigned *gflag_h = nullptr, *on_h = nullptr;
@@ -50,6 +52,16 @@ struct lhmm_hybrid {
 };
 
 namespace {
+
+__global__ void k_accumulate(const double* __restrict__ x, long n, double* __restrict__ sum) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) sum[i] += x[i];
+}
+
+__global__ void k_zero(double* __restrict__ x, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
 
 template <typename T>
 int hy_alloc(lhmm_hybrid* h, T** p, size_t count) {
@@ -142,6 +154,7 @@ int lhmm_hybrid_create(const lhmm_hybrid_params* p, lhmm_sph* sph, lhmm_micro* m
     if (rc == LHMM_OK) rc = hy_alloc(h, &h->gradL, (size_t)n * 9);
     if (rc == LHMM_OK) rc = hy_alloc(h, &h->gradL_r, m * 9);
     if (rc == LHMM_OK) rc = hy_alloc(h, &h->scratch, m * 6);
+    if (rc == LHMM_OK) rc = hy_alloc(h, &h->sigma_sum, (size_t)n * 6);
     if (rc == LHMM_OK && hipHostMalloc((void**)&h->gflag_h, m * sizeof(unsigned)) != hipSuccess)
         rc = lhmm_fail(LHMM_ERR_OOM, "pinned allocation failed");
     if (rc == LHMM_OK && hipHostMalloc((void**)&h->on_h, m * sizeof(unsigned)) != hipSuccess)
@@ -150,6 +163,7 @@ int lhmm_hybrid_create(const lhmm_hybrid_params* p, lhmm_sph* sph, lhmm_micro* m
         LHMM_HIPCHK(hipStreamSynchronize(st));
         LHMM_HIPCHK(hipMemset(h->ring, 0, m * LHMM_SUR_HIST * 4 * sizeof(float)));
         LHMM_HIPCHK(hipMemset(h->sigma, 0, (size_t)n * 6 * sizeof(double)));
+        LHMM_HIPCHK(hipMemset(h->sigma_sum, 0, (size_t)n * 6 * sizeof(double)));
         LHMM_HIPCHK(hipMemset(h->sigma_dpd, 0, m * 6 * sizeof(double)));
         LHMM_HIPCHK(hipMemset(h->gradL, 0, (size_t)n * 9 * sizeof(double)));
         LHMM_HIPCHK(hipMemset(h->mean, 0, m * 3 * sizeof(float)));
@@ -241,6 +255,10 @@ int lhmm_hybrid_step(lhmm_hybrid* h, lhmm_hybrid_stats* stats) {
         rc = restore_and_replay(h, reset, t + 1 - h->p.replay, t);
         if (rc != LHMM_OK) return rc;
     }
+    const long n6 = 6L * h->n;
+    k_accumulate<<<(n6 + 255) / 256, 256, 0, h->stream>>>(h->sigma, n6, h->sigma_sum);
+    LHMM_HIPCHK(hipGetLastError());
+    h->n_sum += 1;
     h->t += 1;
     S.macro_step = h->t;
     S.micro_box_steps = h->box_steps;
@@ -260,6 +278,26 @@ int lhmm_hybrid_state(lhmm_hybrid* h, double* sigma, uint32_t* on_dpd) {
         } else {
             for (int b = 0; b < h->nm; ++b) on_dpd[b] = h->was_on[b] ? 1u : 0u;
         }
+    }
+    return LHMM_OK;
+}
+
+int lhmm_hybrid_mean_stress(lhmm_hybrid* h, double* sigma_mean, int32_t reset) {
+    lhmm_clear_error();
+    if (!h) return lhmm_fail(LHMM_ERR_ARG, "null argument");
+    LHMM_HIPCHK(hipStreamSynchronize(h->stream));
+    const size_t n6 = 6 * (size_t)h->n;
+    if (sigma_mean) {
+        std::vector<double> buf(n6);
+        LHMM_HIPCHK(hipMemcpy(buf.data(), h->sigma_sum, n6 * sizeof(double), hipMemcpyDeviceToHost));
+        const double w = h->n_sum > 0 ? 1.0 / (double)h->n_sum : 0.0;
+        for (size_t i = 0; i < n6; ++i) sigma_mean[i] = buf[i] * w;
+    }
+    if (reset) {
+        k_zero<<<(n6 + 255) / 256, 256, 0, h->stream>>>(h->sigma_sum, (long)n6);
+        LHMM_HIPCHK(hipGetLastError());
+        LHMM_HIPCHK(hipStreamSynchronize(h->stream));
+        h->n_sum = 0;
     }
     return LHMM_OK;
 }

@@ -45,9 +45,9 @@
 namespace {
 
 constexpr int BS = 256;                 // particles per work block
-constexpr int BIN_THREADS = 1024;       // threads of the per-box binning workgroup
+constexpr int BIN_THREADS_MAX = 1024;   // largest binning workgroup (256, 512 or 1024 threads)
 constexpr int MAX_CELLS_PER_BOX = 15360;  // LDS histogram capacity (60 KiB)
-constexpr int GRAPH_CHUNK = 50;         // steps per captured graph
+constexpr int GRAPH_CHUNK = 50;         // default steps per captured graph
 
 thread_local std::string g_err;
 
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
 // One workgroup per box: counting sort by cell in LDS, writing each
 // particle's record (position, local index) in cell order; every cell's
 // records are then sorted by index so all later sums have a fixed order.
-template <typename real>
+template <typename real, int BIN_THREADS>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
     using R = Rec<real>;
     __shared__ int cnt[MAX_CELLS_PER_BOX];
@@ -556,17 +556,18 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 //   the row); each lane scans its own row range two records at a time
 //   (lanes of one home cell read the same records) and appends accepted
 //   neighbours (0 < r < rc; the particle itself has r = 0) to its own LDS
-//   queue of QD entries.
+//   queue of QD entries (a tuning parameter, as is `drain`; neither changes
+//   the order in which a lane evaluates its neighbours, so results do not
+//   depend on them).
 //   Evaluation: a round pops one queued neighbour per lane and evaluates the
 //   pair (relative velocity including the streaming difference L d, Philox
 //   normal, force, virial).  A round runs whenever 56 or more lanes have work
 //   or a queue could overflow, and the queues are drained at the end.
-template <typename real>
-__global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
+template <typename real, int QD>
+__global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain) {
     using R = Rec<real>;
     using V4 = typename R::T;
     constexpr int NW = BS / 64;
-    constexpr int QD = sizeof(real) == 4 ? 8 : 4;  // queue depth per lane (power of two)
     __shared__ V4 qbuf[QD][NW][64];                 // (dx, dy, dz, cell-order position of j)
     __shared__ double red[13 * NW];
 
@@ -719,10 +720,10 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset) {
             while (__ballot(qt > qh) != 0ull) round();
             break;
         }
-        // evaluate until every queue is at most half full
+        // evaluate until every queue holds at most `drain` entries
         do {
             round();
-        } while (__ballot(qt - qh > QD / 2) != 0ull);
+        } while (__ballot(qt - qh > drain) != 0ull);
     }
 
     real wf[6] = {0, 0, 0, 0, 0, 0};
@@ -875,6 +876,7 @@ __global__ void k_finalize(Ctx C, double* __restrict__ stress_out, double* __res
 
 struct lhmm_micro {
     lhmm_params p{};
+    lhmm_micro_config cfg{};
     int n_boxes = 0, n_blocks = 0, precision = LHMM_FP32;
     long long n_total = 0;
     size_t real_size = 4;
@@ -909,6 +911,25 @@ struct lhmm_micro {
 
 namespace {
 
+template <typename real>
+void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st) {
+    switch (m->cfg.bin_threads) {
+        case 256: k_bin_box<real, 256><<<nbox, 256, 0, st>>>(C); break;
+        case 512: k_bin_box<real, 512><<<nbox, 512, 0, st>>>(C); break;
+        default: k_bin_box<real, 1024><<<nbox, 1024, 0, st>>>(C); break;
+    }
+}
+
+template <typename real>
+void launch_forces(lhmm_micro* m, const Ctx& C, int nblk, int step_offset, hipStream_t st) {
+    const int drain = m->cfg.drain;
+    switch (m->cfg.queue_depth) {
+        case 2: k_forces<real, 2><<<nblk, BS, 0, st>>>(C, step_offset, drain); break;
+        case 4: k_forces<real, 4><<<nblk, BS, 0, st>>>(C, step_offset, drain); break;
+        default: k_forces<real, sizeof(real) == 4 ? 8 : 4><<<nblk, BS, 0, st>>>(C, step_offset, drain); break;
+    }
+}
+
 // One step (or a force evaluation) of the boxes C selects: all n_boxes boxes
 // and n_blocks work blocks, or the n_sel selected boxes and their nblk blocks.
 template <typename real>
@@ -917,8 +938,8 @@ void launch_step_kernels(lhmm_micro* m, const Ctx& C, int nbox, int nblk, int st
     const int bt = 256, bg = (nbox + bt - 1) / bt;
     k_cell_step<<<bg, bt, 0, m->stream>>>(C, advance ? 1 : 0);
     k_kick_drift<real><<<nblk, BS, 0, m->stream>>>(C, advance ? 1 : 0);
-    k_bin_box<real><<<nbox, BIN_THREADS, 0, m->stream>>>(C);
-    k_forces<real><<<nblk, BS, 0, m->stream>>>(C, step_offset);
+    launch_bin<real>(m, C, nbox, m->stream);
+    launch_forces<real>(m, C, nblk, step_offset, m->stream);
     if (full_step) {
         k_kick2<real><<<nblk, BS, 0, m->stream>>>(C);
         k_box_stress<<<nbox, 64, 0, m->stream>>>(C);
@@ -938,10 +959,10 @@ void launch_step_timed(lhmm_micro* m, hipEvent_t* ev) {
     k_kick_drift<real><<<m->n_blocks, BS, 0, st>>>(C, 1);
     (void)hipEventRecord(ev[3], st);
     (void)hipEventRecord(ev[4], st);
-    k_bin_box<real><<<m->n_boxes, BIN_THREADS, 0, st>>>(C);
+    launch_bin<real>(m, C, m->n_boxes, st);
     (void)hipEventRecord(ev[5], st);
     (void)hipEventRecord(ev[6], st);
-    k_forces<real><<<m->n_blocks, BS, 0, st>>>(C, 1);
+    launch_forces<real>(m, C, m->n_blocks, 1, st);
     (void)hipEventRecord(ev[7], st);
     (void)hipEventRecord(ev[8], st);
     k_kick2<real><<<m->n_blocks, BS, 0, st>>>(C);
@@ -1105,6 +1126,10 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->p = *p;
     m->n_boxes = n_boxes;
     m->precision = p->precision;
+    m->cfg.queue_depth = p->precision == LHMM_FP64 ? 4 : 8;
+    m->cfg.drain = m->cfg.queue_depth / 2;
+    m->cfg.bin_threads = BIN_THREADS_MAX;
+    m->cfg.graph_chunk = GRAPH_CHUNK;
     m->real_size = p->precision == LHMM_FP64 ? sizeof(double) : sizeof(float);
     m->user_stream = (hipStream_t)stream;
 
@@ -1358,7 +1383,7 @@ int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double*
     if (m->p.flags & LHMM_OPT_NO_GRAPH) {
         for (int k = 0; k < n_steps; ++k) launch_one_step(m);
     } else {
-        const int chunk = n_steps < GRAPH_CHUNK ? n_steps : GRAPH_CHUNK;
+        const int chunk = n_steps < m->cfg.graph_chunk ? n_steps : m->cfg.graph_chunk;
         const int full = n_steps / chunk, rest = n_steps % chunk;
         hipGraphExec_t g = nullptr;
         int rc = get_graph(m, chunk, &g);
@@ -1375,6 +1400,158 @@ int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double*
     HIPCHK(hipEventRecord(m->ev_out, m->stream));
     HIPCHK(hipStreamWaitEvent(m->user_stream, m->ev_out, 0));
     return LHMM_OK;
+}
+
+int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg) {
+    g_err.clear();
+    if (!m || !cfg) return fail(LHMM_ERR_ARG, "null argument");
+    const int qd = cfg->queue_depth;
+    const bool qd_ok = m->precision == LHMM_FP64 ? (qd == 2 || qd == 4) : (qd == 2 || qd == 4 || qd == 8);
+    if (!qd_ok) return fail(LHMM_ERR_ARG, "queue_depth %d not available at this precision", qd);
+    // a scan iteration pushes up to two neighbours per lane before it checks
+    // the queues, so a lane may hold at most qd - 2 when scanning resumes
+    if (cfg->drain < 0 || cfg->drain > qd - 2) return fail(LHMM_ERR_ARG, "drain must be in 0..%d", qd - 2);
+    if (cfg->bin_threads != 256 && cfg->bin_threads != 512 && cfg->bin_threads != 1024)
+        return fail(LHMM_ERR_ARG, "bin_threads must be 256, 512 or 1024");
+    if (cfg->graph_chunk < 1 || cfg->graph_chunk > 1000) return fail(LHMM_ERR_ARG, "graph_chunk must be 1..1000");
+    HIPCHK(hipStreamSynchronize(m->stream));
+    for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
+    m->graphs.clear();
+    m->cfg = *cfg;
+    return LHMM_OK;
+}
+
+int lhmm_micro_get_config(lhmm_micro* m, lhmm_micro_config* cfg) {
+    g_err.clear();
+    if (!m || !cfg) return fail(LHMM_ERR_ARG, "null argument");
+    *cfg = m->cfg;
+    return LHMM_OK;
+}
+
+int lhmm_micro_autotune(lhmm_micro* m, const double* gradL, int32_t trial_steps, lhmm_micro_config* best,
+                        double* best_ms) {
+    g_err.clear();
+    if (!m || !gradL) return fail(LHMM_ERR_ARG, "null argument");
+    if (trial_steps < 1) return fail(LHMM_ERR_ARG, "trial_steps must be positive");
+    if (!m->have_state) return fail(LHMM_ERR_STATE, "no particle state loaded");
+    // keep the state (particles, cells, counter, flags) to put it back after every trial
+    const size_t bytes = 3 * (size_t)m->n_total * m->real_size;
+    void *ss = nullptr, *sc = nullptr, *sf = nullptr, *sdyn = nullptr, *sflags = nullptr, *sout = nullptr;
+    unsigned long long step0 = 0;
+    int rc = dalloc((char**)&ss, bytes);
+    if (rc == LHMM_OK) rc = dalloc((char**)&sc, bytes);
+    if (rc == LHMM_OK) rc = dalloc((char**)&sf, bytes);
+    if (rc == LHMM_OK) rc = dalloc((char**)&sdyn, sizeof(BoxDyn) * m->n_boxes);
+    if (rc == LHMM_OK) rc = dalloc((char**)&sflags, sizeof(unsigned) * m->n_boxes);
+    if (rc == LHMM_OK) rc = dalloc((char**)&sout, sizeof(double) * 6 * m->n_boxes);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto done = [&](int code) {
+        (void)hipStreamSynchronize(m->stream);
+        for (void* q : {ss, sc, sf, sdyn, sflags, sout})
+            if (q) (void)hipFree(q);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return code;
+    };
+    if (rc != LHMM_OK) return done(rc);
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return done(fail(LHMM_ERR_HIP, "hipEventCreate failed"));
+    if (hipStreamSynchronize(m->user_stream) != hipSuccess || sync_engine(m) != LHMM_OK)
+        return done(fail(LHMM_ERR_HIP, "synchronisation failed"));
+    const bool fv = m->forces_valid;
+    auto save = [&]() -> hipError_t {
+        hipError_t e = hipMemcpy(ss, m->d_s, bytes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(sc, m->d_c, bytes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(sf, m->d_f, bytes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(sdyn, m->d_dyn, sizeof(BoxDyn) * m->n_boxes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(sflags, m->d_flags, sizeof(unsigned) * m->n_boxes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(&step0, m->d_step, sizeof step0, hipMemcpyDeviceToHost);
+        return e;
+    };
+    auto load = [&]() -> hipError_t {
+        hipError_t e = hipStreamSynchronize(m->stream);
+        if (e == hipSuccess) e = hipMemcpy(m->d_s, ss, bytes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->d_c, sc, bytes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->d_f, sf, bytes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->d_dyn, sdyn, sizeof(BoxDyn) * m->n_boxes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->d_flags, sflags, sizeof(unsigned) * m->n_boxes, hipMemcpyDeviceToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->d_step, &step0, sizeof step0, hipMemcpyHostToDevice);
+        m->forces_valid = fv;
+        return e;
+    };
+    if (save() != hipSuccess) return done(fail(LHMM_ERR_HIP, "state copy failed"));
+    // mean ms per step of one configuration (one warm-up call, then one timed call)
+    auto trial = [&](const lhmm_micro_config& c, double* ms) -> int {
+        int r = lhmm_micro_set_config(m, &c);
+        if (r != LHMM_OK) return r;
+        r = lhmm_micro_step(m, gradL, trial_steps, (double*)sout);
+        if (r != LHMM_OK) return r;
+        HIPCHK(hipEventRecord(e0, m->user_stream));
+        r = lhmm_micro_step(m, gradL, trial_steps, (double*)sout);
+        if (r != LHMM_OK) return r;
+        HIPCHK(hipEventRecord(e1, m->user_stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float el = 0.0f;
+        HIPCHK(hipEventElapsedTime(&el, e0, e1));
+        *ms = el / trial_steps;
+        return load() == hipSuccess ? LHMM_OK : fail(LHMM_ERR_HIP, "state restore failed");
+    };
+    // coordinate search: force-kernel queue, then binning workgroup, then graph chunk
+    lhmm_micro_config cur = m->cfg;
+    double cur_ms = 0.0;
+    rc = trial(cur, &cur_ms);
+    const int qds32[] = {2, 4, 8}, qds64[] = {2, 4};
+    const int* qds = m->precision == LHMM_FP64 ? qds64 : qds32;
+    const int nq = m->precision == LHMM_FP64 ? 2 : 3;
+    for (int iq = 0; rc == LHMM_OK && iq < nq; ++iq) {
+        const int qd = qds[iq];
+        const int drains[2] = {0, qd / 2 <= qd - 2 ? qd / 2 : 0};
+        for (int d : drains) {
+            lhmm_micro_config c = cur;
+            c.queue_depth = qd;
+            c.drain = d;
+            if (c.queue_depth == cur.queue_depth && c.drain == cur.drain) continue;
+            double ms = 0.0;
+            rc = trial(c, &ms);
+            if (rc != LHMM_OK) break;
+            if (ms < cur_ms) {
+                cur = c;
+                cur_ms = ms;
+            }
+        }
+    }
+    for (int bt : {256, 512, 1024}) {
+        if (rc != LHMM_OK || bt == cur.bin_threads) continue;
+        lhmm_micro_config c = cur;
+        c.bin_threads = bt;
+        double ms = 0.0;
+        rc = trial(c, &ms);
+        if (rc == LHMM_OK && ms < cur_ms) {
+            cur = c;
+            cur_ms = ms;
+        }
+    }
+    for (int ch : {25, 50, 100}) {
+        if (rc != LHMM_OK || ch == cur.graph_chunk) continue;
+        lhmm_micro_config c = cur;
+        c.graph_chunk = ch;
+        double ms = 0.0;
+        rc = trial(c, &ms);
+        if (rc == LHMM_OK && ms < cur_ms) {
+            cur = c;
+            cur_ms = ms;
+        }
+    }
+    if (rc != LHMM_OK) {
+        (void)load();
+        return done(rc);
+    }
+    rc = lhmm_micro_set_config(m, &cur);
+    if (rc == LHMM_OK) {
+        if (best) *best = cur;
+        if (best_ms) *best_ms = cur_ms;
+    }
+    return done(rc);
 }
 
 int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, double* stress_out,

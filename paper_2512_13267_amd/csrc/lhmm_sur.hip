@@ -313,6 +313,39 @@ __global__ void k_ring_to_grad(const float* __restrict__ ring, int n, long s, fl
     L[6] = 0.0; L[7] = 0.0; L[8] = 0.0;
 }
 
+// symmetry image of sample b under the in-plane orthogonal map
+// Q = Rot(theta_b) (diag(1, -1) if mirror_b): every gradient sample
+// L -> Q L Q^T, the stress target S -> Q S Q^T, in place
+__global__ void k_augment(float* __restrict__ X, float* __restrict__ T, int n, const float* __restrict__ theta,
+                          const unsigned* __restrict__ mirror) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const float c = cosf(theta[b]), s = sinf(theta[b]);
+    float q00 = c, q01 = -s, q10 = s, q11 = c;
+    if (mirror[b]) {
+        q01 = s;
+        q11 = -c;
+    }
+    float* x = X + (long)b * LHMM_SUR_FEATURES;
+    for (int k = 0; k < HIST; ++k) {
+        const float l00 = x[4 * k], l01 = x[4 * k + 1], l10 = x[4 * k + 2], l11 = x[4 * k + 3];
+        // A = Q L, then A Q^T
+        const float a00 = q00 * l00 + q01 * l10, a01 = q00 * l01 + q01 * l11;
+        const float a10 = q10 * l00 + q11 * l10, a11 = q10 * l01 + q11 * l11;
+        x[4 * k] = a00 * q00 + a01 * q01;
+        x[4 * k + 1] = a00 * q10 + a01 * q11;
+        x[4 * k + 2] = a10 * q00 + a11 * q01;
+        x[4 * k + 3] = a10 * q10 + a11 * q11;
+    }
+    float* y = T + 3 * (long)b;
+    const float sxx = y[0], sxy = y[1], syy = y[2];
+    const float a00 = q00 * sxx + q01 * sxy, a01 = q00 * sxy + q01 * syy;
+    const float a10 = q10 * sxx + q11 * sxy, a11 = q10 * sxy + q11 * syy;
+    y[0] = a00 * q00 + a01 * q01;
+    y[1] = a00 * q10 + a01 * q11;
+    y[2] = a10 * q10 + a11 * q11;
+}
+
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 }  // namespace
@@ -703,6 +736,14 @@ int lhmm_sur_history_gradient(const float* ring, int32_t n, int64_t t, float inv
     lhmm_clear_error();
     if (!ring || !gradL || n < 1 || t < 0) return lhmm_fail(LHMM_ERR_ARG, "bad history arguments");
     k_ring_to_grad<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(ring, n, t, inv_scale, gradL);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_augment(float* X, float* T, int32_t n, const float* theta, const uint32_t* mirror, void* stream) {
+    lhmm_clear_error();
+    if (!X || !T || !theta || !mirror || n < 1) return lhmm_fail(LHMM_ERR_ARG, "bad augment arguments");
+    k_augment<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(X, T, n, theta, mirror);
     LHMM_HIPCHK(hipGetLastError());
     return LHMM_OK;
 }

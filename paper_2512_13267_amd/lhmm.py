@@ -124,6 +124,12 @@ class Hybrid:
         check(lib().lhmm_hybrid_state(self._h, _dptr(sig), on.ctypes.data_as(C.POINTER(C.c_uint32))))
         return sig, on
 
+    def mean_stress(self, reset: bool = False):
+        """Mean of the stresses handed to SPH since creation or the last reset (n, 6)."""
+        out = np.zeros((self.n, 6))
+        check(lib().lhmm_hybrid_mean_stress(self._h, _dptr(out), 1 if reset else 0))
+        return out
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             check(lib().lhmm_hybrid_destroy(self._h))

@@ -122,6 +122,28 @@ class Micro:
                                                sel.ctypes.data_as(C.POINTER(C.c_int32)), int(sel.size)))
         return out
 
+    def config(self) -> dict:
+        c = _lib.LhmmMicroConfig()
+        check(lib().lhmm_micro_get_config(self._h, C.byref(c)))
+        return {k: int(getattr(c, k)) for k, _ in _lib.LhmmMicroConfig._fields_}
+
+    def set_config(self, **kw):
+        cur = self.config()
+        cur.update({k: int(v) for k, v in kw.items()})
+        c = _lib.LhmmMicroConfig(**cur)
+        check(lib().lhmm_micro_set_config(self._h, C.byref(c)))
+
+    def autotune(self, gradL, trial_steps: int = 20):
+        """Time launch configurations on the loaded boxes and keep the best
+        (the state is unchanged).  Returns (config dict, ms per step)."""
+        g = gradL.reshape(self.n_boxes, 9)
+        c = _lib.LhmmMicroConfig()
+        ms = C.c_double()
+        with self._torch.cuda.stream(self.stream):
+            check(lib().lhmm_micro_autotune(self._h, C.c_void_p(g.data_ptr()), int(trial_steps), C.byref(c),
+                                            C.byref(ms)))
+        return {k: int(getattr(c, k)) for k, _ in _lib.LhmmMicroConfig._fields_}, float(ms.value)
+
     def snapshot(self):
         with self._torch.cuda.stream(self.stream):
             check(lib().lhmm_micro_snapshot(self._h))

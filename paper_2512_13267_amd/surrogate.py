@@ -153,6 +153,16 @@ def history_gradient(ring, t, gradL, stream, inv_scale=1.0):
                                           C.c_void_p(gradL.data_ptr()), C.c_void_p(stream.cuda_stream)))
 
 
+def augment(X, T, theta, mirror, stream):
+    """In-place symmetry images of rows of X (n, 129) and T (n, 3), cuda float32."""
+    n = X.shape[0]
+    if X.shape != (n, SUR_FEATURES) or T.shape != (n, 3) or theta.numel() != n or mirror.numel() != n:
+        raise ValueError("X (n, 129), T (n, 3), theta (n,), mirror (n,)")
+    check(lib().lhmm_sur_augment(C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), n,
+                                 C.c_void_p(theta.data_ptr()), C.c_void_p(mirror.data_ptr()),
+                                 C.c_void_p(stream.cuda_stream)))
+
+
 def targets(sigma, inv_scale, T, stream):
     """sigma: cuda float64 (n, 6) -> T cuda float32 (n, 3)."""
     n = T.shape[0]

@@ -4,8 +4,9 @@ Data: a batch of micro-domains (4000 particles, polymer fraction uniform in
 [0.1, 0.3]) advanced by the batched micro-DPD engine under random
 gradient histories: each box follows piecewise-constant traceless in-plane
 gradients, one per macro step, whose three free entries are independent
-Ornstein-Uhlenbeck sequences (standard deviation GRAD_SD, correlation
-CORR_STEPS macro steps).  A sample is (the box's last LHMM_SUR_HIST
+Ornstein-Uhlenbeck sequences (correlation CORR_STEPS macro steps) with a
+per-box standard deviation GRAD_SD x 10^u, u uniform in AMP_RANGE, so that
+slow and fast flows are both covered.  A sample is (the box's last LHMM_SUR_HIST
 gradients and its polymer fraction) -> (the in-plane deviatoric micro
 stress averaged over the macro step's micro steps), the quantity the
 macro momentum equation takes from a micro-domain (Eq. pip).  Every step of
@@ -20,7 +21,10 @@ restart, so every kept sample's history window was lived by its box.
 
 Training: every member takes the same minibatches (members differ by their
 random initialisation), Adam with a cosine-decayed learning rate, mean
-squared error on targets divided by STRESS_SCALE.  10 % of the boxes are
+squared error on targets divided by STRESS_SCALE.  Each minibatch row is
+replaced by a random image under in-plane rotations and reflections
+(lhmm_sur_augment): the micro model is isotropic, so the image is a sample
+of the same conditional law.  10 % of the boxes are
 held out.  A group of boxes can be run as replicas (same start, same
 gradients, different random-force streams) to measure the DPD noise of a
 target.
@@ -45,6 +49,7 @@ HIST = _lib.SUR_HIST
 N_FEATURES = _lib.SUR_FEATURES
 GRAD_SD = 0.05
 CORR_STEPS = 10.0
+AMP_RANGE = (-1.0, 0.2)
 GRAD_SCALE = 1.0 / GRAD_SD     # features hold L / GRAD_SD
 STRESS_SCALE = 0.1             # the network predicts deviatoric stress / STRESS_SCALE
 K_MICRO = 50
@@ -60,9 +65,10 @@ def phi_feature(phi):
 
 def ou_gradients(n_boxes, n_macro, sd=GRAD_SD, corr=CORR_STEPS, seed=0):
     """(n_macro, n_boxes, 9) piecewise-constant gradients [[a, b, 0], [c, -a, 0], 0]
-    with (a, b, c) stationary OU sequences."""
+    with (a, b, c) stationary OU sequences; sd: a number or one per box."""
     rng = np.random.default_rng(seed)
     rho = math.exp(-1.0 / corr)
+    sd = np.broadcast_to(np.asarray(sd, dtype=np.float64), (n_boxes,))[:, None]
     x = rng.normal(size=(n_boxes, 3)) * sd
     out = np.zeros((n_macro, n_boxes, 9))
     for t in range(n_macro):
@@ -84,7 +90,8 @@ def generate(n_boxes, n_macro, k_micro=K_MICRO, equil=500, seed_k=3, replicas=1,
     boxes = [b for b in wl_u.boxes for _ in range(replicas)]
     wl = inputs.Workload("surrogate_data", wl_u.params, boxes, 0)
     phis = np.repeat(phis_u, replicas)
-    G_u = ou_gradients(n_unique, n_macro, seed=inputs.SEED_BASE + seed_k + 1)
+    sd_u = GRAD_SD * 10.0 ** rng.uniform(*AMP_RANGE, size=n_unique)
+    G_u = ou_gradients(n_unique, n_macro, sd=sd_u, seed=inputs.SEED_BASE + seed_k + 1)
     G_host = np.repeat(G_u, replicas, axis=1)
     t0 = time.time()
     m = from_workload(wl, precision="fp32", rng_ids=list(range(n_boxes)))
@@ -141,7 +148,7 @@ def generate(n_boxes, n_macro, k_micro=K_MICRO, equil=500, seed_k=3, replicas=1,
     torch.cuda.synchronize()
     info = {"n_boxes": n_boxes, "replicas": replicas, "n_macro": n_macro, "k_micro": k_micro, "equil": equil,
             "samples": n, "resets": resets, "bad_samples": bad, "seconds": time.time() - t0,
-            "grad_sd": GRAD_SD, "corr_steps": CORR_STEPS}
+            "grad_sd_range": [float(sd_u.min()), float(sd_u.max())], "corr_steps": CORR_STEPS}
     m.close()
     return X[:n], T[:n], box_id[:n], step_id[:n], info
 
@@ -165,7 +172,7 @@ def evaluate(sur, X, T, batch):
 
 
 def train(X, T, box_id, n_members=5, hidden=256, epochs=30, batch=4096, lr=1e-3, seed=0, held_mod=10,
-          log=print):
+          augment=True, log=print):
     import torch
 
     dev = X.device
@@ -190,7 +197,12 @@ def train(X, T, box_id, n_members=5, hidden=256, epochs=30, batch=4096, lr=1e-3,
             for j in range(steps_per_epoch):
                 idx = perm[j * batch:(j + 1) * batch]
                 rate = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * k / total)))
-                sur.train_step(X[idx].contiguous(), T[idx].contiguous(), rate, loss)
+                Xb, Tb = X[idx].contiguous(), T[idx].contiguous()
+                if augment:
+                    theta = (torch.rand(idx.numel(), generator=gen) * (2.0 * math.pi)).to(dev)
+                    mirror = torch.randint(0, 2, (idx.numel(),), generator=gen, dtype=torch.int32).to(dev)
+                    surrogate.augment(Xb, Tb, theta, mirror, sur.stream)
+                sur.train_step(Xb, Tb, rate, loss)
                 acc += loss
                 k += 1
             torch.cuda.synchronize()
@@ -208,10 +220,49 @@ def train(X, T, box_id, n_members=5, hidden=256, epochs=30, batch=4096, lr=1e-3,
     coef = torch.linalg.lstsq(A[tr].cpu(), T[tr].double().cpu()).solution.to(dev)
     lin = (A[te] @ coef)
     lin_rel = float((lin - T[te].double()).norm() / T[te].double().norm())
-    metrics = {"train_seconds": train_s, "steps": k, "epochs": epochs, "batch": batch, "lr": lr,
+    metrics = {"train_seconds": train_s, "steps": k, "epochs": epochs, "batch": batch, "lr": lr, "augment": augment,
                "train_rows": int(tr.numel()), "held_out_rows": int(te.numel()), "held_out": m_te,
                "train_subset": m_tr, "linear_current_gradient_rel_l2": lin_rel, "epoch_loss": history}
     return sur, metrics
+
+
+def write_summary(metrics, path, command):
+    """Markdown summary of a training run (data, training, errors)."""
+    d, h = metrics["data"], metrics["held_out"]
+    L = ["# Surrogate training: 5-member MLP ensemble 129-256-256-3 (BF16 matrix cores)", "",
+         "Command (MI355X, one GPU):", "", "```", command, "```", "",
+         "## Data generation (batched micro-DPD on the GPU)", "", "| quantity | value |", "|---|---|"]
+    for k in ("n_boxes", "n_macro", "k_micro", "equil", "samples", "resets", "bad_samples", "grad_sd_range",
+              "corr_steps"):
+        L.append(f"| {k} | {d[k]} |")
+    steps = d["n_macro"] * d["k_micro"] + d["equil"]
+    L += [f"| wall time (s) | {d['seconds']:.1f} |",
+          f"| particle-steps/s | {d['n_boxes'] * 4000 * steps / d['seconds']:.3e} |", "",
+          "## Training", "", "| quantity | value |", "|---|---|"]
+    for k in ("steps", "epochs", "batch", "lr", "augment", "train_rows", "held_out_rows"):
+        L.append(f"| {k} | {metrics[k]} |")
+    L += [f"| wall time (s) | {metrics['train_seconds']:.2f} |",
+          f"| ms per Adam step (all members, with row gather) | {1000 * metrics['train_seconds'] / metrics['steps']:.3f} |",
+          "", "## Errors (relative L2 over samples and the three outputs)", "", "| comparison | rel. L2 |", "|---|---|",
+          f"| ensemble mean vs single DPD target, held-out boxes | {h['rel_l2']:.4f} |",
+          f"| ensemble mean vs single DPD target, training boxes | {metrics['train_subset']['rel_l2']:.4f} |",
+          f"| linear map of the current gradient only vs single target, held-out | "
+          f"{metrics['linear_current_gradient_rel_l2']:.4f} |"]
+    r = metrics.get("replicas")
+    if r:
+        R = r["info"]["replicas"]
+        floor = r["dpd_single_noise_rel_l2"] / math.sqrt(R)
+        model = math.sqrt(max(0.0, r["model_vs_replica_mean_rel_l2"] ** 2 - floor ** 2))
+        L += [f"| DPD noise of one target ({R} replicas, same start and gradients) | {r['dpd_single_noise_rel_l2']:.4f} |",
+              f"| ensemble mean vs {R}-replica mean (unseen seeds) | {r['model_vs_replica_mean_rel_l2']:.4f} |",
+              f"| noise left in a {R}-replica mean | {floor:.4f} |",
+              f"| model error with that noise removed in quadrature | {model:.4f} |"]
+    L += ["", f"Mean ensemble spread (scaled units, targets / {STRESS_SCALE}): {h['mean_spread_scaled']:.4f}; "
+          f"target RMS (scaled) {h['rmse_scaled'] / h['rel_l2']:.3f}.", "",
+          "Train MSE (scaled) per epoch, mean over members: " +
+          ", ".join(f"{sum(e) / len(e):.4f}" for e in metrics["epoch_loss"])]
+    with open(path, "w") as f:
+        f.write("\n".join(L) + "\n")
 
 
 def main(argv=None):
@@ -220,8 +271,10 @@ def main(argv=None):
     ap.add_argument("--boxes", type=int, default=4096)
     ap.add_argument("--macro", type=int, default=520)
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--no-augment", action="store_true")
     ap.add_argument("--replica-groups", type=int, default=32)
     ap.add_argument("--replicas", type=int, default=8)
+    ap.add_argument("--summary", default=None, help="also write a markdown summary here")
     args = ap.parse_args(argv)
     import torch
 
@@ -231,7 +284,7 @@ def main(argv=None):
     print(f"generating: {args.boxes} boxes x {args.macro} macro steps", flush=True)
     X, T, box_id, step_id, info = generate(args.boxes, args.macro)
     print(json.dumps(info), flush=True)
-    sur, metrics = train(X, T, box_id, epochs=args.epochs)
+    sur, metrics = train(X, T, box_id, epochs=args.epochs, augment=not args.no_augment)
     metrics["data"] = info
     print(json.dumps({k: v for k, v in metrics.items() if k != "epoch_loss"}), flush=True)
     del X, T
@@ -259,6 +312,10 @@ def main(argv=None):
              n_hidden=256, n_members=len(W), **arrays)
     with open(os.path.join(args.out, "train_metrics.json"), "w") as f:
         json.dump(metrics, f, indent=1)
+    if args.summary:
+        import sys
+
+        write_summary(metrics, args.summary, "python -m paper_2512_13267_amd.train " + " ".join(sys.argv[1:]))
     print("done", flush=True)
 
 

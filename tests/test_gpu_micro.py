@@ -399,3 +399,39 @@ def test_snapshot_restore_returns_boxes_to_saved_state(torch_gpu):
     assert t4 == t5 and np.array_equal(s4[r], s5[r]) and np.array_equal(c4[r], c5[r])
     m.close()
     e.close()
+
+
+def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch_gpu):
+    """Every launch configuration gives the same trajectory bit for bit; the
+    autotuner puts the state and counter back."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.tiny_boxes(4, seed_k=43)
+    G = _grads(torch, wl)
+    for prec, depths in (("fp32", (2, 4, 8)), ("fp64", (2, 4))):
+        ref = None
+        for qd in depths:
+            for drain in sorted({0, qd // 2 if qd > 2 else 0}):
+                for bt in (256, 1024):
+                    print(f"config {prec} qd={qd} drain={drain} bin={bt}", flush=True)
+                    m = micro.from_workload(wl, precision=prec)
+                    m.set_config(queue_depth=qd, drain=drain, bin_threads=bt, graph_chunk=7)
+                    out = m.step(G, 20).cpu().numpy()
+                    s, c, h, st = m.get_state()
+                    if ref is None:
+                        ref = (out, s, c)
+                    else:
+                        assert np.array_equal(out, ref[0]) and np.array_equal(s, ref[1]) and np.array_equal(c, ref[2])
+                    m.close()
+        m = micro.from_workload(wl, precision=prec)
+        m.step(G, 5)
+        s0, c0, h0, t0, f0 = m.get_state(with_forces=True)
+        cfg, ms = m.autotune(G, trial_steps=3)
+        s1, c1, h1, t1, f1 = m.get_state(with_forces=True)
+        assert t1 == t0 and np.array_equal(s0, s1) and np.array_equal(c0, c1) and np.array_equal(f0, f1)
+        assert np.array_equal(h0, h1) and ms > 0 and m.config() == cfg
+        with pytest.raises(_lib.LhmmError):
+            m.set_config(queue_depth=16)
+        with pytest.raises(_lib.LhmmError):
+            m.set_config(queue_depth=2, drain=1)
+        m.close()

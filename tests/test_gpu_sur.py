@@ -229,3 +229,19 @@ def test_targets_blend_and_history_gradient_match_oracle():
     back = torch.zeros((n, 9), dtype=torch.float64, device="cuda")
     sur.history_gradient(ring, 40, back, st, inv_scale=1.0 / 20.0)
     assert np.allclose(back.cpu().numpy(), L, rtol=1e-6, atol=1e-9)
+
+
+def test_augment_matches_oracle():
+    sur = _cuda()
+    st = torch.cuda.current_stream()
+    rng = np.random.default_rng(17)
+    n = 333
+    X = rng.normal(size=(n, 129)).astype(np.float32)
+    T = rng.normal(size=(n, 3)).astype(np.float32)
+    th = rng.uniform(0, 2 * np.pi, size=n).astype(np.float32)
+    mir = (rng.uniform(size=n) < 0.5).astype(np.int32)
+    Xd, Td = torch.from_numpy(X.copy()).cuda(), torch.from_numpy(T.copy()).cuda()
+    sur.augment(Xd, Td, torch.from_numpy(th).cuda(), torch.from_numpy(mir).cuda(), st)
+    Xo, To = mo.augment(X.astype(np.float64), T.astype(np.float64), th.astype(np.float64), mir.astype(bool))
+    assert np.abs(Xd.cpu().numpy() - Xo).max() < 1e-5 * np.abs(Xo).max()
+    assert np.abs(Td.cpu().numpy() - To).max() < 1e-5 * np.abs(To).max()

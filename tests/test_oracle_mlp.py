@@ -154,3 +154,40 @@ def test_targets_and_blend_pins():
     use = np.array([1, 0, 0, 1, 0, 1])
     out = mo.blend(mean, use, sd, 1.0)
     assert np.array_equal(out[use == 1], sd[use == 1])
+
+
+def test_augment_group_pins():
+    rng = np.random.default_rng(16)
+    n = 7
+    X = rng.normal(size=(n, 129))
+    T = rng.normal(size=(n, 3))
+    zero = np.zeros(n)
+    none = np.zeros(n, dtype=bool)
+    # identity and full turn
+    for th in (zero, np.full(n, 2 * math.pi)):
+        X1, T1 = mo.augment(X, T, th, none)
+        assert np.allclose(X1, X, atol=1e-12) and np.allclose(T1, T, atol=1e-12)
+    # two rotations compose; a reflection applied twice is the identity
+    a, b = rng.uniform(0, 6.3, n), rng.uniform(0, 6.3, n)
+    X2, T2 = mo.augment(*mo.augment(X, T, a, none), b, none)
+    X3, T3 = mo.augment(X, T, a + b, none)
+    assert np.allclose(X2, X3) and np.allclose(T2, T3)
+    Xm, Tm = mo.augment(*mo.augment(X, T, zero, ~none), zero, ~none)
+    assert np.allclose(Xm, X) and np.allclose(Tm, T)
+    # a quarter turn maps simple shear u_x = g y to u_y = -g x: L_xy -> -L_yx
+    Xs = np.zeros((1, 129))
+    Xs[0, 1] = 1.0
+    Xq, _ = mo.augment(Xs, np.zeros((1, 3)), np.array([math.pi / 2]), np.array([False]))
+    assert np.allclose(Xq[0, :4], [0.0, 0.0, -1.0, 0.0], atol=1e-12)
+    # invariants: trace and Frobenius norm of every sample and of S; phi kept
+    Xr, Tr = mo.augment(X, T, a, rng.uniform(size=n) < 0.5)
+    for k in range(32):
+        L0, L1 = X[:, 4 * k:4 * k + 4], Xr[:, 4 * k:4 * k + 4]
+        assert np.allclose(L0[:, 0] + L0[:, 3], L1[:, 0] + L1[:, 3])
+        assert np.allclose((L0 ** 2).sum(1), (L1 ** 2).sum(1))
+    assert np.allclose(T[:, 0] + T[:, 2], Tr[:, 0] + Tr[:, 2])
+    assert np.allclose(T[:, 0] ** 2 + 2 * T[:, 1] ** 2 + T[:, 2] ** 2, Tr[:, 0] ** 2 + 2 * Tr[:, 1] ** 2 + Tr[:, 2] ** 2)
+    assert np.array_equal(Xr[:, 128], X[:, 128])
+    # reflection y -> -y flips the sign of every xy / yx component
+    Xf, Tf = mo.augment(X, T, zero, ~none)
+    assert np.allclose(Xf[:, 1:128:4], -X[:, 1:128:4]) and np.allclose(Tf[:, 1], -T[:, 1])
