@@ -37,6 +37,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "lhmm.h"
@@ -906,6 +907,10 @@ struct lhmm_micro {
     bool have_snapshot = false;
     bool have_state = false, forces_valid = false;
     std::map<int, hipGraphExec_t> graphs;
+    // graphs of subset steps, keyed by (boxes, blocks, steps): a shape is
+    // captured the second time it is asked for (history replays repeat it)
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> sub_graphs;
+    std::map<std::tuple<int, int, int>, int> sub_seen;
     Ctx ctx{};
 };
 
@@ -1032,6 +1037,8 @@ void release(lhmm_micro* m) {
     if (m->stream) (void)hipStreamSynchronize(m->stream);
     for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
     m->graphs.clear();
+    for (auto& kv : m->sub_graphs) (void)hipGraphExecDestroy(kv.second);
+    m->sub_graphs.clear();
     void* bufs[] = {m->d_box, m->d_dyn, m->d_flags, m->d_blk_box, m->d_blk_first, m->d_s, m->d_c, m->d_f,
                     m->d_pcell, m->d_cell_start, m->d_cell_pos, m->d_cell_vel, m->d_part_vir, m->d_part_kin,
                     m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_step,
@@ -1048,6 +1055,37 @@ void release(lhmm_micro* m) {
 int sync_engine(lhmm_micro* m) {
     HIPCHK(hipStreamSynchronize(m->stream));
     HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+constexpr size_t MAX_SUB_GRAPHS = 64;
+
+// len steps of the selected boxes: a captured graph for a shape seen before,
+// else eager launches.  The graph reads the selection lists from the fixed
+// device buffers, so any selection of the same shape can replay it.
+int launch_subset_steps(lhmm_micro* m, const Ctx& C, int n_sel, int nblk, int len) {
+    const auto key = std::make_tuple(n_sel, nblk, len);
+    auto it = m->sub_graphs.find(key);
+    if (it == m->sub_graphs.end() && ++m->sub_seen[key] >= 2) {
+        if (m->sub_graphs.size() >= MAX_SUB_GRAPHS) {
+            for (auto& kv : m->sub_graphs) (void)hipGraphExecDestroy(kv.second);
+            m->sub_graphs.clear();
+        }
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < len; ++k) launch_one_step_sel(m, C, n_sel, nblk);
+        HIPCHK(hipStreamEndCapture(m->stream, &g));
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(LHMM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        it = m->sub_graphs.emplace(key, ex).first;
+    }
+    if (it != m->sub_graphs.end()) {
+        HIPCHK(hipGraphLaunch(it->second, m->stream));
+    } else {
+        for (int k = 0; k < len; ++k) launch_one_step_sel(m, C, n_sel, nblk);
+    }
     return LHMM_OK;
 }
 
@@ -1417,6 +1455,9 @@ int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg) {
     HIPCHK(hipStreamSynchronize(m->stream));
     for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
     m->graphs.clear();
+    for (auto& kv : m->sub_graphs) (void)hipGraphExecDestroy(kv.second);
+    m->sub_graphs.clear();
+    m->sub_seen.clear();
     m->cfg = *cfg;
     return LHMM_OK;
 }
@@ -1573,7 +1614,18 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
         launch_force_eval(m);
         m->forces_valid = true;
     }
-    for (int k = 0; k < n_steps; ++k) launch_one_step_sel(m, C, n_sel, nblk);
+    if (m->p.flags & LHMM_OPT_NO_GRAPH) {
+        for (int k = 0; k < n_steps; ++k) launch_one_step_sel(m, C, n_sel, nblk);
+    } else {
+        const int chunk = n_steps < m->cfg.graph_chunk ? n_steps : m->cfg.graph_chunk;
+        int done = 0;
+        while (done < n_steps) {
+            const int len = n_steps - done >= chunk ? chunk : n_steps - done;
+            rc = launch_subset_steps(m, C, n_sel, nblk, len);
+            if (rc != LHMM_OK) return rc;
+            done += len;
+        }
+    }
     k_finalize<<<bg, bt, 0, m->stream>>>(m->ctx, stress_out, m->d_parts, 1.0 / n_steps);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(m->ev_out, m->stream));

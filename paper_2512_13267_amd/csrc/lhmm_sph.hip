@@ -3,9 +3,9 @@
 // lhmm_couple_step).
 //
 // The macro problem is small (10^3-10^4 particles) and double precision:
-// each kernel gives one thread per particle I and loops over all J with the
-// minimum image of the periodic box, which for these sizes costs a few
-// microseconds and keeps every sum in a fixed order.  A step is
+// each kernel gives one wave per particle I; lane l takes J = l, l + 64, ...
+// with the minimum image of the periodic box, and a fixed shuffle tree adds
+// the 64 partial sums, so every sum has a fixed order.  A step is
 //   k_density -> k_accel -> k_kick_drift -> k_density -> k_accel -> k_kick
 //   -> k_gradL
 // (velocity-Verlet, then the micro-domain gradients at the new state).
@@ -20,7 +20,19 @@
 
 namespace {
 
-constexpr int TPB = 128;
+constexpr int TPB = 256;             // threads per block
+constexpr int WPB = TPB / 64;        // particles (waves) per block
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ double pow4(double x) {
+    const double x2 = x * x;
+    return x2 * x2;
+}
 
 struct SphCtx {
     int n, n_mobile, force_mode;  // particles n_mobile .. n-1 are frozen walls
@@ -36,9 +48,9 @@ struct SphCtx {
 __device__ __forceinline__ double kernel_W(double r, double h) {
     const double q = 3.0 * r / h;
     if (q >= 3.0) return 0.0;
-    double w = pow(3.0 - q, 5);
-    if (q < 2.0) w -= 6.0 * pow(2.0 - q, 5);
-    if (q < 1.0) w += 15.0 * pow(1.0 - q, 5);
+    double w = pow4(3.0 - q) * (3.0 - q);
+    if (q < 2.0) w -= 6.0 * pow4(2.0 - q) * (2.0 - q);
+    if (q < 1.0) w += 15.0 * pow4(1.0 - q) * (1.0 - q);
     return 63.0 / (478.0 * M_PI * h * h) * w;
 }
 
@@ -46,9 +58,9 @@ __device__ __forceinline__ double kernel_W(double r, double h) {
 __device__ __forceinline__ double kernel_F(double r, double h) {
     const double q = 3.0 * r / h;
     if (q >= 3.0) return 0.0;
-    double dw = -5.0 * pow(3.0 - q, 4);
-    if (q < 2.0) dw += 30.0 * pow(2.0 - q, 4);
-    if (q < 1.0) dw -= 75.0 * pow(1.0 - q, 4);
+    double dw = -5.0 * pow4(3.0 - q);
+    if (q < 2.0) dw += 30.0 * pow4(2.0 - q);
+    if (q < 1.0) dw -= 75.0 * pow4(1.0 - q);
     return -(63.0 / (478.0 * M_PI * h * h) * dw * 3.0 / h) / r;
 }
 
@@ -57,19 +69,23 @@ __device__ __forceinline__ void min_image(const SphCtx& S, double& dx, double& d
     dy -= S.Ly * rint(dy / S.Ly);
 }
 
-__global__ void k_density(SphCtx S) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= S.n) return;
+__global__ __launch_bounds__(TPB) void k_density(SphCtx S) {
+    const int I = blockIdx.x * WPB + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (I >= S.n) return;  // wave-uniform
     const double xi = S.r[2 * I], yi = S.r[2 * I + 1];
     double s = 0.0;
-    for (int J = 0; J < S.n; ++J) {
+    for (int J = lane; J < S.n; J += 64) {
         double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
         min_image(S, dx, dy);
         s += kernel_W(sqrt(dx * dx + dy * dy), S.h);
     }
-    S.d[I] = s;
-    const double B = S.c * S.c * S.rho0 / 7.0;
-    S.p[I] = B * (pow(S.mass * s / S.rho0, 7) - 1.0) + S.theta * B;
+    s = wave_sum(s);
+    if (lane == 0) {
+        S.d[I] = s;
+        const double B = S.c * S.c * S.rho0 / 7.0;
+        const double x = S.mass * s / S.rho0, x2 = x * x;
+        S.p[I] = B * (x2 * x2 * x2 * x - 1.0) + S.theta * B;
+    }
 }
 
 // polymer stress of particle I: alpha/lambda* x in-plane deviatoric part of
@@ -89,9 +105,9 @@ __device__ __forceinline__ void polymer_stress(const SphCtx& S, const double* si
 }
 
 // Eq. (sph_continuity) divided by the mass, plus the body force
-__global__ void k_accel(SphCtx S, const double* __restrict__ sigma) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= S.n_mobile) return;
+__global__ __launch_bounds__(TPB) void k_accel(SphCtx S, const double* __restrict__ sigma) {
+    const int I = blockIdx.x * WPB + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (I >= S.n_mobile) return;  // wave-uniform
     const double av = 2.0 * S.eta - S.zeta, bv = 4.0 * S.zeta + 2.0 * S.eta;
     const double xi = S.r[2 * I], yi = S.r[2 * I + 1], vxi = S.v[2 * I], vyi = S.v[2 * I + 1];
     const double di = S.d[I], pi_ = S.p[I];
@@ -99,7 +115,7 @@ __global__ void k_accel(SphCtx S, const double* __restrict__ sigma) {
     polymer_stress(S, sigma, I, pxx, pxy, pyy);
     const double i2 = 1.0 / (di * di);
     double fx = 0.0, fy = 0.0;
-    for (int J = 0; J < S.n; ++J) {
+    for (int J = lane; J < S.n; J += 64) {
         if (J == I) continue;
         double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
         min_image(S, dx, dy);
@@ -124,9 +140,13 @@ __global__ void k_accel(SphCtx S, const double* __restrict__ sigma) {
         fx -= (sxx * dx + sxy * dy) * F;
         fy -= (sxy * dx + syy * dy) * F;
     }
-    const double body = (S.force_mode == LHMM_FORCE_UNIFORM || yi >= 0.5 * S.Ly) ? S.F : -S.F;
-    S.acc[2 * I] = fx / S.mass + body;
-    S.acc[2 * I + 1] = fy / S.mass;
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    if (lane == 0) {
+        const double body = (S.force_mode == LHMM_FORCE_UNIFORM || yi >= 0.5 * S.Ly) ? S.F : -S.F;
+        S.acc[2 * I] = fx / S.mass + body;
+        S.acc[2 * I + 1] = fy / S.mass;
+    }
 }
 
 __device__ __forceinline__ double wrap_len(double x, double L) {
@@ -155,16 +175,16 @@ __global__ void k_kick(SphCtx S) {
 
 // Eq. (macro_micro) with 1/d_J: G_ab = d_a v_b; micro gradient
 // L = lambda* x traceless part of G^T (u = L r), 3x3 row-major, zero z.
-__global__ void k_gradL(SphCtx S, double* __restrict__ gradL) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= S.n) return;
+__global__ __launch_bounds__(TPB) void k_gradL(SphCtx S, double* __restrict__ gradL) {
+    const int I = blockIdx.x * WPB + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (I >= S.n) return;  // wave-uniform
     if (I >= S.n_mobile) {
-        for (int k = 0; k < 9; ++k) gradL[9 * I + k] = 0.0;
+        if (lane < 9) gradL[9 * I + lane] = 0.0;
         return;
     }
     const double xi = S.r[2 * I], yi = S.r[2 * I + 1], vxi = S.v[2 * I], vyi = S.v[2 * I + 1];
     double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-    for (int J = 0; J < S.n; ++J) {
+    for (int J = lane; J < S.n; J += 64) {
         if (J == I) continue;
         double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
         min_image(S, dx, dy);
@@ -177,6 +197,11 @@ __global__ void k_gradL(SphCtx S, double* __restrict__ gradL) {
         g2 += F * dy * vx;
         g3 += F * dy * vy;
     }
+    g0 = wave_sum(g0);
+    g1 = wave_sum(g1);
+    g2 = wave_sum(g2);
+    g3 = wave_sum(g3);
+    if (lane != 0) return;
     const double half_tr = 0.5 * (g0 + g3);
     double* o = gradL + 9 * I;
     o[0] = S.lambda_star * (g0 - half_tr);
@@ -209,15 +234,16 @@ void sph_release(lhmm_sph* s) {
 }
 
 void launch_sph_step(lhmm_sph* s, const double* sigma, double* gradL) {
-    const int g = (s->S.n + TPB - 1) / TPB;
+    const int gw = (s->S.n + WPB - 1) / WPB;  // wave per particle
+    const int gt = (s->S.n + TPB - 1) / TPB;  // thread per particle
     hipStream_t st = s->stream;
-    k_density<<<g, TPB, 0, st>>>(s->S);
-    k_accel<<<g, TPB, 0, st>>>(s->S, sigma);
-    k_kick_drift<<<g, TPB, 0, st>>>(s->S);
-    k_density<<<g, TPB, 0, st>>>(s->S);
-    k_accel<<<g, TPB, 0, st>>>(s->S, sigma);
-    k_kick<<<g, TPB, 0, st>>>(s->S);
-    if (gradL) k_gradL<<<g, TPB, 0, st>>>(s->S, gradL);
+    k_density<<<gw, TPB, 0, st>>>(s->S);
+    k_accel<<<gw, TPB, 0, st>>>(s->S, sigma);
+    k_kick_drift<<<gt, TPB, 0, st>>>(s->S);
+    k_density<<<gw, TPB, 0, st>>>(s->S);
+    k_accel<<<gw, TPB, 0, st>>>(s->S, sigma);
+    k_kick<<<gt, TPB, 0, st>>>(s->S);
+    if (gradL) k_gradL<<<gw, TPB, 0, st>>>(s->S, gradL);
 }
 
 }  // namespace
@@ -313,7 +339,7 @@ int lhmm_sph_get_state(lhmm_sph* s, double* r, double* v, double* d) {
     if (v) LHMM_HIPCHK(hipMemcpy(v, s->S.v, 2 * n * sizeof(double), hipMemcpyDeviceToHost));
     if (d) {
         // density at the current positions
-        const int g = (s->S.n + TPB - 1) / TPB;
+        const int g = (s->S.n + WPB - 1) / WPB;
         k_density<<<g, TPB, 0, s->stream>>>(s->S);
         LHMM_HIPCHK(hipGetLastError());
         LHMM_HIPCHK(hipStreamSynchronize(s->stream));

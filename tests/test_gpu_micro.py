@@ -362,6 +362,15 @@ def test_subset_step_equals_full_step_for_selected_boxes(torch_gpu):
             else:
                 assert np.array_equal(s0[r], sb[r]) and np.array_equal(c0[r], cb[r]), (prec, k)
                 assert np.array_equal(h0[k], hb[k]) and not ob[k].any(), (prec, k)
+        # the same selection shape again: the engine replays a captured graph
+        for rep in range(2):
+            oa = a.step(G, 25).cpu().numpy()
+            ob = b.step_subset(G, 25, sel).cpu().numpy()
+        sa, ca, _, _ = a.get_state()
+        sb, cb, _, _ = b.get_state()
+        for k in sel:
+            r = slice(off[k], off[k + 1])
+            assert np.array_equal(sa[r], sb[r]) and np.array_equal(ca[r], cb[r]) and np.array_equal(oa[k], ob[k])
         a.close()
         b.close()
 
