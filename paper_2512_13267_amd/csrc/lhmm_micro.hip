@@ -565,7 +565,7 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 //   normal, force, virial).  A round runs whenever 56 or more lanes have work
 //   or a queue could overflow, and the queues are drained at the end.
 template <typename real, int QD>
-__global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain) {
+__global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain, int prune) {
     using R = Rec<real>;
     using V4 = typename R::T;
     constexpr int NW = BS / 64;
@@ -613,6 +613,29 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
         k2 = pc % n2;
         k1 = (pc / n2) % n1;
         k0 = pc / (n1 * n2);
+    }
+    // Stencil pruning: distances from the particle to the planes bounding
+    // its cell (fractional gap x perpendicular width of the cell); any point
+    // of a neighbour cell across such a plane is at least that far away.  A
+    // row (d0, d1) is skipped when its in-plane lower bound g reaches the
+    // cutoff, and its cells below / above the particle's z cell are scanned
+    // only if they may hold a point within sqrt(rc^2 - g^2).  Bounds are
+    // compared with a 0.1% larger cutoff, so no pair within rc is dropped
+    // and the scan order of the kept candidates is unchanged.
+    real gl0 = 0, gh0 = 0, gl1 = 0, gh1 = 0, zl = 0, zh = 0;
+    const real rcp2 = prune ? (real)(1.002 * C.rc2) : (real)0;
+    if (act && prune) {
+        const int gi = B.off + own_id;
+        const real s0 = s[gi], s1 = s[N + gi], s2 = s[2 * N + gi];
+        const real area = fabs(h00 * h11 - h01 * h10);
+        const real w0 = area / sqrt(h01 * h01 + h11 * h11), w1 = area / sqrt(h00 * h00 + h10 * h10);
+        const real f0 = s0 * (real)n0 - (real)k0, f1 = s1 * (real)n1 - (real)k1, f2 = s2 * (real)n2 - (real)k2;
+        gl0 = fmax(f0, (real)0) * w0 / (real)n0;
+        gh0 = fmax((real)1 - f0, (real)0) * w0 / (real)n0;
+        gl1 = fmax(f1, (real)0) * w1 / (real)n1;
+        gh1 = fmax((real)1 - f1, (real)0) * w1 / (real)n1;
+        zl = fmax(f2, (real)0) * h22 / (real)n2;
+        zh = fmax((real)1 - f2, (real)0) * h22 / (real)n2;
     }
     int qh = 0, qt = 0;  // this lane's queue: popped, pushed
     real fx = 0, fy = 0, fz = 0;
@@ -676,8 +699,18 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
         pz = ri2;
         q = 0;
         qe = 0;
-        if (act) {
-            const int lo = k2 - 1, hi = k2 + 1;
+        int lo = k2 - 1, hi = k2 + 1;
+        bool live = act;
+        if (act && prune) {
+            const real ga = d0 < 0 ? gl0 : (d0 > 0 ? gh0 : (real)0);
+            const real gb = d1 < 0 ? gl1 : (d1 > 0 ? gh1 : (real)0);
+            const real g = fmax(ga, gb);
+            const real zmax2 = rcp2 - g * g;
+            live = zmax2 > (real)0;
+            if (!(zl * zl < zmax2)) lo = k2;
+            if (!(zh * zh < zmax2)) hi = k2;
+        }
+        if (live) {
             if (piece == 0) {
                 q = start[rb + max(lo, 0)];
                 qe = start[rb + min(hi, n2 - 1) + 1];
@@ -927,11 +960,11 @@ void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st) {
 
 template <typename real>
 void launch_forces(lhmm_micro* m, const Ctx& C, int nblk, int step_offset, hipStream_t st) {
-    const int drain = m->cfg.drain;
+    const int drain = m->cfg.drain, prune = m->cfg.prune;
     switch (m->cfg.queue_depth) {
-        case 2: k_forces<real, 2><<<nblk, BS, 0, st>>>(C, step_offset, drain); break;
-        case 4: k_forces<real, 4><<<nblk, BS, 0, st>>>(C, step_offset, drain); break;
-        default: k_forces<real, sizeof(real) == 4 ? 8 : 4><<<nblk, BS, 0, st>>>(C, step_offset, drain); break;
+        case 2: k_forces<real, 2><<<nblk, BS, 0, st>>>(C, step_offset, drain, prune); break;
+        case 4: k_forces<real, 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, prune); break;
+        default: k_forces<real, sizeof(real) == 4 ? 8 : 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, prune); break;
     }
 }
 
@@ -1168,6 +1201,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->cfg.drain = m->cfg.queue_depth / 2;
     m->cfg.bin_threads = BIN_THREADS_MAX;
     m->cfg.graph_chunk = GRAPH_CHUNK;
+    m->cfg.prune = 0;
     m->real_size = p->precision == LHMM_FP64 ? sizeof(double) : sizeof(float);
     m->user_stream = (hipStream_t)stream;
 
@@ -1452,6 +1486,7 @@ int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg) {
     if (cfg->bin_threads != 256 && cfg->bin_threads != 512 && cfg->bin_threads != 1024)
         return fail(LHMM_ERR_ARG, "bin_threads must be 256, 512 or 1024");
     if (cfg->graph_chunk < 1 || cfg->graph_chunk > 1000) return fail(LHMM_ERR_ARG, "graph_chunk must be 1..1000");
+    if (cfg->prune != 0 && cfg->prune != 1) return fail(LHMM_ERR_ARG, "prune must be 0 or 1");
     HIPCHK(hipStreamSynchronize(m->stream));
     for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
     m->graphs.clear();
@@ -1537,7 +1572,7 @@ int lhmm_micro_autotune(lhmm_micro* m, const double* gradL, int32_t trial_steps,
         *ms = el / trial_steps;
         return load() == hipSuccess ? LHMM_OK : fail(LHMM_ERR_HIP, "state restore failed");
     };
-    // coordinate search: force-kernel queue, then binning workgroup, then graph chunk
+    // coordinate search: force-kernel queue, binning workgroup, pruning, graph chunk
     lhmm_micro_config cur = m->cfg;
     double cur_ms = 0.0;
     rc = trial(cur, &cur_ms);
@@ -1565,6 +1600,17 @@ int lhmm_micro_autotune(lhmm_micro* m, const double* gradL, int32_t trial_steps,
         if (rc != LHMM_OK || bt == cur.bin_threads) continue;
         lhmm_micro_config c = cur;
         c.bin_threads = bt;
+        double ms = 0.0;
+        rc = trial(c, &ms);
+        if (rc == LHMM_OK && ms < cur_ms) {
+            cur = c;
+            cur_ms = ms;
+        }
+    }
+    for (int pr : {0, 1}) {
+        if (rc != LHMM_OK || pr == cur.prune) continue;
+        lhmm_micro_config c = cur;
+        c.prune = pr;
         double ms = 0.0;
         rc = trial(c, &ms);
         if (rc == LHMM_OK && ms < cur_ms) {

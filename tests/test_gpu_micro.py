@@ -411,7 +411,8 @@ def test_snapshot_restore_returns_boxes_to_saved_state(torch_gpu):
 
 
 def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch_gpu):
-    """Every launch configuration gives the same trajectory bit for bit; the
+    """Every launch configuration (queue depth, drain, binning workgroup,
+    graph chunk, stencil pruning) gives the same trajectory bit for bit; the
     autotuner puts the state and counter back."""
     torch = torch_gpu
     _lib, inputs, micro = _mod()
@@ -421,10 +422,10 @@ def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch
         ref = None
         for qd in depths:
             for drain in sorted({0, qd // 2 if qd > 2 else 0}):
-                for bt in (256, 1024):
-                    print(f"config {prec} qd={qd} drain={drain} bin={bt}", flush=True)
+                for bt, prune in ((256, 1), (1024, 0), (1024, 1)):
+                    print(f"config {prec} qd={qd} drain={drain} bin={bt} prune={prune}", flush=True)
                     m = micro.from_workload(wl, precision=prec)
-                    m.set_config(queue_depth=qd, drain=drain, bin_threads=bt, graph_chunk=7)
+                    m.set_config(queue_depth=qd, drain=drain, bin_threads=bt, graph_chunk=7, prune=prune)
                     out = m.step(G, 20).cpu().numpy()
                     s, c, h, st = m.get_state()
                     if ref is None:
@@ -444,3 +445,23 @@ def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch
         with pytest.raises(_lib.LhmmError):
             m.set_config(queue_depth=2, drain=1)
         m.close()
+
+
+def test_pruning_keeps_every_pair_on_the_full_batch(torch_gpu):
+    """The benchmark batch (sheared, extended and rotated cells of all
+    sizes): forces and pair counts with and without stencil pruning are
+    identical after 30 steps."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.batch()
+    G = _grads(torch, wl)
+    res = []
+    for prune in (0, 1):
+        m = micro.from_workload(wl, precision="fp32")
+        m.set_config(prune=prune)
+        out = m.step(G, 30).cpu().numpy()
+        s, c, h, st, f = m.get_state(with_forces=True)
+        res.append((out, s, c, f, m.pair_counts()))
+        m.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
