@@ -142,6 +142,48 @@ def bench_pac(macro_steps: int, avg: int):
     return out
 
 
+def bench_surrogate(steps: int = 50):
+    """Training step (5 members 129-256-256-3, batch 4096, the training
+    configuration) and in-loop inference (3572 rows), timed with device
+    synchronisation; matrix-core rate against the BF16 dense peak."""
+    import torch
+
+    from paper_2512_13267_amd import surrogate
+
+    E, nin, nh, nout, B = 5, 129, 256, 3, 4096
+    s = surrogate.Surrogate(surrogate.init_members(E, nin, nh, nout, seed=1), nin, nh, nout, max_batch=B)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(7)
+    X = torch.randn((B, nin), generator=g).cuda()
+    T = torch.randn((B, nout), generator=g).cuda()
+    for _ in range(5):
+        s.train_step(X, T, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.train_step(X, T, 1e-4)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) / steps * 1e3
+    Xi = X[:3572].contiguous()
+    Y = s.forward(Xi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.forward(Xi, out=Y)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) / steps * 1e3
+    s.close()
+    kp, hp = 160, nh  # padded input width, hidden width; outputs padded to 32
+    fwd_flops = lambda b: 2.0 * E * b * (kp * hp + hp * hp + hp * 32)
+    train_flops = fwd_flops(B) + 2.0 * E * B * (hp * 32 * 2 + hp * hp * 2 + kp * hp)
+    peak = 2.5e15
+    return {"train_step_ms": train_ms, "train_TFLOPs": train_flops / (train_ms * 1e-3) / 1e12,
+            "train_mfma_frac": train_flops / (train_ms * 1e-3) / peak,
+            "forward_3572_ms": fwd_ms, "forward_TFLOPs": fwd_flops(3584) / (fwd_ms * 1e-3) / 1e12,
+            "peak_TFLOPs_bf16_dense": peak / 1e12,
+            "shape": "5 members 129-256-256-3 (padded 160-256-256-32), batch 4096 train / 3572 inference"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +198,7 @@ def main():
     ap.add_argument("--pac-steps", type=int, default=500,
                     help="macro steps of each cylinder-array run (all-DPD and surrogate; 0 skips them)")
     ap.add_argument("--pac-avg", type=int, default=100, help="macro steps of the stress average")
+    ap.add_argument("--no-surrogate-timing", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2^27 floats (512 MiB read, 512 MiB written) five "
                          "times, to scale the HBM byte counters of a profiler run")
@@ -248,6 +291,9 @@ def main():
         print("[bench] coupled LHMM run", file=sys.stderr, flush=True)
         rec["lhmm"] = bench_lhmm(args.lhmm_steps)
         print(f"[bench] {rec['lhmm']['value']:.2f} macro steps/s", file=sys.stderr, flush=True)
+    if not args.no_surrogate_timing:
+        print("[bench] surrogate training and inference timing", file=sys.stderr, flush=True)
+        rec["surrogate"] = bench_surrogate()
     if args.pac_steps > 0:
         print("[bench] cylinder-array LHMM: all-DPD and surrogate", file=sys.stderr, flush=True)
         rec["lhmm_pac"] = bench_pac(args.pac_steps, min(args.pac_avg, args.pac_steps))

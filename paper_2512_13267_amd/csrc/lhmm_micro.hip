@@ -460,12 +460,19 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
 }
 
 // One workgroup per box: counting sort by cell in LDS, writing each
-// particle's record (position, local index) in cell order; every cell's
-// records are then sorted by index so all later sums have a fixed order.
+// particle's records (position, local index) and (velocity, local index) in
+// cell order, sorted by index inside every cell so all later sums have a
+// fixed order.  LDS (dynamic): lds_cells counters, then room for lds_parts
+// particle indices.  A box with at most lds_parts particles is sorted as
+// indices in LDS and its records are written once, coalesced; a larger box
+// scatters records to global memory and sorts them there.  Both give the
+// same records in the same order.
 template <typename real, int BIN_THREADS>
-__global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, int lds_parts) {
     using R = Rec<real>;
-    __shared__ int cnt[MAX_CELLS_PER_BOX];
+    extern __shared__ int lds[];
+    int* cnt = lds;
+    int* lidx = lds + lds_cells;
     __shared__ int wsum[BIN_THREADS / 64];
     const int b = C.sel ? C.sel[blockIdx.x] : (int)blockIdx.x;
     const BoxInfo B = C.box[b];
@@ -506,10 +513,38 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
     if (threadIdx.x == 0) start[ncell] = carry;
     __syncthreads();
     typename R::T* rec = (typename R::T*)C.cell_pos + B.off;
+    typename R::T* vel = (typename R::T*)C.cell_vel + B.off;
     const real* s = (const real*)C.s;
+    const real* c = (const real*)C.c;
     const int N = C.n_total;
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
     const real h22 = (real)D.h[8];
+    if (B.n <= lds_parts) {
+        for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) lidx[atomicAdd(&cnt[pc[k]], 1)] = k;
+        __syncthreads();
+        // cnt[k] now ends cell k; sort every cell's indices (a few entries)
+        for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) {
+            const int q0 = k == 0 ? 0 : cnt[k - 1], q1 = cnt[k];
+            for (int q = q0 + 1; q < q1; ++q) {
+                const int key = lidx[q];
+                int r = q - 1;
+                while (r >= q0 && lidx[r] > key) {
+                    lidx[r + 1] = lidx[r];
+                    --r;
+                }
+                lidx[r + 1] = key;
+            }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < B.n; q += BIN_THREADS) {
+            const int k = lidx[q];
+            const int g = B.off + k;
+            const real s0 = s[g], s1 = s[N + g], s2 = s[2 * N + g];
+            rec[q] = R::make(h00 * s0 + h01 * s1, h10 * s0 + h11 * s1, h22 * s2, k);
+            vel[q] = R::make(c[g], c[N + g], c[2 * N + g], k);
+        }
+        return;
+    }
     for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) {
         const int pos = atomicAdd(&cnt[pc[k]], 1);
         const int g = B.off + k;
@@ -533,8 +568,6 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C) {
     }
     __threadfence_block();
     __syncthreads();
-    typename R::T* vel = (typename R::T*)C.cell_vel + B.off;
-    const real* c = (const real*)C.c;
     for (int q = threadIdx.x; q < B.n; q += BIN_THREADS) {
         const int g = B.off + R::id(rec[q]);
         vel[q] = R::make(c[g], c[N + g], c[2 * N + g], g - B.off);
@@ -911,6 +944,7 @@ __global__ void k_finalize(Ctx C, double* __restrict__ stress_out, double* __res
 struct lhmm_micro {
     lhmm_params p{};
     lhmm_micro_config cfg{};
+    int bin_lds_cells = 0, bin_lds_parts = 0;  // dynamic LDS of the binning kernel (ints)
     int n_boxes = 0, n_blocks = 0, precision = LHMM_FP32;
     long long n_total = 0;
     size_t real_size = 4;
@@ -951,10 +985,12 @@ namespace {
 
 template <typename real>
 void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st) {
+    const int lc = m->bin_lds_cells, lp = m->bin_lds_parts;
+    const size_t bytes = sizeof(int) * ((size_t)lc + (size_t)lp);
     switch (m->cfg.bin_threads) {
-        case 256: k_bin_box<real, 256><<<nbox, 256, 0, st>>>(C); break;
-        case 512: k_bin_box<real, 512><<<nbox, 512, 0, st>>>(C); break;
-        default: k_bin_box<real, 1024><<<nbox, 1024, 0, st>>>(C); break;
+        case 256: k_bin_box<real, 256><<<nbox, 256, bytes, st>>>(C, lc, lp); break;
+        case 512: k_bin_box<real, 512><<<nbox, 512, bytes, st>>>(C, lc, lp); break;
+        default: k_bin_box<real, 1024><<<nbox, 1024, bytes, st>>>(C, lc, lp); break;
     }
 }
 
@@ -1254,6 +1290,17 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     }
     m->n_total = off;
     m->n_blocks = blk_off;
+    {
+        // binning LDS: every box's cell counters, and indices for boxes that fit in 64 KiB
+        int max_cells = 0, max_n = 0;
+        for (const BoxInfo& B : m->box) {
+            max_cells = std::max(max_cells, B.cell_cap + 1);
+            max_n = std::max(max_n, B.n);
+        }
+        const int budget = (int)((65536 - 64 * (int)sizeof(int)) / sizeof(int));  // less the scan's wave sums
+        m->bin_lds_cells = max_cells;
+        m->bin_lds_parts = std::max(0, std::min(max_n, budget - max_cells));
+    }
     const size_t N = (size_t)m->n_total;
     int rc = LHMM_OK;
 #define ALLOC(ptr, cnt)                     \

@@ -3,9 +3,13 @@
 // lhmm_couple_step).
 //
 // The macro problem is small (10^3-10^4 particles) and double precision:
-// each kernel gives one wave per particle I; lane l takes J = l, l + 64, ...
-// with the minimum image of the periodic box, and a fixed shuffle tree adds
-// the 64 partial sums, so every sum has a fixed order.  A step is
+// each kernel gives one wave per particle I; lane l takes candidates l,
+// l + 64, ... of a fixed enumeration (the particles of the 3 x 3 cells of
+// side >= h around I, cell by cell and by index inside a cell; every
+// particle when the periodic box holds fewer than 3 cells per side) with the
+// minimum image of the periodic box, and a fixed shuffle tree adds the 64
+// partial sums, so every sum has a fixed order.  The cells are rebuilt by a
+// one-workgroup counting sort before every density pass.  A step is
 //   k_density -> k_accel -> k_kick_drift -> k_density -> k_accel -> k_kick
 //   -> k_gradL
 // (velocity-Verlet, then the micro-domain gradients at the new state).
@@ -36,6 +40,9 @@ __device__ __forceinline__ double pow4(double x) {
 
 struct SphCtx {
     int n, n_mobile, force_mode;  // particles n_mobile .. n-1 are frozen walls
+    int ncx, ncy;                 // cell grid (0: all pairs)
+    int* cstart;                  // ncx * ncy + 1 cell offsets into cidx
+    int* cidx;                    // particle indices in cell order
     double rho0, eta, zeta, c, theta, F, h, dt, mass, Lx, Ly, lambda_star, alpha;
     double* r;    // n x 2
     double* v;    // n x 2
@@ -69,12 +76,117 @@ __device__ __forceinline__ void min_image(const SphCtx& S, double& dx, double& d
     dy -= S.Ly * rint(dy / S.Ly);
 }
 
+__device__ __forceinline__ int cell_x(const SphCtx& S, double x) {
+    return min(max((int)(x * (double)S.ncx / S.Lx), 0), S.ncx - 1);
+}
+__device__ __forceinline__ int cell_y(const SphCtx& S, double y) {
+    return min(max((int)(y * (double)S.ncy / S.Ly), 0), S.ncy - 1);
+}
+
+// The candidates of a particle at (x, y) in their fixed enumeration.
+struct Nbr {
+    int total;
+    int base[9], pre[10];
+    const int* cidx;
+    int cells;
+    __device__ int get(int t) const {
+        if (!cells) return t;
+        int k = 0;
+        while (t >= pre[k + 1]) ++k;
+        return cidx[base[k] + t - pre[k]];
+    }
+};
+
+__device__ __forceinline__ Nbr neighbours(const SphCtx& S, double x, double y) {
+    Nbr nb;
+    nb.cidx = S.cidx;
+    nb.cells = S.ncx > 0;
+    if (!nb.cells) {
+        nb.total = S.n;
+        return nb;
+    }
+    const int cx = cell_x(S, x), cy = cell_y(S, y);
+    int acc = 0;
+    for (int k = 0; k < 9; ++k) {
+        const int ax = (cx + k / 3 - 1 + S.ncx) % S.ncx, ay = (cy + k % 3 - 1 + S.ncy) % S.ncy;
+        const int c = ax * S.ncy + ay;
+        nb.pre[k] = acc;
+        nb.base[k] = S.cstart[c];
+        acc += S.cstart[c + 1] - S.cstart[c];
+    }
+    nb.pre[9] = acc;
+    nb.total = acc;
+    return nb;
+}
+
+// Counting sort of all particles into the cell grid, one workgroup; indices
+// sorted inside every cell.  Dynamic LDS: ncx * ncy counters + n indices.
+__global__ __launch_bounds__(1024) void k_sph_bin(SphCtx S) {
+    extern __shared__ int lds[];
+    __shared__ int wsum[16];
+    const int ncell = S.ncx * S.ncy;
+    int* cnt = lds;
+    int* lidx = lds + ncell;
+    for (int k = threadIdx.x; k < ncell; k += 1024) cnt[k] = 0;
+    __syncthreads();
+    for (int I = threadIdx.x; I < S.n; I += 1024)
+        atomicAdd(&cnt[cell_x(S, S.r[2 * I]) * S.ncy + cell_y(S, S.r[2 * I + 1])], 1);
+    __syncthreads();
+    int carry = 0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int base = 0; base < ncell; base += 1024) {
+        const int k = base + (int)threadIdx.x;
+        const int v = k < ncell ? cnt[k] : 0;
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wv) before += wsum[w];
+            total += wsum[w];
+        }
+        const int excl = carry + before + x - v;
+        __syncthreads();
+        if (k < ncell) {
+            S.cstart[k] = excl;
+            cnt[k] = excl;
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) S.cstart[ncell] = carry;
+    __syncthreads();
+    for (int I = threadIdx.x; I < S.n; I += 1024)
+        lidx[atomicAdd(&cnt[cell_x(S, S.r[2 * I]) * S.ncy + cell_y(S, S.r[2 * I + 1])], 1)] = I;
+    __syncthreads();
+    for (int k = threadIdx.x; k < ncell; k += 1024) {
+        const int q0 = k == 0 ? 0 : cnt[k - 1], q1 = cnt[k];
+        for (int q = q0 + 1; q < q1; ++q) {
+            const int key = lidx[q];
+            int r = q - 1;
+            while (r >= q0 && lidx[r] > key) {
+                lidx[r + 1] = lidx[r];
+                --r;
+            }
+            lidx[r + 1] = key;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < S.n; q += 1024) S.cidx[q] = lidx[q];
+}
+
 __global__ __launch_bounds__(TPB) void k_density(SphCtx S) {
     const int I = blockIdx.x * WPB + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (I >= S.n) return;  // wave-uniform
     const double xi = S.r[2 * I], yi = S.r[2 * I + 1];
+    const Nbr nb = neighbours(S, xi, yi);
     double s = 0.0;
-    for (int J = lane; J < S.n; J += 64) {
+    for (int t = lane; t < nb.total; t += 64) {
+        const int J = nb.get(t);
         double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
         min_image(S, dx, dy);
         s += kernel_W(sqrt(dx * dx + dy * dy), S.h);
@@ -114,8 +226,10 @@ __global__ __launch_bounds__(TPB) void k_accel(SphCtx S, const double* __restric
     double pxx, pxy, pyy;
     polymer_stress(S, sigma, I, pxx, pxy, pyy);
     const double i2 = 1.0 / (di * di);
+    const Nbr nb = neighbours(S, xi, yi);
     double fx = 0.0, fy = 0.0;
-    for (int J = lane; J < S.n; J += 64) {
+    for (int t = lane; t < nb.total; t += 64) {
+        const int J = nb.get(t);
         if (J == I) continue;
         double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
         min_image(S, dx, dy);
@@ -184,7 +298,9 @@ __global__ __launch_bounds__(TPB) void k_gradL(SphCtx S, double* __restrict__ gr
     }
     const double xi = S.r[2 * I], yi = S.r[2 * I + 1], vxi = S.v[2 * I], vyi = S.v[2 * I + 1];
     double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-    for (int J = lane; J < S.n; J += 64) {
+    const Nbr nb = neighbours(S, xi, yi);
+    for (int t = lane; t < nb.total; t += 64) {
+        const int J = nb.get(t);
         if (J == I) continue;
         double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
         min_image(S, dx, dy);
@@ -222,7 +338,7 @@ struct lhmm_sph {
     hipStream_t stream = nullptr;
     double* d_sigma = nullptr;  // n x 6, micro stresses of the last interval (zero at start)
     double* d_gradL = nullptr;  // n x 9
-    void* bufs[7] = {};
+    void* bufs[9] = {};
 };
 
 namespace {
@@ -233,14 +349,24 @@ void sph_release(lhmm_sph* s) {
         if (b) (void)hipFree(b);
 }
 
+// cell lists (when the grid is in use) and densities at the current positions
+void launch_density(lhmm_sph* s) {
+    const int gw = (s->S.n + WPB - 1) / WPB;
+    if (s->S.ncx > 0) {
+        const size_t bytes = sizeof(int) * ((size_t)s->S.ncx * s->S.ncy + (size_t)s->S.n);
+        k_sph_bin<<<1, 1024, bytes, s->stream>>>(s->S);
+    }
+    k_density<<<gw, TPB, 0, s->stream>>>(s->S);
+}
+
 void launch_sph_step(lhmm_sph* s, const double* sigma, double* gradL) {
     const int gw = (s->S.n + WPB - 1) / WPB;  // wave per particle
     const int gt = (s->S.n + TPB - 1) / TPB;  // thread per particle
     hipStream_t st = s->stream;
-    k_density<<<gw, TPB, 0, st>>>(s->S);
+    launch_density(s);
     k_accel<<<gw, TPB, 0, st>>>(s->S, sigma);
     k_kick_drift<<<gt, TPB, 0, st>>>(s->S);
-    k_density<<<gw, TPB, 0, st>>>(s->S);
+    launch_density(s);
     k_accel<<<gw, TPB, 0, st>>>(s->S, sigma);
     k_kick<<<gt, TPB, 0, st>>>(s->S);
     if (gradL) k_gradL<<<gw, TPB, 0, st>>>(s->S, gradL);
@@ -289,9 +415,16 @@ int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const
     S.force_mode = p->force_mode;
     S.rho0 = p->rho0; S.eta = p->eta; S.zeta = p->zeta; S.c = p->c; S.theta = p->theta; S.F = p->F; S.h = p->h;
     S.dt = p->dt; S.mass = p->mass; S.Lx = p->Lx; S.Ly = p->Ly; S.lambda_star = p->lambda_star; S.alpha = p->alpha;
-    const size_t sizes[7] = {2 * (size_t)n, 2 * (size_t)n, (size_t)n, (size_t)n, 2 * (size_t)n, 6 * (size_t)n,
-                             9 * (size_t)n};
-    for (int k = 0; k < 7; ++k) {
+    // cell grid of side >= h: at least 3 x 3 cells, and counters plus indices in 64 KiB of LDS
+    {
+        const int gx = (int)std::floor(p->Lx / p->h), gy = (int)std::floor(p->Ly / p->h);
+        const bool fits = gx >= 3 && gy >= 3 && (long long)gx * gy + n <= (65536 - 64) / 4;
+        S.ncx = fits ? gx : 0;
+        S.ncy = fits ? gy : 0;
+    }
+    const size_t sizes[9] = {2 * (size_t)n, 2 * (size_t)n, (size_t)n, (size_t)n, 2 * (size_t)n, 6 * (size_t)n,
+                             9 * (size_t)n, (size_t)S.ncx * S.ncy + 1, (size_t)n};
+    for (int k = 0; k < 9; ++k) {
         if (hipMalloc(&s->bufs[k], sizes[k] * sizeof(double)) != hipSuccess) {
             sph_release(s);
             delete s;
@@ -305,6 +438,8 @@ int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const
     S.acc = (double*)s->bufs[4];
     s->d_sigma = (double*)s->bufs[5];
     s->d_gradL = (double*)s->bufs[6];
+    S.cstart = (int*)s->bufs[7];
+    S.cidx = (int*)s->bufs[8];
     auto init = [&]() -> int {
         LHMM_HIPCHK(hipMemcpy(S.r, r0, 2 * (size_t)n * sizeof(double), hipMemcpyHostToDevice));
         LHMM_HIPCHK(hipMemcpy(S.v, v0, 2 * (size_t)n * sizeof(double), hipMemcpyHostToDevice));
@@ -339,8 +474,7 @@ int lhmm_sph_get_state(lhmm_sph* s, double* r, double* v, double* d) {
     if (v) LHMM_HIPCHK(hipMemcpy(v, s->S.v, 2 * n * sizeof(double), hipMemcpyDeviceToHost));
     if (d) {
         // density at the current positions
-        const int g = (s->S.n + WPB - 1) / WPB;
-        k_density<<<g, TPB, 0, s->stream>>>(s->S);
+        launch_density(s);
         LHMM_HIPCHK(hipGetLastError());
         LHMM_HIPCHK(hipStreamSynchronize(s->stream));
         LHMM_HIPCHK(hipMemcpy(d, s->S.d, n * sizeof(double), hipMemcpyDeviceToHost));

@@ -5,7 +5,8 @@
 //
 // Every product is one NT GEMM  C[M x N] = A[M x K] * B[N x K]^T  on BF16
 // operands with FP32 accumulation (v_mfma_f32_32x32x16_bf16), one wave per
-// 32 x 32 output tile, batched over the ensemble members (grid z).  Operand
+// 32 x 32 x NT output tile (NT = 4, 2 or 1 as N allows), batched over the
+// ensemble members (grid z).  Operand
 // fragments are loaded straight from global memory as 16-byte vectors (lane
 // l takes row l%32 and k-slice 8*(l/32) .. +7 of A and of B), so every
 // operand is kept in the layout whose reduction index is contiguous:
@@ -60,44 +61,78 @@ struct Gemm {
     long sC, sCt;       // member strides of the M x N and N x M outputs
 };
 
-template <int EPI>
+// One wave computes NT adjacent 32 x 32 output tiles of one member; the A
+// fragment of a k-slice is shared by the NT products, and the fragments of
+// the next k-slice are loaded while the current ones are multiplied.  The
+// accumulation order over k is the same for every NT.
+template <int EPI, int NT>
 __global__ __launch_bounds__(64) void k_gemm_nt(Gemm g) {
     const int e = blockIdx.z;
-    const int n0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
+    const int n0 = blockIdx.x * 32 * NT, m0 = blockIdx.y * 32;
     const int l = threadIdx.x;
     const bf16* A = g.A + e * g.sA + (long)(m0 + (l & 31)) * g.lda + 8 * (l >> 5);
     const bf16* B = g.B + e * g.sB + (long)(n0 + (l & 31)) * g.ldb + 8 * (l >> 5);
-    floatx16 acc = {};
-    for (int k = 0; k < g.K; k += 16) {
-        const bf16x8 a = *(const bf16x8*)(A + k);
-        const bf16x8 b = *(const bf16x8*)(B + k);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-    }
-    const int col = n0 + (l & 31);
-    const long cbase = e * g.sC, tbase = e * g.sCt;
-    float bias = 0.0f;
-    if (EPI == EPI_BIAS_F32 || EPI == EPI_BIAS_GELU) bias = g.bias[e * g.sBias + col];
+    const long bstep = 32L * g.ldb;
+    floatx16 acc[NT];
+    bf16x8 b[NT];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int row = m0 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
-        const long idx = cbase + (long)row * g.N + col;
-        const float c = acc[v];
-        if (EPI == EPI_F32) {
-            g.Cf[idx] = c;
-        } else if (EPI == EPI_BIAS_F32) {
-            g.Cf[idx] = c + bias;
-        } else if (EPI == EPI_BIAS_GELU) {
-            const float z = c + bias;
-            g.Cf[idx] = z;
-            const bf16 h = (bf16)gelu_f(z);
-            g.Cb[idx] = h;
-            g.Ct[tbase + (long)col * g.ldt + row] = h;
-        } else {  // EPI_GELU_GRAD
-            const float dz = c * gelu_grad_f(g.Zin[idx]);
-            g.Cf[idx] = dz;
-            const bf16 hb = (bf16)dz;
-            g.Cb[idx] = hb;
-            g.Ct[tbase + (long)col * g.ldt + row] = hb;
+    for (int j = 0; j < NT; ++j) {
+        acc[j] = floatx16{};
+        b[j] = *(const bf16x8*)(B + j * bstep);
+    }
+    bf16x8 a = *(const bf16x8*)A;
+    const int K = g.K;
+    for (int k = 16; k < K; k += 16) {
+        const bf16x8 an = *(const bf16x8*)(A + k);
+        bf16x8 bn[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bn[j] = *(const bf16x8*)(B + j * bstep + k);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[j], acc[j], 0, 0, 0);
+        a = an;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) b[j] = bn[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[j], acc[j], 0, 0, 0);
+    const long cbase = e * g.sC, tbase = e * g.sCt;
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int col = n0 + 32 * j + (l & 31);
+        float bias = 0.0f;
+        if (EPI == EPI_BIAS_F32 || EPI == EPI_BIAS_GELU) bias = g.bias[e * g.sBias + col];
+        // value v of the tile sits at row 8 (v / 4) + 4 (l / 32) + v % 4: each
+        // group of four is four consecutive rows, stored transposed at once
+#pragma unroll
+        for (int vg = 0; vg < 4; ++vg) {
+            const int row0 = m0 + 8 * vg + 4 * (l >> 5);
+            bf16x4 tq;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int row = row0 + u;
+                const long idx = cbase + (long)row * g.N + col;
+                const float c = acc[j][4 * vg + u];
+                if (EPI == EPI_F32) {
+                    g.Cf[idx] = c;
+                } else if (EPI == EPI_BIAS_F32) {
+                    g.Cf[idx] = c + bias;
+                } else if (EPI == EPI_BIAS_GELU) {
+                    const float z = c + bias;
+                    const bf16 h = (bf16)gelu_f(z);
+                    g.Cb[idx] = h;
+                    if (g.Cf) g.Cf[idx] = z;  // the pre-activation and H^T only feed backward
+                    tq[u] = h;
+                } else {  // EPI_GELU_GRAD
+                    const float dz = c * gelu_grad_f(g.Zin[idx]);
+                    g.Cf[idx] = dz;
+                    const bf16 hb = (bf16)dz;
+                    g.Cb[idx] = hb;
+                    tq[u] = hb;
+                }
+            }
+            if (EPI == EPI_GELU_GRAD || (EPI == EPI_BIAS_GELU && g.Cf))
+                *(bf16x4*)(g.Ct + tbase + (long)col * g.ldt + row0) = tq;
         }
     }
 }
@@ -111,7 +146,7 @@ __global__ void k_inputs(const float* __restrict__ x, int B, int nin, int Bp, in
     const int r = (int)(t / nin_p), c = (int)(t % nin_p);
     const bf16 v = (bf16)((r < B && c < nin) ? x[(long)r * nin + c] : 0.0f);
     X[t] = v;
-    Xt[(long)c * Bp + r] = v;
+    if (Xt) Xt[(long)c * Bp + r] = v;
 }
 
 // MSE gradient and per-block loss partials for every member:
@@ -385,30 +420,37 @@ void sur_release(lhmm_sur* s) {
 
 template <int EPI>
 void gemm(lhmm_sur* s, const Gemm& g) {
-    dim3 grid(g.N / 32, g.M / 32, s->E);
-    k_gemm_nt<EPI><<<grid, 64, 0, s->stream>>>(g);
+    if (g.N % 128 == 0) {
+        k_gemm_nt<EPI, 4><<<dim3(g.N / 128, g.M / 32, s->E), 64, 0, s->stream>>>(g);
+    } else if (g.N % 64 == 0) {
+        k_gemm_nt<EPI, 2><<<dim3(g.N / 64, g.M / 32, s->E), 64, 0, s->stream>>>(g);
+    } else {
+        k_gemm_nt<EPI, 1><<<dim3(g.N / 32, g.M / 32, s->E), 64, 0, s->stream>>>(g);
+    }
 }
 
 long szW1(const lhmm_sur* s) { return (long)s->nin_p * s->nh; }
 long szW2(const lhmm_sur* s) { return (long)s->nh * s->nh; }
 long szW3(const lhmm_sur* s) { return (long)s->nh * s->nout_p; }
 
-// forward of every member on the first Bp rows of s->X / s->Xt
-void forward(lhmm_sur* s, int Bp) {
+// forward of every member on the first Bp rows of s->X / s->Xt; `train`
+// also keeps the pre-activations and transposed activations for backward
+void forward(lhmm_sur* s, int Bp, bool train) {
     Gemm g{};
     // layer 1: Z1 = X W1 + b1
     g.A = s->X; g.lda = s->nin_p; g.sA = 0;
     g.B = s->W1t; g.ldb = s->nin_p; g.sB = szW1(s);
     g.M = Bp; g.N = s->nh; g.K = s->nin_p;
     g.bias = s->b1; g.sBias = s->nh;
-    g.Cf = s->Z1; g.Cb = s->H1; g.Ct = s->H1t; g.ldt = Bp; g.sC = (long)s->Bmax * s->nh; g.sCt = g.sC;
+    g.Cf = train ? s->Z1 : nullptr; g.Cb = s->H1; g.Ct = s->H1t; g.ldt = Bp; g.sC = (long)s->Bmax * s->nh;
+    g.sCt = g.sC;
     gemm<EPI_BIAS_GELU>(s, g);
     // layer 2
     g.A = s->H1; g.lda = s->nh; g.sA = (long)s->Bmax * s->nh;
     g.B = s->W2t; g.ldb = s->nh; g.sB = szW2(s);
     g.M = Bp; g.N = s->nh; g.K = s->nh;
     g.bias = s->b2; g.sBias = s->nh;
-    g.Cf = s->Z2; g.Cb = s->H2; g.Ct = s->H2t; g.ldt = Bp;
+    g.Cf = train ? s->Z2 : nullptr; g.Cb = s->H2; g.Ct = s->H2t; g.ldt = Bp;
     gemm<EPI_BIAS_GELU>(s, g);
     // layer 3: Y = H2 W3 + b3
     g.A = s->H2; g.lda = s->nh; g.sA = (long)s->Bmax * s->nh;
@@ -590,9 +632,10 @@ int lhmm_sur_get_grads(lhmm_sur* s, float* grads) {
 }
 
 // B rows of f32 features (device, B x n_in) into the padded BF16 inputs
-static int load_inputs(lhmm_sur* s, const float* X, int B, int Bp) {
+// (and their transpose, for training)
+static int load_inputs(lhmm_sur* s, const float* X, int B, int Bp, bool train) {
     const long n = (long)Bp * s->nin_p;
-    k_inputs<<<(n + 255) / 256, 256, 0, s->stream>>>(X, B, s->nin, Bp, s->nin_p, s->X, s->Xt);
+    k_inputs<<<(n + 255) / 256, 256, 0, s->stream>>>(X, B, s->nin, Bp, s->nin_p, s->X, train ? s->Xt : nullptr);
     LHMM_HIPCHK(hipGetLastError());
     return LHMM_OK;
 }
@@ -604,9 +647,9 @@ int lhmm_sur_train_step(lhmm_sur* s, const float* X, const float* T, int32_t B, 
     if (!(lr >= 0.0f) || !std::isfinite(lr)) return lhmm_fail(LHMM_ERR_ARG, "bad learning rate");
     const int Bp = round_up(B, 32), E = s->E, nh = s->nh, no = s->nout_p;
     const long Bm = s->Bmax;
-    int rc = load_inputs(s, X, B, Bp);
+    int rc = load_inputs(s, X, B, Bp, true);
     if (rc != LHMM_OK) return rc;
-    forward(s, Bp);
+    forward(s, Bp, true);
     // dY and loss
     const long nY = (long)Bp * no;
     const int nparts = (int)((nY + 255) / 256);
@@ -679,9 +722,9 @@ int lhmm_sur_forward(lhmm_sur* s, const float* X, int32_t B, float* Y) {
     if (!s || !X || !Y) return lhmm_fail(LHMM_ERR_ARG, "null argument");
     if (B < 1 || B > s->Bmax) return lhmm_fail(LHMM_ERR_ARG, "batch %d outside 1..%d", B, s->Bmax);
     const int Bp = round_up(B, 32);
-    int rc = load_inputs(s, X, B, Bp);
+    int rc = load_inputs(s, X, B, Bp, false);
     if (rc != LHMM_OK) return rc;
-    forward(s, Bp);
+    forward(s, Bp, false);
     const long n = (long)s->E * B * s->nout;
     k_outputs<<<(n + 255) / 256, 256, 0, s->stream>>>(s->Y, (long)s->Bmax * s->nout_p, s->nout_p, s->E, B, s->nout, Y);
     LHMM_HIPCHK(hipGetLastError());
