@@ -19,6 +19,7 @@
 // rows to a multiple of 32 (padded rows carry zero gradient).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -59,6 +60,7 @@ struct Gemm {
     bf16* Ct;           // bf16 transposed output [N x M] (ld = ldt)
     int ldt;
     long sC, sCt;       // member strides of the M x N and N x M outputs
+    int ksplit, kchunk;  // EPI_F32: grid z = member x k-chunk, partial sums per chunk
 };
 
 // One wave computes NT adjacent 32 x 32 output tiles of one member; the A
@@ -67,11 +69,15 @@ struct Gemm {
 // accumulation order over k is the same for every NT.
 template <int EPI, int NT>
 __global__ __launch_bounds__(64) void k_gemm_nt(Gemm g) {
-    const int e = blockIdx.z;
+    // with a k-split, z = member x ksplit + chunk and the output at z x sC is
+    // the chunk's partial product
+    const int z = blockIdx.z;
+    const int e = z / g.ksplit, kc = z % g.ksplit;
     const int n0 = blockIdx.x * 32 * NT, m0 = blockIdx.y * 32;
     const int l = threadIdx.x;
-    const bf16* A = g.A + e * g.sA + (long)(m0 + (l & 31)) * g.lda + 8 * (l >> 5);
-    const bf16* B = g.B + e * g.sB + (long)(n0 + (l & 31)) * g.ldb + 8 * (l >> 5);
+    const int koff = kc * g.kchunk;
+    const bf16* A = g.A + e * g.sA + (long)(m0 + (l & 31)) * g.lda + 8 * (l >> 5) + koff;
+    const bf16* B = g.B + e * g.sB + (long)(n0 + (l & 31)) * g.ldb + 8 * (l >> 5) + koff;
     const long bstep = 32L * g.ldb;
     floatx16 acc[NT];
     bf16x8 b[NT];
@@ -81,7 +87,7 @@ __global__ __launch_bounds__(64) void k_gemm_nt(Gemm g) {
         b[j] = *(const bf16x8*)(B + j * bstep);
     }
     bf16x8 a = *(const bf16x8*)A;
-    const int K = g.K;
+    const int K = min(g.kchunk, g.K - koff);
     for (int k = 16; k < K; k += 16) {
         const bf16x8 an = *(const bf16x8*)(A + k);
         bf16x8 bn[NT];
@@ -95,7 +101,7 @@ __global__ __launch_bounds__(64) void k_gemm_nt(Gemm g) {
     }
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[j], acc[j], 0, 0, 0);
-    const long cbase = e * g.sC, tbase = e * g.sCt;
+    const long cbase = z * g.sC, tbase = e * g.sCt;
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
@@ -135,6 +141,20 @@ __global__ __launch_bounds__(64) void k_gemm_nt(Gemm g) {
                 *(bf16x4*)(g.Ct + tbase + (long)col * g.ldt + row0) = tq;
         }
     }
+}
+
+// sum the k-chunk partials of every member in chunk order:
+// out[e][i] = sum_c part[(e ksplit + c) MN + i]
+__global__ void k_splitk_sum(const float* __restrict__ part, int ksplit, long MN, int E, float* __restrict__ out,
+                             long ostride) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)E * MN) return;
+    const int e = (int)(t / MN);
+    const long i = t % MN;
+    const float* p = part + (long)e * ksplit * MN + i;
+    float s = 0.0f;
+    for (int c = 0; c < ksplit; ++c) s += p[(long)c * MN];
+    out[e * ostride + i] = s;
 }
 
 // caller features (B x n_in, f32) -> padded BF16 inputs X [Bp x nin_p] and
@@ -398,6 +418,7 @@ struct lhmm_sur {
     // activations
     bf16 *X, *Xt, *H1, *H1t, *H2, *H2t, *dY, *dYt, *dZ2, *dZ2t, *dZ1, *dZ1t;
     float *Z1, *Z2, *Y, *dYf, *dZ1f, *dZ2f, *part;
+    float* part_k = nullptr;  // k-split partials of the weight gradients
 };
 
 namespace {
@@ -418,15 +439,38 @@ void sur_release(lhmm_sur* s) {
     s->bufs.clear();
 }
 
+constexpr int KCHUNK = 512;  // k-split chunk of the weight-gradient products
+
 template <int EPI>
-void gemm(lhmm_sur* s, const Gemm& g) {
+void launch_gemm(lhmm_sur* s, const Gemm& g, int zdim) {
     if (g.N % 128 == 0) {
-        k_gemm_nt<EPI, 4><<<dim3(g.N / 128, g.M / 32, s->E), 64, 0, s->stream>>>(g);
+        k_gemm_nt<EPI, 4><<<dim3(g.N / 128, g.M / 32, zdim), 64, 0, s->stream>>>(g);
     } else if (g.N % 64 == 0) {
-        k_gemm_nt<EPI, 2><<<dim3(g.N / 64, g.M / 32, s->E), 64, 0, s->stream>>>(g);
+        k_gemm_nt<EPI, 2><<<dim3(g.N / 64, g.M / 32, zdim), 64, 0, s->stream>>>(g);
     } else {
-        k_gemm_nt<EPI, 1><<<dim3(g.N / 32, g.M / 32, s->E), 64, 0, s->stream>>>(g);
+        k_gemm_nt<EPI, 1><<<dim3(g.N / 32, g.M / 32, zdim), 64, 0, s->stream>>>(g);
     }
+}
+
+template <int EPI>
+void gemm(lhmm_sur* s, Gemm g) {
+    g.ksplit = 1;
+    g.kchunk = g.K;
+    if (EPI == EPI_F32 && g.K >= 2 * KCHUNK && s->part_k) {
+        // weight gradients (K = batch): k-chunks in parallel, then a fixed-order sum
+        const int ks = (g.K + KCHUNK - 1) / KCHUNK;
+        float* out = g.Cf;
+        const long ostride = g.sC;
+        g.ksplit = ks;
+        g.kchunk = KCHUNK;
+        g.Cf = s->part_k;
+        g.sC = (long)g.M * g.N;
+        launch_gemm<EPI>(s, g, s->E * ks);
+        const long n = (long)s->E * g.M * g.N;
+        k_splitk_sum<<<(n + 255) / 256, 256, 0, s->stream>>>(s->part_k, ks, (long)g.M * g.N, s->E, out, ostride);
+        return;
+    }
+    launch_gemm<EPI>(s, g, s->E);
 }
 
 long szW1(const lhmm_sur* s) { return (long)s->nin_p * s->nh; }
@@ -526,6 +570,10 @@ int lhmm_sur_create(const lhmm_sur_params* p, const float* weights, void* stream
     rc = rc ? rc : sur_alloc(s, &s->dY, E * Bm * no);
     rc = rc ? rc : sur_alloc(s, &s->dYt, E * Bm * no);
     rc = rc ? rc : sur_alloc(s, &s->part, E * (Bm * no / 256 + 1));
+    if (Bm >= 2 * KCHUNK) {
+        const long mn = std::max(std::max(w1, w2), w3);
+        rc = rc ? rc : sur_alloc(s, &s->part_k, E * ((Bm + KCHUNK - 1) / KCHUNK) * mn);
+    }
     if (rc == LHMM_OK) rc = lhmm_sur_set_weights(s, weights);
     if (rc != LHMM_OK) {
         sur_release(s);

@@ -74,13 +74,15 @@ def test_forward_matches_oracle(E, nin, nh, nout, B):
     s.close()
 
 
-@pytest.mark.parametrize("E,nin,nh,nout,B", [(3, 37, 64, 3, 77), (5, 129, 256, 3, 300)])
+@pytest.mark.parametrize("E,nin,nh,nout,B", [(3, 37, 64, 3, 77), (5, 129, 256, 3, 300), (2, 129, 128, 3, 1500)])
 def test_gradients_and_loss_match_oracle(E, nin, nh, nout, B):
+    """The last case has batch >= 1024: the weight gradients are summed over
+    three k-chunks (512, 512, 480 rows)."""
     sur = _cuda()
     print(f"grads E={E} nin={nin} nh={nh} nout={nout} B={B}", flush=True)
     M = _members(E, nin, nh, nout, seed=30 + E)
     X, T = _data(B, nin, nout, seed=40 + B)
-    s = sur.Surrogate(M, nin, nh, nout, max_batch=512)
+    s = sur.Surrogate(M, nin, nh, nout, max_batch=max(512, B))
     loss = torch.zeros(E, dtype=torch.float32, device="cuda")
     s.train_step(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), 0.0, loss)
     G = s.get_grads()
