@@ -160,10 +160,14 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
  * every sum keeps its order, so all configurations give bit-identical
  * trajectories.
  *   queue_depth: per-lane neighbour queue of the pair-force kernel
- *                (2, 4, 8 in FP32; 2, 4 in FP64);
+ *                (2, 4, 8, 16 in FP32; 2, 4 in FP64);
  *   drain:       evaluation rounds run until every queue holds at most this
- *                many neighbours (0 .. queue_depth - 2: a search iteration
- *                adds up to two before the queues are checked again);
+ *                many neighbours (0 .. queue_depth - u, where a search
+ *                iteration tests u = 4, 2, 1 records per lane for depths
+ *                >= 8, 4, 2 before the queues are checked again);
+ *   busy_lanes:  the search also stops, and rounds also continue, while at
+ *                least this many of a wave's 64 lanes hold a neighbour
+ *                (1 .. 64; 65 turns the rule off);
  *   bin_threads: threads of the per-box binning workgroup (256, 512, 1024);
  *   graph_chunk: micro steps per captured HIP graph (1 .. 1000);
  *   prune:       1 skips stencil cells that lie provably beyond the cutoff
@@ -172,20 +176,21 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
 typedef struct {
     int32_t queue_depth;
     int32_t drain;
+    int32_t busy_lanes;
     int32_t bin_threads;
     int32_t graph_chunk;
     int32_t prune;
 } lhmm_micro_config;
 
 /* Set / read the launch parameters (defaults: depth 8 in FP32, 4 in FP64;
- * drain depth/2; 1024 binning threads; 50-step graphs; no pruning: with
+ * drain depth/2; busy rule off; 1024 binning threads; 50-step graphs; no pruning: with
  * cells barely wider than the cutoff it skips little and costs more).  Set waits for the
  * engine and drops its captured graphs.  Errors: ARG. */
 int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg);
 int lhmm_micro_get_config(lhmm_micro* m, lhmm_micro_config* cfg);
 
 /* Choose the launch parameters for the loaded boxes by timing: a coordinate
- * search over (queue_depth, drain), then bin_threads, prune, graph_chunk,
+ * search over (queue_depth, drain, busy_lanes), then bin_threads, prune, graph_chunk,
  * each candidate timed over trial_steps steps (after trial_steps warm-up
  * steps) under gradL (DEVICE n_boxes x 9) with HIP events.  The particle
  * state, cells, flags and random-force counter are put back after every

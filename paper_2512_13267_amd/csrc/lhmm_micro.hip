@@ -597,11 +597,15 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 //   pair (relative velocity including the streaming difference L d, Philox
 //   normal, force, virial).  A round runs whenever 56 or more lanes have work
 //   or a queue could overflow, and the queues are drained at the end.
+// records tested per lane and search iteration for a queue of depth QD
+__host__ __device__ constexpr int scan_unroll(int qd) { return qd >= 8 ? 4 : (qd >= 4 ? 2 : 1); }
+
 template <typename real, int QD>
-__global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain, int prune) {
+__global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain, int busy, int prune) {
     using R = Rec<real>;
     using V4 = typename R::T;
     constexpr int NW = BS / 64;
+    constexpr int SU = scan_unroll(QD);
     __shared__ V4 qbuf[QD][NW][64];                 // (dx, dy, dz, cell-order position of j)
     __shared__ double red[13 * NW];
 
@@ -774,23 +778,28 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
                 set_range();
                 continue;
             }
-            const bool v0ok = q < qe, v1ok = q + 1 < qe;
-            // out-of-range lanes read record 0 (always present) and discard it
-            const V4 v0 = rec[v0ok ? q : 0];
-            const V4 v1 = rec[v1ok ? q + 1 : 0];
-            push(v0ok, v0, q, bx, by, pz);
-            push(v1ok, v1, q + 1, bx, by, pz);
-            q += 2;
-            if (__ballot(qt - qh > QD - 2) != 0ull) break;
+            // SU records per lane per iteration, all loads issued before the
+            // first test; out-of-range lanes read record 0 (always present)
+            // and discard it
+            V4 cand[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) cand[u] = rec[q + u < qe ? q + u : 0];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) push(q + u < qe, cand[u], q + u, bx, by, pz);
+            q += SU;
+            // evaluate when a queue may not take SU more, or when enough
+            // lanes hold a neighbour for a well-filled round
+            if (__ballot(qt - qh > QD - SU) != 0ull || __popcll(__ballot(qt > qh)) >= busy) break;
         }
         if (!scanning) {
             while (__ballot(qt > qh) != 0ull) round();
             break;
         }
-        // evaluate until every queue holds at most `drain` entries
+        // evaluate until every queue holds at most `drain` entries and fewer
+        // than `busy` lanes hold one
         do {
             round();
-        } while (__ballot(qt - qh > drain) != 0ull);
+        } while (__ballot(qt - qh > drain) != 0ull || __popcll(__ballot(qt > qh)) >= busy);
     }
 
     real wf[6] = {0, 0, 0, 0, 0, 0};
@@ -996,11 +1005,12 @@ void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st) {
 
 template <typename real>
 void launch_forces(lhmm_micro* m, const Ctx& C, int nblk, int step_offset, hipStream_t st) {
-    const int drain = m->cfg.drain, prune = m->cfg.prune;
+    const int drain = m->cfg.drain, busy = m->cfg.busy_lanes, prune = m->cfg.prune;
     switch (m->cfg.queue_depth) {
-        case 2: k_forces<real, 2><<<nblk, BS, 0, st>>>(C, step_offset, drain, prune); break;
-        case 4: k_forces<real, 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, prune); break;
-        default: k_forces<real, sizeof(real) == 4 ? 8 : 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, prune); break;
+        case 2: k_forces<real, 2><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
+        case 4: k_forces<real, 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
+        case 16: k_forces<real, sizeof(real) == 4 ? 16 : 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
+        default: k_forces<real, sizeof(real) == 4 ? 8 : 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
     }
 }
 
@@ -1235,6 +1245,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->precision = p->precision;
     m->cfg.queue_depth = p->precision == LHMM_FP64 ? 4 : 8;
     m->cfg.drain = m->cfg.queue_depth / 2;
+    m->cfg.busy_lanes = 65;
     m->cfg.bin_threads = BIN_THREADS_MAX;
     m->cfg.graph_chunk = GRAPH_CHUNK;
     m->cfg.prune = 0;
@@ -1525,11 +1536,15 @@ int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg) {
     g_err.clear();
     if (!m || !cfg) return fail(LHMM_ERR_ARG, "null argument");
     const int qd = cfg->queue_depth;
-    const bool qd_ok = m->precision == LHMM_FP64 ? (qd == 2 || qd == 4) : (qd == 2 || qd == 4 || qd == 8);
+    const bool qd_ok =
+        m->precision == LHMM_FP64 ? (qd == 2 || qd == 4) : (qd == 2 || qd == 4 || qd == 8 || qd == 16);
     if (!qd_ok) return fail(LHMM_ERR_ARG, "queue_depth %d not available at this precision", qd);
-    // a scan iteration pushes up to two neighbours per lane before it checks
-    // the queues, so a lane may hold at most qd - 2 when scanning resumes
-    if (cfg->drain < 0 || cfg->drain > qd - 2) return fail(LHMM_ERR_ARG, "drain must be in 0..%d", qd - 2);
+    // a search iteration pushes up to scan_unroll(qd) neighbours per lane
+    // before it checks the queues, so a lane may hold at most qd - that many
+    // when the search resumes
+    const int dmax = qd - scan_unroll(qd);
+    if (cfg->drain < 0 || cfg->drain > dmax) return fail(LHMM_ERR_ARG, "drain must be in 0..%d", dmax);
+    if (cfg->busy_lanes < 1 || cfg->busy_lanes > 65) return fail(LHMM_ERR_ARG, "busy_lanes must be in 1..65");
     if (cfg->bin_threads != 256 && cfg->bin_threads != 512 && cfg->bin_threads != 1024)
         return fail(LHMM_ERR_ARG, "bin_threads must be 256, 512 or 1024");
     if (cfg->graph_chunk < 1 || cfg->graph_chunk > 1000) return fail(LHMM_ERR_ARG, "graph_chunk must be 1..1000");
@@ -1623,17 +1638,20 @@ int lhmm_micro_autotune(lhmm_micro* m, const double* gradL, int32_t trial_steps,
     lhmm_micro_config cur = m->cfg;
     double cur_ms = 0.0;
     rc = trial(cur, &cur_ms);
-    const int qds32[] = {2, 4, 8}, qds64[] = {2, 4};
+    const int qds32[] = {4, 8, 16}, qds64[] = {2, 4};
     const int* qds = m->precision == LHMM_FP64 ? qds64 : qds32;
     const int nq = m->precision == LHMM_FP64 ? 2 : 3;
     for (int iq = 0; rc == LHMM_OK && iq < nq; ++iq) {
         const int qd = qds[iq];
-        const int drains[2] = {0, qd / 2 <= qd - 2 ? qd / 2 : 0};
-        for (int d : drains) {
+        // (drain, busy): drain to half / no busy rule, or rounds driven by busy lanes
+        const int dmax = qd - scan_unroll(qd);
+        const int cand[4][2] = {{qd / 2 <= dmax ? qd / 2 : dmax, 65}, {dmax, 48}, {dmax, 56}, {0, 65}};
+        for (const auto& dc : cand) {
             lhmm_micro_config c = cur;
             c.queue_depth = qd;
-            c.drain = d;
-            if (c.queue_depth == cur.queue_depth && c.drain == cur.drain) continue;
+            c.drain = dc[0];
+            c.busy_lanes = dc[1];
+            if (c.queue_depth == cur.queue_depth && c.drain == cur.drain && c.busy_lanes == cur.busy_lanes) continue;
             double ms = 0.0;
             rc = trial(c, &ms);
             if (rc != LHMM_OK) break;

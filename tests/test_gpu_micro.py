@@ -418,14 +418,16 @@ def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch
     _lib, inputs, micro = _mod()
     wl = inputs.tiny_boxes(4, seed_k=43)
     G = _grads(torch, wl)
-    for prec, depths in (("fp32", (2, 4, 8)), ("fp64", (2, 4))):
+    for prec, depths in (("fp32", (2, 4, 8, 16)), ("fp64", (2, 4))):
         ref = None
         for qd in depths:
-            for drain in sorted({0, qd // 2 if qd > 2 else 0}):
-                for bt, prune in ((256, 1), (1024, 0), (1024, 1)):
-                    print(f"config {prec} qd={qd} drain={drain} bin={bt} prune={prune}", flush=True)
+            dmax = qd - (4 if qd >= 8 else (2 if qd >= 4 else 1))  # depth less the records per search step
+            for drain, busy in sorted({(0, 65), (min(qd // 2, dmax), 65), (dmax, 48)}):
+                for bt, prune in ((256, 1), (1024, 0)):
+                    print(f"config {prec} qd={qd} drain={drain} busy={busy} bin={bt} prune={prune}", flush=True)
                     m = micro.from_workload(wl, precision=prec)
-                    m.set_config(queue_depth=qd, drain=drain, bin_threads=bt, graph_chunk=7, prune=prune)
+                    m.set_config(queue_depth=qd, drain=drain, busy_lanes=busy, bin_threads=bt, graph_chunk=7,
+                                 prune=prune)
                     out = m.step(G, 20).cpu().numpy()
                     s, c, h, st = m.get_state()
                     if ref is None:
@@ -441,9 +443,11 @@ def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch
         assert t1 == t0 and np.array_equal(s0, s1) and np.array_equal(c0, c1) and np.array_equal(f0, f1)
         assert np.array_equal(h0, h1) and ms > 0 and m.config() == cfg
         with pytest.raises(_lib.LhmmError):
-            m.set_config(queue_depth=16)
+            m.set_config(queue_depth=32)
         with pytest.raises(_lib.LhmmError):
-            m.set_config(queue_depth=2, drain=1)
+            m.set_config(queue_depth=2, drain=2)
+        with pytest.raises(_lib.LhmmError):
+            m.set_config(queue_depth=8, drain=5)
         m.close()
 
 
