@@ -172,7 +172,10 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
  *   graph_chunk: micro steps per captured HIP graph (1 .. 1000);
  *   prune:       1 skips stencil cells that lie provably beyond the cutoff
  *                (the accepted pairs and their order are unchanged), 0
- *                scans the full 27-cell stencil. */
+ *                scans the full 27-cell stencil;
+ *   fuse_bin:    1 runs the cell step and the half kick and drift inside the
+ *                per-box binning workgroup (two launches fewer per step;
+ *                lhmm_micro_time then reports their time under binning). */
 typedef struct {
     int32_t queue_depth;
     int32_t drain;
@@ -180,17 +183,19 @@ typedef struct {
     int32_t bin_threads;
     int32_t graph_chunk;
     int32_t prune;
+    int32_t fuse_bin;
 } lhmm_micro_config;
 
 /* Set / read the launch parameters (defaults: depth 8 in FP32, 4 in FP64;
- * drain depth/2; busy rule off; 1024 binning threads; 50-step graphs; no pruning: with
+ * drain depth/2; busy rule off; 1024 binning threads; fused binning;
+ * 50-step graphs; no pruning: with
  * cells barely wider than the cutoff it skips little and costs more).  Set waits for the
  * engine and drops its captured graphs.  Errors: ARG. */
 int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg);
 int lhmm_micro_get_config(lhmm_micro* m, lhmm_micro_config* cfg);
 
 /* Choose the launch parameters for the loaded boxes by timing: a coordinate
- * search over (queue_depth, drain, busy_lanes), then bin_threads, prune, graph_chunk,
+ * search over (queue_depth, drain, busy_lanes), then bin_threads, fuse_bin, prune, graph_chunk,
  * each candidate timed over trial_steps steps (after trial_steps warm-up
  * steps) under gradL (DEVICE n_boxes x 9) with HIP events.  The particle
  * state, cells, flags and random-force counter are put back after every

@@ -364,10 +364,15 @@ __global__ void k_zero_acc(Ctx C) {
 
 // One thread per box.  advance = 1: mid-step inverse, deformation and
 // reduction of this step; advance = 0: grid for the current cell only.
+__device__ void cell_step_box(const Ctx& C, int b, int advance);
+
 __global__ void k_cell_step(Ctx C, int advance) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (C.sel ? C.n_sel : C.n_boxes)) return;
-    const int b = C.sel ? C.sel[q] : q;
+    cell_step_box(C, C.sel ? C.sel[q] : q, advance);
+}
+
+__device__ void cell_step_box(const Ctx& C, int b, int advance) {
     BoxDyn& D = C.dyn[b];
     double h[9];
     for (int k = 0; k < 9; ++k) h[k] = D.h[k];
@@ -421,14 +426,10 @@ __device__ __forceinline__ real wrap01(real x) {
     return x >= (real)1 ? (real)0 : x;
 }
 
+// Half kick, drift in fractional coordinates, remap after a reduction,
+// wrap, and the particle's cell; returns the cell.
 template <typename real>
-__global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
-    const int blk = C.blk_list ? C.blk_list[blockIdx.x] : (int)blockIdx.x;
-    const int b = C.blk_box[blk];
-    const BoxInfo B = C.box[b];
-    const int i = C.blk_first[blk] + (int)threadIdx.x;
-    if (i >= B.off + B.n) return;
-    const BoxDyn& D = C.dyn[b];
+__device__ __forceinline__ int kick_drift_particle(const Ctx& C, const BoxDyn& D, int i, int advance) {
     const int N = C.n_total;
     real* s = (real*)C.s;
     real* c = (real*)C.c;
@@ -456,7 +457,19 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
         s0 = wrap01(s0); s1 = wrap01(s1); s2 = wrap01(s2);
         s[i] = s0; s[N + i] = s1; s[2 * N + i] = s2;
     }
-    C.pcell[i] = cell_of(s0, s1, s2, D.nc);
+    const int cell = cell_of(s0, s1, s2, D.nc);
+    C.pcell[i] = cell;
+    return cell;
+}
+
+template <typename real>
+__global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
+    const int blk = C.blk_list ? C.blk_list[blockIdx.x] : (int)blockIdx.x;
+    const int b = C.blk_box[blk];
+    const BoxInfo B = C.box[b];
+    const int i = C.blk_first[blk] + (int)threadIdx.x;
+    if (i >= B.off + B.n) return;
+    kick_drift_particle<real>(C, C.dyn[b], i, advance);
 }
 
 // One workgroup per box: counting sort by cell in LDS, writing each
@@ -467,8 +480,12 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
 // indices in LDS and its records are written once, coalesced; a larger box
 // scatters records to global memory and sorts them there.  Both give the
 // same records in the same order.
+//
+// fuse >= 0: the workgroup first runs the box's cell step and the half kick
+// and drift of its particles (advance = fuse), counting cells as it goes;
+// fuse < 0: k_cell_step and k_kick_drift have run.
 template <typename real, int BIN_THREADS>
-__global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, int lds_parts) {
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, int lds_parts, int fuse) {
     using R = Rec<real>;
     extern __shared__ int lds[];
     int* cnt = lds;
@@ -476,12 +493,33 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     __shared__ int wsum[BIN_THREADS / 64];
     const int b = C.sel ? C.sel[blockIdx.x] : (int)blockIdx.x;
     const BoxInfo B = C.box[b];
+    if (fuse >= 0) {
+        if (threadIdx.x == 0) cell_step_box(C, b, fuse);
+        __threadfence_block();
+        __syncthreads();
+    }
     const BoxDyn& D = C.dyn[b];
     const int ncell = D.nc[0] * D.nc[1] * D.nc[2];
     for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) cnt[k] = 0;
     __syncthreads();
     const int* pc = C.pcell + B.off;
-    for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) atomicAdd(&cnt[pc[k]], 1);
+    if (fuse >= 0) {
+        // four particles per thread and pass: independent loads in flight
+        for (int k0 = threadIdx.x; k0 < B.n; k0 += 4 * BIN_THREADS) {
+            int cell[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + u * BIN_THREADS;
+                cell[u] = k < B.n ? kick_drift_particle<real>(C, D, B.off + k, fuse) : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (cell[u] >= 0) atomicAdd(&cnt[cell[u]], 1);
+        }
+        __threadfence_block();
+    } else {
+        for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) atomicAdd(&cnt[pc[k]], 1);
+    }
     __syncthreads();
     // exclusive scan of cnt[0 .. ncell) in chunks of BIN_THREADS
     int* start = C.cell_start + B.cell_off;
@@ -993,13 +1031,13 @@ struct lhmm_micro {
 namespace {
 
 template <typename real>
-void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st) {
+void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse) {
     const int lc = m->bin_lds_cells, lp = m->bin_lds_parts;
     const size_t bytes = sizeof(int) * ((size_t)lc + (size_t)lp);
     switch (m->cfg.bin_threads) {
-        case 256: k_bin_box<real, 256><<<nbox, 256, bytes, st>>>(C, lc, lp); break;
-        case 512: k_bin_box<real, 512><<<nbox, 512, bytes, st>>>(C, lc, lp); break;
-        default: k_bin_box<real, 1024><<<nbox, 1024, bytes, st>>>(C, lc, lp); break;
+        case 256: k_bin_box<real, 256><<<nbox, 256, bytes, st>>>(C, lc, lp, fuse); break;
+        case 512: k_bin_box<real, 512><<<nbox, 512, bytes, st>>>(C, lc, lp, fuse); break;
+        default: k_bin_box<real, 1024><<<nbox, 1024, bytes, st>>>(C, lc, lp, fuse); break;
     }
 }
 
@@ -1020,9 +1058,13 @@ template <typename real>
 void launch_step_kernels(lhmm_micro* m, const Ctx& C, int nbox, int nblk, int step_offset, bool advance,
                          bool full_step) {
     const int bt = 256, bg = (nbox + bt - 1) / bt;
-    k_cell_step<<<bg, bt, 0, m->stream>>>(C, advance ? 1 : 0);
-    k_kick_drift<real><<<nblk, BS, 0, m->stream>>>(C, advance ? 1 : 0);
-    launch_bin<real>(m, C, nbox, m->stream);
+    if (m->cfg.fuse_bin) {
+        launch_bin<real>(m, C, nbox, m->stream, advance ? 1 : 0);
+    } else {
+        k_cell_step<<<bg, bt, 0, m->stream>>>(C, advance ? 1 : 0);
+        k_kick_drift<real><<<nblk, BS, 0, m->stream>>>(C, advance ? 1 : 0);
+        launch_bin<real>(m, C, nbox, m->stream, -1);
+    }
     launch_forces<real>(m, C, nblk, step_offset, m->stream);
     if (full_step) {
         k_kick2<real><<<nblk, BS, 0, m->stream>>>(C);
@@ -1036,14 +1078,16 @@ void launch_step_timed(lhmm_micro* m, hipEvent_t* ev) {
     const Ctx& C = m->ctx;
     const int bt = 256, bg = (m->n_boxes + bt - 1) / bt;
     hipStream_t st = m->stream;
+    // with the fused binning kernel the cell step and kick-drift pairs time nothing
+    const bool fused = m->cfg.fuse_bin != 0;
     (void)hipEventRecord(ev[0], st);
-    k_cell_step<<<bg, bt, 0, st>>>(C, 1);
+    if (!fused) k_cell_step<<<bg, bt, 0, st>>>(C, 1);
     (void)hipEventRecord(ev[1], st);
     (void)hipEventRecord(ev[2], st);
-    k_kick_drift<real><<<m->n_blocks, BS, 0, st>>>(C, 1);
+    if (!fused) k_kick_drift<real><<<m->n_blocks, BS, 0, st>>>(C, 1);
     (void)hipEventRecord(ev[3], st);
     (void)hipEventRecord(ev[4], st);
-    launch_bin<real>(m, C, m->n_boxes, st);
+    launch_bin<real>(m, C, m->n_boxes, st, fused ? 1 : -1);
     (void)hipEventRecord(ev[5], st);
     (void)hipEventRecord(ev[6], st);
     launch_forces<real>(m, C, m->n_blocks, 1, st);
@@ -1249,6 +1293,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->cfg.bin_threads = BIN_THREADS_MAX;
     m->cfg.graph_chunk = GRAPH_CHUNK;
     m->cfg.prune = 0;
+    m->cfg.fuse_bin = 1;
     m->real_size = p->precision == LHMM_FP64 ? sizeof(double) : sizeof(float);
     m->user_stream = (hipStream_t)stream;
 
@@ -1549,6 +1594,7 @@ int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg) {
         return fail(LHMM_ERR_ARG, "bin_threads must be 256, 512 or 1024");
     if (cfg->graph_chunk < 1 || cfg->graph_chunk > 1000) return fail(LHMM_ERR_ARG, "graph_chunk must be 1..1000");
     if (cfg->prune != 0 && cfg->prune != 1) return fail(LHMM_ERR_ARG, "prune must be 0 or 1");
+    if (cfg->fuse_bin != 0 && cfg->fuse_bin != 1) return fail(LHMM_ERR_ARG, "fuse_bin must be 0 or 1");
     HIPCHK(hipStreamSynchronize(m->stream));
     for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
     m->graphs.clear();
@@ -1665,6 +1711,17 @@ int lhmm_micro_autotune(lhmm_micro* m, const double* gradL, int32_t trial_steps,
         if (rc != LHMM_OK || bt == cur.bin_threads) continue;
         lhmm_micro_config c = cur;
         c.bin_threads = bt;
+        double ms = 0.0;
+        rc = trial(c, &ms);
+        if (rc == LHMM_OK && ms < cur_ms) {
+            cur = c;
+            cur_ms = ms;
+        }
+    }
+    for (int fb : {0, 1}) {
+        if (rc != LHMM_OK || fb == cur.fuse_bin) continue;
+        lhmm_micro_config c = cur;
+        c.fuse_bin = fb;
         double ms = 0.0;
         rc = trial(c, &ms);
         if (rc == LHMM_OK && ms < cur_ms) {

@@ -411,9 +411,9 @@ def test_snapshot_restore_returns_boxes_to_saved_state(torch_gpu):
 
 
 def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch_gpu):
-    """Every launch configuration (queue depth, drain, binning workgroup,
-    graph chunk, stencil pruning) gives the same trajectory bit for bit; the
-    autotuner puts the state and counter back."""
+    """Every launch configuration (queue depth, drain, busy lanes, binning
+    workgroup, graph chunk, stencil pruning, fused binning) gives the same
+    trajectory bit for bit; the autotuner puts the state and counter back."""
     torch = torch_gpu
     _lib, inputs, micro = _mod()
     wl = inputs.tiny_boxes(4, seed_k=43)
@@ -423,11 +423,12 @@ def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch
         for qd in depths:
             dmax = qd - (4 if qd >= 8 else (2 if qd >= 4 else 1))  # depth less the records per search step
             for drain, busy in sorted({(0, 65), (min(qd // 2, dmax), 65), (dmax, 48)}):
-                for bt, prune in ((256, 1), (1024, 0)):
-                    print(f"config {prec} qd={qd} drain={drain} busy={busy} bin={bt} prune={prune}", flush=True)
+                for bt, prune, fuse in ((256, 1, 0), (1024, 0, 0), (512, 0, 1)):
+                    print(f"config {prec} qd={qd} drain={drain} busy={busy} bin={bt} prune={prune} fuse={fuse}",
+                          flush=True)
                     m = micro.from_workload(wl, precision=prec)
                     m.set_config(queue_depth=qd, drain=drain, busy_lanes=busy, bin_threads=bt, graph_chunk=7,
-                                 prune=prune)
+                                 prune=prune, fuse_bin=fuse)
                     out = m.step(G, 20).cpu().numpy()
                     s, c, h, st = m.get_state()
                     if ref is None:
@@ -466,6 +467,26 @@ def test_pruning_keeps_every_pair_on_the_full_batch(torch_gpu):
         out = m.step(G, 30).cpu().numpy()
         s, c, h, st, f = m.get_state(with_forces=True)
         res.append((out, s, c, f, m.pair_counts()))
+        m.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+
+
+def test_fused_binning_on_the_full_batch_and_subsets(torch_gpu):
+    """Fused cell step + kick-drift + binning equals the separate kernels on
+    the benchmark batch (graph replays) and on subset steps."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.batch()
+    G = _grads(torch, wl)
+    res = []
+    for fuse in (0, 1):
+        m = micro.from_workload(wl, precision="fp32")
+        m.set_config(fuse_bin=fuse)
+        out = m.step(G, 30).cpu().numpy()
+        sub = m.step_subset(G, 10, [0, 7, 100, 255]).cpu().numpy()
+        s, c, h, st, f = m.get_state(with_forces=True)
+        res.append((out, sub, s, c, f))
         m.close()
     for a, b in zip(res[0], res[1]):
         assert np.array_equal(a, b)
