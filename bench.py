@@ -109,6 +109,7 @@ def bench_lhmm(macro_steps: int, k_micro: int = 50, equil_steps: int = 500, warm
            "ms_per_macro_step": el / macro_steps * 1e3, "macro_steps": macro_steps, "warmup": warmup,
            "workload": "reverse Poiseuille, 1024 SPH particles, 1024 micro-boxes x 4000 particles, "
                        f"{k_micro} micro steps per macro step", "micro_pair_updates_per_s": pairs / el,
+           "micro_valu_frac": PAIR_LANE_CYCLES * pairs / el / VALU_LANE_OPS_PEAK,
            "max_vx": float(np.abs(v[:, 0]).max()),
            "flagged_boxes": {"bond": int(np.count_nonzero(flags & 1)), "cell": int(np.count_nonzero(flags & 2))}}
     m.close()
