@@ -94,7 +94,7 @@ class Hybrid:
     micro engine must be equilibrated."""
 
     def __init__(self, sph: Sph, micro: Micro, sur=None, phi=None, mode="surrogate", k_micro=50, hold=10,
-                 replay=31, threshold=0.05, floor=0.05, grad_scale=1.0, stress_scale=1.0):
+                 replay=31, threshold=0.05, floor=1.0, grad_scale=1.0, stress_scale=1.0):
         from ._lib import HYBRID_DPD, HYBRID_SURROGATE, LhmmHybridParams
 
         p = LhmmHybridParams(mode={"surrogate": HYBRID_SURROGATE, "dpd": HYBRID_DPD}[mode], k_micro=int(k_micro),
