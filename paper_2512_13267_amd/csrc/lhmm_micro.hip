@@ -503,22 +503,45 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) cnt[k] = 0;
     __syncthreads();
     const int* pc = C.pcell + B.off;
+    // cells of this thread's particles k = threadIdx.x + j BIN_THREADS, kept
+    // for the scatter when the box fits the LDS path
+    constexpr int KEEP = 16384 / BIN_THREADS;
+    int mycell[KEEP];
+    const bool keep = B.n <= lds_parts && B.n <= KEEP * BIN_THREADS;
     if (fuse >= 0) {
         // four particles per thread and pass: independent loads in flight
-        for (int k0 = threadIdx.x; k0 < B.n; k0 += 4 * BIN_THREADS) {
+#pragma unroll
+        for (int j0 = 0; j0 < KEEP; j0 += 4) {
+            if ((int)threadIdx.x + j0 * BIN_THREADS >= B.n) break;
             int cell[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = k0 + u * BIN_THREADS;
+                const int k = (int)threadIdx.x + (j0 + u) * BIN_THREADS;
                 cell[u] = k < B.n ? kick_drift_particle<real>(C, D, B.off + k, fuse) : -1;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) {
+                mycell[j0 + u] = cell[u];
                 if (cell[u] >= 0) atomicAdd(&cnt[cell[u]], 1);
+            }
         }
+        for (int k = (int)threadIdx.x + KEEP * BIN_THREADS; k < B.n; k += BIN_THREADS)
+            atomicAdd(&cnt[kick_drift_particle<real>(C, D, B.off + k, fuse)], 1);
         __threadfence_block();
     } else {
-        for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) atomicAdd(&cnt[pc[k]], 1);
+#pragma unroll
+        for (int j0 = 0; j0 < KEEP; j0 += 4) {
+            if ((int)threadIdx.x + j0 * BIN_THREADS >= B.n) break;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = (int)threadIdx.x + (j0 + u) * BIN_THREADS;
+                mycell[j0 + u] = k < B.n ? pc[k] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (mycell[j0 + u] >= 0) atomicAdd(&cnt[mycell[j0 + u]], 1);
+        }
+        for (int k = (int)threadIdx.x + KEEP * BIN_THREADS; k < B.n; k += BIN_THREADS) atomicAdd(&cnt[pc[k]], 1);
     }
     __syncthreads();
     // exclusive scan of cnt[0 .. ncell) in chunks of BIN_THREADS
@@ -557,8 +580,13 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     const int N = C.n_total;
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
     const real h22 = (real)D.h[8];
-    if (B.n <= lds_parts) {
-        for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) lidx[atomicAdd(&cnt[pc[k]], 1)] = k;
+    if (keep) {
+#pragma unroll
+        for (int j = 0; j < KEEP; ++j) {
+            const int k = (int)threadIdx.x + j * BIN_THREADS;
+            if (k >= B.n) break;
+            lidx[atomicAdd(&cnt[mycell[j]], 1)] = k;
+        }
         __syncthreads();
         // cnt[k] now ends cell k; sort every cell's indices (a few entries)
         for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) {
@@ -574,12 +602,27 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < B.n; q += BIN_THREADS) {
-            const int k = lidx[q];
-            const int g = B.off + k;
-            const real s0 = s[g], s1 = s[N + g], s2 = s[2 * N + g];
-            rec[q] = R::make(h00 * s0 + h01 * s1, h10 * s0 + h11 * s1, h22 * s2, k);
-            vel[q] = R::make(c[g], c[N + g], c[2 * N + g], k);
+        // four records per thread and pass, their loads in flight together
+        for (int q0 = threadIdx.x; q0 < B.n; q0 += 4 * BIN_THREADS) {
+            real v[4][6];
+            int kk[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * BIN_THREADS;
+                kk[u] = q < B.n ? lidx[q] : 0;
+                const int g = B.off + kk[u];
+                v[u][0] = s[g]; v[u][1] = s[N + g]; v[u][2] = s[2 * N + g];
+                v[u][3] = c[g]; v[u][4] = c[N + g]; v[u][5] = c[2 * N + g];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * BIN_THREADS;
+                if (q < B.n) {
+                    const real s0 = v[u][0], s1 = v[u][1], s2 = v[u][2];
+                    rec[q] = R::make(h00 * s0 + h01 * s1, h10 * s0 + h11 * s1, h22 * s2, kk[u]);
+                    vel[q] = R::make(v[u][3], v[u][4], v[u][5], kk[u]);
+                }
+            }
         }
         return;
     }
