@@ -47,7 +47,7 @@ namespace {
 
 constexpr int BS = 256;                 // particles per work block
 constexpr int BIN_THREADS_MAX = 1024;   // largest binning workgroup (256, 512 or 1024 threads)
-constexpr int MAX_CELLS_PER_BOX = 15360;  // LDS histogram capacity (60 KiB)
+constexpr int MAX_CELLS_PER_BOX = 15360;  // binning LDS: cell starts and three per-column offsets (120 KiB)
 constexpr int GRAPH_CHUNK = 50;         // default steps per captured graph
 
 thread_local std::string g_err;
@@ -74,6 +74,7 @@ struct BoxInfo {
     int n_beads;   // n_chains * chain_len
     int cell_off;  // first slot in cell_start (cap + 1 slots per box)
     int cell_cap;  // cell capacity
+    int gcell_off; // first slot in gcell_start (cap + 2 floor(cap / 3) + 1 slots per box)
     int blk_off;   // first work block
     int nblk;      // work blocks
     unsigned rng_id;  // box word of the random-force counter
@@ -108,8 +109,16 @@ struct Ctx {
     void* f;
     int* pcell;
     int* cell_start;
-    void* cell_pos;     // per box, cell-sorted (x, y, z, local index) as 4 reals, r = h s
+    void* cell_pos;     // scratch of the binning of boxes too large for its LDS
     void* cell_vel;     // per box, cell-sorted (cx, cy, cz, local index) as 4 reals
+    // Search layout: per box (at 2 x its particle offset) every cell column
+    // (m0, m1) as [image of its top cell shifted by -h_z][its cells][image
+    // of its bottom cell shifted by +h_z], so the three z cells around any
+    // cell are one contiguous range; gcell_start holds the range starts of
+    // these n0 n1 (n2 + 2) cells.  srec: (x, y, z, cell-order position),
+    // r = h s; padded by four records.
+    int* gcell_start;
+    void* srec;
     double* part_vir;   // n_blocks x 12: pair virial, FENE virial
     double vir_scale;   // 1 when each pair is evaluated once, 1/2 when twice
     double* part_kin;   // n_blocks x 6
@@ -472,14 +481,58 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
     kick_drift_particle<real>(C, C.dyn[b], i, advance);
 }
 
+// Exclusive scan over k in [0, n) of val(k) by a workgroup of BT threads,
+// in chunks of BT (wave shuffles, then the wave totals): out(k, sum of
+// val(0 .. k-1)) for every k, and out(n, total) once.
+template <int BT, class Val, class Out>
+__device__ __forceinline__ void block_scan(int n, int* wsum /* BT / 64 */, Val val, Out out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int carry = 0;
+    for (int base = 0; base < n; base += BT) {
+        const int k = base + (int)threadIdx.x;
+        const int v = k < n ? val(k) : 0;
+        int x = v;  // inclusive scan within the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wv; ++w) before += wsum[w];
+        int total = 0;
+        for (int w = 0; w < BT / 64; ++w) total += wsum[w];
+        __syncthreads();
+        if (k < n) out(k, carry + before + x - v);
+        carry += total;
+    }
+    if (threadIdx.x == 0) out(n, carry);
+}
+
+// Position r = h s of a fractional coordinate in the in-plane cell, with a
+// fixed rounding sequence (the binning and the force kernel must agree to
+// the bit: a particle finds itself at distance exactly zero).
+template <typename real>
+__device__ __forceinline__ void cell_position(real s0, real s1, real s2, real h00, real h01, real h10, real h11,
+                                              real h22, real& x, real& y, real& z) {
+    x = fma(h01, s1, h00 * s0);
+    y = fma(h11, s1, h10 * s0);
+    z = h22 * s2;
+}
+
 // One workgroup per box: counting sort by cell in LDS, writing each
-// particle's records (position, local index) and (velocity, local index) in
-// cell order, sorted by index inside every cell so all later sums have a
-// fixed order.  LDS (dynamic): lds_cells counters, then room for lds_parts
-// particle indices.  A box with at most lds_parts particles is sorted as
-// indices in LDS and its records are written once, coalesced; a larger box
-// scatters records to global memory and sorts them there.  Both give the
-// same records in the same order.
+// particle's velocity record (velocity, local index) in cell order, sorted by
+// index inside every cell so all later sums have a fixed order, and its
+// position record (position, cell-order position) in the search layout: the
+// same order per cell, plus the z images of bottom and top cells.
+// LDS (dynamic): lds_cells cell counters / starts, three arrays of
+// lds_cells / 3 + 1 column offsets (from cell order to the search layout:
+// the column's cells, the image of its top cell, the image of its bottom
+// cell), then room for lds_parts particle entries.  A box with at
+// most lds_parts particles is sorted as entries in LDS and its records are
+// written once; a larger box scatters records to global scratch and sorts
+// them there.  Both give the same records in the same order.
 //
 // fuse >= 0: the workgroup first runs the box's cell step and the half kick
 // and drift of its particles (advance = fuse), counting cells as it goes;
@@ -488,8 +541,12 @@ template <typename real, int BIN_THREADS>
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, int lds_parts, int fuse) {
     using R = Rec<real>;
     extern __shared__ int lds[];
+    const int lds_cols = lds_cells / 3 + 1;  // columns n0 n1 <= cells / 3
     int* cnt = lds;
-    int* lidx = lds + lds_cells;
+    int* col_off = lds + lds_cells;
+    int* lo_off = col_off + lds_cols;
+    int* hi_off = lo_off + lds_cols;
+    int* lidx = hi_off + lds_cols;
     __shared__ int wsum[BIN_THREADS / 64];
     const int b = C.sel ? C.sel[blockIdx.x] : (int)blockIdx.x;
     const BoxInfo B = C.box[b];
@@ -544,51 +601,61 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
         for (int k = (int)threadIdx.x + KEEP * BIN_THREADS; k < B.n; k += BIN_THREADS) atomicAdd(&cnt[pc[k]], 1);
     }
     __syncthreads();
-    // exclusive scan of cnt[0 .. ncell) in chunks of BIN_THREADS
+    // cell starts (cnt[k] <- start of cell k, cnt[ncell] <- n), then the
+    // search layout's starts and every cell's offsets into it
     int* start = C.cell_start + B.cell_off;
-    int carry = 0;
-    for (int base = 0; base < ncell; base += BIN_THREADS) {
-        const int k = base + (int)threadIdx.x;
-        const int v = k < ncell ? cnt[k] : 0;
-        int x = v;  // inclusive scan within the wave
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wsum[wv] = x;
-        __syncthreads();
-        int before = 0;
-        for (int w = 0; w < wv; ++w) before += wsum[w];
-        int total = 0;
-        for (int w = 0; w < BIN_THREADS / 64; ++w) total += wsum[w];
-        const int excl = carry + before + x - v;
-        __syncthreads();
-        if (k < ncell) {
-            start[k] = excl;
-            cnt[k] = excl;  // becomes the fill cursor
-        }
-        carry += total;
-    }
-    if (threadIdx.x == 0) start[ncell] = carry;
+    int* gstart = C.gcell_start + B.gcell_off;
+    block_scan<BIN_THREADS>(ncell, wsum, [&](int k) { return cnt[k]; }, [&](int k, int excl) {
+        start[k] = excl;
+        cnt[k] = excl;
+    });
     __syncthreads();
-    typename R::T* rec = (typename R::T*)C.cell_pos + B.off;
+    const int n2 = D.nc[2], gn2 = n2 + 2, ncol = D.nc[0] * D.nc[1];
+    block_scan<BIN_THREADS>(
+        ncol * gn2, wsum,
+        [&](int g) {
+            const int col = g / gn2, zg = g - col * gn2;
+            const int k = col * n2 + (zg == 0 ? n2 - 1 : (zg == gn2 - 1 ? 0 : zg - 1));
+            return cnt[k + 1] - cnt[k];
+        },
+        [&](int g, int excl) {
+            gstart[g] = excl;
+            if (g == ncol * gn2) return;
+            const int col = g / gn2, zg = g - col * gn2;
+            if (zg == 0) lo_off[col] = excl - cnt[col * n2 + n2 - 1];
+            if (zg == 1) col_off[col] = excl - cnt[col * n2];
+            if (zg == gn2 - 1) hi_off[col] = excl - cnt[col * n2];
+        });
+    __threadfence_block();
+    __syncthreads();
+    typename R::T* rec = (typename R::T*)C.cell_pos + B.off;  // scratch of the global path
     typename R::T* vel = (typename R::T*)C.cell_vel + B.off;
+    typename R::T* srec = (typename R::T*)C.srec + 2 * B.off;
     const real* s = (const real*)C.s;
     const real* c = (const real*)C.c;
     const int N = C.n_total;
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
     const real h22 = (real)D.h[8];
+    // the position record of cell-order position q (cell `cell`) in its
+    // search-layout slot and, for a bottom or top cell, its image's slot;
+    // cell / n2 in single precision is exact for cells < 2^22
+    const float inv_n2 = 1.0f / (float)n2;
+    auto write_search = [&](int q, int cell, real x, real y, real z) {
+        const int col = (int)(((float)cell + 0.5f) * inv_n2), zc = cell - col * n2;
+        srec[q + col_off[col]] = R::make(x, y, z, q);
+        if (zc == n2 - 1) srec[q + lo_off[col]] = R::make(x, y, z - h22, q);
+        if (zc == 0) srec[q + hi_off[col]] = R::make(x, y, z + h22, q);
+    };
     if (keep) {
+        // LDS entries: cell << 14 | local index (cells < 2^14, particles < 2^14)
 #pragma unroll
         for (int j = 0; j < KEEP; ++j) {
             const int k = (int)threadIdx.x + j * BIN_THREADS;
             if (k >= B.n) break;
-            lidx[atomicAdd(&cnt[mycell[j]], 1)] = k;
+            lidx[atomicAdd(&cnt[mycell[j]], 1)] = (mycell[j] << 14) | k;
         }
         __syncthreads();
-        // cnt[k] now ends cell k; sort every cell's indices (a few entries)
+        // cnt[k] now ends cell k; sort every cell's entries by index (a few each)
         for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) {
             const int q0 = k == 0 ? 0 : cnt[k - 1], q1 = cnt[k];
             for (int q = q0 + 1; q < q1; ++q) {
@@ -605,12 +672,12 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
         // four records per thread and pass, their loads in flight together
         for (int q0 = threadIdx.x; q0 < B.n; q0 += 4 * BIN_THREADS) {
             real v[4][6];
-            int kk[4];
+            int e[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int q = q0 + u * BIN_THREADS;
-                kk[u] = q < B.n ? lidx[q] : 0;
-                const int g = B.off + kk[u];
+                e[u] = q < B.n ? lidx[q] : 0;
+                const int g = B.off + (e[u] & 0x3FFF);
                 v[u][0] = s[g]; v[u][1] = s[N + g]; v[u][2] = s[2 * N + g];
                 v[u][3] = c[g]; v[u][4] = c[N + g]; v[u][5] = c[2 * N + g];
             }
@@ -618,9 +685,10 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
             for (int u = 0; u < 4; ++u) {
                 const int q = q0 + u * BIN_THREADS;
                 if (q < B.n) {
-                    const real s0 = v[u][0], s1 = v[u][1], s2 = v[u][2];
-                    rec[q] = R::make(h00 * s0 + h01 * s1, h10 * s0 + h11 * s1, h22 * s2, kk[u]);
-                    vel[q] = R::make(v[u][3], v[u][4], v[u][5], kk[u]);
+                    real x, y, z;
+                    cell_position<real>(v[u][0], v[u][1], v[u][2], h00, h01, h10, h11, h22, x, y, z);
+                    vel[q] = R::make(v[u][3], v[u][4], v[u][5], e[u] & 0x3FFF);
+                    write_search(q, e[u] >> 14, x, y, z);
                 }
             }
         }
@@ -629,8 +697,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     for (int k = threadIdx.x; k < B.n; k += BIN_THREADS) {
         const int pos = atomicAdd(&cnt[pc[k]], 1);
         const int g = B.off + k;
-        const real s0 = s[g], s1 = s[N + g], s2 = s[2 * N + g];
-        rec[pos] = R::make(h00 * s0 + h01 * s1, h10 * s0 + h11 * s1, h22 * s2, k);
+        real x, y, z;
+        cell_position<real>(s[g], s[N + g], s[2 * N + g], h00, h01, h10, h11, h22, x, y, z);
+        rec[pos] = R::make(x, y, z, k);
     }
     __threadfence_block();
     __syncthreads();
@@ -650,8 +719,10 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     __threadfence_block();
     __syncthreads();
     for (int q = threadIdx.x; q < B.n; q += BIN_THREADS) {
-        const int g = B.off + R::id(rec[q]);
-        vel[q] = R::make(c[g], c[N + g], c[2 * N + g], g - B.off);
+        const typename R::T v = rec[q];
+        const int k = R::id(v), g = B.off + k;
+        vel[q] = R::make(c[g], c[N + g], c[2 * N + g], k);
+        write_search(q, pc[k], v.x, v.y, v.z);
     }
 }
 
@@ -667,8 +738,8 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 // particle's force in registers, so every ordered pair is evaluated by its
 // first particle's lane: no atomics, and a fixed summation order.
 //   Search: the wave walks the nine stencil rows in step (cells k2-1 .. k2+1
-//   of a row are contiguous in cell order, except across the periodic end of
-//   the row); each lane scans its own row range two records at a time
+//   of a row, periodic images included, are one contiguous range of the
+//   search layout); each lane scans its own row range SU records at a time
 //   (lanes of one home cell read the same records) and appends accepted
 //   neighbours (0 < r < rc; the particle itself has r = 0) to its own LDS
 //   queue of QD entries (a tuning parameter, as is `drain`; neither changes
@@ -700,30 +771,29 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
     const int p0 = C.blk_first[blk] - B.off;  // first cell-order position of the block
     const int pos = p0 + t;
     const bool act = pos < B.n;
-    const V4* rec = (const V4*)C.cell_pos + B.off;
     const V4* vel = (const V4*)C.cell_vel + B.off;
+    const char* sbase = (const char*)((const V4*)C.srec + 2 * B.off);
     const real* s = (const real*)C.s;
     real* f = (real*)C.f;
-
-    real ri0 = 0, ri1 = 0, ri2 = 0, ci0 = 0, ci1 = 0, ci2 = 0;
-    int own_id = 0;
-    if (act) {
-        const V4 v = rec[pos];
-        ri0 = v.x; ri1 = v.y; ri2 = v.z;
-        own_id = R::id(v);
-        const V4 u = vel[pos];
-        ci0 = u.x; ci1 = u.y; ci2 = u.z;
-    }
 
     // in-plane cell and gradient
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
     const real h22 = (real)D.h[8];
+    real ri0 = 0, ri1 = 0, ri2 = 0, ci0 = 0, ci1 = 0, ci2 = 0;
+    int own_id = 0;
+    if (act) {
+        const V4 u = vel[pos];
+        ci0 = u.x; ci1 = u.y; ci2 = u.z;
+        own_id = R::id(u);
+        const int g = B.off + own_id;
+        cell_position<real>(s[g], s[N + g], s[2 * N + g], h00, h01, h10, h11, h22, ri0, ri1, ri2);
+    }
     const real L00 = (real)D.L[0], L01 = (real)D.L[1], L10 = (real)D.L[3], L11 = (real)D.L[4];
     const int n0 = D.nc[0], n1 = D.nc[1], n2 = D.nc[2];
     const unsigned stepc = (unsigned)(*C.step + (unsigned long long)step_offset);
     const real a = (real)C.a, gam = (real)C.gamma, sig = (real)(C.sigma * C.rdt);
     const real rc2 = (real)C.rc2, irc = (real)(1.0 / C.rc);
-    const int* start = C.cell_start + B.cell_off;
+    const int* gstart = C.gcell_start + B.gcell_off;
 
     int k0 = 0, k1 = 0, k2 = 0;
     if (act) {
@@ -785,25 +855,24 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
             ++npairs;
         }
     };
-    // test one candidate record (position q) against (px, py, pz), the lane's
+    // test one candidate record v against (px, py, pz), the lane's
     // position minus the image shift of the range scanned; queue it if accepted
-    auto push = [&](bool valid, const V4& v, int q, real px, real py, real pz) {
+    auto push = [&](bool valid, const V4& v, real px, real py, real pz) {
         const real dx = px - v.x, dy = py - v.y, dz = pz - v.z;
         const real r2 = dx * dx + dy * dy + dz * dz;
         if (valid && r2 < rc2 && r2 > (real)0) {
-            qbuf[qt & (QD - 1)][wv][lane] = R::make(dx, dy, dz, q);
+            qbuf[qt & (QD - 1)][wv][lane] = R::make(dx, dy, dz, R::id(v));
             ++qt;
         }
     };
 
-    // Scan state: the wave is at stencil row `row` (d0, d1) and range `piece`
-    // of it (0: cells max(k2-1,0) .. min(k2+1,n2-1) unshifted in z; 1: the
-    // cell across the periodic end of the row, if any); each lane scans its
-    // records q .. qe-1 against (bx, by, pz), its position minus the image
-    // shift of that range.
-    int row = 0, piece = 0;
+    // Scan state: the wave is at stencil row `row` (d0, d1); each lane scans
+    // the search-layout records q .. qe-1 (cells k2-1 .. k2+1 of the row's
+    // column, the periodic z images included) against (bx, by, ri2), its
+    // position less the in-plane image shift of the column.
+    int row = 0;
     int q = 0, qe = 0;
-    real bx = 0, by = 0, pz = 0;
+    real bx = 0, by = 0;
     auto set_range = [&]() {
         const int d0 = row / 3 - 1, d1 = row % 3 - 1;
         int m0 = k0 + d0, m1 = k1 + d1;
@@ -811,36 +880,25 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
         const int sh1 = m1 < 0 ? -1 : (m1 >= n1 ? 1 : 0);
         m0 -= sh0 * n0;
         m1 -= sh1 * n1;
-        const int rb = (m0 * n1 + m1) * n2;
+        const int gb = (m0 * n1 + m1) * (n2 + 2) + k2;
         bx = ri0 - (h00 * (real)sh0 + h01 * (real)sh1);
         by = ri1 - (h10 * (real)sh0 + h11 * (real)sh1);
-        pz = ri2;
         q = 0;
         qe = 0;
-        int lo = k2 - 1, hi = k2 + 1;
+        int lo = 0, hi = 3;
         bool live = act;
         if (act && prune) {
             const real ga = d0 < 0 ? gl0 : (d0 > 0 ? gh0 : (real)0);
-            const real gb = d1 < 0 ? gl1 : (d1 > 0 ? gh1 : (real)0);
-            const real g = fmax(ga, gb);
+            const real gb2 = d1 < 0 ? gl1 : (d1 > 0 ? gh1 : (real)0);
+            const real g = fmax(ga, gb2);
             const real zmax2 = rcp2 - g * g;
             live = zmax2 > (real)0;
-            if (!(zl * zl < zmax2)) lo = k2;
-            if (!(zh * zh < zmax2)) hi = k2;
+            if (!(zl * zl < zmax2)) lo = 1;
+            if (!(zh * zh < zmax2)) hi = 2;
         }
         if (live) {
-            if (piece == 0) {
-                q = start[rb + max(lo, 0)];
-                qe = start[rb + min(hi, n2 - 1) + 1];
-            } else if (lo < 0) {
-                q = start[rb + n2 - 1];
-                qe = start[rb + n2];
-                pz = ri2 + h22;
-            } else if (hi >= n2) {
-                q = start[rb];
-                qe = start[rb + 1];
-                pz = ri2 - h22;
-            }
+            q = gstart[gb + lo];
+            qe = gstart[gb + hi];
         }
     };
     set_range();
@@ -849,24 +907,24 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
         // search until the stencil is done or some queue might not take two more
         while (scanning) {
             if (__ballot(q < qe) == 0ull) {
-                if (++piece == 2) {
-                    piece = 0;
-                    if (++row == 9) {
-                        scanning = false;
-                        break;
-                    }
+                if (++row == 9) {
+                    scanning = false;
+                    break;
                 }
                 set_range();
                 continue;
             }
             // SU records per lane per iteration, all loads issued before the
-            // first test; out-of-range lanes read record 0 (always present)
-            // and discard it
+            // first test, addressed by one 32-bit byte offset from the box's
+            // records; slots past the range end read the next records (the
+            // array is padded) and are discarded
             V4 cand[SU];
+            const unsigned qo = (unsigned)q * (unsigned)sizeof(V4);
+            const int rem = qe - q;
 #pragma unroll
-            for (int u = 0; u < SU; ++u) cand[u] = rec[q + u < qe ? q + u : 0];
+            for (int u = 0; u < SU; ++u) cand[u] = *(const V4*)(sbase + qo + u * sizeof(V4));
 #pragma unroll
-            for (int u = 0; u < SU; ++u) push(q + u < qe, cand[u], q + u, bx, by, pz);
+            for (int u = 0; u < SU; ++u) push(u < rem, cand[u], bx, by, ri2);
             q += SU;
             // evaluate when a queue may not take SU more, or when enough
             // lanes hold a neighbour for a well-filled round
@@ -1048,9 +1106,10 @@ struct lhmm_micro {
     unsigned* d_flags = nullptr;
     int *d_blk_box = nullptr, *d_blk_first = nullptr;
     void *d_s = nullptr, *d_c = nullptr, *d_f = nullptr;
-    int *d_pcell = nullptr, *d_cell_start = nullptr;
+    int *d_pcell = nullptr, *d_cell_start = nullptr, *d_gcell_start = nullptr;
     void* d_cell_pos = nullptr;
     void* d_cell_vel = nullptr;
+    void* d_srec = nullptr;
     double *d_part_vir = nullptr, *d_part_kin = nullptr;
     unsigned* d_part_pairs = nullptr;
     double *d_acc = nullptr, *d_parts = nullptr, *d_gradL = nullptr;
@@ -1076,7 +1135,7 @@ namespace {
 template <typename real>
 void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse) {
     const int lc = m->bin_lds_cells, lp = m->bin_lds_parts;
-    const size_t bytes = sizeof(int) * ((size_t)lc + (size_t)lp);
+    const size_t bytes = sizeof(int) * ((size_t)lc + 3 * (size_t)(lc / 3 + 1) + (size_t)lp);
     switch (m->cfg.bin_threads) {
         case 256: k_bin_box<real, 256><<<nbox, 256, bytes, st>>>(C, lc, lp, fuse); break;
         case 512: k_bin_box<real, 512><<<nbox, 512, bytes, st>>>(C, lc, lp, fuse); break;
@@ -1206,7 +1265,8 @@ void release(lhmm_micro* m) {
     for (auto& kv : m->sub_graphs) (void)hipGraphExecDestroy(kv.second);
     m->sub_graphs.clear();
     void* bufs[] = {m->d_box, m->d_dyn, m->d_flags, m->d_blk_box, m->d_blk_first, m->d_s, m->d_c, m->d_f,
-                    m->d_pcell, m->d_cell_start, m->d_cell_pos, m->d_cell_vel, m->d_part_vir, m->d_part_kin,
+                    m->d_pcell, m->d_cell_start, m->d_gcell_start, m->d_cell_pos, m->d_cell_vel, m->d_srec,
+                    m->d_part_vir, m->d_part_kin,
                     m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_step,
                     m->d_sel, m->d_blk_list, m->d_snap_s, m->d_snap_c, m->d_snap_f, m->d_snap_dyn};
     for (void* b : bufs)
@@ -1341,7 +1401,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->user_stream = (hipStream_t)stream;
 
     long long off = 0;
-    int cell_off = 0, blk_off = 0;
+    int cell_off = 0, gcell_off = 0, blk_off = 0;
     m->box.resize(n_boxes);
     for (int b = 0; b < n_boxes; ++b) {
         const lhmm_box& in = boxes[b];
@@ -1372,6 +1432,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
         B.n_beads = in.n_chains * p->chain_len;
         B.cell_off = cell_off;
         B.cell_cap = (int)cap;
+        B.gcell_off = gcell_off;
         B.blk_off = blk_off;
         B.nblk = (in.n_particles + BS - 1) / BS;
         B.rng_id = in.rng_id;
@@ -1381,6 +1442,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
         }
         off += in.n_particles;
         cell_off += (int)cap + 1;
+        gcell_off += (int)cap + 2 * (int)(cap / 3) + 1;  // n0 n1 (n2 + 2) cells, n2 >= 3
         blk_off += B.nblk;
         if (off > (1LL << 30)) {
             delete m;
@@ -1390,15 +1452,36 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->n_total = off;
     m->n_blocks = blk_off;
     {
-        // binning LDS: every box's cell counters, and indices for boxes that fit in 64 KiB
+        // binning LDS: three arrays over every box's cells, and entries for
+        // the boxes that fit in what the workgroup may still use
         int max_cells = 0, max_n = 0;
         for (const BoxInfo& B : m->box) {
             max_cells = std::max(max_cells, B.cell_cap + 1);
             max_n = std::max(max_n, B.n);
         }
-        const int budget = (int)((65536 - 64 * (int)sizeof(int)) / sizeof(int));  // less the scan's wave sums
+        int dev = 0, max_lds = 65536;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            max_lds = 65536;
+        const int budget = (int)((max_lds - 64 * (int)sizeof(int)) / sizeof(int));  // less the scan's wave sums
+        const int fixed = max_cells + 3 * (max_cells / 3 + 1);  // cells and column offsets
+        if (fixed > budget) {
+            delete m;
+            return fail(LHMM_ERR_ARG, "boxes need %d cells, more than the binning LDS holds", max_cells - 1);
+        }
         m->bin_lds_cells = max_cells;
-        m->bin_lds_parts = std::max(0, std::min(max_n, budget - max_cells));
+        m->bin_lds_parts = std::max(0, std::min(max_n, budget - fixed));
+        const size_t bytes = sizeof(int) * ((size_t)fixed + (size_t)m->bin_lds_parts);
+        const void* kernels[] = {(const void*)&k_bin_box<float, 256>, (const void*)&k_bin_box<float, 512>,
+                                 (const void*)&k_bin_box<float, 1024>, (const void*)&k_bin_box<double, 256>,
+                                 (const void*)&k_bin_box<double, 512>, (const void*)&k_bin_box<double, 1024>};
+        for (const void* k : kernels) {
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess) {
+                delete m;
+                return fail(LHMM_ERR_HIP, "binning LDS of %zu bytes: %s", bytes, hipGetErrorString(e));
+            }
+        }
     }
     const size_t N = (size_t)m->n_total;
     int rc = LHMM_OK;
@@ -1411,6 +1494,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     ALLOC(m->d_blk_first, (size_t)m->n_blocks);
     ALLOC(m->d_pcell, N);
     ALLOC(m->d_cell_start, (size_t)cell_off);
+    ALLOC(m->d_gcell_start, (size_t)gcell_off);
     ALLOC(m->d_part_vir, (size_t)m->n_blocks * 12);
     ALLOC(m->d_part_kin, (size_t)m->n_blocks * 6);
     ALLOC(m->d_part_pairs, (size_t)m->n_blocks);
@@ -1422,8 +1506,11 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
 #undef ALLOC
     if (rc == LHMM_OK) {
         const size_t bytes = 3 * N * m->real_size;
-        for (void** pp : {&m->d_s, &m->d_c, &m->d_f, &m->d_cell_pos, &m->d_cell_vel}) {
-            const size_t nb = (pp == &m->d_cell_pos || pp == &m->d_cell_vel) ? 4 * N * m->real_size : bytes;
+        // search layout: each particle at most twice (its cell, and the
+        // image of a bottom or top cell; n2 >= 3)
+        for (void** pp : {&m->d_s, &m->d_c, &m->d_f, &m->d_cell_pos, &m->d_cell_vel, &m->d_srec}) {
+            const size_t nb = (pp == &m->d_cell_pos || pp == &m->d_cell_vel) ? 4 * N * m->real_size
+                              : pp == &m->d_srec ? (8 * N + 16) * m->real_size : bytes;
             if (hipMalloc(pp, nb ? nb : 1) != hipSuccess) {
                 rc = fail(LHMM_ERR_OOM, "hipMalloc of particle arrays failed");
                 break;
@@ -1478,7 +1565,9 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     C.pcell = m->d_pcell;
     C.cell_start = m->d_cell_start;
     C.cell_pos = m->d_cell_pos;
+    C.gcell_start = m->d_gcell_start;
     C.cell_vel = m->d_cell_vel;
+    C.srec = m->d_srec;
     C.vir_scale = 0.5;  // every unordered pair is evaluated from both ends
     C.part_vir = m->d_part_vir;
     C.part_kin = m->d_part_kin;
