@@ -74,7 +74,8 @@ struct BoxInfo {
     int n_beads;   // n_chains * chain_len
     int cell_off;  // first slot in cell_start (cap + 1 slots per box)
     int cell_cap;  // cell capacity
-    int gcell_off; // first slot in gcell_start (cap + 2 floor(cap / 3) + 1 slots per box)
+    int gcell_off; // first slot in gcell_start (2 cap + 1 slots per box)
+    int zsub;      // cells per cutoff along z (1 or 2): the z range of a stencil row is 2 zsub + 1 cells
     int blk_off;   // first work block
     int nblk;      // work blocks
     unsigned rng_id;  // box word of the random-force counter
@@ -112,11 +113,11 @@ struct Ctx {
     void* cell_pos;     // scratch of the binning of boxes too large for its LDS
     void* cell_vel;     // per box, cell-sorted (cx, cy, cz, local index) as 4 reals
     // Search layout: per box (at 2 x its particle offset) every cell column
-    // (m0, m1) as [image of its top cell shifted by -h_z][its cells][image
-    // of its bottom cell shifted by +h_z], so the three z cells around any
-    // cell are one contiguous range; gcell_start holds the range starts of
-    // these n0 n1 (n2 + 2) cells.  srec: (x, y, z, cell-order position),
-    // r = h s; padded by four records.
+    // (m0, m1) as [images of its top zsub cells shifted by -h_z][its cells]
+    // [images of its bottom zsub cells shifted by +h_z], so the z cells
+    // k2 - zsub .. k2 + zsub around any cell are one contiguous range;
+    // gcell_start holds the range starts of these n0 n1 (n2 + 2 zsub) cells.
+    // srec: (x, y, z, cell-order position), r = h s; padded by four records.
     int* gcell_start;
     void* srec;
     double* part_vir;   // n_blocks x 12: pair virial, FENE virial
@@ -402,17 +403,21 @@ __device__ void cell_step_box(const Ctx& C, int b, int advance) {
     m3_widths(h, w);
     int nc[3];
     bool narrow = false;
+    const int zsub = C.box[b].zsub, zmin = 2 * zsub + 1;
     for (int a = 0; a < 3; ++a) {
-        int n = (int)floor(w[a] / C.rc);
+        const int sub = a == 2 ? zsub : 1;
+        int n = (int)floor(sub * w[a] / C.rc);
         if (!(w[a] >= 3.0 * C.rc)) narrow = true;
-        if (n < 3) n = 3;
+        if (n < 2 * sub + 1) n = 2 * sub + 1;
         nc[a] = n;
     }
     const int cap = C.box[b].cell_cap;
     while ((long long)nc[0] * nc[1] * nc[2] > cap) {  // only reachable for a flagged (narrow) cell
         int a = nc[0] >= nc[1] ? 0 : 1;
-        if (nc[a] <= 3) a = 2;
-        if (nc[a] <= 3) break;
+        if (nc[a] <= 3) {
+            if (nc[2] <= zmin) break;
+            a = 2;
+        }
         nc[a] -= 1;
     }
     if (narrow) C.flags[b] |= LHMM_FLAG_CELL;
@@ -529,10 +534,11 @@ __device__ __forceinline__ void cell_position(real s0, real s1, real s2, real h0
 // LDS (dynamic): lds_cells cell counters / starts, three arrays of
 // lds_cells / 3 + 1 column offsets (from cell order to the search layout:
 // the column's cells, the image of its top cell, the image of its bottom
-// cell), then room for lds_parts particle entries.  A box with at
-// most lds_parts particles is sorted as entries in LDS and its records are
-// written once; a larger box scatters records to global scratch and sorts
-// them there.  Both give the same records in the same order.
+// cell), then room for lds_parts ints.  A box with at most lds_parts / 2
+// particles is sorted as entries in LDS, their cell-order positions are
+// inverted in LDS, and each thread stores the records of its own particles;
+// a larger box scatters records to global scratch and sorts them there.
+// Both give the same records in the same order.
 //
 // fuse >= 0: the workgroup first runs the box's cell step and the half kick
 // and drift of its particles (advance = fuse), counting cells as it goes;
@@ -564,7 +570,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     // for the scatter when the box fits the LDS path
     constexpr int KEEP = 16384 / BIN_THREADS;
     int mycell[KEEP];
-    const bool keep = B.n <= lds_parts && B.n <= KEEP * BIN_THREADS;
+    const bool keep = 2 * B.n <= lds_parts && B.n <= KEEP * BIN_THREADS;
     if (fuse >= 0) {
         // four particles per thread and pass: independent loads in flight
 #pragma unroll
@@ -610,21 +616,21 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
         cnt[k] = excl;
     });
     __syncthreads();
-    const int n2 = D.nc[2], gn2 = n2 + 2, ncol = D.nc[0] * D.nc[1];
+    const int n2 = D.nc[2], zs = B.zsub, gn2 = n2 + 2 * zs, ncol = D.nc[0] * D.nc[1];
     block_scan<BIN_THREADS>(
         ncol * gn2, wsum,
         [&](int g) {
             const int col = g / gn2, zg = g - col * gn2;
-            const int k = col * n2 + (zg == 0 ? n2 - 1 : (zg == gn2 - 1 ? 0 : zg - 1));
+            const int k = col * n2 + (zg < zs ? n2 - zs + zg : (zg >= zs + n2 ? zg - zs - n2 : zg - zs));
             return cnt[k + 1] - cnt[k];
         },
         [&](int g, int excl) {
             gstart[g] = excl;
             if (g == ncol * gn2) return;
             const int col = g / gn2, zg = g - col * gn2;
-            if (zg == 0) lo_off[col] = excl - cnt[col * n2 + n2 - 1];
-            if (zg == 1) col_off[col] = excl - cnt[col * n2];
-            if (zg == gn2 - 1) hi_off[col] = excl - cnt[col * n2];
+            if (zg == 0) lo_off[col] = excl - cnt[col * n2 + n2 - zs];
+            if (zg == zs) col_off[col] = excl - cnt[col * n2];
+            if (zg == zs + n2) hi_off[col] = excl - cnt[col * n2];
         });
     __threadfence_block();
     __syncthreads();
@@ -637,14 +643,14 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
     const real h22 = (real)D.h[8];
     // the position record of cell-order position q (cell `cell`) in its
-    // search-layout slot and, for a bottom or top cell, its image's slot;
+    // search-layout slot and, for the zsub bottom or top cells, its image's slot;
     // cell / n2 in single precision is exact for cells < 2^22
     const float inv_n2 = 1.0f / (float)n2;
     auto write_search = [&](int q, int cell, real x, real y, real z) {
         const int col = (int)(((float)cell + 0.5f) * inv_n2), zc = cell - col * n2;
         srec[q + col_off[col]] = R::make(x, y, z, q);
-        if (zc == n2 - 1) srec[q + lo_off[col]] = R::make(x, y, z - h22, q);
-        if (zc == 0) srec[q + hi_off[col]] = R::make(x, y, z + h22, q);
+        if (zc >= n2 - zs) srec[q + lo_off[col]] = R::make(x, y, z - h22, q);
+        if (zc < zs) srec[q + hi_off[col]] = R::make(x, y, z + h22, q);
     };
     if (keep) {
         // LDS entries: cell << 14 | local index (cells < 2^14, particles < 2^14)
@@ -669,26 +675,32 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
             }
         }
         __syncthreads();
-        // four records per thread and pass, their loads in flight together
-        for (int q0 = threadIdx.x; q0 < B.n; q0 += 4 * BIN_THREADS) {
+        // cell-order position of every particle
+        int* posof = lidx + B.n;
+        for (int q = threadIdx.x; q < B.n; q += BIN_THREADS) posof[lidx[q] & 0x3FFF] = q;
+        __syncthreads();
+        // the thread's own particles, four per pass with their (coalesced)
+        // loads in flight together, each record stored to its slot
+#pragma unroll
+        for (int j0 = 0; j0 < KEEP; j0 += 4) {
+            if ((int)threadIdx.x + j0 * BIN_THREADS >= B.n) break;
             real v[4][6];
-            int e[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int q = q0 + u * BIN_THREADS;
-                e[u] = q < B.n ? lidx[q] : 0;
-                const int g = B.off + (e[u] & 0x3FFF);
+                const int k = (int)threadIdx.x + (j0 + u) * BIN_THREADS;
+                const int g = B.off + (k < B.n ? k : 0);
                 v[u][0] = s[g]; v[u][1] = s[N + g]; v[u][2] = s[2 * N + g];
                 v[u][3] = c[g]; v[u][4] = c[N + g]; v[u][5] = c[2 * N + g];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int q = q0 + u * BIN_THREADS;
-                if (q < B.n) {
+                const int k = (int)threadIdx.x + (j0 + u) * BIN_THREADS;
+                if (k < B.n) {
+                    const int q = posof[k];
                     real x, y, z;
                     cell_position<real>(v[u][0], v[u][1], v[u][2], h00, h01, h10, h11, h22, x, y, z);
-                    vel[q] = R::make(v[u][3], v[u][4], v[u][5], e[u] & 0x3FFF);
-                    write_search(q, e[u] >> 14, x, y, z);
+                    vel[q] = R::make(v[u][3], v[u][4], v[u][5], k);
+                    write_search(q, mycell[j0 + u], x, y, z);
                 }
             }
         }
@@ -737,9 +749,11 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 // fene_force).  Each lane owns one particle in cell order and sums that
 // particle's force in registers, so every ordered pair is evaluated by its
 // first particle's lane: no atomics, and a fixed summation order.
-//   Search: the wave walks the nine stencil rows in step (cells k2-1 .. k2+1
-//   of a row, periodic images included, are one contiguous range of the
-//   search layout); each lane scans its own row range SU records at a time
+//   Search: the wave walks the nine stencil rows in step (z cells
+//   k2 - zsub .. k2 + zsub of a row, periodic images included, are one
+//   contiguous range of the search layout; with two cells per cutoff along z
+//   the rows hold ~20% fewer candidates); each lane scans its own row range
+//   SU records at a time
 //   (lanes of one home cell read the same records) and appends accepted
 //   neighbours (0 < r < rc; the particle itself has r = 0) to its own LDS
 //   queue of QD entries (a tuning parameter, as is `drain`; neither changes
@@ -789,7 +803,9 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
         cell_position<real>(s[g], s[N + g], s[2 * N + g], h00, h01, h10, h11, h22, ri0, ri1, ri2);
     }
     const real L00 = (real)D.L[0], L01 = (real)D.L[1], L10 = (real)D.L[3], L11 = (real)D.L[4];
-    const int n0 = D.nc[0], n1 = D.nc[1], n2 = D.nc[2];
+    const int n0 = D.nc[0], n1 = D.nc[1], n2 = D.nc[2], zs = B.zsub;
+    const real dzc = h22 / (real)n2;  // cell height
+    auto sqr = [](real x) { return x * x; };
     const unsigned stepc = (unsigned)(*C.step + (unsigned long long)step_offset);
     const real a = (real)C.a, gam = (real)C.gamma, sig = (real)(C.sigma * C.rdt);
     const real rc2 = (real)C.rc2, irc = (real)(1.0 / C.rc);
@@ -867,8 +883,8 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
     };
 
     // Scan state: the wave is at stencil row `row` (d0, d1); each lane scans
-    // the search-layout records q .. qe-1 (cells k2-1 .. k2+1 of the row's
-    // column, the periodic z images included) against (bx, by, ri2), its
+    // the search-layout records q .. qe-1 (z cells k2 - zsub .. k2 + zsub of
+    // the row's column, the periodic images included) against (bx, by, ri2), its
     // position less the in-plane image shift of the column.
     int row = 0;
     int q = 0, qe = 0;
@@ -880,12 +896,12 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
         const int sh1 = m1 < 0 ? -1 : (m1 >= n1 ? 1 : 0);
         m0 -= sh0 * n0;
         m1 -= sh1 * n1;
-        const int gb = (m0 * n1 + m1) * (n2 + 2) + k2;
+        const int gb = (m0 * n1 + m1) * (n2 + 2 * zs) + k2;
         bx = ri0 - (h00 * (real)sh0 + h01 * (real)sh1);
         by = ri1 - (h10 * (real)sh0 + h11 * (real)sh1);
         q = 0;
         qe = 0;
-        int lo = 0, hi = 3;
+        int lo = 0, hi = 2 * zs + 1;
         bool live = act;
         if (act && prune) {
             const real ga = d0 < 0 ? gl0 : (d0 > 0 ? gh0 : (real)0);
@@ -893,8 +909,9 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
             const real g = fmax(ga, gb2);
             const real zmax2 = rcp2 - g * g;
             live = zmax2 > (real)0;
-            if (!(zl * zl < zmax2)) lo = 1;
-            if (!(zh * zh < zmax2)) hi = 2;
+            // z cells below (above) the particle's, farthest first
+            for (int j = zs; j >= 1 && !(sqr(zl + (real)(j - 1) * dzc) < zmax2); --j) ++lo;
+            for (int j = zs; j >= 1 && !(sqr(zh + (real)(j - 1) * dzc) < zmax2); --j) --hi;
         }
         if (live) {
             q = gstart[gb + lo];
@@ -1417,11 +1434,18 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
             delete m;
             return fail(LHMM_ERR_ARG, "box %d: cell must be finite, in-plane, with det > 0", b);
         }
-        // n0 n1 <= w0 w1 <= area and n2 = floor(z extent / rc): the grid never needs more
+        // n0 n1 <= w0 w1 <= area and n2 = floor(zsub z extent / rc): the grid
+        // never needs more; two cells per cutoff along z unless that exceeds
+        // the cell limit
         const double area = fabs(in.h0[0] * in.h0[4] - in.h0[1] * in.h0[3]);
         const long long inplane = (long long)std::floor(area / (p->rc * p->rc) * (1.0 + 1e-9));
-        const long long nz = (long long)std::floor(in.h0[8] / p->rc * (1.0 + 1e-9));
-        long long cap = std::max(27LL, std::max(inplane, 9LL) * std::max(nz, 3LL));
+        long long cap = 0;
+        int zsub = 2;
+        for (; zsub >= 1; --zsub) {
+            const long long nz = (long long)std::floor(zsub * in.h0[8] / p->rc * (1.0 + 1e-9));
+            cap = std::max(9LL * (2 * zsub + 1), std::max(inplane, 9LL) * std::max(nz, 2LL * zsub + 1));
+            if (cap <= MAX_CELLS_PER_BOX) break;
+        }
         if (cap > MAX_CELLS_PER_BOX) {
             delete m;
             return fail(LHMM_ERR_ARG, "box %d: needs %lld cells, more than %d", b, cap, MAX_CELLS_PER_BOX);
@@ -1433,6 +1457,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
         B.cell_off = cell_off;
         B.cell_cap = (int)cap;
         B.gcell_off = gcell_off;
+        B.zsub = zsub;
         B.blk_off = blk_off;
         B.nblk = (in.n_particles + BS - 1) / BS;
         B.rng_id = in.rng_id;
@@ -1442,7 +1467,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
         }
         off += in.n_particles;
         cell_off += (int)cap + 1;
-        gcell_off += (int)cap + 2 * (int)(cap / 3) + 1;  // n0 n1 (n2 + 2) cells, n2 >= 3
+        gcell_off += 2 * (int)cap + 1;  // n0 n1 (n2 + 2 zsub) cells, n2 >= 2 zsub + 1
         blk_off += B.nblk;
         if (off > (1LL << 30)) {
             delete m;
@@ -1470,7 +1495,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
             return fail(LHMM_ERR_ARG, "boxes need %d cells, more than the binning LDS holds", max_cells - 1);
         }
         m->bin_lds_cells = max_cells;
-        m->bin_lds_parts = std::max(0, std::min(max_n, budget - fixed));
+        m->bin_lds_parts = std::max(0, std::min(2 * max_n, budget - fixed));  // entries and their inverse
         const size_t bytes = sizeof(int) * ((size_t)fixed + (size_t)m->bin_lds_parts);
         const void* kernels[] = {(const void*)&k_bin_box<float, 256>, (const void*)&k_bin_box<float, 512>,
                                  (const void*)&k_bin_box<float, 1024>, (const void*)&k_bin_box<double, 256>,
