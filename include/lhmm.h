@@ -160,7 +160,7 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
  * every sum keeps its order, so all configurations give bit-identical
  * trajectories.
  *   queue_depth: per-lane neighbour queue of the pair-force kernel
- *                (2, 4, 8, 16 in FP32; 2, 4 in FP64);
+ *                (2, 4, 8, 16, 32 entries of 4 bytes);
  *   drain:       evaluation rounds run until every queue holds at most this
  *                many neighbours (0 .. queue_depth - u, where a search
  *                iteration tests u = 4, 2, 1 records per lane for depths
@@ -186,8 +186,8 @@ typedef struct {
     int32_t fuse_bin;
 } lhmm_micro_config;
 
-/* Set / read the launch parameters (defaults: depth 8 in FP32, 4 in FP64;
- * drain depth/2; busy rule off; 1024 binning threads; fused binning;
+/* Set / read the launch parameters (defaults: depth 16, drain 8; busy rule
+ * off; 1024 binning threads; fused binning;
  * 50-step graphs; no pruning: with
  * cells barely wider than the cutoff it skips little and costs more).  Set waits for the
  * engine and drops its captured graphs.  Errors: ARG. */

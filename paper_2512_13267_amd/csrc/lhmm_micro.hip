@@ -110,14 +110,15 @@ struct Ctx {
     void* f;
     int* pcell;
     int* cell_start;
-    void* cell_pos;     // scratch of the binning of boxes too large for its LDS
+    void* cell_pos;     // per box, cell-sorted (x, y, z, local index) as 4 reals, r = h s
     void* cell_vel;     // per box, cell-sorted (cx, cy, cz, local index) as 4 reals
     // Search layout: per box (at 2 x its particle offset) every cell column
     // (m0, m1) as [images of its top zsub cells shifted by -h_z][its cells]
     // [images of its bottom zsub cells shifted by +h_z], so the z cells
     // k2 - zsub .. k2 + zsub around any cell are one contiguous range;
     // gcell_start holds the range starts of these n0 n1 (n2 + 2 zsub) cells.
-    // srec: (x, y, z, cell-order position), r = h s; padded by four records.
+    // srec: (x, y, z, cell-order position << 2 | z image: 0 none, 1 below,
+    // 2 above), r = h s; padded by four records.
     int* gcell_start;
     void* srec;
     double* part_vir;   // n_blocks x 12: pair virial, FENE virial
@@ -486,33 +487,37 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
     kick_drift_particle<real>(C, C.dyn[b], i, advance);
 }
 
-// Exclusive scan over k in [0, n) of val(k) by a workgroup of BT threads,
-// in chunks of BT (wave shuffles, then the wave totals): out(k, sum of
-// val(0 .. k-1)) for every k, and out(n, total) once.
+// Exclusive scan over k in [0, n) of val(k) by a workgroup of BT threads:
+// each thread sums a run of consecutive k, the run totals are scanned
+// (wave shuffles, then the wave totals), and each thread walks its run
+// again calling out(k, sum of val(0 .. k-1)); out(n, total) once.  val(k)
+// is read before out(k) is called, by the same thread.
 template <int BT, class Val, class Out>
 __device__ __forceinline__ void block_scan(int n, int* wsum /* BT / 64 */, Val val, Out out) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int carry = 0;
-    for (int base = 0; base < n; base += BT) {
-        const int k = base + (int)threadIdx.x;
-        const int v = k < n ? val(k) : 0;
-        int x = v;  // inclusive scan within the wave
+    const int per = (n + BT - 1) / BT;
+    const int k0 = min((int)threadIdx.x * per, n), k1 = min(k0 + per, n);
+    int run = 0;
+    for (int k = k0; k < k1; ++k) run += val(k);
+    int x = run;  // inclusive scan of the run totals within the wave
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wsum[wv] = x;
-        __syncthreads();
-        int before = 0;
-        for (int w = 0; w < wv; ++w) before += wsum[w];
-        int total = 0;
-        for (int w = 0; w < BT / 64; ++w) total += wsum[w];
-        __syncthreads();
-        if (k < n) out(k, carry + before + x - v);
-        carry += total;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
-    if (threadIdx.x == 0) out(n, carry);
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int excl = x - run;
+    for (int w = 0; w < wv; ++w) excl += wsum[w];
+    int total = 0;
+    for (int w = 0; w < BT / 64; ++w) total += wsum[w];
+    __syncthreads();
+    for (int k = k0; k < k1; ++k) {
+        const int v = val(k);
+        out(k, excl);
+        excl += v;
+    }
+    if (threadIdx.x == 0) out(n, total);
 }
 
 // Position r = h s of a fractional coordinate in the in-plane cell, with a
@@ -634,7 +639,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
         });
     __threadfence_block();
     __syncthreads();
-    typename R::T* rec = (typename R::T*)C.cell_pos + B.off;  // scratch of the global path
+    typename R::T* rec = (typename R::T*)C.cell_pos + B.off;
     typename R::T* vel = (typename R::T*)C.cell_vel + B.off;
     typename R::T* srec = (typename R::T*)C.srec + 2 * B.off;
     const real* s = (const real*)C.s;
@@ -648,9 +653,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     const float inv_n2 = 1.0f / (float)n2;
     auto write_search = [&](int q, int cell, real x, real y, real z) {
         const int col = (int)(((float)cell + 0.5f) * inv_n2), zc = cell - col * n2;
-        srec[q + col_off[col]] = R::make(x, y, z, q);
-        if (zc >= n2 - zs) srec[q + lo_off[col]] = R::make(x, y, z - h22, q);
-        if (zc < zs) srec[q + hi_off[col]] = R::make(x, y, z + h22, q);
+        srec[q + col_off[col]] = R::make(x, y, z, q << 2);
+        if (zc >= n2 - zs) srec[q + lo_off[col]] = R::make(x, y, z - h22, (q << 2) | 1);
+        if (zc < zs) srec[q + hi_off[col]] = R::make(x, y, z + h22, (q << 2) | 2);
     };
     if (keep) {
         // LDS entries: cell << 14 | local index (cells < 2^14, particles < 2^14)
@@ -699,6 +704,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
                     const int q = posof[k];
                     real x, y, z;
                     cell_position<real>(v[u][0], v[u][1], v[u][2], h00, h01, h10, h11, h22, x, y, z);
+                    rec[q] = R::make(x, y, z, k);
                     vel[q] = R::make(v[u][3], v[u][4], v[u][5], k);
                     write_search(q, mycell[j0 + u], x, y, z);
                 }
@@ -738,6 +744,17 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     }
 }
 
+// In-plane image shift sh0 a + sh1 b of the cell's lattice vectors for the
+// code ic = 3 (sh0 + 1) + (sh1 + 1) (0 .. 8), with a fixed rounding sequence:
+// the search and the evaluation of a pair form the same separation.
+template <typename real>
+__device__ __forceinline__ void image_shift(int ic, real h00, real h01, real h10, real h11, real& sx, real& sy) {
+    const int c0 = (ic * 11) >> 5;  // ic / 3 for 0 <= ic <= 8
+    const real a = (real)(c0 - 1), b = (real)(ic - 3 * c0 - 1);
+    sx = fma(h01, b, h00 * a);
+    sy = fma(h11, b, h10 * a);
+}
+
 template <typename real>
 __device__ __forceinline__ real inv_sqrt(real x);
 template <>
@@ -753,26 +770,33 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 //   k2 - zsub .. k2 + zsub of a row, periodic images included, are one
 //   contiguous range of the search layout; with two cells per cutoff along z
 //   the rows hold ~20% fewer candidates); each lane scans its own row range
-//   SU records at a time
-//   (lanes of one home cell read the same records) and appends accepted
-//   neighbours (0 < r < rc; the particle itself has r = 0) to its own LDS
-//   queue of QD entries (a tuning parameter, as is `drain`; neither changes
-//   the order in which a lane evaluates its neighbours, so results do not
-//   depend on them).
-//   Evaluation: a round pops one queued neighbour per lane and evaluates the
-//   pair (relative velocity including the streaming difference L d, Philox
-//   normal, force, virial).  A round runs whenever 56 or more lanes have work
-//   or a queue could overflow, and the queues are drained at the end.
+//   SU records at a time (lanes of one home cell read the same records) and
+//   appends each accepted neighbour (0 < r < rc; the particle itself has
+//   r = 0) to its own LDS queue of QD four-byte entries: the neighbour's
+//   cell-order position and its image codes.  QD, `drain` and `busy` are
+//   tuning parameters; none changes the order in which a lane evaluates its
+//   neighbours, so results do not depend on them.
+//   Evaluation: a round pops one queued neighbour per lane, reloads its
+//   position and velocity records, re-forms the separation with the same
+//   rounding as the search, and evaluates the pair (relative velocity
+//   including the streaming difference L d, Philox normal, force, virial).
+//   Rounds run when a queue could overflow, until every queue holds at most
+//   `drain` entries (and while `busy` or more lanes have work), and the
+//   queues are drained at the end.  Deep queues let most lanes hold work in
+//   every round; the float kernel is bounded to 96 VGPRs so five waves share
+//   each SIMD (the loop is latency-bound).
 // records tested per lane and search iteration for a queue of depth QD
 __host__ __device__ constexpr int scan_unroll(int qd) { return qd >= 8 ? 4 : (qd >= 4 ? 2 : 1); }
 
 template <typename real, int QD>
-__global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain, int busy, int prune) {
+__global__ __launch_bounds__(BS, sizeof(real) == 4 ? 5 : 1) void k_forces(Ctx C, int step_offset, int drain, int busy, int prune) {
     using R = Rec<real>;
     using V4 = typename R::T;
     constexpr int NW = BS / 64;
     constexpr int SU = scan_unroll(QD);
-    __shared__ V4 qbuf[QD][NW][64];                 // (dx, dy, dz, cell-order position of j)
+    // queue entry: cell-order position of j << 6 | z image (0 none, 1 below,
+    // 2 above) << 4 | in-plane image code
+    __shared__ int qbuf[QD][NW][64];
     __shared__ double red[13 * NW];
 
     int blk = xcd_local_work(blockIdx.x, gridDim.x);
@@ -785,6 +809,7 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
     const int p0 = C.blk_first[blk] - B.off;  // first cell-order position of the block
     const int pos = p0 + t;
     const bool act = pos < B.n;
+    const V4* rec = (const V4*)C.cell_pos + B.off;
     const V4* vel = (const V4*)C.cell_vel + B.off;
     const char* sbase = (const char*)((const V4*)C.srec + 2 * B.off);
     const real* s = (const real*)C.s;
@@ -846,13 +871,19 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
     real w[6] = {0, 0, 0, 0, 0, 0};
     unsigned npairs = 0;
 
+    int ic = 4;  // in-plane image code of the row being scanned
     // one evaluation round: each lane with a queued neighbour takes the oldest
     auto round = [&]() {
         if (qt > qh) {
-            const V4 e = qbuf[qh & (QD - 1)][wv][lane];
+            const int e = qbuf[qh & (QD - 1)][wv][lane];
             ++qh;
-            const real dx = e.x, dy = e.y, dz = e.z;
-            const V4 cj = vel[R::id(e)];
+            const int qj = e >> 6, zi = (e >> 4) & 3;
+            const V4 pj = rec[qj];
+            const V4 cj = vel[qj];
+            real sx, sy;
+            image_shift<real>(e & 15, h00, h01, h10, h11, sx, sy);
+            const real zj = zi == 0 ? pj.z : (zi == 1 ? pj.z - h22 : pj.z + h22);
+            const real dx = (ri0 - sx) - pj.x, dy = (ri1 - sy) - pj.y, dz = ri2 - zj;
             const real r2 = dx * dx + dy * dy + dz * dz;
             const real ir = inv_sqrt(r2);
             const real r = r2 * ir;
@@ -877,7 +908,7 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
         const real dx = px - v.x, dy = py - v.y, dz = pz - v.z;
         const real r2 = dx * dx + dy * dy + dz * dz;
         if (valid && r2 < rc2 && r2 > (real)0) {
-            qbuf[qt & (QD - 1)][wv][lane] = R::make(dx, dy, dz, R::id(v));
+            qbuf[qt & (QD - 1)][wv][lane] = (R::id(v) << 4) | ic;
             ++qt;
         }
     };
@@ -897,8 +928,11 @@ __global__ __launch_bounds__(BS) void k_forces(Ctx C, int step_offset, int drain
         m0 -= sh0 * n0;
         m1 -= sh1 * n1;
         const int gb = (m0 * n1 + m1) * (n2 + 2 * zs) + k2;
-        bx = ri0 - (h00 * (real)sh0 + h01 * (real)sh1);
-        by = ri1 - (h10 * (real)sh0 + h11 * (real)sh1);
+        ic = 3 * (sh0 + 1) + (sh1 + 1);
+        real sx, sy;
+        image_shift<real>(ic, h00, h01, h10, h11, sx, sy);
+        bx = ri0 - sx;
+        by = ri1 - sy;
         q = 0;
         qe = 0;
         int lo = 0, hi = 2 * zs + 1;
@@ -1166,8 +1200,9 @@ void launch_forces(lhmm_micro* m, const Ctx& C, int nblk, int step_offset, hipSt
     switch (m->cfg.queue_depth) {
         case 2: k_forces<real, 2><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
         case 4: k_forces<real, 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
-        case 16: k_forces<real, sizeof(real) == 4 ? 16 : 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
-        default: k_forces<real, sizeof(real) == 4 ? 8 : 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
+        case 8: k_forces<real, 8><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
+        case 32: k_forces<real, 32><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
+        default: k_forces<real, 16><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
     }
 }
 
@@ -1407,8 +1442,8 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->p = *p;
     m->n_boxes = n_boxes;
     m->precision = p->precision;
-    m->cfg.queue_depth = p->precision == LHMM_FP64 ? 4 : 8;
-    m->cfg.drain = m->cfg.queue_depth / 2;
+    m->cfg.queue_depth = 16;
+    m->cfg.drain = 8;
     m->cfg.busy_lanes = 65;
     m->cfg.bin_threads = BIN_THREADS_MAX;
     m->cfg.graph_chunk = GRAPH_CHUNK;
@@ -1422,7 +1457,8 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->box.resize(n_boxes);
     for (int b = 0; b < n_boxes; ++b) {
         const lhmm_box& in = boxes[b];
-        if (in.n_particles < 2 || in.n_chains < 0 || (long long)in.n_chains * p->chain_len > in.n_particles) {
+        if (in.n_particles < 2 || in.n_particles > (1 << 25) || in.n_chains < 0 ||
+            (long long)in.n_chains * p->chain_len > in.n_particles) {
             delete m;
             return fail(LHMM_ERR_ARG, "box %d: bad particle/chain counts", b);
         }
@@ -1738,9 +1774,8 @@ int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg) {
     g_err.clear();
     if (!m || !cfg) return fail(LHMM_ERR_ARG, "null argument");
     const int qd = cfg->queue_depth;
-    const bool qd_ok =
-        m->precision == LHMM_FP64 ? (qd == 2 || qd == 4) : (qd == 2 || qd == 4 || qd == 8 || qd == 16);
-    if (!qd_ok) return fail(LHMM_ERR_ARG, "queue_depth %d not available at this precision", qd);
+    const bool qd_ok = qd == 2 || qd == 4 || qd == 8 || qd == 16 || qd == 32;
+    if (!qd_ok) return fail(LHMM_ERR_ARG, "queue_depth must be 2, 4, 8, 16 or 32");
     // a search iteration pushes up to scan_unroll(qd) neighbours per lane
     // before it checks the queues, so a lane may hold at most qd - that many
     // when the search resumes
@@ -1841,14 +1876,12 @@ int lhmm_micro_autotune(lhmm_micro* m, const double* gradL, int32_t trial_steps,
     lhmm_micro_config cur = m->cfg;
     double cur_ms = 0.0;
     rc = trial(cur, &cur_ms);
-    const int qds32[] = {4, 8, 16}, qds64[] = {2, 4};
-    const int* qds = m->precision == LHMM_FP64 ? qds64 : qds32;
-    const int nq = m->precision == LHMM_FP64 ? 2 : 3;
-    for (int iq = 0; rc == LHMM_OK && iq < nq; ++iq) {
+    const int qds[] = {8, 16, 32};
+    for (int iq = 0; rc == LHMM_OK && iq < 3; ++iq) {
         const int qd = qds[iq];
-        // (drain, busy): drain to half / no busy rule, or rounds driven by busy lanes
+        // (drain, busy): full drain range / no busy rule, or rounds driven by busy lanes
         const int dmax = qd - scan_unroll(qd);
-        const int cand[4][2] = {{qd / 2 <= dmax ? qd / 2 : dmax, 65}, {dmax, 48}, {dmax, 56}, {0, 65}};
+        const int cand[4][2] = {{dmax, 65}, {qd / 2 <= dmax ? qd / 2 : dmax, 65}, {dmax, 56}, {0, 65}};
         for (const auto& dc : cand) {
             lhmm_micro_config c = cur;
             c.queue_depth = qd;

@@ -68,7 +68,8 @@ def test_micro_rejects_bad_arguments_and_stays_usable(torch_gpu):
         assert ei.value.code == _lib.LHMM_ERR_ARG
     with pytest.raises(_lib.LhmmError):
         m.restore([0])  # no snapshot yet
-    for kw in ({"bin_threads": 128}, {"graph_chunk": 0}, {"drain": 7}, {"prune": 2}, {"busy_lanes": 0}):
+    for kw in ({"bin_threads": 128}, {"graph_chunk": 0}, {"queue_depth": 8, "drain": 7}, {"queue_depth": 12},
+               {"prune": 2}, {"busy_lanes": 0}):
         with pytest.raises(_lib.LhmmError):
             m.set_config(**kw)
     out = m.step(G, 5).cpu().numpy()

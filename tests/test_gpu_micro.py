@@ -418,7 +418,7 @@ def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch
     _lib, inputs, micro = _mod()
     wl = inputs.tiny_boxes(4, seed_k=43)
     G = _grads(torch, wl)
-    for prec, depths in (("fp32", (2, 4, 8, 16)), ("fp64", (2, 4))):
+    for prec, depths in (("fp32", (2, 4, 8, 16, 32)), ("fp64", (2, 8, 32))):
         ref = None
         for qd in depths:
             dmax = qd - (4 if qd >= 8 else (2 if qd >= 4 else 1))  # depth less the records per search step
@@ -444,7 +444,7 @@ def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch
         assert t1 == t0 and np.array_equal(s0, s1) and np.array_equal(c0, c1) and np.array_equal(f0, f1)
         assert np.array_equal(h0, h1) and ms > 0 and m.config() == cfg
         with pytest.raises(_lib.LhmmError):
-            m.set_config(queue_depth=32)
+            m.set_config(queue_depth=64)
         with pytest.raises(_lib.LhmmError):
             m.set_config(queue_depth=2, drain=2)
         with pytest.raises(_lib.LhmmError):
