@@ -240,7 +240,7 @@ int lhmm_micro_flags(lhmm_micro* m, uint32_t* flags_out, int32_t clear);
 #define LHMM_K_KICK_DRIFT 1 /* half kick, drift, wrap, cell index            */
 #define LHMM_K_BIN 2        /* counting sort by cell (per box)               */
 #define LHMM_K_FORCES 3     /* DPD pair forces, FENE bonds, virial           */
-#define LHMM_K_KICK2 4      /* second half kick, kinetic stress              */
+#define LHMM_K_KICK2 4      /* second half kick (inside the force kernel: 0) */
 #define LHMM_K_STRESS 5     /* per-box stress of the step, accumulation      */
 #define LHMM_N_KERNELS 6
 

@@ -3,23 +3,24 @@
 //
 // One step of every box (velocity-Verlet of the micro-scale equation of
 // motion, Eq. motion, in a periodic cell deformed by the box's velocity
-// gradient; Appendix "Detailed Coupling Protocol", Step 3) is six launches
-// over a flattened index of all boxes:
-//   k_cell_step    one thread per box, FP64: mid-step cell inverse, cell
-//                  deformation h <- exp(L dt) h, Lagrange-Gauss reduction of
-//                  the in-plane basis, cell-grid size, width guard;
-//   k_kick_drift   per particle: half kick c += dt/2 (F/m - L c), drift of
-//                  the fractional coordinate with the mid-step cell, remap
-//                  by the reduction, wrap, cell index;
-//   k_bin_box      one workgroup per box: counting sort of the particles by
-//                  cell in LDS (histogram, scan, scatter), then each cell's
-//                  list sorted by id so every sum has a fixed order;
+// gradient; Appendix "Detailed Coupling Protocol", Step 3) is three launches
+// over a flattened index of all boxes (five with unfused binning):
+//   k_bin_box      one workgroup per box: the cell step (FP64: mid-step
+//                  cell inverse, deformation h <- exp(L dt) h,
+//                  Lagrange-Gauss reduction of the in-plane basis, cell
+//                  grid, width guard), the half kick c += dt/2 (F/m - L c)
+//                  and drift of the fractional coordinates with the
+//                  mid-step cell (remap by the reduction, wrap, cell index),
+//                  then a counting sort of the particles by cell in LDS with
+//                  each cell sorted by id so every sum has a fixed order
+//                  (k_cell_step and k_kick_drift run the first two parts as
+//                  separate launches when binning is not fused);
 //   k_forces       per particle: conservative + dissipative + random pair
 //                  forces (Eqs. conservative, dissipative, random) over the
-//                  27 neighbour cells, FENE springs (Eq. fene_force), and the
-//                  block's virial partial sums in FP64;
-//   k_kick2        per particle: second half kick, kinetic partial sums;
-//   k_box_stress   one thread per box: virial stress of the step (Eqs.
+//                  neighbour cells, FENE springs (Eq. fene_force), the
+//                  second half kick with the final force, and the block's
+//                  virial and kinetic partial sums in FP64;
+//   k_box_stress   one wave per box: virial stress of the step (Eqs.
 //                  IKtotal, kinetic_stress, potential_stress with a uniform
 //                  weight over the cell), accumulated over the call.
 // The per-particle kernels run over work blocks of BS particles; a block
@@ -789,7 +790,8 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 __host__ __device__ constexpr int scan_unroll(int qd) { return qd >= 8 ? 4 : (qd >= 4 ? 2 : 1); }
 
 template <typename real, int QD>
-__global__ __launch_bounds__(BS, sizeof(real) == 4 ? 5 : 1) void k_forces(Ctx C, int step_offset, int drain, int busy, int prune) {
+__global__ __launch_bounds__(BS, sizeof(real) == 4 ? 5 : 1) void k_forces(Ctx C, int step_offset, int drain, int busy,
+                                                                          int prune, int kick) {
     using R = Rec<real>;
     using V4 = typename R::T;
     constexpr int NW = BS / 64;
@@ -797,7 +799,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? 5 : 1) void k_forces(Ctx C,
     // queue entry: cell-order position of j << 6 | z image (0 none, 1 below,
     // 2 above) << 4 | in-plane image code
     __shared__ int qbuf[QD][NW][64];
-    __shared__ double red[13 * NW];
+    __shared__ double red[19 * NW];
 
     int blk = xcd_local_work(blockIdx.x, gridDim.x);
     if (C.blk_list) blk = C.blk_list[blk];
@@ -1021,47 +1023,36 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? 5 : 1) void k_forces(Ctx C,
         }
         f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
     }
-    double v[13];
+    double v[19];
     for (int k = 0; k < 6; ++k) {
         v[k] = (double)w[k];
         v[6 + k] = (double)wf[k];
+        v[13 + k] = 0.0;
     }
     v[12] = (double)npairs;
-    block_sum<13>(v, red);
+    // second half kick of the velocity-Verlet step, c += dt/2 (F/m - L c),
+    // with the particle's final force, and the kinetic partial sums m c c
+    if (kick && act) {
+        const int i = B.off + own_id;
+        real* c = (real*)C.c;
+        const real hdt = (real)(0.5 * C.dt), im = (real)C.inv_mass;
+        real c0 = ci0, c1 = ci1, c2 = ci2;
+        const real lc0 = L00 * c0 + L01 * c1, lc1 = L10 * c0 + L11 * c1;
+        c0 += hdt * (fx * im - lc0);
+        c1 += hdt * (fy * im - lc1);
+        c2 += hdt * (fz * im);
+        c[i] = c0; c[N + i] = c1; c[2 * N + i] = c2;
+        const double mm = C.mass, x = (double)c0, y = (double)c1, z = (double)c2;
+        v[13] = mm * x * x; v[14] = mm * y * y; v[15] = mm * z * z;
+        v[16] = mm * x * y; v[17] = mm * x * z; v[18] = mm * y * z;
+    }
+    block_sum<19>(v, red);
     if (threadIdx.x == 0) {
         for (int k = 0; k < 12; ++k) C.part_vir[12 * blk + k] = v[k];
         C.part_pairs[blk] = (unsigned)v[12];
+        if (kick)
+            for (int k = 0; k < 6; ++k) C.part_kin[6 * blk + k] = v[13 + k];
     }
-}
-
-template <typename real>
-__global__ __launch_bounds__(BS) void k_kick2(Ctx C) {
-    __shared__ double sh[6 * (BS / 64)];
-    const int blk = C.blk_list ? C.blk_list[blockIdx.x] : (int)blockIdx.x;
-    const int b = C.blk_box[blk];
-    const BoxInfo B = C.box[b];
-    const BoxDyn& D = C.dyn[b];
-    const int i = C.blk_first[blk] + (int)threadIdx.x;
-    const int N = C.n_total;
-    double k6[6] = {0, 0, 0, 0, 0, 0};
-    if (i < B.off + B.n) {
-        real* c = (real*)C.c;
-        const real* f = (const real*)C.f;
-        const real hdt = (real)(0.5 * C.dt), im = (real)C.inv_mass;
-        real c0 = c[i], c1 = c[N + i], c2 = c[2 * N + i];
-        const real L0 = (real)D.L[0], L1 = (real)D.L[1], L3 = (real)D.L[3], L4 = (real)D.L[4];
-        const real lc0 = L0 * c0 + L1 * c1, lc1 = L3 * c0 + L4 * c1;
-        c0 += hdt * (f[i] * im - lc0);
-        c1 += hdt * (f[N + i] * im - lc1);
-        c2 += hdt * (f[2 * N + i] * im);
-        c[i] = c0; c[N + i] = c1; c[2 * N + i] = c2;
-        const double m = C.mass, x = (double)c0, y = (double)c1, z = (double)c2;
-        k6[0] = m * x * x; k6[1] = m * y * y; k6[2] = m * z * z;
-        k6[3] = m * x * y; k6[4] = m * x * z; k6[5] = m * y * z;
-    }
-    block_sum<6>(k6, sh);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 6; ++k) C.part_kin[6 * blk + k] = k6[k];
 }
 
 // One wave per box: the step's stress, sigma = -(K + W)/V, by part.  Lane l
@@ -1194,15 +1185,16 @@ void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse)
     }
 }
 
+// kick = 1: a full step's force pass, which ends with the second half kick
 template <typename real>
-void launch_forces(lhmm_micro* m, const Ctx& C, int nblk, int step_offset, hipStream_t st) {
+void launch_forces(lhmm_micro* m, const Ctx& C, int nblk, int step_offset, int kick, hipStream_t st) {
     const int drain = m->cfg.drain, busy = m->cfg.busy_lanes, prune = m->cfg.prune;
     switch (m->cfg.queue_depth) {
-        case 2: k_forces<real, 2><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
-        case 4: k_forces<real, 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
-        case 8: k_forces<real, 8><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
-        case 32: k_forces<real, 32><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
-        default: k_forces<real, 16><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune); break;
+        case 2: k_forces<real, 2><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
+        case 4: k_forces<real, 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
+        case 8: k_forces<real, 8><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
+        case 32: k_forces<real, 32><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
+        default: k_forces<real, 16><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
     }
 }
 
@@ -1219,11 +1211,8 @@ void launch_step_kernels(lhmm_micro* m, const Ctx& C, int nbox, int nblk, int st
         k_kick_drift<real><<<nblk, BS, 0, m->stream>>>(C, advance ? 1 : 0);
         launch_bin<real>(m, C, nbox, m->stream, -1);
     }
-    launch_forces<real>(m, C, nblk, step_offset, m->stream);
-    if (full_step) {
-        k_kick2<real><<<nblk, BS, 0, m->stream>>>(C);
-        k_box_stress<<<nbox, 64, 0, m->stream>>>(C);
-    }
+    launch_forces<real>(m, C, nblk, step_offset, full_step ? 1 : 0, m->stream);
+    if (full_step) k_box_stress<<<nbox, 64, 0, m->stream>>>(C);
 }
 
 // One step with an event pair around each kernel (ev: 2 * LHMM_N_KERNELS events).
@@ -1244,10 +1233,9 @@ void launch_step_timed(lhmm_micro* m, hipEvent_t* ev) {
     launch_bin<real>(m, C, m->n_boxes, st, fused ? 1 : -1);
     (void)hipEventRecord(ev[5], st);
     (void)hipEventRecord(ev[6], st);
-    launch_forces<real>(m, C, m->n_blocks, 1, st);
+    launch_forces<real>(m, C, m->n_blocks, 1, 1, st);
     (void)hipEventRecord(ev[7], st);
-    (void)hipEventRecord(ev[8], st);
-    k_kick2<real><<<m->n_blocks, BS, 0, st>>>(C);
+    (void)hipEventRecord(ev[8], st);  // the second half kick runs inside the force kernel
     (void)hipEventRecord(ev[9], st);
     (void)hipEventRecord(ev[10], st);
     k_box_stress<<<m->n_boxes, 64, 0, st>>>(C);
