@@ -175,7 +175,12 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
  *                scans the full 27-cell stencil;
  *   fuse_bin:    1 runs the cell step and the half kick and drift inside the
  *                per-box binning workgroup (two launches fewer per step;
- *                lhmm_micro_time then reports their time under binning). */
+ *                lhmm_micro_time then reports their time under binning);
+ *   groups:      1 .. 4: with fused binning, a captured step splits the
+ *                boxes by particle count into this many groups of about
+ *                equal particle numbers, each binned and force-evaluated on
+ *                its own stream, so that the force pass of small boxes runs
+ *                while large boxes are still being binned (1: one stream). */
 typedef struct {
     int32_t queue_depth;
     int32_t drain;
@@ -184,6 +189,7 @@ typedef struct {
     int32_t graph_chunk;
     int32_t prune;
     int32_t fuse_bin;
+    int32_t groups;
 } lhmm_micro_config;
 
 /* Set / read the launch parameters (defaults: depth 16, drain 8; busy rule
@@ -195,7 +201,7 @@ int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg);
 int lhmm_micro_get_config(lhmm_micro* m, lhmm_micro_config* cfg);
 
 /* Choose the launch parameters for the loaded boxes by timing: a coordinate
- * search over (queue_depth, drain, busy_lanes), then bin_threads, fuse_bin, prune, graph_chunk,
+ * search over (queue_depth, drain, busy_lanes), then bin_threads, fuse_bin, prune, groups, graph_chunk,
  * each candidate timed over trial_steps steps (after trial_steps warm-up
  * steps) under gradL (DEVICE n_boxes x 9) with HIP events.  The particle
  * state, cells, flags and random-force counter are put back after every

@@ -67,7 +67,8 @@ class LhmmSphParams(C.Structure):
 
 
 class LhmmMicroConfig(C.Structure):
-    _fields_ = [(k, C.c_int32) for k in ("queue_depth", "drain", "busy_lanes", "bin_threads", "graph_chunk", "prune", "fuse_bin")]
+    _fields_ = [(k, C.c_int32) for k in ("queue_depth", "drain", "busy_lanes", "bin_threads", "graph_chunk", "prune", "fuse_bin",
+                                         "groups")]
 
 
 class LhmmSurParams(C.Structure):

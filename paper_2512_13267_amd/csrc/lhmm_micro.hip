@@ -50,6 +50,7 @@ constexpr int BS = 256;                 // particles per work block
 constexpr int BIN_THREADS_MAX = 1024;   // largest binning workgroup (256, 512 or 1024 threads)
 constexpr int MAX_CELLS_PER_BOX = 15360;  // binning LDS: cell starts and three per-column offsets (120 KiB)
 constexpr int GRAPH_CHUNK = 50;         // default steps per captured graph
+constexpr int MAX_GROUPS = 4;           // overlapped box groups of a captured step
 
 thread_local std::string g_err;
 
@@ -428,13 +429,22 @@ __device__ void cell_step_box(const Ctx& C, int b, int advance) {
 }
 
 template <typename real>
+__device__ __forceinline__ void cell_coords(real s0, real s1, real s2, const int* nc, int& k0, int& k1, int& k2) {
+    k0 = min(max((int)(s0 * (real)nc[0]), 0), nc[0] - 1);
+    k1 = min(max((int)(s1 * (real)nc[1]), 0), nc[1] - 1);
+    k2 = min(max((int)(s2 * (real)nc[2]), 0), nc[2] - 1);
+}
+
+template <typename real>
 __device__ __forceinline__ int cell_of(real s0, real s1, real s2, const int* nc) {
-    int k0 = (int)(s0 * (real)nc[0]), k1 = (int)(s1 * (real)nc[1]), k2 = (int)(s2 * (real)nc[2]);
-    k0 = min(max(k0, 0), nc[0] - 1);
-    k1 = min(max(k1, 0), nc[1] - 1);
-    k2 = min(max(k2, 0), nc[2] - 1);
+    int k0, k1, k2;
+    cell_coords(s0, s1, s2, nc, k0, k1, k2);
     return (k0 * nc[1] + k1) * nc[2] + k2;
 }
+
+// a / d for 0 <= a < 2^22 and d >= 1, given inv = 1.0f / d: single-precision
+// rounding moves (a + 1/2) / d by less than the 1/(2d) it keeps from integers
+__device__ __forceinline__ int div_small(int a, float inv) { return (int)(((float)a + 0.5f) * inv); }
 
 template <typename real>
 __device__ __forceinline__ real wrap01(real x) {
@@ -443,9 +453,11 @@ __device__ __forceinline__ real wrap01(real x) {
 }
 
 // Half kick, drift in fractional coordinates, remap after a reduction,
-// wrap, and the particle's cell; returns the cell.
+// wrap, and the particle's cell; returns the cell (stored to pcell when
+// store_cell is set).
 template <typename real>
-__device__ __forceinline__ int kick_drift_particle(const Ctx& C, const BoxDyn& D, int i, int advance) {
+__device__ __forceinline__ int kick_drift_particle(const Ctx& C, const BoxDyn& D, int i, int advance,
+                                                   bool store_cell = true) {
     const int N = C.n_total;
     real* s = (real*)C.s;
     real* c = (real*)C.c;
@@ -474,7 +486,7 @@ __device__ __forceinline__ int kick_drift_particle(const Ctx& C, const BoxDyn& D
         s[i] = s0; s[N + i] = s1; s[2 * N + i] = s2;
     }
     const int cell = cell_of(s0, s1, s2, D.nc);
-    C.pcell[i] = cell;
+    if (store_cell) C.pcell[i] = cell;
     return cell;
 }
 
@@ -586,7 +598,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = (int)threadIdx.x + (j0 + u) * BIN_THREADS;
-                cell[u] = k < B.n ? kick_drift_particle<real>(C, D, B.off + k, fuse) : -1;
+                cell[u] = k < B.n ? kick_drift_particle<real>(C, D, B.off + k, fuse, !keep) : -1;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -623,17 +635,18 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     });
     __syncthreads();
     const int n2 = D.nc[2], zs = B.zsub, gn2 = n2 + 2 * zs, ncol = D.nc[0] * D.nc[1];
+    const float inv_gn2 = 1.0f / (float)gn2;
     block_scan<BIN_THREADS>(
         ncol * gn2, wsum,
         [&](int g) {
-            const int col = g / gn2, zg = g - col * gn2;
+            const int col = div_small(g, inv_gn2), zg = g - col * gn2;
             const int k = col * n2 + (zg < zs ? n2 - zs + zg : (zg >= zs + n2 ? zg - zs - n2 : zg - zs));
             return cnt[k + 1] - cnt[k];
         },
         [&](int g, int excl) {
             gstart[g] = excl;
             if (g == ncol * gn2) return;
-            const int col = g / gn2, zg = g - col * gn2;
+            const int col = div_small(g, inv_gn2), zg = g - col * gn2;
             if (zg == 0) lo_off[col] = excl - cnt[col * n2 + n2 - zs];
             if (zg == zs) col_off[col] = excl - cnt[col * n2];
             if (zg == zs + n2) hi_off[col] = excl - cnt[col * n2];
@@ -649,23 +662,25 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
     const real h22 = (real)D.h[8];
     // the position record of cell-order position q (cell `cell`) in its
-    // search-layout slot and, for the zsub bottom or top cells, its image's slot;
-    // cell / n2 in single precision is exact for cells < 2^22
+    // search-layout slot and, for the zsub bottom or top cells, its image's slot
     const float inv_n2 = 1.0f / (float)n2;
     auto write_search = [&](int q, int cell, real x, real y, real z) {
-        const int col = (int)(((float)cell + 0.5f) * inv_n2), zc = cell - col * n2;
+        const int col = div_small(cell, inv_n2), zc = cell - col * n2;
         srec[q + col_off[col]] = R::make(x, y, z, q << 2);
         if (zc >= n2 - zs) srec[q + lo_off[col]] = R::make(x, y, z - h22, (q << 2) | 1);
         if (zc < zs) srec[q + hi_off[col]] = R::make(x, y, z + h22, (q << 2) | 2);
     };
     if (keep) {
         // LDS entries: cell << 14 | local index (cells < 2^14, particles < 2^14)
+        int slot[KEEP];
 #pragma unroll
         for (int j = 0; j < KEEP; ++j) {
             const int k = (int)threadIdx.x + j * BIN_THREADS;
-            if (k >= B.n) break;
-            lidx[atomicAdd(&cnt[mycell[j]], 1)] = (mycell[j] << 14) | k;
+            slot[j] = k < B.n ? atomicAdd(&cnt[mycell[j]], 1) : -1;
         }
+#pragma unroll
+        for (int j = 0; j < KEEP; ++j)
+            if (slot[j] >= 0) lidx[slot[j]] = (mycell[j] << 14) | ((int)threadIdx.x + j * BIN_THREADS);
         __syncthreads();
         // cnt[k] now ends cell k; sort every cell's entries by index (a few each)
         for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) {
@@ -821,13 +836,15 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? 5 : 1) void k_forces(Ctx C,
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
     const real h22 = (real)D.h[8];
     real ri0 = 0, ri1 = 0, ri2 = 0, ci0 = 0, ci1 = 0, ci2 = 0;
+    real own_s0 = 0, own_s1 = 0, own_s2 = 0;
     int own_id = 0;
     if (act) {
         const V4 u = vel[pos];
         ci0 = u.x; ci1 = u.y; ci2 = u.z;
         own_id = R::id(u);
         const int g = B.off + own_id;
-        cell_position<real>(s[g], s[N + g], s[2 * N + g], h00, h01, h10, h11, h22, ri0, ri1, ri2);
+        own_s0 = s[g]; own_s1 = s[N + g]; own_s2 = s[2 * N + g];
+        cell_position<real>(own_s0, own_s1, own_s2, h00, h01, h10, h11, h22, ri0, ri1, ri2);
     }
     const real L00 = (real)D.L[0], L01 = (real)D.L[1], L10 = (real)D.L[3], L11 = (real)D.L[4];
     const int n0 = D.nc[0], n1 = D.nc[1], n2 = D.nc[2], zs = B.zsub;
@@ -839,12 +856,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? 5 : 1) void k_forces(Ctx C,
     const int* gstart = C.gcell_start + B.gcell_off;
 
     int k0 = 0, k1 = 0, k2 = 0;
-    if (act) {
-        const int pc = C.pcell[B.off + own_id];
-        k2 = pc % n2;
-        k1 = (pc / n2) % n1;
-        k0 = pc / (n1 * n2);
-    }
+    if (act) cell_coords(own_s0, own_s1, own_s2, D.nc, k0, k1, k2);  // as the binning found it
     // Stencil pruning: distances from the particle to the planes bounding
     // its cell (fractional gap x perpendicular width of the cell); any point
     // of a neighbour cell across such a plane is at least that far away.  A
@@ -1169,14 +1181,28 @@ struct lhmm_micro {
     // captured the second time it is asked for (history replays repeat it)
     std::map<std::tuple<int, int, int>, hipGraphExec_t> sub_graphs;
     std::map<std::tuple<int, int, int>, int> sub_seen;
+    // overlapped groups of boxes (cfg.groups > 1): boxes by particle count,
+    // smallest first; each group's binning and forces run on their own
+    // stream inside the captured step, joined before the stress
+    struct Group {
+        int* d_sel = nullptr;
+        int* d_blk = nullptr;
+        int n_sel = 0, nblk = 0, lds_cells = 0, lds_parts = 0;
+    };
+    std::vector<Group> groups;
+    hipStream_t aux[MAX_GROUPS - 1] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[MAX_GROUPS - 1] = {};
     Ctx ctx{};
 };
 
 namespace {
 
 template <typename real>
-void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse) {
-    const int lc = m->bin_lds_cells, lp = m->bin_lds_parts;
+void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse, int lc = 0, int lp = 0) {
+    if (lc == 0) {
+        lc = m->bin_lds_cells;
+        lp = m->bin_lds_parts;
+    }
     const size_t bytes = sizeof(int) * ((size_t)lc + 3 * (size_t)(lc / 3 + 1) + (size_t)lp);
     switch (m->cfg.bin_threads) {
         case 256: k_bin_box<real, 256><<<nbox, 256, bytes, st>>>(C, lc, lp, fuse); break;
@@ -1242,6 +1268,30 @@ void launch_step_timed(lhmm_micro* m, hipEvent_t* ev) {
     (void)hipEventRecord(ev[11], st);
 }
 
+// One captured step with the boxes in overlapped groups: fork, each group's
+// fused binning and forces on its own stream, join, then every box's stress.
+template <typename real>
+void launch_step_grouped(lhmm_micro* m) {
+    const int G = (int)m->groups.size();
+    (void)hipEventRecord(m->ev_fork, m->stream);
+    for (int g = 1; g < G; ++g) (void)hipStreamWaitEvent(m->aux[g - 1], m->ev_fork, 0);
+    for (int g = 0; g < G; ++g) {
+        const lhmm_micro::Group& gr = m->groups[g];
+        hipStream_t st = g == 0 ? m->stream : m->aux[g - 1];
+        Ctx C = m->ctx;
+        C.sel = gr.d_sel;
+        C.blk_list = gr.d_blk;
+        C.n_sel = gr.n_sel;
+        launch_bin<real>(m, C, gr.n_sel, st, 1, gr.lds_cells, gr.lds_parts);
+        launch_forces<real>(m, C, gr.nblk, 1, 1, st);
+    }
+    for (int g = 1; g < G; ++g) {
+        (void)hipEventRecord(m->ev_join[g - 1], m->aux[g - 1]);
+        (void)hipStreamWaitEvent(m->stream, m->ev_join[g - 1], 0);
+    }
+    k_box_stress<<<m->n_boxes, 64, 0, m->stream>>>(m->ctx);
+}
+
 void launch_one_step(lhmm_micro* m) {
     if (m->precision == LHMM_FP64)
         launch_step_kernels<double>(m, m->ctx, m->n_boxes, m->n_blocks, 1, true, true);
@@ -1270,8 +1320,16 @@ int get_graph(lhmm_micro* m, int nsteps, hipGraphExec_t* out) {
         return LHMM_OK;
     }
     hipGraph_t g = nullptr;
+    const bool grouped = m->groups.size() > 1 && m->cfg.fuse_bin;
     HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < nsteps; ++k) launch_one_step(m);
+    for (int k = 0; k < nsteps; ++k) {
+        if (!grouped)
+            launch_one_step(m);
+        else if (m->precision == LHMM_FP64)
+            launch_step_grouped<double>(m);
+        else
+            launch_step_grouped<float>(m);
+    }
     HIPCHK(hipStreamEndCapture(m->stream, &g));
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -1311,6 +1369,16 @@ void release(lhmm_micro* m) {
                     m->d_sel, m->d_blk_list, m->d_snap_s, m->d_snap_c, m->d_snap_f, m->d_snap_dyn};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (auto& gr : m->groups) {
+        if (gr.d_sel) (void)hipFree(gr.d_sel);
+        if (gr.d_blk) (void)hipFree(gr.d_blk);
+    }
+    m->groups.clear();
+    for (int g = 0; g < MAX_GROUPS - 1; ++g) {
+        if (m->aux[g]) (void)hipStreamDestroy(m->aux[g]);
+        if (m->ev_join[g]) (void)hipEventDestroy(m->ev_join[g]);
+    }
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
     if (m->h_sel) (void)hipHostFree(m->h_sel);
     if (m->ev_sel) (void)hipEventDestroy(m->ev_sel);
     if (m->ev_in) (void)hipEventDestroy(m->ev_in);
@@ -1351,6 +1419,64 @@ int launch_subset_steps(lhmm_micro* m, const Ctx& C, int n_sel, int nblk, int le
         HIPCHK(hipGraphLaunch(it->second, m->stream));
     } else {
         for (int k = 0; k < len; ++k) launch_one_step_sel(m, C, n_sel, nblk);
+    }
+    return LHMM_OK;
+}
+
+// Partition the boxes into G groups of about equal particle counts, by
+// particle count (smallest first), with their block lists and binning LDS.
+int prepare_groups(lhmm_micro* m, int G) {
+    HIPCHK(hipStreamSynchronize(m->stream));
+    for (auto& gr : m->groups) {
+        if (gr.d_sel) (void)hipFree(gr.d_sel);
+        if (gr.d_blk) (void)hipFree(gr.d_blk);
+    }
+    m->groups.clear();
+    if (G <= 1) return LHMM_OK;
+    if (!m->ev_fork) {
+        HIPCHK(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+        for (int g = 0; g < MAX_GROUPS - 1; ++g) {
+            HIPCHK(hipStreamCreateWithFlags(&m->aux[g], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&m->ev_join[g], hipEventDisableTiming));
+        }
+    }
+    std::vector<int> order(m->n_boxes);
+    for (int b = 0; b < m->n_boxes; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return m->box[a].n < m->box[b].n; });
+    std::vector<std::vector<int>> members(G);
+    long long acc = 0;
+    for (int b : order) {
+        int g = (int)(acc * G / std::max(1LL, m->n_total));
+        members[std::min(g, G - 1)].push_back(b);
+        acc += m->box[b].n;
+    }
+    for (int g = 0; g < G; ++g) {
+        if (members[g].empty()) continue;
+        std::sort(members[g].begin(), members[g].end());
+        lhmm_micro::Group gr;
+        std::vector<int> blks;
+        int max_cells = 0, max_n = 0;
+        for (int b : members[g]) {
+            const BoxInfo& B = m->box[b];
+            for (int k = 0; k < B.nblk; ++k) blks.push_back(B.blk_off + k);
+            max_cells = std::max(max_cells, B.cell_cap + 1);
+            max_n = std::max(max_n, B.n);
+        }
+        gr.n_sel = (int)members[g].size();
+        gr.nblk = (int)blks.size();
+        gr.lds_cells = max_cells;
+        const int fixed = max_cells + 3 * (max_cells / 3 + 1);
+        const int room = m->bin_lds_cells + 3 * (m->bin_lds_cells / 3 + 1) + m->bin_lds_parts - fixed;
+        gr.lds_parts = std::max(0, std::min(2 * max_n, room));
+        int rc = dalloc(&gr.d_sel, gr.n_sel);
+        if (rc == LHMM_OK) rc = dalloc(&gr.d_blk, gr.nblk);
+        if (rc != LHMM_OK) {
+            if (gr.d_sel) (void)hipFree(gr.d_sel);
+            return rc;
+        }
+        m->groups.push_back(gr);
+        HIPCHK(hipMemcpy(gr.d_sel, members[g].data(), sizeof(int) * gr.n_sel, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(gr.d_blk, blks.data(), sizeof(int) * gr.nblk, hipMemcpyHostToDevice));
     }
     return LHMM_OK;
 }
@@ -1437,6 +1563,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->cfg.graph_chunk = GRAPH_CHUNK;
     m->cfg.prune = 0;
     m->cfg.fuse_bin = 1;
+    m->cfg.groups = 2;
     m->real_size = p->precision == LHMM_FP64 ? sizeof(double) : sizeof(float);
     m->user_stream = (hipStream_t)stream;
 
@@ -1637,6 +1764,12 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     C.inv_R02 = 1.0 / (p->R0 * p->R0);
     C.key0 = (unsigned)(p->seed & 0xFFFFFFFFull);
     C.key1 = (unsigned)(p->seed >> 32);
+    rc = prepare_groups(m, m->cfg.groups);
+    if (rc != LHMM_OK) {
+        release(m);
+        delete m;
+        return rc;
+    }
     *out = m;
     return LHMM_OK;
 }
@@ -1775,14 +1908,16 @@ int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg) {
     if (cfg->graph_chunk < 1 || cfg->graph_chunk > 1000) return fail(LHMM_ERR_ARG, "graph_chunk must be 1..1000");
     if (cfg->prune != 0 && cfg->prune != 1) return fail(LHMM_ERR_ARG, "prune must be 0 or 1");
     if (cfg->fuse_bin != 0 && cfg->fuse_bin != 1) return fail(LHMM_ERR_ARG, "fuse_bin must be 0 or 1");
+    if (cfg->groups < 1 || cfg->groups > MAX_GROUPS) return fail(LHMM_ERR_ARG, "groups must be 1..%d", MAX_GROUPS);
     HIPCHK(hipStreamSynchronize(m->stream));
     for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
     m->graphs.clear();
     for (auto& kv : m->sub_graphs) (void)hipGraphExecDestroy(kv.second);
     m->sub_graphs.clear();
     m->sub_seen.clear();
+    const bool regroup = cfg->groups != m->cfg.groups;
     m->cfg = *cfg;
-    return LHMM_OK;
+    return regroup ? prepare_groups(m, cfg->groups) : LHMM_OK;
 }
 
 int lhmm_micro_get_config(lhmm_micro* m, lhmm_micro_config* cfg) {
@@ -1911,6 +2046,17 @@ int lhmm_micro_autotune(lhmm_micro* m, const double* gradL, int32_t trial_steps,
         if (rc != LHMM_OK || pr == cur.prune) continue;
         lhmm_micro_config c = cur;
         c.prune = pr;
+        double ms = 0.0;
+        rc = trial(c, &ms);
+        if (rc == LHMM_OK && ms < cur_ms) {
+            cur = c;
+            cur_ms = ms;
+        }
+    }
+    for (int gr : {1, 2, 3}) {
+        if (rc != LHMM_OK || gr == cur.groups) continue;
+        lhmm_micro_config c = cur;
+        c.groups = gr;
         double ms = 0.0;
         rc = trial(c, &ms);
         if (rc == LHMM_OK && ms < cur_ms) {

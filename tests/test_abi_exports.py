@@ -37,6 +37,7 @@ def test_binding_struct_layout_matches_header():
     assert ctypes.sizeof(_lib.LhmmBox) == 16 + 72
     assert ctypes.sizeof(_lib.LhmmSphParams) == 13 * 8 + 2 * 4
     assert ctypes.sizeof(_lib.LhmmSurParams) == 5 * 4
+    assert ctypes.sizeof(_lib.LhmmMicroConfig) == 8 * 4
     assert ctypes.sizeof(_lib.LhmmHybridParams) == 8 * 4
     assert ctypes.sizeof(_lib.LhmmHybridStats) == 2 * 8 + 4 * 4
     assert _lib.LhmmBox.h0.offset == 16

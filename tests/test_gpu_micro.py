@@ -412,8 +412,9 @@ def test_snapshot_restore_returns_boxes_to_saved_state(torch_gpu):
 
 def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch_gpu):
     """Every launch configuration (queue depth, drain, busy lanes, binning
-    workgroup, graph chunk, stencil pruning, fused binning) gives the same
-    trajectory bit for bit; the autotuner puts the state and counter back."""
+    workgroup, graph chunk, stencil pruning, fused binning, overlapped box
+    groups) gives the same trajectory bit for bit; the autotuner puts the
+    state and counter back."""
     torch = torch_gpu
     _lib, inputs, micro = _mod()
     wl = inputs.tiny_boxes(4, seed_k=43)
@@ -423,12 +424,12 @@ def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch
         for qd in depths:
             dmax = qd - (4 if qd >= 8 else (2 if qd >= 4 else 1))  # depth less the records per search step
             for drain, busy in sorted({(0, 65), (min(qd // 2, dmax), 65), (dmax, 48)}):
-                for bt, prune, fuse in ((256, 1, 0), (1024, 0, 0), (512, 0, 1)):
-                    print(f"config {prec} qd={qd} drain={drain} busy={busy} bin={bt} prune={prune} fuse={fuse}",
-                          flush=True)
+                for bt, prune, fuse, groups in ((256, 1, 0, 2), (1024, 0, 0, 1), (512, 0, 1, 3), (1024, 0, 1, 1)):
+                    print(f"config {prec} qd={qd} drain={drain} busy={busy} bin={bt} prune={prune} fuse={fuse} "
+                          f"groups={groups}", flush=True)
                     m = micro.from_workload(wl, precision=prec)
                     m.set_config(queue_depth=qd, drain=drain, busy_lanes=busy, bin_threads=bt, graph_chunk=7,
-                                 prune=prune, fuse_bin=fuse)
+                                 prune=prune, fuse_bin=fuse, groups=groups)
                     out = m.step(G, 20).cpu().numpy()
                     s, c, h, st = m.get_state()
                     if ref is None:
@@ -445,6 +446,8 @@ def test_launch_configs_give_identical_trajectories_and_tuning_keeps_state(torch
         assert np.array_equal(h0, h1) and ms > 0 and m.config() == cfg
         with pytest.raises(_lib.LhmmError):
             m.set_config(queue_depth=64)
+        with pytest.raises(_lib.LhmmError):
+            m.set_config(groups=5)
         with pytest.raises(_lib.LhmmError):
             m.set_config(queue_depth=2, drain=2)
         with pytest.raises(_lib.LhmmError):
@@ -472,21 +475,25 @@ def test_pruning_keeps_every_pair_on_the_full_batch(torch_gpu):
         assert np.array_equal(a, b)
 
 
-def test_fused_binning_on_the_full_batch_and_subsets(torch_gpu):
+def test_fused_binning_and_box_groups_on_the_full_batch_and_subsets(torch_gpu):
     """Fused cell step + kick-drift + binning equals the separate kernels on
-    the benchmark batch (graph replays) and on subset steps."""
+    the benchmark batch (graph replays) and on subset steps, with the boxes
+    on one stream or in two or three overlapped groups."""
     torch = torch_gpu
     _lib, inputs, micro = _mod()
     wl = inputs.batch()
     G = _grads(torch, wl)
     res = []
-    for fuse in (0, 1):
+    for fuse, groups in ((0, 1), (1, 1), (1, 2), (1, 3)):
+        print(f"fuse={fuse} groups={groups}", flush=True)
         m = micro.from_workload(wl, precision="fp32")
-        m.set_config(fuse_bin=fuse)
+        m.set_config(fuse_bin=fuse, groups=groups)
         out = m.step(G, 30).cpu().numpy()
         sub = m.step_subset(G, 10, [0, 7, 100, 255]).cpu().numpy()
+        out2 = m.step(G, 7).cpu().numpy()
         s, c, h, st, f = m.get_state(with_forces=True)
-        res.append((out, sub, s, c, f))
+        res.append((out, sub, out2, s, c, f))
         m.close()
-    for a, b in zip(res[0], res[1]):
-        assert np.array_equal(a, b)
+    for r in res[1:]:
+        for a, b in zip(res[0], r):
+            assert np.array_equal(a, b)
