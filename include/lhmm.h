@@ -192,8 +192,8 @@ typedef struct {
     int32_t groups;
 } lhmm_micro_config;
 
-/* Set / read the launch parameters (defaults: depth 16, drain 8; busy rule
- * off; 1024 binning threads; fused binning;
+/* Set / read the launch parameters (defaults: depth 16, drain 12; busy rule
+ * off; 1024 binning threads; fused binning; two box groups;
  * 50-step graphs; no pruning: with
  * cells barely wider than the cutoff it skips little and costs more).  Set waits for the
  * engine and drops its captured graphs.  Errors: ARG. */

@@ -804,9 +804,12 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 // records tested per lane and search iteration for a queue of depth QD
 __host__ __device__ constexpr int scan_unroll(int qd) { return qd >= 8 ? 4 : (qd >= 4 ? 2 : 1); }
 
-template <typename real, int QD>
-__global__ __launch_bounds__(BS, sizeof(real) == 4 ? 5 : 1) void k_forces(Ctx C, int step_offset, int drain, int busy,
-                                                                          int prune, int kick) {
+// PRUNE selects the stencil-pruning variant; without it the float kernel
+// fits 80 VGPRs, six waves per SIMD.
+template <typename real, int QD, bool PRUNE>
+__global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k_forces(Ctx C, int step_offset, int drain,
+                                                                                        int busy, int kick) {
+    constexpr bool prune = PRUNE;
     using R = Rec<real>;
     using V4 = typename R::T;
     constexpr int NW = BS / 64;
@@ -1214,14 +1217,22 @@ void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse,
 // kick = 1: a full step's force pass, which ends with the second half kick
 template <typename real>
 void launch_forces(lhmm_micro* m, const Ctx& C, int nblk, int step_offset, int kick, hipStream_t st) {
-    const int drain = m->cfg.drain, busy = m->cfg.busy_lanes, prune = m->cfg.prune;
+    const int drain = m->cfg.drain, busy = m->cfg.busy_lanes;
+#define LHMM_FORCES(QD)                                                                 \
+    do {                                                                                \
+        if (m->cfg.prune)                                                               \
+            k_forces<real, QD, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);  \
+        else                                                                            \
+            k_forces<real, QD, false><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick); \
+    } while (0)
     switch (m->cfg.queue_depth) {
-        case 2: k_forces<real, 2><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
-        case 4: k_forces<real, 4><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
-        case 8: k_forces<real, 8><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
-        case 32: k_forces<real, 32><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
-        default: k_forces<real, 16><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, prune, kick); break;
+        case 2: LHMM_FORCES(2); break;
+        case 4: LHMM_FORCES(4); break;
+        case 8: LHMM_FORCES(8); break;
+        case 32: LHMM_FORCES(32); break;
+        default: LHMM_FORCES(16); break;
     }
+#undef LHMM_FORCES
 }
 
 // One step (or a force evaluation) of the boxes C selects: all n_boxes boxes
@@ -1557,7 +1568,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->n_boxes = n_boxes;
     m->precision = p->precision;
     m->cfg.queue_depth = 16;
-    m->cfg.drain = 8;
+    m->cfg.drain = 12;
     m->cfg.busy_lanes = 65;
     m->cfg.bin_threads = BIN_THREADS_MAX;
     m->cfg.graph_chunk = GRAPH_CHUNK;
