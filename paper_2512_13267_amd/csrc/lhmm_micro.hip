@@ -165,7 +165,8 @@ __device__ __forceinline__ float box_muller<float>(unsigned w0, unsigned w1) {
     const float u0 = ((float)(w0 >> 9) + 0.5f) * 1.1920928955078125e-07f;  // 2^-23
     const float u1 = ((float)(w1 >> 9) + 0.5f) * 1.1920928955078125e-07f;
     // v_log_f32 is log2; v_cos_f32 takes its argument in revolutions
-    const float r = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));  // -2 ln u0
+    // -2 ln u0 lies in [1e-7, 35]: the hardware square root (1 ulp) needs no range handling
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));  // -2 ln u0
     return r * __builtin_amdgcn_cosf(u1);
 }
 
@@ -818,6 +819,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
     // 2 above) << 4 | in-plane image code
     __shared__ int qbuf[QD][NW][64];
     __shared__ double red[19 * NW];
+    __shared__ real shift_tab[9][2];  // image_shift of the block's box for codes 0 .. 8
 
     int blk = xcd_local_work(blockIdx.x, gridDim.x);
     if (C.blk_list) blk = C.blk_list[blk];
@@ -838,6 +840,8 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
     // in-plane cell and gradient
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
     const real h22 = (real)D.h[8];
+    if (t < 9) image_shift<real>(t, h00, h01, h10, h11, shift_tab[t][0], shift_tab[t][1]);
+    __syncthreads();
     real ri0 = 0, ri1 = 0, ri2 = 0, ci0 = 0, ci1 = 0, ci2 = 0;
     real own_s0 = 0, own_s1 = 0, own_s2 = 0;
     int own_id = 0;
@@ -897,8 +901,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
             const int qj = e >> 6, zi = (e >> 4) & 3;
             const V4 pj = rec[qj];
             const V4 cj = vel[qj];
-            real sx, sy;
-            image_shift<real>(e & 15, h00, h01, h10, h11, sx, sy);
+            const real sx = shift_tab[e & 15][0], sy = shift_tab[e & 15][1];
             const real zj = zi == 0 ? pj.z : (zi == 1 ? pj.z - h22 : pj.z + h22);
             const real dx = (ri0 - sx) - pj.x, dy = (ri1 - sy) - pj.y, dz = ri2 - zj;
             const real r2 = dx * dx + dy * dy + dz * dz;
@@ -946,10 +949,8 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
         m1 -= sh1 * n1;
         const int gb = (m0 * n1 + m1) * (n2 + 2 * zs) + k2;
         ic = 3 * (sh0 + 1) + (sh1 + 1);
-        real sx, sy;
-        image_shift<real>(ic, h00, h01, h10, h11, sx, sy);
-        bx = ri0 - sx;
-        by = ri1 - sy;
+        bx = ri0 - shift_tab[ic][0];
+        by = ri1 - shift_tab[ic][1];
         q = 0;
         qe = 0;
         int lo = 0, hi = 2 * zs + 1;
