@@ -177,10 +177,11 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
  *                per-box binning workgroup (two launches fewer per step;
  *                lhmm_micro_time then reports their time under binning);
  *   groups:      1 .. 4: with fused binning, a captured step splits the
- *                boxes by particle count into this many groups of about
- *                equal particle numbers, each binned and force-evaluated on
- *                its own stream, so that the force pass of small boxes runs
- *                while large boxes are still being binned (1: one stream). */
+ *                boxes by particle count into this many groups (the largest
+ *                boxes, two thirds of the particles, in the last), each
+ *                binned and force-evaluated on its own stream, so that the
+ *                force pass of small boxes runs while large boxes are still
+ *                being binned (1: one stream). */
 typedef struct {
     int32_t queue_depth;
     int32_t drain;

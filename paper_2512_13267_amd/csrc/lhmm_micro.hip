@@ -1435,8 +1435,8 @@ int launch_subset_steps(lhmm_micro* m, const Ctx& C, int n_sel, int nblk, int le
     return LHMM_OK;
 }
 
-// Partition the boxes into G groups of about equal particle counts, by
-// particle count (smallest first), with their block lists and binning LDS.
+// Partition the boxes into G groups by particle count (smallest first), with
+// their block lists and binning LDS.
 int prepare_groups(lhmm_micro* m, int G) {
     HIPCHK(hipStreamSynchronize(m->stream));
     for (auto& gr : m->groups) {
@@ -1455,10 +1455,14 @@ int prepare_groups(lhmm_micro* m, int G) {
     std::vector<int> order(m->n_boxes);
     for (int b = 0; b < m->n_boxes; ++b) order[b] = b;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return m->box[a].n < m->box[b].n; });
+    // the largest boxes, two thirds of the particles, form the last group
+    // (their binning is the longest; measured best on uneven batches), the
+    // rest is shared equally by the others
     std::vector<std::vector<int>> members(G);
     long long acc = 0;
+    const long long third = std::max(1LL, m->n_total / 3);
     for (int b : order) {
-        int g = (int)(acc * G / std::max(1LL, m->n_total));
+        const int g = acc >= third ? G - 1 : (int)(acc * (G - 1) / third);
         members[std::min(g, G - 1)].push_back(b);
         acc += m->box[b].n;
     }
