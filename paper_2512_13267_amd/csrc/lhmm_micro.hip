@@ -112,8 +112,11 @@ struct Ctx {
     void* f;
     int* pcell;
     int* cell_start;
-    void* cell_pos;     // per box, cell-sorted (x, y, z, local index) as 4 reals, r = h s
-    void* cell_vel;     // per box, cell-sorted (cx, cy, cz, local index) as 4 reals
+    // per box, cell-sorted pairs of records: (x, y, z, local index), r = h s,
+    // then (cx, cy, cz, local index), 2 x 4 reals per particle (one scattered
+    // 32-byte store in the binning, one 32-byte segment per neighbour in the
+    // force kernel's evaluation)
+    void* cell_pv;
     // Search layout: per box (at 2 x its particle offset) every cell column
     // (m0, m1) as [images of its top zsub cells shifted by -h_z][its cells]
     // [images of its bottom zsub cells shifted by +h_z], so the z cells
@@ -654,8 +657,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
         });
     __threadfence_block();
     __syncthreads();
-    typename R::T* rec = (typename R::T*)C.cell_pos + B.off;
-    typename R::T* vel = (typename R::T*)C.cell_vel + B.off;
+    typename R::T* pv = (typename R::T*)C.cell_pv + 2 * (size_t)B.off;
     typename R::T* srec = (typename R::T*)C.srec + 2 * B.off;
     const real* s = (const real*)C.s;
     const real* c = (const real*)C.c;
@@ -721,8 +723,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
                     const int q = posof[k];
                     real x, y, z;
                     cell_position<real>(v[u][0], v[u][1], v[u][2], h00, h01, h10, h11, h22, x, y, z);
-                    rec[q] = R::make(x, y, z, k);
-                    vel[q] = R::make(v[u][3], v[u][4], v[u][5], k);
+                    pv[2 * q] = R::make(x, y, z, k);
+                    pv[2 * q + 1] = R::make(v[u][3], v[u][4], v[u][5], k);
                     write_search(q, mycell[j0 + u], x, y, z);
                 }
             }
@@ -734,29 +736,29 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
         const int g = B.off + k;
         real x, y, z;
         cell_position<real>(s[g], s[N + g], s[2 * N + g], h00, h01, h10, h11, h22, x, y, z);
-        rec[pos] = R::make(x, y, z, k);
+        pv[2 * pos] = R::make(x, y, z, k);
     }
     __threadfence_block();
     __syncthreads();
     for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) {
         const int q0 = start[k], q1 = start[k + 1];
         for (int q = q0 + 1; q < q1; ++q) {  // insertion sort by index, a few entries
-            const typename R::T v = rec[q];
+            const typename R::T v = pv[2 * q];
             const int key = R::id(v);
             int r = q - 1;
-            while (r >= q0 && R::id(rec[r]) > key) {
-                rec[r + 1] = rec[r];
+            while (r >= q0 && R::id(pv[2 * r]) > key) {
+                pv[2 * (r + 1)] = pv[2 * r];
                 --r;
             }
-            rec[r + 1] = v;
+            pv[2 * (r + 1)] = v;
         }
     }
     __threadfence_block();
     __syncthreads();
     for (int q = threadIdx.x; q < B.n; q += BIN_THREADS) {
-        const typename R::T v = rec[q];
+        const typename R::T v = pv[2 * q];
         const int k = R::id(v), g = B.off + k;
-        vel[q] = R::make(c[g], c[N + g], c[2 * N + g], k);
+        pv[2 * q + 1] = R::make(c[g], c[N + g], c[2 * N + g], k);
         write_search(q, pc[k], v.x, v.y, v.z);
     }
 }
@@ -831,8 +833,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
     const int p0 = C.blk_first[blk] - B.off;  // first cell-order position of the block
     const int pos = p0 + t;
     const bool act = pos < B.n;
-    const V4* rec = (const V4*)C.cell_pos + B.off;
-    const V4* vel = (const V4*)C.cell_vel + B.off;
+    const V4* pv = (const V4*)C.cell_pv + 2 * (size_t)B.off;
     const char* sbase = (const char*)((const V4*)C.srec + 2 * B.off);
     const real* s = (const real*)C.s;
     real* f = (real*)C.f;
@@ -846,7 +847,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
     real own_s0 = 0, own_s1 = 0, own_s2 = 0;
     int own_id = 0;
     if (act) {
-        const V4 u = vel[pos];
+        const V4 u = pv[2 * pos + 1];
         ci0 = u.x; ci1 = u.y; ci2 = u.z;
         own_id = R::id(u);
         const int g = B.off + own_id;
@@ -899,8 +900,8 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
             const int e = qbuf[qh & (QD - 1)][wv][lane];
             ++qh;
             const int qj = e >> 6, zi = (e >> 4) & 3;
-            const V4 pj = rec[qj];
-            const V4 cj = vel[qj];
+            const V4 pj = pv[2 * qj];
+            const V4 cj = pv[2 * qj + 1];
             const real sx = shift_tab[e & 15][0], sy = shift_tab[e & 15][1];
             const real zj = zi == 0 ? pj.z : (zi == 1 ? pj.z - h22 : pj.z + h22);
             const real dx = (ri0 - sx) - pj.x, dy = (ri1 - sy) - pj.y, dz = ri2 - zj;
@@ -1165,8 +1166,7 @@ struct lhmm_micro {
     int *d_blk_box = nullptr, *d_blk_first = nullptr;
     void *d_s = nullptr, *d_c = nullptr, *d_f = nullptr;
     int *d_pcell = nullptr, *d_cell_start = nullptr, *d_gcell_start = nullptr;
-    void* d_cell_pos = nullptr;
-    void* d_cell_vel = nullptr;
+    void* d_cell_pv = nullptr;
     void* d_srec = nullptr;
     double *d_part_vir = nullptr, *d_part_kin = nullptr;
     unsigned* d_part_pairs = nullptr;
@@ -1375,7 +1375,7 @@ void release(lhmm_micro* m) {
     for (auto& kv : m->sub_graphs) (void)hipGraphExecDestroy(kv.second);
     m->sub_graphs.clear();
     void* bufs[] = {m->d_box, m->d_dyn, m->d_flags, m->d_blk_box, m->d_blk_first, m->d_s, m->d_c, m->d_f,
-                    m->d_pcell, m->d_cell_start, m->d_gcell_start, m->d_cell_pos, m->d_cell_vel, m->d_srec,
+                    m->d_pcell, m->d_cell_start, m->d_gcell_start, m->d_cell_pv, m->d_srec,
                     m->d_part_vir, m->d_part_kin,
                     m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_step,
                     m->d_sel, m->d_blk_list, m->d_snap_s, m->d_snap_c, m->d_snap_f, m->d_snap_dyn};
@@ -1700,8 +1700,8 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
         const size_t bytes = 3 * N * m->real_size;
         // search layout: each particle at most twice (its cell, and the
         // image of a bottom or top cell; n2 >= 3)
-        for (void** pp : {&m->d_s, &m->d_c, &m->d_f, &m->d_cell_pos, &m->d_cell_vel, &m->d_srec}) {
-            const size_t nb = (pp == &m->d_cell_pos || pp == &m->d_cell_vel) ? 4 * N * m->real_size
+        for (void** pp : {&m->d_s, &m->d_c, &m->d_f, &m->d_cell_pv, &m->d_srec}) {
+            const size_t nb = pp == &m->d_cell_pv ? 8 * N * m->real_size
                               : pp == &m->d_srec ? (8 * N + 16) * m->real_size : bytes;
             if (hipMalloc(pp, nb ? nb : 1) != hipSuccess) {
                 rc = fail(LHMM_ERR_OOM, "hipMalloc of particle arrays failed");
@@ -1756,9 +1756,8 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     C.f = m->d_f;
     C.pcell = m->d_pcell;
     C.cell_start = m->d_cell_start;
-    C.cell_pos = m->d_cell_pos;
     C.gcell_start = m->d_gcell_start;
-    C.cell_vel = m->d_cell_vel;
+    C.cell_pv = m->d_cell_pv;
     C.srec = m->d_srec;
     C.vir_scale = 0.5;  // every unordered pair is evaluated from both ends
     C.part_vir = m->d_part_vir;
