@@ -640,21 +640,36 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     __syncthreads();
     const int n2 = D.nc[2], zs = B.zsub, gn2 = n2 + 2 * zs, ncol = D.nc[0] * D.nc[1];
     const float inv_gn2 = 1.0f / (float)gn2;
+    // images before each column (its top and bottom zsub cells' particles
+    // appear once more), scanned over columns; each column's offsets from
+    // cell order to its three segments of the search layout
+    __shared__ int n_images;
     block_scan<BIN_THREADS>(
-        ncol * gn2, wsum,
-        [&](int g) {
-            const int col = div_small(g, inv_gn2), zg = g - col * gn2;
-            const int k = col * n2 + (zg < zs ? n2 - zs + zg : (zg >= zs + n2 ? zg - zs - n2 : zg - zs));
-            return cnt[k + 1] - cnt[k];
+        ncol, wsum,
+        [&](int col) {
+            const int k = col * n2;
+            return (cnt[k + n2] - cnt[k + n2 - zs]) + (cnt[k + zs] - cnt[k]);
         },
-        [&](int g, int excl) {
-            gstart[g] = excl;
-            if (g == ncol * gn2) return;
-            const int col = div_small(g, inv_gn2), zg = g - col * gn2;
-            if (zg == 0) lo_off[col] = excl - cnt[col * n2 + n2 - zs];
-            if (zg == zs) col_off[col] = excl - cnt[col * n2];
-            if (zg == zs + n2) hi_off[col] = excl - cnt[col * n2];
+        [&](int col, int excl) {
+            if (col == ncol) {
+                n_images = excl;
+                return;
+            }
+            const int k = col * n2;
+            const int first = cnt[k] + excl, top = cnt[k + n2] - cnt[k + n2 - zs];
+            lo_off[col] = first - cnt[k + n2 - zs];
+            col_off[col] = first + top - cnt[k];
+            hi_off[col] = first + top + (cnt[k + n2] - cnt[k]) - cnt[k];
         });
+    __syncthreads();
+    // starts of the search-layout cells: a segment's offset plus the start
+    // of the cell it repeats
+    for (int g = threadIdx.x; g < ncol * gn2; g += BIN_THREADS) {
+        const int col = div_small(g, inv_gn2), zg = g - col * gn2, k = col * n2;
+        gstart[g] = zg < zs ? lo_off[col] + cnt[k + n2 - zs + zg]
+                            : (zg < zs + n2 ? col_off[col] + cnt[k + zg - zs] : hi_off[col] + cnt[k + zg - zs - n2]);
+    }
+    if (threadIdx.x == 0) gstart[ncol * gn2] = B.n + n_images;
     __threadfence_block();
     __syncthreads();
     typename R::T* pv = (typename R::T*)C.cell_pv + 2 * (size_t)B.off;
