@@ -556,11 +556,11 @@ __device__ __forceinline__ void cell_position(real s0, real s1, real s2, real h0
 // LDS (dynamic): lds_cells cell counters / starts, three arrays of
 // lds_cells / 3 + 1 column offsets (from cell order to the search layout:
 // the column's cells, the image of its top cell, the image of its bottom
-// cell), then room for lds_parts ints.  A box with at most lds_parts / 2
-// particles is sorted as entries in LDS, their cell-order positions are
-// inverted in LDS, and each thread stores the records of its own particles;
-// a larger box scatters records to global scratch and sorts them there.
-// Both give the same records in the same order.
+// cell), then room for lds_parts ints.  A box with at most lds_parts
+// particles is scattered as entries into LDS, each thread ranks its own
+// particles inside their cells and stores their records; a larger box
+// scatters records to global scratch and sorts them there.  Both give the
+// same records in the same order.
 //
 // fuse >= 0: the workgroup first runs the box's cell step and the half kick
 // and drift of its particles (advance = fuse), counting cells as it goes;
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     // for the scatter when the box fits the LDS path
     constexpr int KEEP = 16384 / BIN_THREADS;
     int mycell[KEEP];
-    const bool keep = 2 * B.n <= lds_parts && B.n <= KEEP * BIN_THREADS;
+    const bool keep = B.n <= lds_parts && B.n <= KEEP * BIN_THREADS;
     if (fuse >= 0) {
         // four particles per thread and pass: independent loads in flight
 #pragma unroll
@@ -700,24 +700,18 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
         for (int j = 0; j < KEEP; ++j)
             if (slot[j] >= 0) lidx[slot[j]] = (mycell[j] << 14) | ((int)threadIdx.x + j * BIN_THREADS);
         __syncthreads();
-        // cnt[k] now ends cell k; sort every cell's entries by index (a few each)
-        for (int k = threadIdx.x; k < ncell; k += BIN_THREADS) {
-            const int q0 = k == 0 ? 0 : cnt[k - 1], q1 = cnt[k];
-            for (int q = q0 + 1; q < q1; ++q) {
-                const int key = lidx[q];
-                int r = q - 1;
-                while (r >= q0 && lidx[r] > key) {
-                    lidx[r + 1] = lidx[r];
-                    --r;
-                }
-                lidx[r + 1] = key;
-            }
+        // cnt[k] now ends cell k: a particle's cell-order position is its
+        // cell's start plus the number of its cell's entries with a smaller
+        // index (a few each), so every cell is in index order
+#pragma unroll
+        for (int j = 0; j < KEEP; ++j) {
+            if (slot[j] < 0) continue;
+            const int cell = mycell[j], key = (cell << 14) | ((int)threadIdx.x + j * BIN_THREADS);
+            const int q0 = cell == 0 ? 0 : cnt[cell - 1], q1 = cnt[cell];
+            int rank = 0;
+            for (int q = q0; q < q1; ++q) rank += lidx[q] < key;
+            slot[j] = q0 + rank;
         }
-        __syncthreads();
-        // cell-order position of every particle
-        int* posof = lidx + B.n;
-        for (int q = threadIdx.x; q < B.n; q += BIN_THREADS) posof[lidx[q] & 0x3FFF] = q;
-        __syncthreads();
         // the thread's own particles, four per pass with their (coalesced)
         // loads in flight together, each record stored to its slot
 #pragma unroll
@@ -735,7 +729,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
             for (int u = 0; u < 4; ++u) {
                 const int k = (int)threadIdx.x + (j0 + u) * BIN_THREADS;
                 if (k < B.n) {
-                    const int q = posof[k];
+                    const int q = slot[j0 + u];
                     real x, y, z;
                     cell_position<real>(v[u][0], v[u][1], v[u][2], h00, h01, h10, h11, h22, x, y, z);
                     pv[2 * q] = R::make(x, y, z, k);
@@ -1498,7 +1492,7 @@ int prepare_groups(lhmm_micro* m, int G) {
         gr.lds_cells = max_cells;
         const int fixed = max_cells + 3 * (max_cells / 3 + 1);
         const int room = m->bin_lds_cells + 3 * (m->bin_lds_cells / 3 + 1) + m->bin_lds_parts - fixed;
-        gr.lds_parts = std::max(0, std::min(2 * max_n, room));
+        gr.lds_parts = std::max(0, std::min(max_n, room));
         int rc = dalloc(&gr.d_sel, gr.n_sel);
         if (rc == LHMM_OK) rc = dalloc(&gr.d_blk, gr.nblk);
         if (rc != LHMM_OK) {
@@ -1677,7 +1671,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
             return fail(LHMM_ERR_ARG, "boxes need %d cells, more than the binning LDS holds", max_cells - 1);
         }
         m->bin_lds_cells = max_cells;
-        m->bin_lds_parts = std::max(0, std::min(2 * max_n, budget - fixed));  // entries and their inverse
+        m->bin_lds_parts = std::max(0, std::min(max_n, budget - fixed));
         const size_t bytes = sizeof(int) * ((size_t)fixed + (size_t)m->bin_lds_parts);
         const void* kernels[] = {(const void*)&k_bin_box<float, 256>, (const void*)&k_bin_box<float, 512>,
                                  (const void*)&k_bin_box<float, 1024>, (const void*)&k_bin_box<double, 256>,
