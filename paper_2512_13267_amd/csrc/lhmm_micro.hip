@@ -456,40 +456,62 @@ __device__ __forceinline__ real wrap01(real x) {
     return x >= (real)1 ? (real)0 : x;
 }
 
-// Half kick, drift in fractional coordinates, remap after a reduction,
-// wrap, and the particle's cell; returns the cell (stored to pcell when
-// store_cell is set).
+// A box's step constants for the half kick and drift, read once into
+// registers (the per-particle stores could otherwise force reloads).
 template <typename real>
-__device__ __forceinline__ int kick_drift_particle(const Ctx& C, const BoxDyn& D, int i, int advance,
+struct KickDrift {
+    real hdt, im, dt, L0, L1, L3, L4, M[9];
+    int changed, U[4], nc[3];
+    __device__ explicit KickDrift(const Ctx& C, const BoxDyn& D) {
+        hdt = (real)(0.5 * C.dt);
+        im = (real)C.inv_mass;
+        dt = (real)C.dt;
+        L0 = (real)D.L[0]; L1 = (real)D.L[1]; L3 = (real)D.L[3]; L4 = (real)D.L[4];
+        for (int k = 0; k < 9; ++k) M[k] = (real)D.hmi[k];
+        changed = D.changed;
+        for (int k = 0; k < 4; ++k) U[k] = D.U[k];
+        for (int k = 0; k < 3; ++k) nc[k] = D.nc[k];
+    }
+};
+
+// Half kick c += dt/2 (F/m - L c), drift of the fractional coordinate with
+// the mid-step cell, remap after a reduction, wrap (in registers).
+template <typename real>
+__device__ __forceinline__ void kick_drift(const KickDrift<real>& K, real (&sv)[3], real (&cv)[3], const real (&fv)[3]) {
+    // in-plane L: (L c)_z = 0
+    const real lc0 = K.L0 * cv[0] + K.L1 * cv[1], lc1 = K.L3 * cv[0] + K.L4 * cv[1];
+    cv[0] += K.hdt * (fv[0] * K.im - lc0);
+    cv[1] += K.hdt * (fv[1] * K.im - lc1);
+    cv[2] += K.hdt * (fv[2] * K.im);
+    real s0 = sv[0] + K.dt * (K.M[0] * cv[0] + K.M[1] * cv[1] + K.M[2] * cv[2]);
+    real s1 = sv[1] + K.dt * (K.M[3] * cv[0] + K.M[4] * cv[1] + K.M[5] * cv[2]);
+    const real s2 = sv[2] + K.dt * (K.M[6] * cv[0] + K.M[7] * cv[1] + K.M[8] * cv[2]);
+    if (K.changed) {  // s <- U^{-1} s in the plane, U^{-1} = [[u11, -u01], [-u10, u00]]
+        const real x = s0, y = s1;
+        s0 = (real)K.U[3] * x - (real)K.U[1] * y;
+        s1 = -(real)K.U[2] * x + (real)K.U[0] * y;
+    }
+    sv[0] = wrap01(s0); sv[1] = wrap01(s1); sv[2] = wrap01(s2);
+}
+
+// Half kick and drift of particle i (advance = 1) and its cell; returns the
+// cell (stored to pcell when store_cell is set).
+template <typename real>
+__device__ __forceinline__ int kick_drift_particle(const Ctx& C, const KickDrift<real>& K, int i, int advance,
                                                    bool store_cell = true) {
     const int N = C.n_total;
     real* s = (real*)C.s;
     real* c = (real*)C.c;
     const real* f = (const real*)C.f;
-    real s0 = s[i], s1 = s[N + i], s2 = s[2 * N + i];
+    real sv[3] = {s[i], s[N + i], s[2 * N + i]};
     if (advance) {
-        const real hdt = (real)(0.5 * C.dt), im = (real)C.inv_mass, dt = (real)C.dt;
-        real c0 = c[i], c1 = c[N + i], c2 = c[2 * N + i];
-        const real L0 = (real)D.L[0], L1 = (real)D.L[1], L3 = (real)D.L[3], L4 = (real)D.L[4];
-        // in-plane L: (L c)_z = 0
-        const real lc0 = L0 * c0 + L1 * c1, lc1 = L3 * c0 + L4 * c1;
-        c0 += hdt * (f[i] * im - lc0);
-        c1 += hdt * (f[N + i] * im - lc1);
-        c2 += hdt * (f[2 * N + i] * im);
-        c[i] = c0; c[N + i] = c1; c[2 * N + i] = c2;
-        const double* M = D.hmi;
-        s0 += dt * ((real)M[0] * c0 + (real)M[1] * c1 + (real)M[2] * c2);
-        s1 += dt * ((real)M[3] * c0 + (real)M[4] * c1 + (real)M[5] * c2);
-        s2 += dt * ((real)M[6] * c0 + (real)M[7] * c1 + (real)M[8] * c2);
-        if (D.changed) {  // s <- U^{-1} s in the plane, U^{-1} = [[u11, -u01], [-u10, u00]]
-            const real x = s0, y = s1;
-            s0 = (real)D.U[3] * x - (real)D.U[1] * y;
-            s1 = -(real)D.U[2] * x + (real)D.U[0] * y;
-        }
-        s0 = wrap01(s0); s1 = wrap01(s1); s2 = wrap01(s2);
-        s[i] = s0; s[N + i] = s1; s[2 * N + i] = s2;
+        real cv[3] = {c[i], c[N + i], c[2 * N + i]};
+        const real fv[3] = {f[i], f[N + i], f[2 * N + i]};
+        kick_drift<real>(K, sv, cv, fv);
+        c[i] = cv[0]; c[N + i] = cv[1]; c[2 * N + i] = cv[2];
+        s[i] = sv[0]; s[N + i] = sv[1]; s[2 * N + i] = sv[2];
     }
-    const int cell = cell_of(s0, s1, s2, D.nc);
+    const int cell = cell_of(sv[0], sv[1], sv[2], K.nc);
     if (store_cell) C.pcell[i] = cell;
     return cell;
 }
@@ -501,7 +523,8 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
     const BoxInfo B = C.box[b];
     const int i = C.blk_first[blk] + (int)threadIdx.x;
     if (i >= B.off + B.n) return;
-    kick_drift_particle<real>(C, C.dyn[b], i, advance);
+    const KickDrift<real> K(C, C.dyn[b]);
+    kick_drift_particle<real>(C, K, i, advance);
 }
 
 // Exclusive scan over k in [0, n) of val(k) by a workgroup of BT threads:
@@ -594,15 +617,44 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     int mycell[KEEP];
     const bool keep = B.n <= lds_parts && B.n <= KEEP * BIN_THREADS;
     if (fuse >= 0) {
-        // four particles per thread and pass: independent loads in flight
+        const KickDrift<real> K(C, D);
+        real* s = (real*)C.s;
+        real* c = (real*)C.c;
+        const real* f = (const real*)C.f;
+        const int N = C.n_total;
+        // four particles per thread and pass: all their loads issued before
+        // any store, so the loads stay in flight together
 #pragma unroll
         for (int j0 = 0; j0 < KEEP; j0 += 4) {
             if ((int)threadIdx.x + j0 * BIN_THREADS >= B.n) break;
             int cell[4];
+            real sv[4][3], cv[4][3], fv[4][3];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = (int)threadIdx.x + (j0 + u) * BIN_THREADS;
-                cell[u] = k < B.n ? kick_drift_particle<real>(C, D, B.off + k, fuse, !keep) : -1;
+                const int i = B.off + (k < B.n ? k : 0);
+                for (int a = 0; a < 3; ++a) {
+                    sv[u][a] = s[a * N + i];
+                    cv[u][a] = c[a * N + i];
+                    fv[u][a] = f[a * N + i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = (int)threadIdx.x + (j0 + u) * BIN_THREADS;
+                const int i = B.off + k;
+                cell[u] = -1;
+                if (k < B.n) {
+                    if (fuse) {
+                        kick_drift<real>(K, sv[u], cv[u], fv[u]);
+                        for (int a = 0; a < 3; ++a) {
+                            c[a * N + i] = cv[u][a];
+                            s[a * N + i] = sv[u][a];
+                        }
+                    }
+                    cell[u] = cell_of(sv[u][0], sv[u][1], sv[u][2], K.nc);
+                    if (!keep) C.pcell[i] = cell[u];
+                }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -611,7 +663,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
             }
         }
         for (int k = (int)threadIdx.x + KEEP * BIN_THREADS; k < B.n; k += BIN_THREADS)
-            atomicAdd(&cnt[kick_drift_particle<real>(C, D, B.off + k, fuse)], 1);
+            atomicAdd(&cnt[kick_drift_particle<real>(C, K, B.off + k, fuse)], 1);
         __threadfence_block();
     } else {
 #pragma unroll
