@@ -1,17 +1,20 @@
 """Launch-parameter tuning of the micro engine with a JSON cache.
 
-The engine's own search (``lhmm_micro_autotune``: queue depth and drain level
-of the pair-force kernel, binning workgroup size, steps per captured graph;
-state put back after every trial) is run once per workload shape; the
-result is cached under a key made of the GPU architecture, the precision
-and a histogram of the box sizes (boxes per power-of-two particle-count
-bucket), so a later engine over boxes of the same shape reuses it without
-timing.  No parameter changes results, only speed.
+The engine's own search (``lhmm_micro_autotune``: queue depth, drain level
+and busy-lane rule of the pair-force kernel, binning workgroup size, fused
+binning, stencil pruning, box groups, steps per captured graph; state put
+back after every trial) is run once per workload shape; the result is cached
+under a key made of the GPU architecture, the precision, a histogram of the
+box sizes (boxes per power-of-two particle-count bucket) and a digest of the
+built library, so a later engine over boxes of the same shape reuses it
+without timing, and a rebuilt engine tunes afresh.  No parameter changes
+results, only speed.
 
 Cache file: ``$LHMM_TUNE_CACHE`` or ``~/.cache/lhmm/autotune.json``.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import math
 import os
@@ -32,8 +35,19 @@ def size_histogram(sizes) -> str:
     return ",".join(f"2^{k}:{hist[k]}" for k in sorted(hist))
 
 
-def cache_key(arch: str, precision: str, sizes) -> str:
-    return f"{arch}|{precision}|{size_histogram(sizes)}"
+def library_digest() -> str:
+    """First 12 hex digits of the SHA-256 of the loaded library file."""
+    from . import _lib
+
+    try:
+        with open(_lib.LIB_PATH, "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()[:12]
+    except OSError:
+        return "unknown"
+
+
+def cache_key(arch: str, precision: str, sizes, library: str | None = None) -> str:
+    return f"{arch}|{precision}|{size_histogram(sizes)}|{library if library is not None else library_digest()}"
 
 
 def load_cache(path=None) -> dict:

@@ -9,6 +9,9 @@ def test_histogram_and_key():
     k2 = autotune.cache_key("gfx950", "fp32", [4001, 4000])
     assert k1 == k2 and k1.startswith("gfx950|fp32|")
     assert autotune.cache_key("gfx950", "fp64", [4000]) != autotune.cache_key("gfx950", "fp32", [4000])
+    # a different build of the library never reuses an entry
+    assert autotune.cache_key("gfx950", "fp32", [4000], "aaaa") != autotune.cache_key("gfx950", "fp32", [4000], "bbbb")
+    assert len(autotune.library_digest()) == 12
 
 
 def test_store_and_load_roundtrip(tmp_path):
