@@ -1,0 +1,240 @@
+"""Virtual rheometer: steady simple-shear sweeps of micro-boxes and their
+Carreau-Yasuda description (Section "Rheological characterization";
+Appendix "Carreau-Yasuda Model Details", Eq. Yasuda; Appendix "Normal
+Stress Coefficients and Relaxation Time Definitions", Eqs. psi1_appendix,
+tau0_def, tau0_def_appendix).
+
+One batched engine call shears every box of a sweep at once: each shear
+rate gets `replicas` independent boxes (own random start and random-force
+stream), all are first driven to steady state, then the mean Irving-Kirkwood
+stress of a second call is the measurement.  Per rate:
+  eta(g)     = sigma_xy / g                   (shear viscosity)
+  N1(g)      = sigma_xx - sigma_yy            (first normal stress difference)
+  psi1(g)    = N1 / g^2                        (Eq. psi1_appendix)
+  lambda(g)  = 0.5 psi1 / eta                  (Eq. tau0_def)
+with standard errors over the replicas, and the Carreau-Yasuda fit
+  eta(g) = eta_inf + (eta0 - eta_inf) [1 + (lam g)^a]^((n - 1) / a)
+by least squares in log eta.  Stresses are the engine's (tension positive,
+total = kinetic + pair + bond parts).
+
+The micro model is the engine's (3-D DPD with FENE chains); the paper's
+table of fitted parameters is for its 2-D melt with adaptive boundary
+conditions, so the numbers are not expected to agree.
+
+Command line: ``python -m paper_2512_13267_amd.rheometer [--rates ...]
+[--replicas 16] [--chain-len 10] [--equil 5000] [--steps 20000] [--out FILE]``;
+``--report a.json,b.json --md FILE`` writes a summary of earlier runs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import inputs
+
+
+def carreau_yasuda(gdot, eta0, eta_inf, lam, a, n):
+    """Eq. Yasuda."""
+    g = np.asarray(gdot, dtype=np.float64)
+    return eta_inf + (eta0 - eta_inf) * (1.0 + (lam * g) ** a) ** ((n - 1.0) / a)
+
+
+def fit_carreau_yasuda(gdot, eta, weights=None) -> dict:
+    """Least-squares fit of Eq. Yasuda to eta(gdot) in log eta (weights:
+    1 / relative standard error, optional), with 0 <= eta_inf < eta0,
+    0.05 <= a <= 20 and 0 <= n <= 1.  Returns the five parameters and the
+    RMS relative residual."""
+    from scipy.optimize import least_squares
+
+    g = np.asarray(gdot, dtype=np.float64)
+    e = np.asarray(eta, dtype=np.float64)
+    if g.shape != e.shape or g.size < 5 or np.any(g <= 0) or np.any(e <= 0):
+        raise ValueError("need at least five positive (rate, viscosity) points")
+    w = np.ones_like(e) if weights is None else np.asarray(weights, dtype=np.float64)
+    order = np.argsort(g)
+    e_top = float(e.max())
+    g_mid = float(np.sqrt(g[order[0]] * g[order[-1]]))
+
+    # x = (log eta0, logit(eta_inf / eta0), log lam, log a, n)
+    def params(x):
+        eta0 = float(np.exp(x[0]))
+        return eta0, eta0 / (1.0 + float(np.exp(-x[1]))), float(np.exp(x[2])), float(np.exp(x[3])), float(x[4])
+
+    def resid(x):
+        with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+            r = w * (np.log(carreau_yasuda(g, *params(x))) - np.log(e))
+        return np.where(np.isfinite(r), r, 1e6)
+
+    lo = [math.log(e_top) - 10.0, -30.0, math.log(1.0 / g_mid) - 25.0, math.log(0.05), 0.0]
+    hi = [math.log(e_top) + 10.0, 30.0, math.log(1.0 / g_mid) + 25.0, math.log(20.0), 1.0]
+    best = None
+    for ratio, lam_shift, a0, n0 in ((0.1, 0.0, 1.0, 0.5), (1e-4, 1.0, 1.0, 0.3), (0.3, -1.0, 2.0, 0.5),
+                                      (1e-4, 3.0, 0.7, 0.3), (0.05, -3.0, 1.5, 0.2)):
+        start = np.array([math.log(e_top), math.log(ratio / (1.0 - ratio)), math.log(1.0 / g_mid) + lam_shift,
+                          math.log(a0), n0])
+        r = least_squares(resid, start, bounds=(lo, hi), x_scale="jac", max_nfev=5000)
+        if best is None or r.cost < best.cost:
+            best = r
+    eta0, eta_inf, lam, a, n = params(best.x)
+    rel = carreau_yasuda(g, eta0, eta_inf, lam, a, n) / e - 1.0
+    return {"eta0": eta0, "eta_inf": eta_inf, "lam": lam, "a": a, "n": n,
+            "rms_rel_residual": float(np.sqrt(np.mean(rel ** 2)))}
+
+
+def normal_stress_and_relaxation(gdot, sigma):
+    """psi1 = N1 / g^2 (Eq. psi1_appendix) and lambda = 0.5 psi1 / eta
+    (Eq. tau0_def) from mean stresses (rows (xx, yy, zz, xy, xz, yz))."""
+    g = np.asarray(gdot, dtype=np.float64)
+    s = np.asarray(sigma, dtype=np.float64)
+    eta = s[:, 3] / g
+    n1 = s[:, 0] - s[:, 1]
+    psi1 = n1 / g ** 2
+    return eta, n1, psi1, 0.5 * psi1 / eta
+
+
+def sweep_workload(rates, replicas: int = 16, chain_len: int = 10, edge: float = 10.0, density: float = 3.0,
+                   polymer_fraction: float = 1.0, seed_k: int = 60, **param_over) -> inputs.Workload:
+    """Boxes of a shear sweep: for every rate, `replicas` cubic boxes of
+    chains (polymer fraction 1: a melt) under simple shear u_x = rate y."""
+    p = inputs.default_params(seed=inputs.SEED_BASE + seed_k, chain_len=chain_len, **param_over)
+    rng = np.random.default_rng(inputs.SEED_BASE + seed_k)
+    N = int(round(density * edge ** 3))
+    n_chains = int(polymer_fraction * N) // chain_len  # whole chains; the rest is solvent
+    h = inputs.cubic_cell(edge)
+    boxes = []
+    for rate in rates:
+        for _ in range(replicas):
+            s, c = inputs.random_box(rng, h, N, n_chains, chain_len, p["kBT"], p["mass"])
+            boxes.append(inputs.BoxInit(s=s, c=c, h=h, n_chains=n_chains, L=inputs.shear_gradient(float(rate)),
+                                        edge=edge, phi=polymer_fraction))
+    return inputs.Workload("shear_sweep", p, boxes, 0)
+
+
+def run_sweep(rates, replicas: int = 16, chain_len: int = 10, equil: int = 5000, steps: int = 20000,
+              edge: float = 10.0, seed_k: int = 60, log=print) -> dict:
+    """Shear every box of the sweep for `equil` steps, then average the
+    stress over `steps` more; per-rate means and standard errors."""
+    import torch
+
+    from . import micro
+
+    rates = np.asarray(rates, dtype=np.float64)
+    wl = sweep_workload(rates, replicas, chain_len, edge, seed_k=seed_k)
+    m = micro.from_workload(wl, precision="fp32")
+    G = torch.tensor(np.stack([b.L for b in wl.boxes]), dtype=torch.float64, device="cuda").contiguous()
+    t0 = time.time()
+    chunk = 1000
+    for k in range(0, equil, chunk):
+        m.step(G, min(chunk, equil - k))
+        torch.cuda.synchronize()
+        log(f"  equilibration under shear: {min(k + chunk, equil)}/{equil} steps, {time.time() - t0:.1f} s",
+            flush=True)
+    # the mean over several calls of equal length is the mean over all steps
+    acc = np.zeros((len(wl.boxes), 6))
+    n_calls = 0
+    for k in range(0, steps, chunk):
+        acc += m.step(G, min(chunk, steps - k)).cpu().numpy() * min(chunk, steps - k)
+        n_calls += min(chunk, steps - k)
+        log(f"  averaging: {n_calls}/{steps} steps, {time.time() - t0:.1f} s", flush=True)
+    flags = m.flags()
+    m.close()
+    per_box = (acc / n_calls).reshape(len(rates), replicas, 6)
+    mean = per_box.mean(axis=1)
+    se = per_box.std(axis=1, ddof=1) / math.sqrt(replicas)
+    eta, n1, psi1, lam = normal_stress_and_relaxation(rates, mean)
+    out = {"rates": rates.tolist(), "replicas": replicas, "chain_len": chain_len, "edge": edge,
+           "equil_steps": equil, "avg_steps": steps, "dt": wl.params["dt"],
+           "n_particles": wl.n_particles, "seconds": time.time() - t0,
+           "flagged_boxes": int(np.count_nonzero(flags)),
+           "eta": eta.tolist(), "eta_se": (se[:, 3] / rates).tolist(),
+           "N1": n1.tolist(), "N1_se": np.sqrt(se[:, 0] ** 2 + se[:, 1] ** 2).tolist(),
+           "psi1": psi1.tolist(), "lambda": lam.tolist(), "sigma_mean": mean.tolist()}
+    ok = eta > 0
+    if ok.sum() >= 5:
+        w = 1.0 / np.maximum(np.asarray(out["eta_se"])[ok] / eta[ok], 1e-3)
+        out["carreau_yasuda"] = fit_carreau_yasuda(rates[ok], eta[ok], weights=w)
+    return out
+
+
+def chain_scaling(chain_lens, lams) -> dict:
+    """Power law lambda ~ N_d^b by least squares in log-log (the paper's
+    Rouse comparison, Fig. 2(e))."""
+    x = np.log(np.asarray(chain_lens, dtype=np.float64))
+    y = np.log(np.asarray(lams, dtype=np.float64))
+    b, c = np.polyfit(x, y, 1)
+    return {"b": float(b), "prefactor": float(math.exp(c))}
+
+
+def report(results, command: str) -> str:
+    """Markdown summary of one or more sweeps (one per chain length)."""
+    L = ["# Virtual rheometer: steady simple shear of DPD/FENE melts", "",
+         "Boxes: cubic, edge {edge} rc, density 3, polymer fraction 1 (whole chains, the few leftover particles "
+         "solvent), DPD a = 25, gamma = 4.5, kBT = 1, FENE H = 30, R0 = 1.5, dt = 0.01; every rate has {rep} "
+         "boxes with their own start and random-force stream, all rates of a chain length in one batched "
+         "engine call.  Stress: the engine's Irving-Kirkwood mean (tension positive).".format(
+             edge=results[0]["edge"], rep=results[0]["replicas"]), "",
+         "Command (MI355X, one GPU):", "", "```", command, "```", ""]
+    for r in results:
+        L += [f"## N_d = {r['chain_len']} ({r['equil_steps']} steps to steady state, then {r['avg_steps']} "
+              f"averaged; {r['n_particles']} particles, {r['seconds']:.1f} s; flagged boxes {r['flagged_boxes']})", "",
+              "| rate | eta | SE | N1 | SE | psi1 = N1 / rate^2 | lambda = 0.5 psi1 / eta |", "|---|---|---|---|---|---|---|"]
+        for row in zip(r["rates"], r["eta"], r["eta_se"], r["N1"], r["N1_se"], r["psi1"], r["lambda"]):
+            L.append("| {:.3g} | {:.4g} | {:.2g} | {:.4g} | {:.2g} | {:.4g} | {:.4g} |".format(*row))
+        cy = r.get("carreau_yasuda")
+        if cy:
+            L += ["", "Carreau-Yasuda fit (Eq. Yasuda, weighted by the standard errors): eta0 = {eta0:.4g}, "
+                  "eta_inf = {eta_inf:.4g}, lambda = {lam:.4g}, a = {a:.3g}, n = {n:.3g}; RMS relative residual "
+                  "{rms_rel_residual:.3g}.".format(**cy)]
+        L.append("")
+    fits = [(r["chain_len"], r["carreau_yasuda"]["lam"]) for r in results if r.get("carreau_yasuda")]
+    if len(fits) >= 2:
+        sc = chain_scaling([f[0] for f in fits], [f[1] for f in fits])
+        L += ["## Relaxation time against chain length", "",
+              "| N_d | lambda (Carreau-Yasuda) |", "|---|---|"] + [f"| {n} | {lam:.4g} |" for n, lam in fits] + [
+              "", f"lambda ~ N_d^b with b = {sc['b']:.3f} (least squares in log-log); the Rouse model gives 2.", ""]
+    L += ["The micro model is the engine's 3-D DPD/FENE model, not the paper's 2-D melt with adaptive boundary "
+          "conditions, so these parameters are not comparable with the paper's table.", ""]
+    return "\n".join(L)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--rates", default="0.01,0.02,0.05,0.1,0.2,0.5,1.0,2.0")
+    ap.add_argument("--replicas", type=int, default=16)
+    ap.add_argument("--chain-len", type=int, default=10)
+    ap.add_argument("--equil", type=int, default=5000)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--report", default=None, help="comma-separated result files: write a summary, no GPU")
+    ap.add_argument("--md", default=None, help="summary file for --report")
+    ap.add_argument("--command", default="", help="command line quoted in the summary")
+    args = ap.parse_args(argv)
+    if args.report:
+        results = []
+        for path in args.report.split(","):
+            with open(path) as f:
+                results.append(json.load(f))
+        text = report(results, args.command)
+        if args.md:
+            with open(args.md, "w") as f:
+                f.write(text)
+        print(text)
+        return
+    import torch
+
+    if not torch.cuda.is_available():
+        raise SystemExit("needs the GPU")
+    rates = [float(x) for x in args.rates.split(",")]
+    res = run_sweep(rates, args.replicas, args.chain_len, args.equil, args.steps)
+    print(json.dumps(res), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
