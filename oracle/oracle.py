@@ -77,9 +77,9 @@ def lib():
                                        u64p, dp, C.c_int, dp, dp, up, C.c_int, C.POINTER(C.c_longlong)]
         L.oracle_run_batch.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
-        L.oracle_sph_W.argtypes = [C.c_double, C.c_double]
+        L.oracle_sph_W.argtypes = [C.c_double, C.c_double, C.c_int]
         L.oracle_sph_W.restype = C.c_double
-        L.oracle_sph_F.argtypes = [C.c_double, C.c_double]
+        L.oracle_sph_F.argtypes = [C.c_double, C.c_double, C.c_int]
         L.oracle_sph_F.restype = C.c_double
         L.oracle_sph_density.argtypes = [dp, C.c_int, dp, dp, dp]
         L.oracle_sph_gradv.argtypes = [dp, C.c_int, dp, dp, dp, dp]
@@ -284,16 +284,18 @@ def max_threads() -> int:
 
 def sph_params_vector(q) -> np.ndarray:
     keys = ["rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly", "lambda_star", "alpha"]
-    vals = [float(q[k]) for k in keys] + [float(q.get("n_fixed", 0)), float(q.get("force_mode", 0))]
+    vals = [float(q[k]) for k in keys] + [float(q.get("n_fixed", 0)), float(q.get("force_mode", 0)),
+                                          float(q.get("kernel", 0))]
     return np.array(vals, dtype=np.float64)
 
 
-def sph_W(r, h):
-    return lib().oracle_sph_W(float(r), float(h))
+def sph_W(r, h, kernel=0):
+    """kernel 0: quintic spline, 1: Lucy (Eq. lucy_kernel)."""
+    return lib().oracle_sph_W(float(r), float(h), int(kernel))
 
 
-def sph_F(r, h):
-    return lib().oracle_sph_F(float(r), float(h))
+def sph_F(r, h, kernel=0):
+    return lib().oracle_sph_F(float(r), float(h), int(kernel))
 
 
 def sph_density(q, r):

@@ -22,25 +22,30 @@
  *     particles that take part in every sum as neighbours (density,
  *     pressure, viscous term with their zero velocity) but never move,
  *     carry no micro-domain and no polymer stress, and get no gradient.
- * Kernel: the quintic spline with support radius h (q = 3 r / h),
- * W = 63/(478 pi h^2) [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5] (terms where the
- * bracket is positive); F_IJ = -W'(r_IJ)/r_IJ.
+ * Kernels (S_KERNEL), both of support radius h, F_IJ = -W'(r_IJ)/r_IJ:
+ *   0: the quintic spline, q = 3 r / h,
+ *      W = 63/(478 pi h^2) [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5] (terms where
+ *      the bracket is positive);
+ *   1: the 2-D Lucy kernel of Appendix "Kernel function approximation",
+ *      Eq. (lucy_kernel), q = r / h: W = 5/(pi h^2) (1 + 3q) (1 - q)^3 for
+ *      q < 1; its derivative is taken by the product rule of that form.
  */
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
 
-/* parameter vector layout (double[S_COUNT]); S_NFIXED: number of trailing
+/* parameter vector layout (double[S_COUNT]); S_KERNEL: 0 quintic, 1 Lucy;
+ * S_NFIXED: number of trailing
  * wall particles; S_FMODE: 0 = body force +F for y >= Ly/2, -F below
  * (reverse Poiseuille), 1 = +F everywhere */
 enum {
     S_RHO0 = 0, S_ETA, S_ZETA, S_C, S_THETA, S_F, S_H, S_DT, S_MASS, S_LX, S_LY, S_LAMBDA, S_ALPHA, S_NFIXED,
-    S_FMODE, S_COUNT
+    S_FMODE, S_KERNEL, S_COUNT
 };
 
 static int n_mobile(const double *P, int n) { return n - (int)P[S_NFIXED]; }
 
-double oracle_sph_W(double r, double h)
+static double quintic_W(double r, double h)
 {
     double q = 3.0 * r / h;
     if (q >= 3.0) return 0.0;
@@ -51,7 +56,7 @@ double oracle_sph_W(double r, double h)
 }
 
 /* F = -W'(r)/r, r > 0 */
-double oracle_sph_F(double r, double h)
+static double quintic_F(double r, double h)
 {
     double q = 3.0 * r / h;
     if (q >= 3.0) return 0.0;
@@ -62,6 +67,30 @@ double oracle_sph_F(double r, double h)
     return -dWdr / r;
 }
 
+static double lucy_W(double r, double h)
+{
+    double q = r / h;
+    if (q >= 1.0) return 0.0;
+    return 5.0 / (M_PI * h * h) * (1.0 + 3.0 * q) * pow(1.0 - q, 3);
+}
+
+/* d/dr of (1 + 3q)(1 - q)^3 = (3/h)(1 - q)^3 - (3/h)(1 + 3q)(1 - q)^2 */
+static double lucy_F(double r, double h)
+{
+    double q = r / h;
+    if (q >= 1.0) return 0.0;
+    double dWdr = 5.0 / (M_PI * h * h) * (3.0 / h * pow(1.0 - q, 3) - 3.0 / h * (1.0 + 3.0 * q) * pow(1.0 - q, 2));
+    return -dWdr / r;
+}
+
+double oracle_sph_W(double r, double h, int kernel) { return kernel == 1 ? lucy_W(r, h) : quintic_W(r, h); }
+
+/* F = -W'(r)/r, r > 0 */
+double oracle_sph_F(double r, double h, int kernel) { return kernel == 1 ? lucy_F(r, h) : quintic_F(r, h); }
+
+static double kern_W(const double *P, double r) { return oracle_sph_W(r, P[S_H], (int)P[S_KERNEL]); }
+static double kern_F(const double *P, double r) { return oracle_sph_F(r, P[S_H], (int)P[S_KERNEL]); }
+
 static void min_image(const double *P, double *dx, double *dy)
 {
     *dx -= P[S_LX] * round(*dx / P[S_LX]);
@@ -71,14 +100,14 @@ static void min_image(const double *P, double *dx, double *dy)
 /* d (n) and p (n) */
 void oracle_sph_density(const double *P, int n, const double *r, double *d, double *p)
 {
-    const double rho0 = P[S_RHO0], c = P[S_C], h = P[S_H], m = P[S_MASS];
+    const double rho0 = P[S_RHO0], c = P[S_C], m = P[S_MASS];
     const double B = c * c * rho0 / 7.0;
     for (int I = 0; I < n; ++I) {
         double s = 0.0;
         for (int J = 0; J < n; ++J) {
             double dx = r[2 * I] - r[2 * J], dy = r[2 * I + 1] - r[2 * J + 1];
             min_image(P, &dx, &dy);
-            s += oracle_sph_W(sqrt(dx * dx + dy * dy), h);
+            s += kern_W(P, sqrt(dx * dx + dy * dy));
         }
         d[I] = s;
         double rho = m * s;
@@ -98,7 +127,7 @@ void oracle_sph_gradv(const double *P, int n, const double *r, const double *v, 
             min_image(P, &dx, &dy);
             double rr = sqrt(dx * dx + dy * dy);
             if (rr >= h || rr == 0.0) continue;
-            double F = oracle_sph_F(rr, h) / d[J];
+            double F = kern_F(P, rr) / d[J];
             double vx = v[2 * I] - v[2 * J], vy = v[2 * I + 1] - v[2 * J + 1];
             g[0] += F * dx * vx;
             g[1] += F * dx * vy;
@@ -131,7 +160,7 @@ void oracle_sph_accel(const double *P, int n, const double *r, const double *v, 
             min_image(P, &dx, &dy);
             double rr = sqrt(dx * dx + dy * dy);
             if (rr >= h || rr == 0.0) continue;
-            double F = oracle_sph_F(rr, h);
+            double F = kern_F(P, rr);
             double ex = dx / rr, ey = dy / rr;
             double vx = v[2 * I] - v[2 * J], vy = v[2 * I + 1] - v[2 * J + 1];
             /* pressure */

@@ -342,27 +342,89 @@ class MacroInit:
         return int(self.r.shape[0])
 
 
+KERNELS = {"quintic": 0, "lucy": 1}
+SUPPORT = {"quintic": 3.0, "lucy": 4.0}   # support radius h in units of the spacing dh
+
+
+def sound_speed(v_max: float, eta_tot: float, length: float, f_ext: float, delta: float = 0.1) -> float:
+    """Artificial sound speed, Eq. (sound_speed) (Appendix "Artificial sound
+    speed"): the largest of v_max/delta, sqrt(eta_tot v_max / (delta L)) and
+    sqrt(|f| L / delta), so that the Mach number stays near delta."""
+    return max(v_max / delta, math.sqrt(eta_tot * v_max / (delta * length)), math.sqrt(abs(f_ext) * length / delta))
+
+
+def cfl_dt(h: float, v_max: float, c: float, f_ext: float, nu: float, safety: float = 0.25) -> float:
+    """SPH time step of Eq. (cfl_condition): safety x the smallest of the
+    acoustic limit h/(|v|max + c), the body-force limit (h/|f|)^(1/2) and
+    the viscous limit h^2/(2 nu); a zero force or viscosity drops its limit."""
+    lims = [h / (v_max + c)]
+    if f_ext != 0.0:
+        lims.append(math.sqrt(h / abs(f_ext)))
+    if nu > 0.0:
+        lims.append(h * h / (2.0 * nu))
+    return safety * min(lims)
+
+
 def reverse_poiseuille(nx: int = 16, ny: int = 64, width: float = 1.0, force: float = 0.2, eta_s: float = 0.1,
                        beta: float = 0.5, rho0: float = 1.0, dt: float = 1e-3, lambda_star: float = 0.2,
-                       alpha: float = 0.07, theta: float = 0.5, n_steps: int = 200) -> MacroInit:
+                       alpha: float = 0.07, theta: float = 0.5, n_steps: int = 200,
+                       kernel: str = "quintic") -> MacroInit:
     """Reverse Poiseuille flow: a periodic channel of two counter-flowing
     halves of the given width (Ly = 2 width), body force +force along x for
     y >= width and -force below, SPH particles on an nx x ny lattice of
-    spacing dh = 2 width / ny, quintic kernel of support h = 3 dh.  The sound
-    speed follows Eq. (sound_speed) with delta = 0.1, the characteristic
-    length = width and the expected peak velocity of the Newtonian profile
+    spacing dh = 2 width / ny; quintic kernel of support h = 3 dh, or the
+    Lucy kernel of support h = 4 dh (kernel="lucy").  The sound speed
+    follows Eq. (sound_speed) with delta = 0.1, the characteristic length =
+    width and the expected peak velocity of the Newtonian profile
     force width^2 / (8 nu_tot), nu_tot = eta_s / ((1 - beta) rho0)."""
     dh = 2.0 * width / ny
     Lx, Ly = nx * dh, ny * dh
     eta_tot = eta_s / (1.0 - beta)
     vmax = force * width * width / (8.0 * eta_tot / rho0)
-    delta = 0.1
-    c = max(vmax / delta, math.sqrt(eta_tot * vmax / (delta * width)), math.sqrt(force * width / delta))
+    c = sound_speed(vmax, eta_tot, width, force)
     xs, ys = np.meshgrid((np.arange(nx) + 0.5) * dh, (np.arange(ny) + 0.5) * dh, indexing="ij")
     r = np.stack([xs.ravel(), ys.ravel()], axis=1)
-    params = dict(rho0=rho0, eta=eta_s, zeta=0.0, c=c, theta=theta, F=force, h=3.0 * dh, dt=dt,
-                  mass=rho0 * dh * dh, Lx=Lx, Ly=Ly, lambda_star=lambda_star, alpha=alpha, n_fixed=0, force_mode=0)
+    params = dict(rho0=rho0, eta=eta_s, zeta=0.0, c=c, theta=theta, F=force, h=SUPPORT[kernel] * dh, dt=dt,
+                  mass=rho0 * dh * dh, Lx=Lx, Ly=Ly, lambda_star=lambda_star, alpha=alpha, n_fixed=0, force_mode=0,
+                  kernel=KERNELS[kernel])
     return MacroInit(r=r, v=np.zeros_like(r), params=params, n_steps=n_steps)
+
+
+def reverse_poiseuille_paper(force: float = 1.0e-2, eta_s: float = 0.02, eta_p: float = 0.02, L: float = 4.0,
+                             nx: int | None = None, dh: float = 0.1, rho0: float = 1.0, lambda_star: float = 1.0,
+                             alpha: float = 0.02, theta: float = 0.5, delta_t: float = 0.32,
+                             dt_sph: float | None = 0.04, dt_micro: float = 0.005) -> MacroInit:
+    """Reverse Poiseuille flow set up as in the paper (Sec. "Reverse
+    Poiseuille Flow"): a periodic box of height Ly = L = 4 (and width L, or
+    nx columns), SPH spacing dh = 0.1, rho = 1, solvent viscosity 0.02, the
+    Lucy kernel of support h = 4 dh and the Tait equation with background
+    pressure theta c^2 rho0 / 7.  The sound speed follows Eq. (sound_speed)
+    with the Newtonian peak velocity of Appendix "Analytical velocity
+    profile", force rho0 L^2 / (32 eta_tot), eta_tot = eta_s + eta_p (eta_p:
+    the viscosity the micro-domains are expected to add).  The exchange
+    interval is delta_t = M_bar dt_SPH = k' dt_micro (Sec. "Temporal Coupling
+    Scheme"; the paper: 0.32 = 8 x 0.04 = 64 x 0.005).  dt_SPH is the given
+    step (None: the step of Eq. (cfl_condition)), lowered if needed so that
+    it stays within Eq. (cfl_condition) and M_bar = delta_t / dt_SPH is an
+    integer.  params carries "m_bar", "k_micro", "dt_cfl", "eta_tot" and
+    "v_max" beside the engine parameters."""
+    n_y = int(round(L / dh))
+    n_x = n_y if nx is None else int(nx)
+    eta_tot = eta_s + eta_p
+    vmax = force * rho0 * L * L / (32.0 * eta_tot)
+    c = sound_speed(vmax, eta_tot, L, force)
+    h = SUPPORT["lucy"] * dh
+    dt_cfl = cfl_dt(h, vmax, c, force, eta_tot / rho0)
+    dt = dt_cfl if dt_sph is None else min(float(dt_sph), dt_cfl)
+    m_bar = max(1, int(math.ceil(delta_t / dt - 1e-9)))
+    k_micro = int(round(delta_t / dt_micro))
+    xs, ys = np.meshgrid((np.arange(n_x) + 0.5) * dh, (np.arange(n_y) + 0.5) * dh, indexing="ij")
+    r = np.stack([xs.ravel(), ys.ravel()], axis=1)
+    params = dict(rho0=rho0, eta=eta_s, zeta=0.0, c=c, theta=theta, F=force, h=h, dt=delta_t / m_bar,
+                  mass=rho0 * dh * dh, Lx=n_x * dh, Ly=n_y * dh, lambda_star=lambda_star, alpha=alpha, n_fixed=0,
+                  force_mode=0, kernel=KERNELS["lucy"], m_bar=m_bar, k_micro=k_micro, dt_cfl=dt_cfl,
+                  eta_tot=eta_tot, v_max=vmax)
+    return MacroInit(r=r, v=np.zeros_like(r), params=params)
 
 
 def cylinder_array(n: int = 64, radius: float = 0.2, force: float = 1.0, eta_s: float = 0.1, beta: float = 0.5,
@@ -383,8 +445,7 @@ def cylinder_array(n: int = 64, radius: float = 0.2, force: float = 1.0, eta_s: 
     eta_tot = eta_s / (1.0 - beta)
     gap = 1.0 - 2.0 * radius
     vmax = force * gap * gap / (8.0 * eta_tot / rho0)
-    delta = 0.1
-    c = max(vmax / delta, math.sqrt(eta_tot * vmax / (delta * radius)), math.sqrt(force * radius / delta))
+    c = sound_speed(vmax, eta_tot, radius, force)
     params = dict(rho0=rho0, eta=eta_s, zeta=0.0, c=c, theta=theta, F=force, h=3.0 * dh, dt=dt,
                   mass=rho0 * dh * dh, Lx=1.0, Ly=1.0, lambda_star=lambda_star, alpha=alpha,
                   n_fixed=int(inside.sum()), force_mode=1)

@@ -3,6 +3,9 @@ Eqs. tait, sph_continuity, macro_micro).
 
 * the quintic kernel integrates to one; F = -W'/r against finite
   differences of W;
+* the Lucy kernel (Eq. lucy_kernel): unit integral, W(0) = 5/(pi h^2), and
+  F = -W'/r against finite differences and against its own simplified
+  closed form 60 (1 - r/h)^2 / (pi h^4);
 * number density on the uniform lattice is 1/dh^2 (kernel consistency);
 * the velocity gradient of a smooth periodic field approaches the analytic
   derivative;
@@ -28,6 +31,34 @@ def test_kernel_normalised_and_derivative(orc, h):
         dW = (orc.sph_W(r + eps, h) - orc.sph_W(r - eps, h)) / (2 * eps)
         assert abs(orc.sph_F(r, h) - (-dW / r)) < 1e-6 * abs(dW / r) + 1e-8 / h ** 3
     assert orc.sph_W(h, h) == 0.0 and orc.sph_F(1.01 * h, h) == 0.0
+
+
+@pytest.mark.parametrize("h", [0.05, 0.4, 1.0])
+def test_lucy_kernel_closed_forms(orc, h):
+    I, _ = integrate.quad(lambda r: 2 * math.pi * r * orc.sph_W(r, h, 1), 0, h)
+    assert abs(I - 1.0) < 1e-10
+    assert orc.sph_W(0.0, h, 1) == pytest.approx(5.0 / (math.pi * h * h), rel=1e-15)
+    for r in np.linspace(0.03 * h, 0.98 * h, 25):
+        F = orc.sph_F(r, h, 1)
+        assert F == pytest.approx(60.0 * (1.0 - r / h) ** 2 / (math.pi * h ** 4), rel=1e-12)
+        eps = 1e-6 * h
+        dW = (orc.sph_W(r + eps, h, 1) - orc.sph_W(r - eps, h, 1)) / (2 * eps)
+        assert abs(F - (-dW / r)) < 1e-6 * abs(dW / r) + 1e-8 / h ** 3
+        # a different function from the quintic spline of the same support
+        assert orc.sph_W(r, h, 1) != orc.sph_W(r, h, 0)
+    assert orc.sph_W(h, h, 1) == 0.0 and orc.sph_F(h, h, 1) == 0.0 and orc.sph_W(1.5 * h, h, 1) == 0.0
+
+
+@pytest.mark.parametrize("kernel", ["quintic", "lucy"])
+def test_lattice_density_of_each_kernel(orc, kernel):
+    """Lattice sums of a unit-integral kernel reproduce 1/dh^2: the quintic
+    spline at h = 3 dh to 6e-5, the Lucy kernel at h = 4 dh to 6e-4 (the sum
+    over the square lattice differs from the integral by aliasing terms)."""
+    m = inputs.reverse_poiseuille(nx=16, ny=16, kernel=kernel)
+    d, _ = orc.sph_density(m.params, m.r)
+    dh = m.params["Lx"] / 16
+    assert np.allclose(d, 1.0 / dh ** 2, rtol=1e-3)
+    assert np.ptp(d) < 1e-9 * d.mean()
 
 
 def test_lattice_density(orc):
@@ -57,9 +88,10 @@ def test_velocity_gradient_of_smooth_field(orc):
     assert np.abs(G[:, 0, 0]).max() < 1e-10 and np.abs(G[:, 1, 1]).max() < 1e-10
 
 
-def test_momentum_balance(orc):
+@pytest.mark.parametrize("kernel", ["quintic", "lucy"])
+def test_momentum_balance(orc, kernel):
     rng = np.random.default_rng(3)
-    m = inputs.reverse_poiseuille(nx=8, ny=32)
+    m = inputs.reverse_poiseuille(nx=8, ny=32, kernel=kernel)
     q = dict(m.params)
     r = m.r + rng.normal(scale=0.01, size=m.r.shape)
     r[:, 0] %= q["Lx"]
@@ -74,8 +106,9 @@ def test_momentum_balance(orc):
     assert abs(total[1]) < 1e-10 * q["mass"] * m.n
 
 
-def test_newtonian_startup_matches_fourier_series(orc):
-    m = inputs.reverse_poiseuille(nx=8, ny=32, alpha=0.0, beta=0.0)
+@pytest.mark.parametrize("kernel", ["quintic", "lucy"])
+def test_newtonian_startup_matches_fourier_series(orc, kernel):
+    m = inputs.reverse_poiseuille(nx=8, ny=32, alpha=0.0, beta=0.0, kernel=kernel)
     q = m.params
     r, v = m.r.copy(), m.v.copy()
     pi = np.zeros((m.n, 3))
