@@ -279,8 +279,11 @@ int lhmm_micro_destroy(lhmm_micro* m);
  *     the viscous term with their velocity) but never move, carry no
  *     micro-domain and no polymer stress (their rows of sigma are ignored),
  *     and get zero gradient rows;
- *   - quintic kernel of support radius h: W = 63/(478 pi h^2)
- *     [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5]_+, q = 3 r / h;
+ *   - kernel of support radius h (kernel): the quintic spline
+ *     W = 63/(478 pi h^2) [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5]_+, q = 3 r / h,
+ *     or the 2-D Lucy kernel of Appendix "Kernel function approximation",
+ *     Eq. (lucy_kernel), W = 5/(pi h^2) (1 + 3q)(1 - q)^3, q = r / h < 1
+ *     (the paper's choice, with h = 4 dh);
  *   - velocity-Verlet steps (Appendix "Detailed Coupling Protocol");
  *   - velocity gradient for the micro-domains, Eq. (macro_micro) with the
  *     volume factor 1/d_J; the micro-domain of particle I is driven by
@@ -306,10 +309,13 @@ typedef struct {
     double alpha;       /* viscosity ratio alpha                             */
     int32_t n_fixed;    /* trailing wall particles (see below)               */
     int32_t force_mode; /* LHMM_FORCE_REVERSE or LHMM_FORCE_UNIFORM          */
+    int32_t kernel;     /* LHMM_KERNEL_QUINTIC or LHMM_KERNEL_LUCY           */
 } lhmm_sph_params;
 
 #define LHMM_FORCE_REVERSE 0 /* +F x-hat where y >= Ly/2, -F below            */
 #define LHMM_FORCE_UNIFORM 1 /* +F x-hat everywhere                          */
+#define LHMM_KERNEL_QUINTIC 0 /* quintic spline, support h                   */
+#define LHMM_KERNEL_LUCY 1    /* Lucy kernel, Eq. (lucy_kernel), support h   */
 
 /* Allocate an SPH engine of n particles.  r0, v0: host n x 2.  stream: the
  * caller's hipStream_t (all SPH work is launched on it).  Errors: ARG, HIP,
@@ -334,14 +340,16 @@ int lhmm_sph_get_state(lhmm_sph* s, double* r, double* v, double* d);
  * Synchronous. */
 int lhmm_sph_coupling_state(lhmm_sph* s, double* sigma, double* gradL);
 
-/* One exchange interval of the coupling protocol (Appendix "Detailed
- * Coupling Protocol", Steps 1-4, with one SPH step per interval): SPH step
- * with the stored micro stresses, gradients to the micro-domains, k_micro
- * micro steps of every box, their mean stresses stored for the next
- * interval.  The micro engine must hold one box per mobile SPH particle, in order,
- * and both engines must have been created on the same stream.  No host
- * synchronisation.  Errors: ARG, STATE, HIP. */
-int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t k_micro);
+/* One exchange interval delta_t = m_bar dt_SPH = k_micro dt_micro of the
+ * coupling protocol (Appendix "Detailed Coupling Protocol", Steps 1-4;
+ * Sec. "Temporal Coupling Scheme"): m_bar SPH steps with the stored micro
+ * stresses held fixed, the velocity gradients at the end of the last one to
+ * the micro-domains, k_micro micro steps of every box, their mean stresses
+ * stored for the next interval.  The micro engine must hold one box per
+ * mobile SPH particle, in order, and both engines must have been created on
+ * the same stream.  m_bar, k_micro >= 1.  No host synchronisation.
+ * Errors: ARG, STATE, HIP. */
+int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t m_bar, int32_t k_micro);
 
 int lhmm_sph_destroy(lhmm_sph* s);
 

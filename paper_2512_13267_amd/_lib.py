@@ -63,7 +63,8 @@ class LhmmBox(C.Structure):
 class LhmmSphParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly",
                                             "lambda_star", "alpha")] + [("n_fixed", C.c_int32),
-                                                                        ("force_mode", C.c_int32)]
+                                                                        ("force_mode", C.c_int32),
+                                                                        ("kernel", C.c_int32)]
 
 
 class LhmmMicroConfig(C.Structure):
@@ -129,7 +130,7 @@ def lib():
         L.lhmm_sph_step.argtypes = [vp, vp, vp]
         L.lhmm_sph_get_state.argtypes = [vp, dp, dp, dp]
         L.lhmm_sph_coupling_state.argtypes = [vp, dp, dp]
-        L.lhmm_couple_step.argtypes = [vp, vp, C.c_int32]
+        L.lhmm_couple_step.argtypes = [vp, vp, C.c_int32, C.c_int32]
         L.lhmm_sph_destroy.argtypes = [vp]
         fp = C.POINTER(C.c_float)
         L.lhmm_sur_create.argtypes = [C.POINTER(LhmmSurParams), fp, vp, C.POINTER(vp)]

@@ -40,6 +40,7 @@ __device__ __forceinline__ double pow4(double x) {
 
 struct SphCtx {
     int n, n_mobile, force_mode;  // particles n_mobile .. n-1 are frozen walls
+    int kernel;                   // LHMM_KERNEL_QUINTIC or LHMM_KERNEL_LUCY
     int ncx, ncy;                 // cell grid (0: all pairs)
     int* cstart;                  // ncx * ncy + 1 cell offsets into cidx
     int* cidx;                    // particle indices in cell order
@@ -52,7 +53,7 @@ struct SphCtx {
 };
 
 // quintic kernel of support radius h, q = 3 r / h
-__device__ __forceinline__ double kernel_W(double r, double h) {
+__device__ __forceinline__ double quintic_W(double r, double h) {
     const double q = 3.0 * r / h;
     if (q >= 3.0) return 0.0;
     double w = pow4(3.0 - q) * (3.0 - q);
@@ -62,13 +63,38 @@ __device__ __forceinline__ double kernel_W(double r, double h) {
 }
 
 // F = -W'(r) / r
-__device__ __forceinline__ double kernel_F(double r, double h) {
+__device__ __forceinline__ double quintic_F(double r, double h) {
     const double q = 3.0 * r / h;
     if (q >= 3.0) return 0.0;
     double dw = -5.0 * pow4(3.0 - q);
     if (q < 2.0) dw += 30.0 * pow4(2.0 - q);
     if (q < 1.0) dw -= 75.0 * pow4(1.0 - q);
     return -(63.0 / (478.0 * M_PI * h * h) * dw * 3.0 / h) / r;
+}
+
+// 2-D Lucy kernel, Eq. (lucy_kernel): W = 5/(pi h^2) (1 + 3q)(1 - q)^3, q = r/h
+__device__ __forceinline__ double lucy_W(double r, double h) {
+    const double q = r / h;
+    if (q >= 1.0) return 0.0;
+    const double u = 1.0 - q;
+    return 5.0 / (M_PI * h * h) * (1.0 + 3.0 * q) * (u * u * u);
+}
+
+// its -W'(r)/r reduces to 60 (1 - q)^2 / (pi h^4)
+__device__ __forceinline__ double lucy_F(double r, double h) {
+    const double q = r / h;
+    if (q >= 1.0) return 0.0;
+    const double u = 1.0 - q, h2 = h * h;
+    return 60.0 / (M_PI * h2 * h2) * (u * u);
+}
+
+// the kernel choice is one value per engine, so the branch is uniform
+__device__ __forceinline__ double kernel_W(const SphCtx& S, double r) {
+    return S.kernel == LHMM_KERNEL_LUCY ? lucy_W(r, S.h) : quintic_W(r, S.h);
+}
+
+__device__ __forceinline__ double kernel_F(const SphCtx& S, double r) {
+    return S.kernel == LHMM_KERNEL_LUCY ? lucy_F(r, S.h) : quintic_F(r, S.h);
 }
 
 __device__ __forceinline__ void min_image(const SphCtx& S, double& dx, double& dy) {
@@ -189,7 +215,7 @@ __global__ __launch_bounds__(TPB) void k_density(SphCtx S) {
         const int J = nb.get(t);
         double dx = xi - S.r[2 * J], dy = yi - S.r[2 * J + 1];
         min_image(S, dx, dy);
-        s += kernel_W(sqrt(dx * dx + dy * dy), S.h);
+        s += kernel_W(S, sqrt(dx * dx + dy * dy));
     }
     s = wave_sum(s);
     if (lane == 0) {
@@ -235,7 +261,7 @@ __global__ __launch_bounds__(TPB) void k_accel(SphCtx S, const double* __restric
         min_image(S, dx, dy);
         const double rr = sqrt(dx * dx + dy * dy);
         if (rr >= S.h || rr == 0.0) continue;
-        const double F = kernel_F(rr, S.h);
+        const double F = kernel_F(S, rr);
         const double ex = dx / rr, ey = dy / rr;
         const double vx = vxi - S.v[2 * J], vy = vyi - S.v[2 * J + 1];
         const double dj = S.d[J];
@@ -306,7 +332,7 @@ __global__ __launch_bounds__(TPB) void k_gradL(SphCtx S, double* __restrict__ gr
         min_image(S, dx, dy);
         const double rr = sqrt(dx * dx + dy * dy);
         if (rr >= S.h || rr == 0.0) continue;
-        const double F = kernel_F(rr, S.h) / S.d[J];
+        const double F = kernel_F(S, rr) / S.d[J];
         const double vx = vxi - S.v[2 * J], vy = vyi - S.v[2 * J + 1];
         g0 += F * dx * vx;
         g1 += F * dx * vy;
@@ -392,6 +418,8 @@ int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const
     if (p->n_fixed < 0 || p->n_fixed >= n) return lhmm_fail(LHMM_ERR_ARG, "n_fixed must be in 0..n-1 (got %d)", p->n_fixed);
     if (p->force_mode != LHMM_FORCE_REVERSE && p->force_mode != LHMM_FORCE_UNIFORM)
         return lhmm_fail(LHMM_ERR_ARG, "unknown force_mode %d", p->force_mode);
+    if (p->kernel != LHMM_KERNEL_QUINTIC && p->kernel != LHMM_KERNEL_LUCY)
+        return lhmm_fail(LHMM_ERR_ARG, "unknown kernel %d", p->kernel);
     const double vals[] = {p->rho0, p->eta, p->zeta, p->c, p->theta, p->F, p->h, p->dt, p->mass, p->Lx, p->Ly,
                            p->lambda_star, p->alpha};
     for (double x : vals)
@@ -413,6 +441,7 @@ int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const
     S.n = n;
     S.n_mobile = n - p->n_fixed;
     S.force_mode = p->force_mode;
+    S.kernel = p->kernel;
     S.rho0 = p->rho0; S.eta = p->eta; S.zeta = p->zeta; S.c = p->c; S.theta = p->theta; S.F = p->F; S.h = p->h;
     S.dt = p->dt; S.mass = p->mass; S.Lx = p->Lx; S.Ly = p->Ly; S.lambda_star = p->lambda_star; S.alpha = p->alpha;
     // cell grid of side >= h: at least 3 x 3 cells, and counters plus indices in 64 KiB of LDS
@@ -492,9 +521,10 @@ int lhmm_sph_coupling_state(lhmm_sph* s, double* sigma, double* gradL) {
     return LHMM_OK;
 }
 
-int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t k_micro) {
+int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t m_bar, int32_t k_micro) {
     lhmm_clear_error();
     if (!s || !m) return lhmm_fail(LHMM_ERR_ARG, "null engine");
+    if (m_bar <= 0) return lhmm_fail(LHMM_ERR_ARG, "m_bar must be positive (got %d)", m_bar);
     if (k_micro <= 0) return lhmm_fail(LHMM_ERR_ARG, "k_micro must be positive (got %d)", k_micro);
     int32_t nb = 0;
     int rc = lhmm_micro_sizes(m, nullptr, &nb);
@@ -503,7 +533,9 @@ int lhmm_couple_step(lhmm_sph* s, lhmm_micro* m, int32_t k_micro) {
         return lhmm_fail(LHMM_ERR_ARG, "micro engine holds %d boxes for %d mobile SPH particles", nb, s->S.n_mobile);
     if (lhmm_micro_caller_stream(m) != s->stream)
         return lhmm_fail(LHMM_ERR_ARG, "the SPH and micro engines must share one stream");
-    launch_sph_step(s, s->d_sigma, s->d_gradL);
+    // m_bar SPH steps under the stored micro stresses; the gradient of the
+    // last one drives the micro-domains
+    for (int k = 0; k < m_bar; ++k) launch_sph_step(s, s->d_sigma, k + 1 == m_bar ? s->d_gradL : nullptr);
     LHMM_HIPCHK(hipGetLastError());
     return lhmm_micro_step(m, s->d_gradL, k_micro, s->d_sigma);
 }

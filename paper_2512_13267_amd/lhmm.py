@@ -27,7 +27,7 @@ class Sph:
             raise RuntimeError("the SPH engine needs a ROCm GPU")
         self._torch = torch
         p = LhmmSphParams(**{k: float(params[k]) for k in SPH_KEYS}, n_fixed=int(params.get("n_fixed", 0)),
-                          force_mode=int(params.get("force_mode", 0)))
+                          force_mode=int(params.get("force_mode", 0)), kernel=int(params.get("kernel", 0)))
         self.n_fixed = int(params.get("n_fixed", 0))
         r0 = np.ascontiguousarray(r0, dtype=np.float64).reshape(-1, 2)
         v0 = np.ascontiguousarray(v0, dtype=np.float64).reshape(-1, 2)
@@ -76,9 +76,10 @@ class Coupled:
             raise ValueError("one micro-box per mobile SPH particle is required")
         self.sph, self.micro = sph, micro
 
-    def step(self, k_micro: int):
+    def step(self, k_micro: int, m_bar: int = 1):
+        """One exchange interval: m_bar SPH steps, then k_micro micro steps."""
         with self.sph._torch.cuda.stream(self.sph.stream):
-            check(lib().lhmm_couple_step(self.sph._h, self.micro._h, int(k_micro)))
+            check(lib().lhmm_couple_step(self.sph._h, self.micro._h, int(m_bar), int(k_micro)))
 
     def coupling_state(self):
         """Host copies of the stored micro stresses (n, 6) and gradients (n, 3, 3)."""

@@ -91,6 +91,8 @@ def test_sph_surrogate_and_hybrid_reject_bad_arguments(torch_gpu):
         lhmm.Sph(dict(q, n_fixed=mac.r.shape[0]), mac.r, mac.v)  # no mobile particle
     with pytest.raises(_lib.LhmmError):
         lhmm.Sph(dict(q, force_mode=7), mac.r, mac.v)
+    with pytest.raises(_lib.LhmmError, match="kernel"):
+        lhmm.Sph(dict(q, kernel=2), mac.r, mac.v)
     r_out = mac.r.copy()
     r_out[0, 0] = 1.5
     with pytest.raises(_lib.LhmmError):

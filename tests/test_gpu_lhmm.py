@@ -21,10 +21,11 @@ def torch_gpu():
     return torch
 
 
-def test_sph_matches_oracle(torch_gpu, orc):
+@pytest.mark.parametrize("kernel,nx", [("quintic", 8), ("lucy", 10)])
+def test_sph_matches_oracle(torch_gpu, orc, kernel, nx):
     from paper_2512_13267_amd import inputs, lhmm
 
-    m = inputs.reverse_poiseuille(nx=8, ny=32)
+    m = inputs.reverse_poiseuille(nx=nx, ny=32, kernel=kernel)
     q = m.params
     torch = torch_gpu
     rng = np.random.default_rng(5)
@@ -109,6 +110,71 @@ def test_coupled_interval_matches_oracle(torch_gpu, orc):
     rg, vg, _ = s.get_state()
     assert np.abs(vg - v).max() < 1e-9 * max(1.0, np.abs(v).max())
     assert not np.any(m.flags())
+    m.close()
+    s.close()
+
+
+def test_paper_channel_on_the_cell_grid_matches_oracle(torch_gpu, orc):
+    """The paper's reverse-Poiseuille set-up (40 x 40 particles, Lucy kernel
+    of support 4 dh, background pressure, dt 0.04): the GPU engine bins the
+    particles into 10 x 10 cells of side h, the oracle sums all pairs."""
+    from paper_2512_13267_amd import inputs, lhmm
+
+    torch = torch_gpu
+    m = inputs.reverse_poiseuille_paper()
+    q = m.params
+    rng = np.random.default_rng(12)
+    sig = rng.normal(scale=0.5, size=(m.n, 6))
+    sig_dev = torch.tensor(sig, dtype=torch.float64, device="cuda")
+    L_dev = torch.zeros((m.n, 9), dtype=torch.float64, device="cuda")
+    v0 = rng.normal(scale=0.05, size=m.r.shape)
+    s = lhmm.Sph(q, m.r, v0)
+    r, v = m.r.copy(), v0.copy()
+    pi = orc.sph_polymer_stress(q, sig)
+    for _ in range(6):
+        s.step(sig_dev, L_dev)
+        Lo = orc.sph_step(q, r, v, pi)
+    rg, vg, dg = s.get_state()
+    dr = rg - r
+    dr -= q["Lx"] * np.round(dr / q["Lx"])
+    assert np.abs(dr).max() < 1e-11
+    assert np.abs(vg - v).max() < 1e-11 * max(1.0, np.abs(v).max())
+    Lg = L_dev.cpu().numpy().reshape(-1, 3, 3)
+    assert np.abs(Lg - Lo).max() < 1e-9 * np.abs(Lo).max()
+    s.close()
+
+
+def test_coupled_interval_with_several_sph_steps_matches_oracle(torch_gpu, orc):
+    """An exchange interval of m_bar = 3 SPH steps (Lucy kernel) and 6 micro
+    steps: the stresses stay fixed over the three SPH steps and the gradient
+    of the last one drives the boxes."""
+    from paper_2512_13267_amd import inputs, lhmm, micro
+
+    mac = inputs.reverse_poiseuille(nx=10, ny=16, force=2.0, kernel="lucy")
+    q = mac.params
+    wl = inputs.lhmm_boxes(mac.n, n_particles=300, polymer_fraction=0.2, seed_k=10)
+    p = wl.params
+    m = micro.from_workload(wl, precision="fp64")
+    s = lhmm.Sph(q, mac.r, mac.v)
+    cp = lhmm.Coupled(s, m)
+    k, m_bar = 6, 3
+    r, v = mac.r.copy(), mac.v.copy()
+    boxes = [orc.OracleBox(s=b.s, c=b.c, h=b.h, n_chains=b.n_chains, box_id=i) for i, b in enumerate(wl.boxes)]
+    pi = np.zeros((mac.n, 3))
+    for _ in range(3):
+        cp.step(k, m_bar=m_bar)
+        for _ in range(m_bar):
+            L = orc.sph_step(q, r, v, pi)
+        means, _ = orc.run_batch(p, p["seed"], p["chain_len"], boxes, list(L), k)
+        pi = orc.sph_polymer_stress(q, means)
+    sig, grad = cp.coupling_state()
+    assert np.abs(grad - L).max() <= 1e-10 * max(1e-3, np.abs(L).max())
+    assert np.abs(sig - means).max() <= 1e-8 * np.abs(means).max()
+    rg, vg, _ = s.get_state()
+    assert np.abs(vg - v).max() < 1e-9 * max(1.0, np.abs(v).max())
+    assert not np.any(m.flags())
+    with pytest.raises(Exception, match="m_bar"):
+        cp.step(k, m_bar=0)
     m.close()
     s.close()
 
