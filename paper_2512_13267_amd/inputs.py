@@ -77,18 +77,28 @@ def _wrap_f32(s: np.ndarray) -> np.ndarray:
 
 
 def random_box(rng: np.random.Generator, h: np.ndarray, N: int, n_chains: int, chain_len: int,
-               kBT: float = 1.0, mass: float = 1.0, b0: float = 0.9) -> tuple:
+               kBT: float = 1.0, mass: float = 1.0, b0: float = 0.9, planar: bool = False) -> tuple:
     """Random positions (chains first, as random walks of step b0), Maxwell
-    velocities with the mean removed.  Returns (s, c)."""
+    velocities with the mean removed.  Returns (s, c).  planar: a 2-D
+    system in the plane z = 0 of the cell (s_z = 0, c_z = 0, walks in the
+    plane); every pair separation and force then has a zero z component,
+    so the particles never leave the plane (the cell's z edge must be
+    diagonal and at least 3 rc)."""
     h = np.asarray(h, dtype=np.float64).reshape(3, 3)
     hinv = np.linalg.inv(h)
     s = rng.random((N, 3))
+    if planar:
+        if h[0, 2] != 0.0 or h[1, 2] != 0.0 or h[2, 0] != 0.0 or h[2, 1] != 0.0:
+            raise ValueError("a planar box needs a cell whose z edge is orthogonal to the plane")
+        s[:, 2] = 0.0
     n_beads = n_chains * chain_len
     if n_beads > N:
         raise ValueError("more chain beads than particles")
     if n_chains > 0:
         # random walks of step b0 from a uniform first bead
         u = rng.normal(size=(n_chains, chain_len - 1, 3))
+        if planar:
+            u[:, :, 2] = 0.0
         u /= np.linalg.norm(u, axis=2, keepdims=True)
         first = s[0:n_beads:chain_len] @ h.T  # (n_chains, 3)
         walk = first[:, None, :] + np.concatenate([np.zeros((n_chains, 1, 3)), np.cumsum(b0 * u, axis=1)],
@@ -96,8 +106,21 @@ def random_box(rng: np.random.Generator, h: np.ndarray, N: int, n_chains: int, c
         s[:n_beads] = walk.reshape(n_beads, 3) @ hinv.T
     s = _wrap_f32(s)
     c = rng.normal(scale=math.sqrt(kBT / mass), size=(N, 3))
+    if planar:
+        c[:, 2] = 0.0
     c -= c.mean(axis=0, keepdims=True)
     return s, _f32(c)
+
+
+def paper_melt_params(chain_len: int = 8, **over) -> dict:
+    """DPD/FENE parameters of the paper's 2-D melts (Tab. 1): kBT = 1,
+    a = 25, gamma = 4.5 (sigma = 3), m = 1, rc = 1, H = 50, R0 = 1.5,
+    dt = 0.005; number density n = 4 per unit area is the box's, not a
+    parameter here."""
+    p = default_params(a=25.0, gamma=4.5, sigma=3.0, kBT=1.0, mass=1.0, rc=1.0, dt=0.005, H=50.0, R0=1.5,
+                       chain_len=chain_len)
+    p.update(over)
+    return p
 
 
 def shear_gradient(rate: float) -> np.ndarray:

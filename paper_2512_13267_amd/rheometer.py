@@ -17,13 +17,18 @@ with standard errors over the replicas, and the Carreau-Yasuda fit
 by least squares in log eta.  Stresses are the engine's (tension positive,
 total = kinetic + pair + bond parts).
 
-The micro model is the engine's (3-D DPD with FENE chains); the paper's
-table of fitted parameters is for its 2-D melt with adaptive boundary
-conditions, so the numbers are not expected to agree.
+Two micro models: the engine's 3-D boxes (DPD with FENE chains at density
+3), and --planar, the paper's 2-D melt (Tab. 1 parameters, n = 4 per unit
+area, no solvent) held in the plane z = 0 of a periodic cell and sheared
+homogeneously.  The paper measures its melts in open micro-domains with
+adaptive boundary conditions; the planar sweep is the same material in a
+periodic sheared cell, so its Carreau-Yasuda parameters are compared with
+the paper's table (PAPER_CY).
 
-Command line: ``python -m paper_2512_13267_amd.rheometer [--rates ...]
-[--replicas 16] [--chain-len 10] [--equil 5000] [--steps 20000] [--out FILE]``;
-``--report a.json,b.json --md FILE`` writes a summary of earlier runs.
+Command line: ``python -m paper_2512_13267_amd.rheometer [--planar]
+[--rates ...] [--replicas 16] [--chain-len 10] [--edge E] [--equil 5000]
+[--steps 20000] [--out FILE]``; ``--report a.json,b.json --md FILE`` writes
+a summary of earlier runs.
 """
 from __future__ import annotations
 
@@ -35,6 +40,11 @@ import time
 import numpy as np
 
 from . import inputs
+
+# Carreau-Yasuda parameters the paper fits to its 2-D melts
+# (Tab. yasuda_params): N_d -> (eta0, eta_inf, lambda, a, n)
+PAPER_CY = {4: (13.20, 0.0, 23.50, 0.71, 0.60), 8: (34.29, 3.15, 89.75, 0.95, 0.37),
+            16: (173.18, 4.45, 353.48, 0.55, 0.18), 32: (242.83, 4.81, 1307.88, 1.23, 0.29)}
 
 
 def carreau_yasuda(gdot, eta0, eta_inf, lam, a, n):
@@ -96,34 +106,52 @@ def normal_stress_and_relaxation(gdot, sigma):
     return eta, n1, psi1, 0.5 * psi1 / eta
 
 
+PLANAR_THICKNESS = 3.5  # z edge of a planar cell: above the 3.3 rc at which a cell counts as thin
+
+
 def sweep_workload(rates, replicas: int = 16, chain_len: int = 10, edge: float = 10.0, density: float = 3.0,
-                   polymer_fraction: float = 1.0, seed_k: int = 60, **param_over) -> inputs.Workload:
-    """Boxes of a shear sweep: for every rate, `replicas` cubic boxes of
-    chains (polymer fraction 1: a melt) under simple shear u_x = rate y."""
-    p = inputs.default_params(seed=inputs.SEED_BASE + seed_k, chain_len=chain_len, **param_over)
+                   polymer_fraction: float = 1.0, seed_k: int = 60, planar: bool = False,
+                   **param_over) -> inputs.Workload:
+    """Boxes of a shear sweep: for every rate, `replicas` boxes of chains
+    (polymer fraction 1: a melt) under simple shear u_x = rate y.  Cubic
+    boxes of the given edge and number density per volume, or (planar) 2-D
+    systems of edge x edge at the given density per area, held in the
+    plane z = 0 of a cell of z edge PLANAR_THICKNESS, with the paper's
+    melt parameters (Tab. 1) unless overridden."""
+    if planar:
+        p = inputs.paper_melt_params(chain_len=chain_len, seed=inputs.SEED_BASE + seed_k, **param_over)
+        N = int(round(density * edge ** 2))
+        h = np.diag([edge, edge, PLANAR_THICKNESS])
+    else:
+        p = inputs.default_params(seed=inputs.SEED_BASE + seed_k, chain_len=chain_len, **param_over)
+        N = int(round(density * edge ** 3))
+        h = inputs.cubic_cell(edge)
     rng = np.random.default_rng(inputs.SEED_BASE + seed_k)
-    N = int(round(density * edge ** 3))
     n_chains = int(polymer_fraction * N) // chain_len  # whole chains; the rest is solvent
-    h = inputs.cubic_cell(edge)
     boxes = []
     for rate in rates:
         for _ in range(replicas):
-            s, c = inputs.random_box(rng, h, N, n_chains, chain_len, p["kBT"], p["mass"])
+            s, c = inputs.random_box(rng, h, N, n_chains, chain_len, p["kBT"], p["mass"], planar=planar)
             boxes.append(inputs.BoxInit(s=s, c=c, h=h, n_chains=n_chains, L=inputs.shear_gradient(float(rate)),
                                         edge=edge, phi=polymer_fraction))
-    return inputs.Workload("shear_sweep", p, boxes, 0)
+    return inputs.Workload("shear_sweep_2d" if planar else "shear_sweep", p, boxes, 0)
 
 
 def run_sweep(rates, replicas: int = 16, chain_len: int = 10, equil: int = 5000, steps: int = 20000,
-              edge: float = 10.0, seed_k: int = 60, log=print) -> dict:
+              edge: float = 10.0, seed_k: int = 60, planar: bool = False, density: float | None = None,
+              log=print) -> dict:
     """Shear every box of the sweep for `equil` steps, then average the
-    stress over `steps` more; per-rate means and standard errors."""
+    stress over `steps` more; per-rate means and standard errors.  Planar
+    sweeps report the 2-D stress (force per length: the cell stress times
+    its z edge)."""
     import torch
 
     from . import micro
 
     rates = np.asarray(rates, dtype=np.float64)
-    wl = sweep_workload(rates, replicas, chain_len, edge, seed_k=seed_k)
+    if density is None:
+        density = 4.0 if planar else 3.0
+    wl = sweep_workload(rates, replicas, chain_len, edge, density=density, seed_k=seed_k, planar=planar)
     m = micro.from_workload(wl, precision="fp32")
     G = torch.tensor(np.stack([b.L for b in wl.boxes]), dtype=torch.float64, device="cuda").contiguous()
     t0 = time.time()
@@ -143,10 +171,13 @@ def run_sweep(rates, replicas: int = 16, chain_len: int = 10, equil: int = 5000,
     flags = m.flags()
     m.close()
     per_box = (acc / n_calls).reshape(len(rates), replicas, 6)
+    if planar:
+        per_box = per_box * PLANAR_THICKNESS
     mean = per_box.mean(axis=1)
     se = per_box.std(axis=1, ddof=1) / math.sqrt(replicas)
     eta, n1, psi1, lam = normal_stress_and_relaxation(rates, mean)
     out = {"rates": rates.tolist(), "replicas": replicas, "chain_len": chain_len, "edge": edge,
+           "dims": 2 if planar else 3, "density": density,
            "equil_steps": equil, "avg_steps": steps, "dt": wl.params["dt"],
            "n_particles": wl.n_particles, "seconds": time.time() - t0,
            "flagged_boxes": int(np.count_nonzero(flags)),
@@ -171,12 +202,20 @@ def chain_scaling(chain_lens, lams) -> dict:
 
 def report(results, command: str) -> str:
     """Markdown summary of one or more sweeps (one per chain length)."""
+    planar = results[0].get("dims", 3) == 2
+    if planar:
+        box = ("Boxes: the paper's 2-D melt (Tab. 1: DPD a = 25, gamma = 4.5, kBT = 1, FENE H = 50, R0 = 1.5, "
+               "dt = 0.005; n = 4 per unit area, polymer fraction 1), {edge} x {edge} rc periodic, held in the "
+               "plane z = 0 of a cell of z edge {th} rc and sheared homogeneously (Lees-Edwards); stresses are 2-D "
+               "(the cell stress times its z edge)").format(edge=results[0]["edge"], th=PLANAR_THICKNESS)
+    else:
+        box = ("Boxes: cubic, edge {edge} rc, density 3, polymer fraction 1 (whole chains, the few leftover "
+               "particles solvent), DPD a = 25, gamma = 4.5, kBT = 1, FENE H = 30, R0 = 1.5, dt = 0.01").format(
+                   edge=results[0]["edge"])
     L = ["# Virtual rheometer: steady simple shear of DPD/FENE melts", "",
-         "Boxes: cubic, edge {edge} rc, density 3, polymer fraction 1 (whole chains, the few leftover particles "
-         "solvent), DPD a = 25, gamma = 4.5, kBT = 1, FENE H = 30, R0 = 1.5, dt = 0.01; every rate has {rep} "
-         "boxes with their own start and random-force stream, all rates of a chain length in one batched "
-         "engine call.  Stress: the engine's Irving-Kirkwood mean (tension positive).".format(
-             edge=results[0]["edge"], rep=results[0]["replicas"]), "",
+         box + "; every rate has {rep} boxes with their own start and random-force stream, all rates of a chain "
+         "length in one batched engine call.  Stress: the engine's Irving-Kirkwood mean (tension positive).".format(
+             rep=results[0]["replicas"]), "",
          "Command (MI355X, one GPU):", "", "```", command, "```", ""]
     for r in results:
         L += [f"## N_d = {r['chain_len']} ({r['equil_steps']} steps to steady state, then {r['avg_steps']} "
@@ -189,6 +228,12 @@ def report(results, command: str) -> str:
             L += ["", "Carreau-Yasuda fit (Eq. Yasuda, weighted by the standard errors): eta0 = {eta0:.4g}, "
                   "eta_inf = {eta_inf:.4g}, lambda = {lam:.4g}, a = {a:.3g}, n = {n:.3g}; RMS relative residual "
                   "{rms_rel_residual:.3g}.".format(**cy)]
+        if planar and r["chain_len"] in PAPER_CY:
+            e0, ei, lam, a, n = PAPER_CY[r["chain_len"]]
+            pred = carreau_yasuda(np.asarray(r["rates"]), e0, ei, lam, a, n)
+            L += ["", f"The paper's fit for N_d = {r['chain_len']} (Tab. yasuda_params): eta0 = {e0}, "
+                  f"eta_inf = {ei}, lambda = {lam}, a = {a}, n = {n}; its curve at the rates above: "
+                  + ", ".join(f"{x:.4g}" for x in pred) + "."]
         L.append("")
     fits = [(r["chain_len"], r["carreau_yasuda"]["lam"]) for r in results if r.get("carreau_yasuda")]
     if len(fits) >= 2:
@@ -196,8 +241,22 @@ def report(results, command: str) -> str:
         L += ["## Relaxation time against chain length", "",
               "| N_d | lambda (Carreau-Yasuda) |", "|---|---|"] + [f"| {n} | {lam:.4g} |" for n, lam in fits] + [
               "", f"lambda ~ N_d^b with b = {sc['b']:.3f} (least squares in log-log); the Rouse model gives 2.", ""]
-    L += ["The micro model is the engine's 3-D DPD/FENE model, not the paper's 2-D melt with adaptive boundary "
-          "conditions, so these parameters are not comparable with the paper's table.", ""]
+    if not planar:
+        L += ["The micro model is the engine's 3-D DPD/FENE model, not the paper's 2-D melt, so these parameters "
+              "are not comparable with the paper's table.", ""]
+    else:
+        rows = [r for r in results if r.get("carreau_yasuda") and r["chain_len"] in PAPER_CY]
+        if rows:
+            L += ["## Against the paper's table (Tab. yasuda_params)", "",
+                  "| N_d | eta0 here / paper | eta_inf here / paper | lambda here / paper | eta at the highest rate "
+                  "here / paper's curve |", "|---|---|---|---|---|"]
+            for r in rows:
+                cy, (e0, ei, lam, a, n) = r["carreau_yasuda"], PAPER_CY[r["chain_len"]]
+                g = r["rates"][-1]
+                L.append(f"| {r['chain_len']} | {cy['eta0']:.4g} / {e0} | {cy['eta_inf']:.4g} / {ei} | "
+                         f"{cy['lam']:.4g} / {lam} | {r['eta'][-1]:.4g} / "
+                         f"{float(carreau_yasuda(g, e0, ei, lam, a, n)):.4g} (rate {g:g}) |")
+            L.append("")
     return "\n".join(L)
 
 
@@ -206,6 +265,8 @@ def main(argv=None):
     ap.add_argument("--rates", default="0.01,0.02,0.05,0.1,0.2,0.5,1.0,2.0")
     ap.add_argument("--replicas", type=int, default=16)
     ap.add_argument("--chain-len", type=int, default=10)
+    ap.add_argument("--planar", action="store_true", help="the paper's 2-D melt (Tab. 1, n = 4)")
+    ap.add_argument("--edge", type=float, default=None, help="box edge (default 10, planar 32)")
     ap.add_argument("--equil", type=int, default=5000)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--out", default=None)
@@ -229,7 +290,8 @@ def main(argv=None):
     if not torch.cuda.is_available():
         raise SystemExit("needs the GPU")
     rates = [float(x) for x in args.rates.split(",")]
-    res = run_sweep(rates, args.replicas, args.chain_len, args.equil, args.steps)
+    edge = args.edge if args.edge is not None else (32.0 if args.planar else 10.0)
+    res = run_sweep(rates, args.replicas, args.chain_len, args.equil, args.steps, edge=edge, planar=args.planar)
     print(json.dumps(res), flush=True)
     if args.out:
         with open(args.out, "w") as f:

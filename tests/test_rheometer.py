@@ -6,7 +6,7 @@ import math
 import numpy as np
 import pytest
 
-from paper_2512_13267_amd import rheometer
+from paper_2512_13267_amd import inputs, rheometer
 
 
 @pytest.fixture(scope="module")
@@ -91,6 +91,66 @@ def test_sweep_workload_layout():
     assert [b.L[0, 1] for b in wl.boxes] == [0.1] * 3 + [1.0] * 3
     # replicas start from different states
     assert not np.array_equal(wl.boxes[0].s, wl.boxes[1].s)
+
+
+def test_planar_melt_stays_in_its_plane_at_kBT(orc):
+    """The paper's 2-D melt (Tab. 1, n = 4, N_d = 8) held in the plane z = 0
+    of a periodic cell: every z separation is zero, so positions and
+    velocities never leave the plane (exactly), and the fluctuation-
+    dissipation balance gives kBT per in-plane degree of freedom (time
+    average of the kinetic stress, 2 %)."""
+    wl = rheometer.sweep_workload([0.0, 0.05], replicas=1, chain_len=8, edge=6.0, density=4.0, planar=True)
+    p = wl.params
+    assert p["H"] == 50.0 and p["dt"] == 0.005 and wl.boxes[0].N == 144 and wl.boxes[0].n_chains == 18
+    for k, b in enumerate(wl.boxes):
+        assert not b.s[:, 2].any() and not b.c[:, 2].any()
+        ob = orc.OracleBox(s=b.s, c=b.c, h=b.h, n_chains=b.n_chains, box_id=k)
+        orc.run_box(p, p["seed"], 8, ob, b.L, 400)
+        mean, parts, _ = orc.run_box(p, p["seed"], 8, ob, b.L, 3000)
+        assert not ob.s[:, 2].any() and not ob.c[:, 2].any() and ob.err == 0
+        V = float(np.linalg.det(ob.h))
+        Tx, Ty, Tz = (-parts[0][:3] * V / b.N).tolist()
+        assert Tz == 0.0 and mean[4] == 0.0 and mean[5] == 0.0
+        if k == 0:
+            assert Tx == pytest.approx(1.0, abs=0.02) and Ty == pytest.approx(1.0, abs=0.02)
+    with pytest.raises(ValueError):
+        inputs.random_box(np.random.default_rng(0), np.array([[5.0, 0, 1.0], [0, 5.0, 0], [0, 0, 3.5]]), 10, 0, 8,
+                          planar=True)
+
+
+@pytest.mark.gpu
+def test_planar_melt_matches_oracle_and_sweeps(torch_gpu, orc):
+    """FP64 planar boxes on the device against the oracle (200 steps, the
+    tolerances of the 3-D trajectory tests), then a short FP32 planar sweep
+    at the paper's parameters: positive viscosity, in-plane stress only."""
+    from paper_2512_13267_amd import micro
+
+    torch = torch_gpu
+    wl = rheometer.sweep_workload([0.05, 0.5], replicas=1, chain_len=8, edge=8.0, density=4.0, planar=True)
+    p = wl.params
+    m = micro.from_workload(wl, precision="fp64", graphs=False)
+    G = torch.tensor(np.stack([b.L for b in wl.boxes]), dtype=torch.float64, device="cuda").contiguous()
+    out = m.step(G, 200).cpu().numpy()
+    s, c, h, _ = m.get_state()
+    obs = [orc.OracleBox(s=b.s, c=b.c, h=b.h, n_chains=b.n_chains, box_id=k) for k, b in enumerate(wl.boxes)]
+    means, _ = orc.run_batch(p, p["seed"], 8, obs, [b.L for b in wl.boxes], 200)
+    n = wl.boxes[0].N
+    for k, ob in enumerate(obs):
+        sk = s[k * n:(k + 1) * n]
+        d = sk - ob.s
+        d -= np.round(d)
+        assert np.abs(d @ ob.h.T).max() <= 1e-4, k
+        assert np.abs(c[k * n:(k + 1) * n] - ob.c).max() <= 1e-4, k
+        assert np.abs(out[k] - means[k]).max() <= 1e-6 * np.abs(means[k]).max(), k
+        assert not sk[:, 2].any() and not c[k * n:(k + 1) * n, 2].any()
+    assert not m.flags().any()
+    m.close()
+    res = rheometer.run_sweep([0.05, 0.5], replicas=4, chain_len=8, equil=400, steps=800, edge=16.0, planar=True,
+                              log=lambda *a, **k: None)
+    assert res["dims"] == 2 and res["flagged_boxes"] == 0
+    assert all(e > 0 for e in res["eta"]), res["eta"]
+    sig = np.asarray(res["sigma_mean"])
+    assert np.abs(sig[:, 4:]).max() == 0.0
 
 
 @pytest.mark.gpu
