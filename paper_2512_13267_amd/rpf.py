@@ -63,6 +63,21 @@ def rpf_velocity(y, F: float, rho: float, eta: float, Ly: float):
     return np.where(lower, -vmax, vmax) * shape
 
 
+def rpf_startup_velocity(y, t: float, F: float, rho: float, eta: float, Ly: float, n_modes: int = 400):
+    """Newtonian start-up from rest: v_t = nu v_yy + f(y), nu = eta / rho,
+    with the square-wave forcing f = -F (y < Ly/2), +F above, expanded as
+    f = -(4F/pi) sum over odd k of sin(2 pi k y / Ly) / k; every mode
+    relaxes as (1 - exp(-nu kappa^2 t)) / (nu kappa^2)."""
+    y = np.asarray(y, dtype=np.float64)
+    nu = eta / rho
+    v = np.zeros_like(y)
+    for k in range(1, 2 * n_modes, 2):
+        kap = 2.0 * math.pi * k / Ly
+        lam = nu * kap * kap
+        v += -(4.0 * F / math.pi) * np.sin(kap * y) / k * (-math.expm1(-lam * t)) / lam
+    return v
+
+
 def sph_shear_viscosity(eta: float, zeta: float) -> float:
     """Shear viscosity realised by the pair viscous term of Eq.
     (sph_continuity) in 2-D: with friction coefficients a = 2 eta - zeta and

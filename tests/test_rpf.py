@@ -46,6 +46,22 @@ def test_closed_forms_satisfy_the_momentum_balance():
     assert y[np.argmax(v)] == pytest.approx(0.75 * Ly, abs=dy)
 
 
+def test_startup_series_reaches_the_parabola_and_solves_the_diffusion_equation():
+    F, rho, eta, Ly = 0.01, 1.0, 0.025, 4.0
+    y = np.linspace(0.05, Ly - 0.05, 40)
+    assert not rpf.rpf_startup_velocity(y, 0.0, F, rho, eta, Ly).any()
+    late = rpf.rpf_startup_velocity(y, 1e5, F, rho, eta, Ly, n_modes=4000)
+    assert np.abs(late - rpf.rpf_velocity(y, F, rho, eta, Ly)).max() < 1e-4 * F * rho * Ly ** 2 / (32 * eta)
+    # v_t = nu v_yy + f away from the switches, by central differences
+    yy = np.array([0.6, 1.0, 1.4, 2.6, 3.0, 3.4])
+    t, dt, dy, nu = 7.0, 1e-3, 1e-3, eta / rho
+    vt = (rpf.rpf_startup_velocity(yy, t + dt, F, rho, eta, Ly) - rpf.rpf_startup_velocity(yy, t - dt, F, rho, eta, Ly)) / (2 * dt)
+    vyy = (rpf.rpf_startup_velocity(yy + dy, t, F, rho, eta, Ly) - 2 * rpf.rpf_startup_velocity(yy, t, F, rho, eta, Ly)
+           + rpf.rpf_startup_velocity(yy - dy, t, F, rho, eta, Ly)) / dy ** 2
+    f = np.where(yy >= 0.5 * Ly, F, -F)
+    assert np.allclose(vt, nu * vyy + f, rtol=0, atol=2e-3 * F)
+
+
 def test_sound_speed_and_cfl_limits():
     # each branch of Eq. (sound_speed) dominates in its own regime
     assert inputs.sound_speed(1.0, 1e-6, 1.0, 1e-6) == pytest.approx(10.0)
@@ -77,17 +93,23 @@ def test_paper_set_up():
 @pytest.mark.gpu
 def test_sph_alone_reaches_the_newtonian_parabola(torch_gpu):
     """SPH only (no polymer), the paper's macro set-up on a 10-column strip,
-    time step from Eq. (cfl_condition): after six start-up time constants
-    the time-averaged velocity is the parabola of Appendix "Analytical
-    velocity profile" of the viscosity the SPH viscous term realises
-    (5/4 eta_s), and the velocity gradient carries the exact shear stress
-    of Eq. RPF."""
+    time step from Eq. (cfl_condition): the start-up follows the Newtonian
+    Fourier series, and after six start-up time constants the time-averaged
+    velocity is the parabola of Appendix "Analytical velocity profile", both
+    of the viscosity the SPH viscous term realises (5/4 eta_s); the velocity
+    gradient carries the exact shear stress of Eq. RPF."""
     res = rpf.run(force=1.0e-2, alpha=0.0, eta_p_guess=0.0, nx=10, n_particles=0, startup=100.0, average=60.0,
                   log=None)
     print({k: res[k] for k in ("total_dev_rms", "total_dev_max", "vmax", "vmax_newtonian", "v_shape_rms",
                                "m_bar", "dt_sph", "seconds")})
     assert res["dt_sph"] <= res["dt_cfl"] and res["m_bar"] == 9
     assert res["vmax"] == pytest.approx(res["vmax_newtonian"], rel=0.03)
+    # the start-up transient follows the Fourier series of the same viscosity
+    mac = inputs.reverse_poiseuille_paper(force=1.0e-2, eta_p=0.0, alpha=0.0, nx=10)
+    yrows = np.unique(mac.r[:, 1])
+    for t, vmean in res["vmean_trace"][:12]:
+        ref = np.abs(rpf.rpf_startup_velocity(yrows, t, 1.0e-2, 1.0, res["eta_sph"], 4.0)).mean()
+        assert vmean == pytest.approx(ref, rel=0.03), (t, vmean, ref)
     assert res["v_shape_rms"] < 0.02
     assert res["total_dev_rms"] < 0.03 and res["total_dev_max"] < 0.05
 
