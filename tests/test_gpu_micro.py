@@ -497,3 +497,39 @@ def test_fused_binning_and_box_groups_on_the_full_batch_and_subsets(torch_gpu):
     for r in res[1:]:
         for a, b in zip(res[0], r):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-12)])
+def test_forces_match_oracle_in_strongly_deformed_cells(torch_gpu, orc, precision, tol):
+    """Reduced cells that long runs under time-varying gradients reach:
+    elongated 4:1 and 9:1, negative diagonal entries, nearly axis-aligned
+    long vectors (in-plane columns a, b; z edge 11.01)."""
+    _lib, inputs, micro = _mod()
+    wl = inputs.lhmm_boxes(1, n_particles=4000, polymer_fraction=0.1, seed_k=41)
+    p = wl.params
+    cells = [((-5.6, 0.2), (-2.6, -21.4)), ((-9.7, 4.3), (-5.7, -10.0)), ((3.4, 0.5), (-5.0, 34.0)),
+             ((-7.2, -6.1), (7.8, -10.3)), ((11.0, 0.0), (5.4, 11.0))]
+    rng = np.random.default_rng(31)
+    boxes, states = [], []
+    for k, (a, b) in enumerate(cells):
+        h = np.array([[a[0], b[0], 0.0], [a[1], b[1], 0.0], [0.0, 0.0, 11.01]])
+        N = int(round(3.0 * abs(np.linalg.det(h))))
+        nch = N // 100
+        s, c = inputs.random_box(rng, h, N, nch, 10)
+        boxes.append((N, nch, h, 700 + k))
+        states.append((s, c, h, nch))
+    m = micro.Micro(p, boxes, precision=precision)
+    m.set_state(np.concatenate([st[0] for st in states]), np.concatenate([st[1] for st in states]),
+                np.stack([st[2] for st in states]), step=57)
+    L = np.zeros((len(cells), 9))
+    L[:, 0], L[:, 1], L[:, 3], L[:, 4] = 0.02, -0.16, -0.01, -0.02
+    f, vir = m.forces(L)
+    off = np.concatenate([[0], np.cumsum([bx[0] for bx in boxes])])
+    for k, (s, c, h, nch) in enumerate(states):
+        Fr, Wr, err = orc.forces(p, p["seed"], 10, 700 + k, nch, s, c, h, L[k].reshape(3, 3), 57)
+        assert err == 0
+        rel = np.linalg.norm(f[off[k]:off[k + 1]] - Fr) / np.linalg.norm(Fr)
+        assert rel <= tol, (k, cells[k], rel)
+        Wpair = Wr[:3].sum(axis=0)
+        assert np.abs(vir[k, 0] - Wpair).max() <= 10 * tol * np.abs(Wpair).max() + 1e-9, k
+    m.close()
