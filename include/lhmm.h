@@ -139,9 +139,14 @@ int lhmm_micro_get_state(lhmm_micro* m, double* s, double* c, double* f, double*
  *   gradL: DEVICE pointer, n_boxes x 9 doubles (u = L r per box);
  *   stress_out: DEVICE pointer, n_boxes x 6 doubles.
  * A gradient that is not finite, in-plane and traceless sets LHMM_FLAG_ARG
- * on its box, which then advances with L = 0.  Asynchronous with respect to
- * the host; ordered on the caller's stream.  Errors: ARG (n_steps <= 0),
- * STATE (no state loaded), HIP. */
+ * on its box, which then advances with L = 0.  Every call (and every call of
+ * lhmm_micro_step_subset and lhmm_micro_time, for the boxes it advances)
+ * first removes each box's mean peculiar velocity: the micro-domain moves
+ * with its macro particle, and since pair forces cancel, the mean would
+ * otherwise follow d<c>/dt = -L <c> and grow wherever the flow compresses
+ * the box, seeded by rounding.  Asynchronous with respect to the host;
+ * ordered on the caller's stream.  Errors: ARG (n_steps <= 0), STATE (no
+ * state loaded), HIP. */
 int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double* stress_out);
 
 /* As lhmm_micro_step, for the listed boxes only: boxes is a HOST array of

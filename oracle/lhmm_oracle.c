@@ -497,6 +497,17 @@ int oracle_run_box(const double *P, uint64_t seed, int chain_len, uint32_t box, 
         *err |= ORACLE_ERR_ARG;
         return -1;
     }
+    /* every call starts from zero mean peculiar velocity: the micro-domain
+     * moves with its macro particle (pair forces cancel, so under a
+     * compressing gradient the mean would follow d<c>/dt = -L <c>) */
+    if (N > 0) {
+        double mean[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) mean[k] += c[3 * i + k];
+        for (int k = 0; k < 3; ++k) mean[k] /= N;
+        for (int i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) c[3 * i + k] -= mean[k];
+    }
     if (!*fvalid) {
         oracle_forces(P, seed, chain_len, box, N, n_chains, s, c, h, L, (uint32_t)*step, F, W, err, mode, NULL);
         *fvalid = 1;

@@ -373,6 +373,33 @@ __global__ void k_setup_call(Ctx C, const double* __restrict__ gradL) {
     expm_planar(L, 0.5 * C.dt, D.Eh);
 }
 
+// Remove each box's mean peculiar velocity (one workgroup per box, or per
+// selected box).  The pair forces cancel, so the mean obeys
+// d<c>/dt = -L <c>: a flow that compresses the box amplifies it, and the
+// rounding of the two-sided single-precision pair forces seeds it.  The
+// micro-domain moves with its macro particle, so its mean is zero.
+template <typename real>
+__global__ __launch_bounds__(256) void k_remove_mean(Ctx C) {
+    const int b = C.sel ? C.sel[blockIdx.x] : blockIdx.x;
+    const BoxInfo B = C.box[b];
+    const int N = C.n_total;
+    real* c = (real*)C.c;
+    __shared__ double red[3][256];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < B.n; i += blockDim.x)
+        for (int k = 0; k < 3; ++k) acc[k] += (double)c[(long)k * N + B.off + i];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    const real mean[3] = {(real)(red[0][0] / B.n), (real)(red[1][0] / B.n), (real)(red[2][0] / B.n)};
+    for (int i = threadIdx.x; i < B.n; i += blockDim.x)
+        for (int k = 0; k < 3; ++k) c[(long)k * N + B.off + i] -= mean[k];
+}
+
 __global__ void k_zero_acc(Ctx C) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 18 * C.n_boxes) C.acc[t] = 0.0;
@@ -1379,6 +1406,13 @@ void launch_one_step_sel(lhmm_micro* m, const Ctx& C, int nbox, int nblk) {
         launch_step_kernels<float>(m, C, nbox, nblk, 1, true, true);
 }
 
+void launch_remove_mean(lhmm_micro* m, const Ctx& C, int nbox) {
+    if (m->precision == LHMM_FP64)
+        k_remove_mean<double><<<nbox, 256, 0, m->stream>>>(C);
+    else
+        k_remove_mean<float><<<nbox, 256, 0, m->stream>>>(C);
+}
+
 void launch_force_eval(lhmm_micro* m) {
     if (m->precision == LHMM_FP64)
         launch_step_kernels<double>(m, m->ctx, m->n_boxes, m->n_blocks, 0, false, false);
@@ -1940,6 +1974,7 @@ int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double*
     HIPCHK(hipStreamWaitEvent(m->stream, m->ev_in, 0));
     k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, gradL);
     k_zero_acc<<<(18 * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
+    launch_remove_mean(m, m->ctx, m->n_boxes);
     if (!m->forces_valid) {
         launch_force_eval(m);
         m->forces_valid = true;
@@ -2178,6 +2213,7 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
     if (rc != LHMM_OK) return rc;
     k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, gradL);
     k_zero_acc<<<(18 * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
+    launch_remove_mean(m, C, n_sel);
     if (!m->forces_valid) {
         launch_force_eval(m);
         m->forces_valid = true;
@@ -2300,6 +2336,7 @@ int lhmm_micro_time(lhmm_micro* m, const double* gradL, int32_t n_steps, double*
     HIPCHK(hipStreamWaitEvent(m->stream, m->ev_in, 0));
     k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, gradL);
     k_zero_acc<<<(18 * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
+    launch_remove_mean(m, m->ctx, m->n_boxes);
     if (!m->forces_valid) {
         launch_force_eval(m);
         m->forces_valid = true;

@@ -533,3 +533,38 @@ def test_forces_match_oracle_in_strongly_deformed_cells(torch_gpu, orc, precisio
         Wpair = Wr[:3].sum(axis=0)
         assert np.abs(vir[k, 0] - Wpair).max() <= 10 * tol * np.abs(Wpair).max() + 1e-9, k
     m.close()
+
+
+def test_calls_start_from_zero_mean_peculiar_velocity(torch_gpu):
+    """Every call removes each box's mean peculiar velocity first: a state
+    carrying a uniform offset continues like the centred state (FP64, a
+    compressing planar gradient under which d<c>/dt = -L <c> would amplify
+    the offset), and the mean stays at rounding level in FP32."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.lhmm_boxes(2, n_particles=1500, polymer_fraction=0.2, seed_k=43)
+    Lp = inputs.planar_gradient(-0.2, 0.1, 0.0)
+    G = torch.tensor(np.stack([Lp, Lp]).reshape(2, 9), dtype=torch.float64, device="cuda")
+    s0 = np.concatenate([b.s for b in wl.boxes])
+    c0 = np.concatenate([b.c for b in wl.boxes])
+    n = wl.boxes[0].N
+    off = np.zeros_like(c0)
+    off[:n] = (0.7, -0.4, 0.2)
+    off[n:] = (-0.3, 0.5, 0.1)
+    for prec in ("fp64", "fp32"):
+        a = micro.from_workload(wl, precision=prec)
+        b = micro.from_workload(wl, precision=prec)
+        a.set_state(s0, c0)
+        b.set_state(s0, c0 + off)
+        for _ in range(2):
+            sa_ = a.step(G, 100).cpu().numpy()
+            sb_ = b.step(G, 100).cpu().numpy()
+        _, ca, _, _ = a.get_state()
+        _, cb, _, _ = b.get_state()
+        if prec == "fp64":
+            assert np.abs(ca - cb).max() < 1e-8 and np.abs(sa_ - sb_).max() < 1e-8
+        for k in range(2):
+            assert np.abs(cb[k * n:(k + 1) * n].mean(axis=0)).max() < (1e-12 if prec == "fp64" else 1e-4), (prec, k)
+        assert not a.flags().any() and not b.flags().any()
+        a.close()
+        b.close()
