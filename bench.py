@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 # MI355X (gfx950): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz; one full-rate
 # VALU lane-operation per lane per cycle (FMA counted once).
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8.0e12  # bytes/s, HBM3E
 # Algorithmic VALU lane-cycles of one unordered pair:
 # Philox4x32-10 (10 rounds x (2 quarter-rate 32x32->64-bit
 # multiplies + 2 three-input xors) = 100), Box-Muller (3 quarter-rate
@@ -262,7 +263,8 @@ def main():
                 "unit": "T VALU lane-ops/s", "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch", "kernel": "k_forces", "kernel_ms": f_ms,
                 "kernel_ms_all": kt, "pairs_per_launch": pairs_timing,
-                "hbm_GBps": (traffic / (f_ms * 1e-3) / 1e9) if traffic else None}
+                "hbm_GBps": (traffic / (f_ms * 1e-3) / 1e9) if traffic else None,
+                "hbm_frac": (traffic / (f_ms * 1e-3) / HBM_PEAK) if traffic else None}
 
     rec = {
         "metric": "micro-DPD pair-force updates/s",
