@@ -475,20 +475,32 @@ def cylinder_array(n: int = 64, radius: float = 0.2, force: float = 1.0, eta_s: 
     return MacroInit(r=r, v=np.zeros_like(r), params=params, n_steps=n_steps)
 
 
+PLANAR_THICKNESS = 3.5  # z edge of a planar cell: above the 3.3 rc at which a cell counts as thin
+
+
 def lhmm_boxes(n_boxes: int, n_particles: int = 4000, density: float = 3.0, polymer_fraction=0.1,
-               seed_k: int = 2, **param_over) -> Workload:
+               seed_k: int = 2, planar: bool = False, **param_over) -> Workload:
     """One cubic micro-box per SPH particle, each of n_particles at the given
-    density (edge (n/density)^(1/3)), 10-bead chains holding the polymer
-    fraction (a number, or one value per box), random start, no gradient
-    (the macro side supplies it)."""
-    p = default_params(seed=SEED_BASE + seed_k, **param_over)
+    density (edge (n/density)^(1/3)), chains holding the polymer fraction (a
+    number, or one value per box), random start, no gradient (the macro side
+    supplies it).  planar: the paper's 2-D material instead (Tab. 1
+    parameters unless overridden, density per unit area, edge
+    (n/density)^(1/2)), held in the plane z = 0 of a cell of z edge
+    PLANAR_THICKNESS; its 2-D stress is the cell stress times that edge."""
+    if planar:
+        p = paper_melt_params(seed=SEED_BASE + seed_k, **param_over)
+        edge = (n_particles / density) ** 0.5
+        h = np.diag([edge, edge, PLANAR_THICKNESS])
+    else:
+        p = default_params(seed=SEED_BASE + seed_k, **param_over)
+        edge = (n_particles / density) ** (1.0 / 3.0)
+        h = cubic_cell(edge)
     rng = np.random.default_rng(SEED_BASE + seed_k)
-    edge = (n_particles / density) ** (1.0 / 3.0)
     phis = np.broadcast_to(np.asarray(polymer_fraction, dtype=np.float64), (n_boxes,))
-    h = cubic_cell(edge)
     boxes = []
     for b in range(n_boxes):
-        n_chains = int(round(phis[b] * n_particles / p["chain_len"]))
-        s, c = random_box(rng, h, n_particles, n_chains, p["chain_len"], p["kBT"], p["mass"])
+        n_chains = int(phis[b] * n_particles) // p["chain_len"] if planar else \
+            int(round(phis[b] * n_particles / p["chain_len"]))
+        s, c = random_box(rng, h, n_particles, n_chains, p["chain_len"], p["kBT"], p["mass"], planar=planar)
         boxes.append(BoxInit(s=s, c=c, h=h, n_chains=n_chains, L=np.zeros((3, 3)), edge=edge, phi=float(phis[b])))
     return Workload("lhmm_boxes", p, boxes, 0)

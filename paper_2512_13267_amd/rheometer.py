@@ -106,7 +106,7 @@ def normal_stress_and_relaxation(gdot, sigma):
     return eta, n1, psi1, 0.5 * psi1 / eta
 
 
-PLANAR_THICKNESS = 3.5  # z edge of a planar cell: above the 3.3 rc at which a cell counts as thin
+PLANAR_THICKNESS = inputs.PLANAR_THICKNESS
 
 
 def sweep_workload(rates, replicas: int = 16, chain_len: int = 10, edge: float = 10.0, density: float = 3.0,

@@ -98,18 +98,33 @@ def _bin_mean(idx, vals, nb):
 def run(force: float = 1.0e-2, alpha: float = 0.02, eta_p_guess: float = 0.02, nx: int | None = None,
         n_particles: int = 4000, polymer_fraction: float = 0.1, equil_micro: int = 1000,
         startup: float = 60.0, average: float = 60.0, sample_every: int = 4, n_bins: int = 20,
-        replay: int = 10, precision: str = "fp32", log=print) -> dict:
+        replay: int = 10, precision: str = "fp32", micro_model: str = "3d", chain_len: int = 10,
+        lam: float | None = None, log=print) -> dict:
     """Coupled reverse-Poiseuille run; startup and average in macro time
-    units, replay in exchange intervals.  Returns the binned profiles and
-    the comparison figures; "flagged_boxes" counts box-intervals that ended
-    with a hard flag (cell below 3 rc, bond at R0, non-finite stress),
-    "restored_boxes" the box-intervals that were restored and replayed."""
+    units, replay in exchange intervals.  micro_model "3d": cubic boxes of
+    solvent and chains (density 3); "planar": the paper's 2-D melt (Tab. 1,
+    n = 4 per unit area, polymer fraction 1, chain_len beads) in planar
+    cells, whose 2-D stress (the cell stress times the cell's z edge) is
+    what alpha multiplies.  lam: the micro model's relaxation time, for the
+    Weissenberg number Wi = 2 U0 lam / L (U0: the mean |v_x|; Sec. "Reverse
+    Poiseuille Flow"), with Re = U0 L / (2 eta_tot).  Returns the binned
+    profiles and the comparison figures; "flagged_boxes" counts
+    box-intervals that ended with a hard flag (cell below 3 rc, bond at R0,
+    non-finite stress), "restored_boxes" the box-intervals that were
+    restored and replayed."""
     import torch
 
     from . import inputs, lhmm, micro
 
+    planar = micro_model == "planar"
+    if micro_model not in ("3d", "planar"):
+        raise ValueError("micro_model must be '3d' or 'planar'")
     mac = inputs.reverse_poiseuille_paper(force=force, alpha=alpha, eta_p=eta_p_guess, nx=nx)
     q = mac.params
+    # alpha multiplies the micro-domain's stress in the material's own
+    # dimension: for planar cells the engine's (volume) stress times the z edge
+    alpha_feed = alpha * (inputs.PLANAR_THICKNESS if planar else 1.0)
+    q["alpha"] = alpha_feed
     m_bar, k_micro = int(q["m_bar"]), int(q["k_micro"])
     delta_t = m_bar * q["dt"]
     dt_micro = delta_t / k_micro
@@ -117,8 +132,12 @@ def run(force: float = 1.0e-2, alpha: float = 0.02, eta_p_guess: float = 0.02, n
     t0 = time.perf_counter()
     sph = lhmm.Sph(q, mac.r, mac.v)
     if coupled:
-        wl = inputs.lhmm_boxes(mac.n, n_particles=n_particles, polymer_fraction=polymer_fraction, seed_k=21,
-                               dt=dt_micro)
+        if planar:
+            wl = inputs.lhmm_boxes(mac.n, n_particles=n_particles, density=4.0, polymer_fraction=1.0, seed_k=21,
+                                   planar=True, chain_len=chain_len, dt=dt_micro)
+        else:
+            wl = inputs.lhmm_boxes(mac.n, n_particles=n_particles, polymer_fraction=polymer_fraction, seed_k=21,
+                                   dt=dt_micro)
         mi = micro.from_workload(wl, precision=precision)
         zero = torch.zeros((mac.n, 9), dtype=torch.float64, device="cuda")
         mi.step(zero, equil_micro)
@@ -129,13 +148,13 @@ def run(force: float = 1.0e-2, alpha: float = 0.02, eta_p_guess: float = 0.02, n
         L_dev = torch.zeros((mac.n, 9), dtype=torch.float64, device="cuda")
     n_start = int(math.ceil(startup / delta_t))
     n_avg = int(math.ceil(average / delta_t))
-    Ly, lam = q["Ly"], q["lambda_star"]
+    Ly, lam_star = q["Ly"], q["lambda_star"]
     eta_sph = sph_shear_viscosity(q["eta"], q["zeta"])
     edges = np.linspace(0.0, Ly, n_bins + 1)
     yb = 0.5 * (edges[1:] + edges[:-1])
     # reference profiles are binned from the particles' own positions, so
     # they carry the same bin averaging as the measured ones
-    samples = {"v": [], "solvent": [], "polymer": [], "rate": [], "shape": [], "tau_ref": []}
+    samples = {"v": [], "solvent": [], "polymer": [], "rate": [], "shape": [], "tau_ref": [], "speed": []}
     cell_flags = restored = 0
     vmean_trace = []
     for it in range(n_start + n_avg):
@@ -167,13 +186,14 @@ def run(force: float = 1.0e-2, alpha: float = 0.02, eta_p_guess: float = 0.02, n
             else:
                 sig, grad = np.zeros((mac.n, 6)), L_dev.cpu().numpy().reshape(-1, 3, 3)
             idx = np.clip(np.searchsorted(edges, r[:, 1], side="right") - 1, 0, n_bins - 1)
-            rate = (grad[:, 0, 1] + grad[:, 1, 0]) / lam
+            rate = (grad[:, 0, 1] + grad[:, 1, 0]) / lam_star
             vmean_trace.append((round((it + 1) * delta_t, 6), float(np.mean(np.abs(v[:, 0])))))
             if it >= n_start:
                 samples["v"].append(_bin_mean(idx, v[:, 0], n_bins))
                 samples["rate"].append(_bin_mean(idx, rate, n_bins))
                 samples["solvent"].append(_bin_mean(idx, eta_sph * rate, n_bins))
-                samples["polymer"].append(_bin_mean(idx, alpha / lam * sig[:, 3], n_bins))
+                samples["polymer"].append(_bin_mean(idx, alpha_feed / lam_star * sig[:, 3], n_bins))
+                samples["speed"].append(float(np.mean(np.abs(v[:, 0]))))
                 unit = rpf_velocity(r[:, 1], 1.0, 1.0, 1.0, Ly) * 32.0 / (Ly * Ly)
                 samples["shape"].append(_bin_mean(idx, unit, n_bins))
                 samples["tau_ref"].append(_bin_mean(idx, rpf_shear_stress(r[:, 1], force, q["rho0"], Ly), n_bins))
@@ -186,6 +206,7 @@ def run(force: float = 1.0e-2, alpha: float = 0.02, eta_p_guess: float = 0.02, n
         mi.close()
     sph.close()
 
+    U0 = float(np.mean(samples.pop("speed")))
     S = {k: np.asarray(a) for k, a in samples.items()}
     ns = S["v"].shape[0]
     mean = {k: a.mean(axis=0) for k, a in S.items()}
@@ -212,9 +233,13 @@ def run(force: float = 1.0e-2, alpha: float = 0.02, eta_p_guess: float = 0.02, n
     vmax_meas = float(np.dot(mean["v"], shape) / np.dot(shape, shape))
     out = {
         "workload": f"reverse Poiseuille flow, {mac.n} SPH particles ({q['Lx']:.1f} x {Ly:.1f}, dh 0.1, Lucy "
-                    f"kernel h = {q['h']:.2f}), " + (f"one {n_particles}-particle DPD micro-box per particle" if coupled
+                    f"kernel h = {q['h']:.2f}), " + ((f"one {n_particles}-particle 2-D melt micro-domain of {chain_len}-bead "
+                                           f"chains per particle (Tab. 1 parameters, planar cell)" if planar else
+                                           f"one {n_particles}-particle DPD micro-box per particle") if coupled
                                           else "SPH only (Newtonian reference)"),
-        "force": force, "alpha": alpha, "lambda_star": lam, "eta_s": q["eta"], "eta_sph": eta_sph, "c": q["c"],
+        "force": force, "alpha": alpha, "lambda_star": lam_star, "eta_s": q["eta"], "eta_sph": eta_sph, "c": q["c"],
+        "micro_model": micro_model, "chain_len": chain_len if planar else None, "U0": U0,
+        "Re": U0 * Ly / (2.0 * eta_tot / q["rho0"]), "Wi": (2.0 * U0 * lam / Ly) if lam else None, "lam": lam,
         "theta": q["theta"],
         "dt_sph": q["dt"], "dt_cfl": q["dt_cfl"], "m_bar": m_bar, "k_micro": k_micro, "dt_micro": dt_micro,
         "delta_t": delta_t, "intervals": n_start + n_avg, "startup_intervals": n_start, "samples": ns,
@@ -257,6 +282,8 @@ def report(res: dict, command: str) -> str:
         f"than h from the force switches (all bins: RMS {res['total_dev_rms_all']:.3f})",
         f"* polymer viscosity from the micro-domains eta_p = {res['eta_p']:.4g}, polymer fraction "
         f"beta = {res['beta']:.3f}",
+        f"* mean speed U0 = {res['U0']:.4g}, Re = U0 L / (2 eta_tot) = {res['Re']:.3g}"
+        + (f", Wi = 2 U0 lambda / L = {res['Wi']:.3g} with lambda = {res['lam']:g}" if res.get("Wi") else ""),
         f"* peak velocity {res['vmax']:.4g} against the Newtonian {res['vmax_newtonian']:.4g} of "
         f"eta_SPH + eta_p ({res['vmax'] / res['vmax_newtonian']:.3f}); RMS shape deviation of v/v_max "
         f"{res['v_shape_rms']:.3f}",
@@ -279,6 +306,10 @@ def main(argv=None):
     ap.add_argument("--n-particles", type=int, default=4000, help="DPD particles per micro-box (0: SPH only)")
     ap.add_argument("--eta-p-guess", type=float, default=0.02,
                     help="polymer viscosity assumed for the sound speed and time step")
+    ap.add_argument("--micro", default="3d", choices=("3d", "planar"),
+                    help="micro model: 3-D boxes of solvent and chains, or the paper's 2-D melt")
+    ap.add_argument("--chain-len", type=int, default=8, help="beads per chain of the planar melt")
+    ap.add_argument("--lam", type=float, default=None, help="micro relaxation time for Wi")
     ap.add_argument("--startup", type=float, default=60.0)
     ap.add_argument("--average", type=float, default=60.0)
     ap.add_argument("--out", default=None, help="JSON output file")
@@ -286,10 +317,10 @@ def main(argv=None):
     ap.add_argument("--command", default=None, help="command line recorded in the report")
     a = ap.parse_args(argv)
     res = run(force=a.force, alpha=a.alpha, eta_p_guess=a.eta_p_guess, nx=a.nx, n_particles=a.n_particles,
-              startup=a.startup, average=a.average)
+              startup=a.startup, average=a.average, micro_model=a.micro, chain_len=a.chain_len, lam=a.lam)
     summary = {k: res[k] for k in ("workload", "intervals", "seconds", "total_dev_rms", "total_dev_max", "eta_p",
                                    "beta", "vmax", "vmax_newtonian", "v_shape_rms", "flagged_boxes",
-                                   "restored_boxes")}
+                                   "restored_boxes", "U0", "Re", "Wi")}
     print(json.dumps(summary), flush=True)
     if a.out:
         with open(a.out, "w") as f:

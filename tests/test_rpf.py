@@ -132,3 +132,20 @@ def test_coupled_loop_reaches_the_exact_steady_stress(torch_gpu):
     assert 0.2 < res["beta"] < 0.8
     assert res["vmax"] == pytest.approx(res["vmax_newtonian"], rel=0.05)
     assert res["v_shape_rms"] < 0.04
+
+
+@pytest.mark.gpu
+def test_coupled_loop_with_the_papers_2d_melt(torch_gpu):
+    """The paper's combination on a 20 x 40 strip: its macro set-up with
+    planar micro-domains of its 2-D melt (Tab. 1, N_d = 8, 1024 particles
+    each) and alpha = 2e-3 (its RPF case (c)); the total shear stress
+    follows the exact profile and the melt carries a real share of it."""
+    res = rpf.run(nx=20, n_particles=1024, micro_model="planar", chain_len=8, alpha=2.0e-3, eta_p_guess=0.026,
+                  startup=60.0, average=60.0, lam=9.06, log=None)
+    print({k: res[k] for k in ("total_dev_rms", "total_dev_max", "eta_p", "beta", "vmax", "vmax_newtonian",
+                               "v_shape_rms", "seconds", "restored_boxes", "Re", "Wi")})
+    assert res["flagged_boxes"] == 0
+    assert res["total_dev_rms"] < 0.03 and res["total_dev_max"] < 0.06
+    assert 0.2 < res["beta"] < 0.8
+    assert res["vmax"] == pytest.approx(res["vmax_newtonian"], rel=0.05)
+    assert res["v_shape_rms"] < 0.04
