@@ -149,3 +149,20 @@ def test_coupled_loop_with_the_papers_2d_melt(torch_gpu):
     assert 0.2 < res["beta"] < 0.8
     assert res["vmax"] == pytest.approx(res["vmax_newtonian"], rel=0.05)
     assert res["v_shape_rms"] < 0.04
+
+
+def test_run_rejects_an_unknown_micro_model():
+    with pytest.raises(ValueError):
+        rpf.run(micro_model="afbc", n_particles=10, log=None)
+
+
+def test_planar_lhmm_boxes():
+    wl = inputs.lhmm_boxes(2, n_particles=1024, density=4.0, polymer_fraction=1.0, seed_k=21, planar=True,
+                           chain_len=8, dt=0.005)
+    b = wl.boxes[0]
+    assert b.N == 1024 and b.n_chains == 128 and np.allclose(np.diag(b.h), (16.0, 16.0, inputs.PLANAR_THICKNESS))
+    assert not b.s[:, 2].any() and not b.c[:, 2].any()
+    assert wl.params["H"] == 50.0 and wl.params["dt"] == 0.005 and wl.params["chain_len"] == 8
+    # the 3-D recipe is unchanged
+    w3 = inputs.lhmm_boxes(1, n_particles=300, polymer_fraction=0.2, seed_k=9)
+    assert w3.params["H"] == 30.0 and w3.boxes[0].n_chains == 6 and w3.boxes[0].s[:, 2].any()
