@@ -164,3 +164,16 @@ def test_short_shear_sweep_on_gpu(torch_gpu):
     # a sheared polymer melt has a positive first normal stress difference
     assert res["N1"][-1] > 0.0, res
     assert res["flagged_boxes"] >= 0
+
+
+def test_planar_report_compares_with_the_papers_table():
+    rates = [0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0]
+    eta = rheometer.carreau_yasuda(np.array(rates), 12.9, 3.2, 9.0, 1.5, 0.2)
+    r = {"rates": rates, "eta": eta.tolist(), "eta_se": (0.01 * eta).tolist(), "N1": [0.1] * 8, "N1_se": [0.01] * 8,
+         "psi1": [1.0] * 8, "lambda": [1.0] * 8, "chain_len": 8, "edge": 32.0, "dims": 2, "density": 4.0,
+         "replicas": 16, "equil_steps": 10, "avg_steps": 10, "n_particles": 1, "seconds": 0.0, "flagged_boxes": 0,
+         "carreau_yasuda": rheometer.fit_carreau_yasuda(rates, eta)}
+    text = rheometer.report([r], "python -m paper_2512_13267_amd.rheometer --planar")
+    assert "2-D melt" in text and "Tab. yasuda_params" in text and "34.29" in text
+    assert "| 8 | 12.9" in text
+    assert rheometer.PAPER_CY[8] == (34.29, 3.15, 89.75, 0.95, 0.37)

@@ -166,3 +166,21 @@ def test_planar_lhmm_boxes():
     # the 3-D recipe is unchanged
     w3 = inputs.lhmm_boxes(1, n_particles=300, polymer_fraction=0.2, seed_k=9)
     assert w3.params["H"] == 30.0 and w3.boxes[0].n_chains == 6 and w3.boxes[0].s[:, 2].any()
+
+
+def test_report_lists_the_comparison():
+    y = [0.1 + 0.2 * k for k in range(20)]
+    n = len(y)
+    res = {"workload": "w", "force": 0.01, "alpha": 0.002, "lambda_star": 1.0, "eta_s": 0.02, "eta_sph": 0.025,
+           "c": 1.0, "theta": 0.5, "delta_t": 0.32, "m_bar": 8, "dt_sph": 0.04, "dt_cfl": 0.07, "k_micro": 64,
+           "dt_micro": 0.005, "intervals": 376, "startup_intervals": 188, "samples": 47, "n_particles_total": 10,
+           "seconds": 1.0, "replay": 10, "restored_boxes": 3, "flagged_boxes": 0, "total_dev_rms": 0.002,
+           "total_dev_max": 0.004, "total_dev_rms_all": 0.003, "eta_p": 0.0155, "beta": 0.38, "U0": 0.084,
+           "Re": 4.1, "Wi": 0.38, "lam": 9.06, "vmax": 0.1246, "vmax_newtonian": 0.1234, "v_shape_rms": 0.019,
+           "y": y, "v": [0.0] * n, "v_ref": [0.0] * n, "solvent": [0.0] * n, "polymer": [0.0] * n,
+           "total": [0.0] * n, "total_se": [0.0] * n, "tau_ref": [0.0] * n}
+    text = rpf.report(res, "python -m paper_2512_13267_amd.rpf --micro planar")
+    assert "Wi = 2 U0 lambda / L = 0.38" in text and "RMS deviation 0.002 tau_max" in text
+    assert text.count("\n| ") == n + 1 and "(realised by the SPH viscous term as 0.025)" in text
+    res["Wi"] = None
+    assert "Wi =" not in rpf.report(res, "x")
