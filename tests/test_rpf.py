@@ -184,3 +184,15 @@ def test_report_lists_the_comparison():
     assert text.count("\n| ") == n + 1 and "(realised by the SPH viscous term as 0.025)" in text
     res["Wi"] = None
     assert "Wi =" not in rpf.report(res, "x")
+
+
+@pytest.mark.parametrize("force,eta_p", [(1.8e-4, 0.0), (1.8e-4, 0.07), (1.0e-3, 0.02), (1.0e-2, 0.02),
+                                         (1.0e-2, 0.07)])
+def test_paper_forces_keep_the_papers_exchange_interval(force, eta_p):
+    """The three body forces of the paper's reverse-Poiseuille table, with a
+    polymer viscosity that keeps the flow within the CFL bound of the
+    paper's step, give its interval 0.32 = 8 x 0.04 = 64 x 0.005; the sound
+    speed keeps the Mach number at or below 0.1."""
+    q = inputs.reverse_poiseuille_paper(force=force, eta_p=eta_p).params
+    assert q["m_bar"] == 8 and q["dt"] == pytest.approx(0.04) and q["k_micro"] == 64
+    assert q["dt"] <= q["dt_cfl"] and q["v_max"] / q["c"] <= 0.1 + 1e-12
