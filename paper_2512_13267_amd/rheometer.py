@@ -91,8 +91,11 @@ def fit_carreau_yasuda(gdot, eta, weights=None) -> dict:
             best = r
     eta0, eta_inf, lam, a, n = params(best.x)
     rel = carreau_yasuda(g, eta0, eta_inf, lam, a, n) / e - 1.0
+    # parameters the fit pushed onto a bound are not determined by the data
+    names = ("eta0", "eta_inf", "lam", "a", "n")
+    at_bounds = [nm for nm, x, l, h in zip(names, best.x, lo, hi) if min(x - l, h - x) < 1e-4 * (h - l)]
     return {"eta0": eta0, "eta_inf": eta_inf, "lam": lam, "a": a, "n": n,
-            "rms_rel_residual": float(np.sqrt(np.mean(rel ** 2)))}
+            "rms_rel_residual": float(np.sqrt(np.mean(rel ** 2))), "at_bounds": at_bounds}
 
 
 def normal_stress_and_relaxation(gdot, sigma):
@@ -184,11 +187,22 @@ def run_sweep(rates, replicas: int = 16, chain_len: int = 10, equil: int = 5000,
            "eta": eta.tolist(), "eta_se": (se[:, 3] / rates).tolist(),
            "N1": n1.tolist(), "N1_se": np.sqrt(se[:, 0] ** 2 + se[:, 1] ** 2).tolist(),
            "psi1": psi1.tolist(), "lambda": lam.tolist(), "sigma_mean": mean.tolist()}
-    ok = eta > 0
-    if ok.sum() >= 5:
-        w = 1.0 / np.maximum(np.asarray(out["eta_se"])[ok] / eta[ok], 1e-3)
-        out["carreau_yasuda"] = fit_carreau_yasuda(rates[ok], eta[ok], weights=w)
+    cy = sweep_fit(out)
+    if cy:
+        out["carreau_yasuda"] = cy
     return out
+
+
+def sweep_fit(res: dict):
+    """Carreau-Yasuda fit of a sweep's viscosities, weighted by their
+    relative standard errors (None with fewer than five positive points)."""
+    rates = np.asarray(res["rates"], dtype=np.float64)
+    eta = np.asarray(res["eta"], dtype=np.float64)
+    ok = eta > 0
+    if ok.sum() < 5:
+        return None
+    w = 1.0 / np.maximum(np.asarray(res["eta_se"])[ok] / eta[ok], 1e-3)
+    return fit_carreau_yasuda(rates[ok], eta[ok], weights=w)
 
 
 def chain_scaling(chain_lens, lams) -> dict:
@@ -224,10 +238,14 @@ def report(results, command: str) -> str:
         for row in zip(r["rates"], r["eta"], r["eta_se"], r["N1"], r["N1_se"], r["psi1"], r["lambda"]):
             L.append("| {:.3g} | {:.4g} | {:.2g} | {:.4g} | {:.2g} | {:.4g} | {:.4g} |".format(*row))
         cy = r.get("carreau_yasuda")
+        if cy and "at_bounds" not in cy:
+            cy = sweep_fit(r) or cy  # results written before the bound check: the same fit again
         if cy:
             L += ["", "Carreau-Yasuda fit (Eq. Yasuda, weighted by the standard errors): eta0 = {eta0:.4g}, "
                   "eta_inf = {eta_inf:.4g}, lambda = {lam:.4g}, a = {a:.3g}, n = {n:.3g}; RMS relative residual "
-                  "{rms_rel_residual:.3g}.".format(**cy)]
+                  "{rms_rel_residual:.3g}.".format(**cy)
+                  + (" At a bound of the fit (not determined by the data): " + ", ".join(cy["at_bounds"]) + "."
+                     if cy.get("at_bounds") else "")]
         if planar and r["chain_len"] in PAPER_CY:
             e0, ei, lam, a, n = PAPER_CY[r["chain_len"]]
             pred = carreau_yasuda(np.asarray(r["rates"]), e0, ei, lam, a, n)

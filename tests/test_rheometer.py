@@ -42,6 +42,7 @@ def test_fit_recovers_known_parameters():
         # the viscosity curve is recovered; eta0 and lam are well determined
         assert fit["eta0"] == pytest.approx(truth[0], rel=1e-3)
         assert fit["lam"] == pytest.approx(truth[2], rel=2e-2)
+        assert fit["at_bounds"] == []
     # noisy data: parameters within a few per cent
     rng = np.random.default_rng(5)
     truth = (20.0, 2.0, 10.0, 1.0, 0.4)
@@ -52,6 +53,10 @@ def test_fit_recovers_known_parameters():
     assert fit["rms_rel_residual"] < 0.02
     with pytest.raises(ValueError):
         rheometer.fit_carreau_yasuda(g[:4], eta[:4])
+    # a curve that keeps thinning as 1 / rate (n = 0 exactly) puts n on its bound
+    g = np.logspace(-2, 2, 12)
+    fit = rheometer.fit_carreau_yasuda(g, rheometer.carreau_yasuda(g, 10.0, 0.5, 3.0, 2.0, 0.0))
+    assert "n" in fit["at_bounds"] and fit["n"] == pytest.approx(0.0, abs=1e-4)
 
 
 def test_normal_stress_and_relaxation_of_a_maxwell_fluid():
