@@ -79,6 +79,11 @@ extern "C" {
 #define LHMM_FP64 1 /* double-precision particle state and pair forces     */
 
 #define LHMM_OPT_NO_GRAPH 1 /* launch every kernel eagerly (no HIP graphs) */
+/* keep the virials of the conservative, dissipative and random pair forces
+ * apart (lhmm_micro_components); the steps use a variant of the pair-force
+ * kernel with 18 more accumulators, and the pair stress they return is
+ * summed exactly as without the option */
+#define LHMM_OPT_COMPONENTS 2
 
 typedef struct lhmm_micro lhmm_micro;
 
@@ -239,9 +244,27 @@ int lhmm_micro_forces(lhmm_micro* m, const double* gradL, double* f_out, double*
  * (kinetic, DPD pairs, FENE bonds; their sum is the stress).  Synchronous. */
 int lhmm_micro_stress_parts(lhmm_micro* m, double* parts_out);
 
+/* Mean stress of the last lhmm_micro_step call by force type, Eqs.
+ * (IKtotal), (kinetic_stress), (potential_stress): host n_boxes x 5 x 6 in
+ * the order kinetic, conservative (Eq. conservative), dissipative (Eq.
+ * dissipative), random (Eq. random), FENE (Eq. fene_force); their sum is the
+ * stress.  Needs LHMM_OPT_COMPONENTS at create (else STATE).  Synchronous. */
+int lhmm_micro_components(lhmm_micro* m, double* out);
+
 /* Unordered DPD pairs within the cutoff, summed over the steps of the last
  * lhmm_micro_step call: host n_boxes uint64.  Synchronous. */
 int lhmm_micro_pair_counts(lhmm_micro* m, uint64_t* pairs_out);
+
+/* The same count summed over every step of every call (full, subset and
+ * timed steps, fallback replays included) since the engine was created:
+ * host n_boxes uint64.  Synchronous. */
+int lhmm_micro_pair_total(lhmm_micro* m, uint64_t* pairs_out);
+
+/* Capture and instantiate the HIP graphs a later lhmm_micro_step call of
+ * n_steps steps will replay (a graph of graph_chunk steps and one of the
+ * remainder), without running any step, so that the first such call does
+ * no capture.  No effect with LHMM_OPT_NO_GRAPH.  Errors: ARG, HIP. */
+int lhmm_micro_prepare(lhmm_micro* m, int32_t n_steps);
 
 /* Sticky physics flags per box: host n_boxes uint32 (LHMM_FLAG_*).
  * clear != 0 resets them after reading.  Synchronous. */
@@ -295,7 +318,9 @@ int lhmm_micro_destroy(lhmm_micro* m);
  *     L_I = lambda* x the traceless part of (grad v_I)^T (the isochoric part
  *     of the weakly compressible flow);
  *   - the polymer stress fed back is alpha/lambda* x the in-plane part of
- *     the micro-domain's deviatoric mean stress (Eq. pip).
+ *     the micro-domain's deviatoric mean stress (Eq. pip): an isotropic micro
+ *     stress (3-D boxes) or an isotropic in-plane stress (planar cells, see
+ *     micro_dim) feeds back nothing; the macro EOS supplies the pressure.
  * ------------------------------------------------------------------------ */
 typedef struct lhmm_sph lhmm_sph;
 
@@ -315,6 +340,10 @@ typedef struct {
     int32_t n_fixed;    /* trailing wall particles (see below)               */
     int32_t force_mode; /* LHMM_FORCE_REVERSE or LHMM_FORCE_UNIFORM          */
     int32_t kernel;     /* LHMM_KERNEL_QUINTIC or LHMM_KERNEL_LUCY           */
+    int32_t micro_dim;  /* dimension of the micro-domains: 3 (or 0) for 3-D  */
+                        /* boxes, whose deviatoric part removes tr/3; 2 for  */
+                        /* planar cells (no zz stress), whose in-plane       */
+                        /* deviatoric part removes (xx + yy)/2               */
 } lhmm_sph_params;
 
 #define LHMM_FORCE_REVERSE 0 /* +F x-hat where y >= Ly/2, -F below            */

@@ -285,7 +285,7 @@ def max_threads() -> int:
 def sph_params_vector(q) -> np.ndarray:
     keys = ["rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly", "lambda_star", "alpha"]
     vals = [float(q[k]) for k in keys] + [float(q.get("n_fixed", 0)), float(q.get("force_mode", 0)),
-                                          float(q.get("kernel", 0))]
+                                          float(q.get("kernel", 0)), float(q.get("micro_dim", 3))]
     return np.array(vals, dtype=np.float64)
 
 

@@ -35,12 +35,13 @@
 #include <string.h>
 
 /* parameter vector layout (double[S_COUNT]); S_KERNEL: 0 quintic, 1 Lucy;
+ * S_MICRO_DIM: 3 for 3-D micro-domains, 2 for planar ones;
  * S_NFIXED: number of trailing
  * wall particles; S_FMODE: 0 = body force +F for y >= Ly/2, -F below
  * (reverse Poiseuille), 1 = +F everywhere */
 enum {
     S_RHO0 = 0, S_ETA, S_ZETA, S_C, S_THETA, S_F, S_H, S_DT, S_MASS, S_LX, S_LY, S_LAMBDA, S_ALPHA, S_NFIXED,
-    S_FMODE, S_KERNEL, S_COUNT
+    S_FMODE, S_KERNEL, S_MICRO_DIM, S_COUNT
 };
 
 static int n_mobile(const double *P, int n) { return n - (int)P[S_NFIXED]; }
@@ -233,16 +234,20 @@ void oracle_sph_step(const double *P, int n, double *r, double *v, const double 
 }
 
 /* polymer stress for the macro side from the micro-domains' mean stress
- * (n x 6: xx, yy, zz, xy, xz, yz): alpha / lambda* x in-plane part of the
- * deviatoric stress, as (xx, xy, yy). */
+ * (n x 6: xx, yy, zz, xy, xz, yz), Eq. (pip): alpha / lambda* x the in-plane
+ * components of the deviatoric stress, as (xx, xy, yy).  The deviatoric
+ * part of a 3-D micro stress removes its isotropic part tr/3; a planar
+ * micro-domain (S_MICRO_DIM = 2) has no zz stress, and its deviatoric part
+ * is taken in its own plane, removing (xx + yy)/2. */
 void oracle_sph_polymer_stress(const double *P, int n, const double *sig, double *pi)
 {
     const double s = P[S_ALPHA] / P[S_LAMBDA];
+    const int planar = (int)P[S_MICRO_DIM] == 2;
     for (int I = 0; I < n; ++I) {
         const double *g = &sig[6 * I];
-        double tr3 = (g[0] + g[1] + g[2]) / 3.0;
-        pi[3 * I] = s * (g[0] - tr3);
+        double iso = planar ? (g[0] + g[1]) / 2.0 : (g[0] + g[1] + g[2]) / 3.0;
+        pi[3 * I] = s * (g[0] - iso);
         pi[3 * I + 1] = s * g[3];
-        pi[3 * I + 2] = s * (g[1] - tr3);
+        pi[3 * I + 2] = s * (g[1] - iso);
     }
 }

@@ -28,6 +28,7 @@ THIN_WIDTH = 3.3
 FP32 = 0
 FP64 = 1
 OPT_NO_GRAPH = 1
+OPT_COMPONENTS = 2
 
 # every symbol include/lhmm.h declares
 EXPORTS = (
@@ -36,6 +37,7 @@ EXPORTS = (
     "lhmm_micro_sizes", "lhmm_micro_destroy", "lhmm_last_error", "lhmm_micro_time",
     "lhmm_micro_step_subset", "lhmm_micro_snapshot", "lhmm_micro_restore",
     "lhmm_micro_set_config", "lhmm_micro_get_config", "lhmm_micro_autotune",
+    "lhmm_micro_components", "lhmm_micro_pair_total", "lhmm_micro_prepare",
     "lhmm_sph_create", "lhmm_sph_step", "lhmm_sph_get_state", "lhmm_sph_coupling_state", "lhmm_couple_step",
     "lhmm_sph_destroy",
     "lhmm_sur_create", "lhmm_sur_set_weights", "lhmm_sur_get_weights", "lhmm_sur_get_grads", "lhmm_sur_train_step", "lhmm_sur_forward",
@@ -64,7 +66,8 @@ class LhmmSphParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("rho0", "eta", "zeta", "c", "theta", "F", "h", "dt", "mass", "Lx", "Ly",
                                             "lambda_star", "alpha")] + [("n_fixed", C.c_int32),
                                                                         ("force_mode", C.c_int32),
-                                                                        ("kernel", C.c_int32)]
+                                                                        ("kernel", C.c_int32),
+                                                                        ("micro_dim", C.c_int32)]
 
 
 class LhmmMicroConfig(C.Structure):
@@ -122,6 +125,9 @@ def lib():
         L.lhmm_micro_forces.argtypes = [vp, dp, dp, dp]
         L.lhmm_micro_stress_parts.argtypes = [vp, dp]
         L.lhmm_micro_pair_counts.argtypes = [vp, u64p]
+        L.lhmm_micro_pair_total.argtypes = [vp, u64p]
+        L.lhmm_micro_components.argtypes = [vp, dp]
+        L.lhmm_micro_prepare.argtypes = [vp, C.c_int32]
         L.lhmm_micro_flags.argtypes = [vp, C.POINTER(C.c_uint32), C.c_int32]
         L.lhmm_micro_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.lhmm_micro_destroy.argtypes = [vp]

@@ -11,10 +11,14 @@ OUT = os.path.join(HERE, "liblhmm.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed FP32 VALU forms are kept out of the device code
+    # packed FP32 VALU forms are kept out of the device code.  The driver
+    # cannot forward a -Xclang pair to the device pass alone (-Xarch_device
+    # rejects options that take arguments), so the host pass receives it too
+    # and ignores it with a notice, which build() drops from its log.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
+HOST_NOTICE = "'-packed-fp32-ops' is not a recognized feature for this target (ignoring feature)"
 
 
 def build(verbose: bool = False) -> str:
@@ -22,10 +26,11 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *SOURCES]
     res = subprocess.run(cmd, capture_output=True, text=True)
+    log = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if l.strip() != HOST_NOTICE)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    if verbose:
-        print(res.stderr)
+        raise RuntimeError("hipcc failed:\n" + log)
+    if verbose and log:
+        print(log)
     os.replace(tmp, OUT)
     return OUT
 

@@ -51,6 +51,7 @@ constexpr int BIN_THREADS_MAX = 1024;   // largest binning workgroup (256, 512 o
 constexpr int MAX_CELLS_PER_BOX = 15360;  // binning LDS: cell starts and three per-column offsets (120 KiB)
 constexpr int GRAPH_CHUNK = 50;         // default steps per captured graph
 constexpr int MAX_GROUPS = 4;           // overlapped box groups of a captured step
+constexpr int ACC = 36;                 // per-box stress sums: kinetic, pair, FENE, C, D, R (6 each)
 
 thread_local std::string g_err;
 
@@ -126,12 +127,14 @@ struct Ctx {
     // 2 above), r = h s; padded by four records.
     int* gcell_start;
     void* srec;
-    double* part_vir;   // n_blocks x 12: pair virial, FENE virial
+    double* part_vir;   // n_blocks x pv_stride: pair virial, FENE virial (+ C, D, R parts)
+    int pv_stride;      // 12, or 30 when the conservative, dissipative and random parts are kept
     double vir_scale;   // 1 when each pair is evaluated once, 1/2 when twice
     double* part_kin;   // n_blocks x 6
     unsigned* part_pairs;  // n_blocks: ordered pairs within the cutoff
-    double* acc;        // n_boxes x 18: kinetic, pair, FENE stress sums
+    double* acc;        // n_boxes x ACC: kinetic, pair, FENE, C, D, R stress sums
     unsigned long long* acc_pairs;  // n_boxes
+    unsigned long long* tot_pairs;  // n_boxes, every step since the engine was created
     unsigned long long* step;       // completed steps
     double a, gamma, sigma, rdt, dt, mass, inv_mass, rc, rc2, H, inv_R02;
     unsigned key0, key1;
@@ -402,7 +405,7 @@ __global__ __launch_bounds__(256) void k_remove_mean(Ctx C) {
 
 __global__ void k_zero_acc(Ctx C) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < 18 * C.n_boxes) C.acc[t] = 0.0;
+    if (t < ACC * C.n_boxes) C.acc[t] = 0.0;
     if (t < C.n_boxes) C.acc_pairs[t] = 0ull;
 }
 
@@ -896,11 +899,14 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 __host__ __device__ constexpr int scan_unroll(int qd) { return qd >= 8 ? 4 : (qd >= 4 ? 2 : 1); }
 
 // PRUNE selects the stencil-pruning variant; without it the float kernel
-// fits 80 VGPRs, six waves per SIMD.
-template <typename real, int QD, bool PRUNE>
-__global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k_forces(Ctx C, int step_offset, int drain,
-                                                                                        int busy, int kick) {
+// fits 80 VGPRs, six waves per SIMD.  COMP keeps the virials of the
+// conservative, dissipative and random forces apart as well (their sum is
+// accumulated as in the default variant), at the cost of 18 more registers.
+template <typename real, int QD, bool PRUNE, bool COMP = false>
+__global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (PRUNE ? 5 : 6)) : 1) void k_forces(
+    Ctx C, int step_offset, int drain, int busy, int kick) {
     constexpr bool prune = PRUNE;
+    constexpr int NV = COMP ? 37 : 19;  // block partial sums
     using R = Rec<real>;
     using V4 = typename R::T;
     constexpr int NW = BS / 64;
@@ -908,7 +914,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
     // queue entry: cell-order position of j << 6 | z image (0 none, 1 below,
     // 2 above) << 4 | in-plane image code
     __shared__ int qbuf[QD][NW][64];
-    __shared__ double red[19 * NW];
+    __shared__ double red[NV * NW];
     __shared__ real shift_tab[9][2];  // image_shift of the block's box for codes 0 .. 8
 
     int blk = xcd_local_work(blockIdx.x, gridDim.x);
@@ -979,6 +985,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
     int qh = 0, qt = 0;  // this lane's queue: popped, pushed
     real fx = 0, fy = 0, fz = 0;
     real w[6] = {0, 0, 0, 0, 0, 0};
+    real wc[COMP ? 6 : 1] = {}, wd[COMP ? 6 : 1] = {}, wr[COMP ? 6 : 1] = {};  // C, D, R parts
     unsigned npairs = 0;
 
     int ic = 4;  // in-plane image code of the row being scanned
@@ -1008,6 +1015,17 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
             fx += gx; fy += gy; fz += gz;
             w[0] += dx * gx; w[1] += dy * gy; w[2] += dz * gz;
             w[3] += dx * gy; w[4] += dx * gz; w[5] += dy * gz;
+            if constexpr (COMP) {
+                // d (x) e times each force's magnitude
+                const real mc = wR * a, md = -(wR * gam * wR * ev), mr = wR * sig * th;
+                const real de[6] = {dx * ex, dy * ey, dz * ez, dx * ey, dx * ez, dy * ez};
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    wc[k] += mc * de[k];
+                    wd[k] += md * de[k];
+                    wr[k] += mr * de[k];
+                }
+            }
             ++npairs;
         }
     };
@@ -1128,11 +1146,16 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
         }
         f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
     }
-    double v[19];
+    double v[NV];
     for (int k = 0; k < 6; ++k) {
         v[k] = (double)w[k];
         v[6 + k] = (double)wf[k];
         v[13 + k] = 0.0;
+        if constexpr (COMP) {
+            v[19 + k] = (double)wc[k];
+            v[25 + k] = (double)wd[k];
+            v[31 + k] = (double)wr[k];
+        }
     }
     v[12] = (double)npairs;
     // second half kick of the velocity-Verlet step, c += dt/2 (F/m - L c),
@@ -1151,9 +1174,11 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
         v[13] = mm * x * x; v[14] = mm * y * y; v[15] = mm * z * z;
         v[16] = mm * x * y; v[17] = mm * x * z; v[18] = mm * y * z;
     }
-    block_sum<19>(v, red);
+    block_sum<NV>(v, red);
     if (threadIdx.x == 0) {
-        for (int k = 0; k < 12; ++k) C.part_vir[12 * blk + k] = v[k];
+        for (int k = 0; k < 12; ++k) C.part_vir[(size_t)C.pv_stride * blk + k] = v[k];
+        if constexpr (COMP)
+            for (int k = 0; k < 18; ++k) C.part_vir[(size_t)C.pv_stride * blk + 12 + k] = v[19 + k];
         C.part_pairs[blk] = (unsigned)v[12];
         if (kick)
             for (int k = 0; k < 6; ++k) C.part_kin[6 * blk + k] = v[13 + k];
@@ -1162,26 +1187,30 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (PRUNE ? 5 : 6) : 1) void k
 
 // One wave per box: the step's stress, sigma = -(K + W)/V, by part.  Lane l
 // sums the partials of blocks l, l+64, ...; a fixed shuffle tree combines
-// the lanes, so the order of every sum is fixed.
+// the lanes, so the order of every sum is fixed.  With the C, D, R parts
+// kept (pv_stride 30) they are reduced alongside.
 __global__ __launch_bounds__(64) void k_box_stress(Ctx C) {
     const int b = C.sel ? C.sel[blockIdx.x] : (int)blockIdx.x;
     const int lane = threadIdx.x;
     const BoxInfo B = C.box[b];
-    double v[19];
-    for (int q = 0; q < 19; ++q) v[q] = 0.0;
+    const bool comp = C.pv_stride > 12;
+    double v[37];
+    for (int q = 0; q < 37; ++q) v[q] = 0.0;
     for (int k = lane; k < B.nblk; k += 64) {
         const int blk = B.blk_off + k;
         for (int q = 0; q < 6; ++q) v[q] += C.part_kin[6 * blk + q];
-        for (int q = 0; q < 12; ++q) v[6 + q] += C.part_vir[12 * blk + q];
+        for (int q = 0; q < 12; ++q) v[6 + q] += C.part_vir[(size_t)C.pv_stride * blk + q];
         v[18] += (double)C.part_pairs[blk];
+        if (comp)
+            for (int q = 0; q < 18; ++q) v[19 + q] += C.part_vir[(size_t)C.pv_stride * blk + 12 + q];
     }
 #pragma unroll
-    for (int q = 0; q < 19; ++q)
+    for (int q = 0; q < 37; ++q)
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
     if (lane == 0) {
         const double iv = 1.0 / C.dyn[b].vol;
-        double* acc = C.acc + 18 * b;
+        double* acc = C.acc + ACC * b;
         bool finite = true;
         for (int q = 0; q < 6; ++q) {
             const double sk = -v[q] * iv, sp = -C.vir_scale * v[6 + q] * iv, sf = -v[12 + q] * iv;
@@ -1189,10 +1218,14 @@ __global__ __launch_bounds__(64) void k_box_stress(Ctx C) {
             acc[6 + q] += sp;
             acc[12 + q] += sf;
             if (!(fabs(sk + sp + sf) <= 1e300)) finite = false;
+            if (comp)
+                for (int r = 0; r < 3; ++r) acc[18 + 6 * r + q] += -C.vir_scale * v[19 + 6 * r + q] * iv;
         }
         if (!finite) C.flags[b] |= LHMM_FLAG_NONFINITE;
         const unsigned long long np = (unsigned long long)v[18];
-        C.acc_pairs[b] += C.vir_scale < 1.0 ? np / 2 : np;
+        const unsigned long long up = C.vir_scale < 1.0 ? np / 2 : np;
+        C.acc_pairs[b] += up;
+        C.tot_pairs[b] += up;
         if (blockIdx.x == 0) *C.step += 1ull;
     }
 }
@@ -1225,9 +1258,9 @@ __global__ void k_finalize(Ctx C, double* __restrict__ stress_out, double* __res
                            double inv_steps) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= C.n_boxes) return;
-    const double* acc = C.acc + 18 * b;
+    const double* acc = C.acc + ACC * b;
     for (int q = 0; q < 6; ++q) stress_out[6 * b + q] = (acc[q] + acc[6 + q] + acc[12 + q]) * inv_steps;
-    for (int q = 0; q < 18; ++q) parts_out[18 * b + q] = acc[q] * inv_steps;
+    for (int q = 0; q < ACC; ++q) parts_out[ACC * b + q] = acc[q] * inv_steps;
 }
 
 }  // namespace
@@ -1259,7 +1292,7 @@ struct lhmm_micro {
     double *d_part_vir = nullptr, *d_part_kin = nullptr;
     unsigned* d_part_pairs = nullptr;
     double *d_acc = nullptr, *d_parts = nullptr, *d_gradL = nullptr;
-    unsigned long long *d_acc_pairs = nullptr, *d_step = nullptr;
+    unsigned long long *d_acc_pairs = nullptr, *d_tot_pairs = nullptr, *d_step = nullptr;
     // selection lists (device) and their pinned staging, reused once ev_sel completes
     int *d_sel = nullptr, *d_blk_list = nullptr, *h_sel = nullptr;
     hipEvent_t ev_sel = nullptr;
@@ -1307,12 +1340,14 @@ void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse,
 template <typename real>
 void launch_forces(lhmm_micro* m, const Ctx& C, int nblk, int step_offset, int kick, hipStream_t st) {
     const int drain = m->cfg.drain, busy = m->cfg.busy_lanes;
-#define LHMM_FORCES(QD)                                                                 \
-    do {                                                                                \
-        if (m->cfg.prune)                                                               \
-            k_forces<real, QD, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);  \
-        else                                                                            \
-            k_forces<real, QD, false><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick); \
+#define LHMM_FORCES(QD)                                                                       \
+    do {                                                                                      \
+        if (C.pv_stride > 12)                                                                 \
+            k_forces<real, QD, false, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick); \
+        else if (m->cfg.prune)                                                                \
+            k_forces<real, QD, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);        \
+        else                                                                                  \
+            k_forces<real, QD, false><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);       \
     } while (0)
     switch (m->cfg.queue_depth) {
         case 2: LHMM_FORCES(2); break;
@@ -1472,7 +1507,7 @@ void release(lhmm_micro* m) {
     void* bufs[] = {m->d_box, m->d_dyn, m->d_flags, m->d_blk_box, m->d_blk_first, m->d_s, m->d_c, m->d_f,
                     m->d_pcell, m->d_cell_start, m->d_gcell_start, m->d_cell_pv, m->d_srec,
                     m->d_part_vir, m->d_part_kin,
-                    m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_step,
+                    m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_tot_pairs, m->d_step,
                     m->d_sel, m->d_blk_list, m->d_snap_s, m->d_snap_c, m->d_snap_f, m->d_snap_dyn};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -1782,13 +1817,15 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     ALLOC(m->d_pcell, N);
     ALLOC(m->d_cell_start, (size_t)cell_off);
     ALLOC(m->d_gcell_start, (size_t)gcell_off);
-    ALLOC(m->d_part_vir, (size_t)m->n_blocks * 12);
+    const int pv_stride = (p->flags & LHMM_OPT_COMPONENTS) ? 30 : 12;
+    ALLOC(m->d_part_vir, (size_t)m->n_blocks * pv_stride);
     ALLOC(m->d_part_kin, (size_t)m->n_blocks * 6);
     ALLOC(m->d_part_pairs, (size_t)m->n_blocks);
-    ALLOC(m->d_acc, (size_t)n_boxes * 18);
-    ALLOC(m->d_parts, (size_t)n_boxes * 18);
+    ALLOC(m->d_acc, (size_t)n_boxes * ACC);
+    ALLOC(m->d_parts, (size_t)n_boxes * ACC);
     ALLOC(m->d_gradL, (size_t)n_boxes * 9);
     ALLOC(m->d_acc_pairs, (size_t)n_boxes);
+    ALLOC(m->d_tot_pairs, (size_t)n_boxes);
     ALLOC(m->d_step, (size_t)1);
 #undef ALLOC
     if (rc == LHMM_OK) {
@@ -1823,9 +1860,10 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
         }
         HIPCHK(hipMemcpy(m->d_dyn, dyn.data(), n_boxes * sizeof(BoxDyn), hipMemcpyHostToDevice));
         HIPCHK(hipMemset(m->d_flags, 0, n_boxes * sizeof(unsigned)));
-        HIPCHK(hipMemset(m->d_acc, 0, n_boxes * 18 * sizeof(double)));
-        HIPCHK(hipMemset(m->d_parts, 0, n_boxes * 18 * sizeof(double)));
+        HIPCHK(hipMemset(m->d_acc, 0, n_boxes * ACC * sizeof(double)));
+        HIPCHK(hipMemset(m->d_parts, 0, n_boxes * ACC * sizeof(double)));
         HIPCHK(hipMemset(m->d_acc_pairs, 0, n_boxes * sizeof(unsigned long long)));
+        HIPCHK(hipMemset(m->d_tot_pairs, 0, n_boxes * sizeof(unsigned long long)));
         HIPCHK(hipMemset(m->d_step, 0, sizeof(unsigned long long)));
         if (N) HIPCHK(hipMemset(m->d_f, 0, 3 * N * m->real_size));
         return LHMM_OK;
@@ -1856,10 +1894,12 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     C.srec = m->d_srec;
     C.vir_scale = 0.5;  // every unordered pair is evaluated from both ends
     C.part_vir = m->d_part_vir;
+    C.pv_stride = pv_stride;
     C.part_kin = m->d_part_kin;
     C.part_pairs = m->d_part_pairs;
     C.acc = m->d_acc;
     C.acc_pairs = m->d_acc_pairs;
+    C.tot_pairs = m->d_tot_pairs;
     C.step = m->d_step;
     C.a = p->a;
     C.gamma = p->gamma;
@@ -1973,7 +2013,7 @@ int lhmm_micro_step(lhmm_micro* m, const double* gradL, int32_t n_steps, double*
     HIPCHK(hipEventRecord(m->ev_in, m->user_stream));
     HIPCHK(hipStreamWaitEvent(m->stream, m->ev_in, 0));
     k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, gradL);
-    k_zero_acc<<<(18 * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
+    k_zero_acc<<<(ACC * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
     launch_remove_mean(m, m->ctx, m->n_boxes);
     if (!m->forces_valid) {
         launch_force_eval(m);
@@ -2212,7 +2252,7 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
     int rc = select_boxes(m, boxes, n_sel, &C, &nblk);
     if (rc != LHMM_OK) return rc;
     k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, gradL);
-    k_zero_acc<<<(18 * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
+    k_zero_acc<<<(ACC * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
     launch_remove_mean(m, C, n_sel);
     if (!m->forces_valid) {
         launch_force_eval(m);
@@ -2311,13 +2351,14 @@ int lhmm_micro_forces(lhmm_micro* m, const double* gradL, double* f_out, double*
             f_out[3 * i + k] = m->precision == LHMM_FP64 ? ((double*)buf.data())[k * N + i]
                                                          : (double)((float*)buf.data())[k * N + i];
     if (virial_out) {
-        std::vector<double> pv((size_t)m->n_blocks * 12);
+        const size_t ps = (size_t)m->ctx.pv_stride;
+        std::vector<double> pv((size_t)m->n_blocks * ps);
         HIPCHK(hipMemcpy(pv.data(), m->d_part_vir, pv.size() * sizeof(double), hipMemcpyDeviceToHost));
         for (int b = 0; b < m->n_boxes; ++b) {
             double* o = virial_out + 12 * b;
             for (int q = 0; q < 12; ++q) o[q] = 0.0;
             for (int k = 0; k < m->box[b].nblk; ++k)
-                for (int q = 0; q < 12; ++q) o[q] += pv[12 * (size_t)(m->box[b].blk_off + k) + q];
+                for (int q = 0; q < 12; ++q) o[q] += pv[ps * (size_t)(m->box[b].blk_off + k) + q];
             for (int q = 0; q < 6; ++q) o[q] *= m->ctx.vir_scale;  // ordered pairs count each pair twice
         }
     }
@@ -2335,7 +2376,7 @@ int lhmm_micro_time(lhmm_micro* m, const double* gradL, int32_t n_steps, double*
     HIPCHK(hipEventRecord(m->ev_in, m->user_stream));
     HIPCHK(hipStreamWaitEvent(m->stream, m->ev_in, 0));
     k_setup_call<<<bg, bt, 0, m->stream>>>(m->ctx, gradL);
-    k_zero_acc<<<(18 * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
+    k_zero_acc<<<(ACC * m->n_boxes + 255) / 256, 256, 0, m->stream>>>(m->ctx);
     launch_remove_mean(m, m->ctx, m->n_boxes);
     if (!m->forces_valid) {
         launch_force_eval(m);
@@ -2377,8 +2418,51 @@ int lhmm_micro_stress_parts(lhmm_micro* m, double* parts_out) {
     if (!m || !parts_out) return fail(LHMM_ERR_ARG, "null argument");
     int rc = sync_engine(m);
     if (rc != LHMM_OK) return rc;
-    HIPCHK(hipMemcpy(parts_out, m->d_parts, 18 * m->n_boxes * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> v((size_t)ACC * m->n_boxes);
+    HIPCHK(hipMemcpy(v.data(), m->d_parts, v.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int b = 0; b < m->n_boxes; ++b)
+        for (int q = 0; q < 18; ++q) parts_out[18 * (size_t)b + q] = v[(size_t)ACC * b + q];
     return LHMM_OK;
+}
+
+int lhmm_micro_components(lhmm_micro* m, double* out) {
+    g_err.clear();
+    if (!m || !out) return fail(LHMM_ERR_ARG, "null argument");
+    if (!(m->p.flags & LHMM_OPT_COMPONENTS))
+        return fail(LHMM_ERR_STATE, "the engine was created without LHMM_OPT_COMPONENTS");
+    int rc = sync_engine(m);
+    if (rc != LHMM_OK) return rc;
+    std::vector<double> v((size_t)ACC * m->n_boxes);
+    HIPCHK(hipMemcpy(v.data(), m->d_parts, v.size() * sizeof(double), hipMemcpyDeviceToHost));
+    // sums: kinetic 0, pair 6, FENE 12, C 18, D 24, R 30 -> kin, C, D, R, FENE
+    const int src[5] = {0, 18, 24, 30, 12};
+    for (int b = 0; b < m->n_boxes; ++b)
+        for (int part = 0; part < 5; ++part)
+            for (int q = 0; q < 6; ++q) out[30 * (size_t)b + 6 * part + q] = v[(size_t)ACC * b + src[part] + q];
+    return LHMM_OK;
+}
+
+int lhmm_micro_pair_total(lhmm_micro* m, uint64_t* pairs_out) {
+    g_err.clear();
+    if (!m || !pairs_out) return fail(LHMM_ERR_ARG, "null argument");
+    int rc = sync_engine(m);
+    if (rc != LHMM_OK) return rc;
+    std::vector<unsigned long long> v(m->n_boxes);
+    HIPCHK(hipMemcpy(v.data(), m->d_tot_pairs, m->n_boxes * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (int b = 0; b < m->n_boxes; ++b) pairs_out[b] = v[b];
+    return LHMM_OK;
+}
+
+int lhmm_micro_prepare(lhmm_micro* m, int32_t n_steps) {
+    g_err.clear();
+    if (!m) return fail(LHMM_ERR_ARG, "null engine");
+    if (n_steps <= 0) return fail(LHMM_ERR_ARG, "n_steps must be positive (got %d)", n_steps);
+    if (m->p.flags & LHMM_OPT_NO_GRAPH) return LHMM_OK;
+    const int chunk = n_steps < m->cfg.graph_chunk ? n_steps : m->cfg.graph_chunk;
+    hipGraphExec_t g = nullptr;
+    int rc = get_graph(m, chunk, &g);
+    if (rc == LHMM_OK && n_steps % chunk) rc = get_graph(m, n_steps % chunk, &g);
+    return rc;
 }
 
 int lhmm_micro_pair_counts(lhmm_micro* m, uint64_t* pairs_out) {

@@ -41,6 +41,7 @@ __device__ __forceinline__ double pow4(double x) {
 struct SphCtx {
     int n, n_mobile, force_mode;  // particles n_mobile .. n-1 are frozen walls
     int kernel;                   // LHMM_KERNEL_QUINTIC or LHMM_KERNEL_LUCY
+    int micro_dim;                // 3: micro-domains are 3-D boxes; 2: planar cells (no zz stress)
     int ncx, ncy;                 // cell grid (0: all pairs)
     int* cstart;                  // ncx * ncy + 1 cell offsets into cidx
     int* cidx;                    // particle indices in cell order
@@ -226,8 +227,11 @@ __global__ __launch_bounds__(TPB) void k_density(SphCtx S) {
     }
 }
 
-// polymer stress of particle I: alpha/lambda* x in-plane deviatoric part of
-// its micro-domain's mean stress (xx, yy, zz, xy, xz, yz)
+// polymer stress of particle I: alpha/lambda* x in-plane part of the
+// deviatoric part of its micro-domain's mean stress (xx, yy, zz, xy, xz,
+// yz).  A 3-D micro-domain loses its isotropic part tr/3; a planar one has
+// no zz stress (its particles and forces lie in the plane), so its
+// deviatoric part is taken in the plane, (xx + yy)/2 off the diagonal.
 __device__ __forceinline__ void polymer_stress(const SphCtx& S, const double* sigma, int I, double& xx, double& xy,
                                                double& yy) {
     if (!sigma) {
@@ -236,10 +240,10 @@ __device__ __forceinline__ void polymer_stress(const SphCtx& S, const double* si
     }
     const double* g = sigma + 6 * I;
     const double s = S.alpha / S.lambda_star;
-    const double tr3 = (g[0] + g[1] + g[2]) / 3.0;
-    xx = s * (g[0] - tr3);
+    const double iso = S.micro_dim == 2 ? 0.5 * (g[0] + g[1]) : (g[0] + g[1] + g[2]) / 3.0;
+    xx = s * (g[0] - iso);
     xy = s * g[3];
-    yy = s * (g[1] - tr3);
+    yy = s * (g[1] - iso);
 }
 
 // Eq. (sph_continuity) divided by the mass, plus the body force
@@ -420,6 +424,8 @@ int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const
         return lhmm_fail(LHMM_ERR_ARG, "unknown force_mode %d", p->force_mode);
     if (p->kernel != LHMM_KERNEL_QUINTIC && p->kernel != LHMM_KERNEL_LUCY)
         return lhmm_fail(LHMM_ERR_ARG, "unknown kernel %d", p->kernel);
+    if (p->micro_dim != 0 && p->micro_dim != 2 && p->micro_dim != 3)
+        return lhmm_fail(LHMM_ERR_ARG, "micro_dim must be 0, 2 or 3 (got %d)", p->micro_dim);
     const double vals[] = {p->rho0, p->eta, p->zeta, p->c, p->theta, p->F, p->h, p->dt, p->mass, p->Lx, p->Ly,
                            p->lambda_star, p->alpha};
     for (double x : vals)
@@ -442,6 +448,7 @@ int lhmm_sph_create(const lhmm_sph_params* p, int32_t n, const double* r0, const
     S.n_mobile = n - p->n_fixed;
     S.force_mode = p->force_mode;
     S.kernel = p->kernel;
+    S.micro_dim = p->micro_dim == 2 ? 2 : 3;
     S.rho0 = p->rho0; S.eta = p->eta; S.zeta = p->zeta; S.c = p->c; S.theta = p->theta; S.F = p->F; S.h = p->h;
     S.dt = p->dt; S.mass = p->mass; S.Lx = p->Lx; S.Ly = p->Ly; S.lambda_star = p->lambda_star; S.alpha = p->alpha;
     // cell grid of side >= h: at least 3 x 3 cells, and counters plus indices in 64 KiB of LDS

@@ -27,7 +27,8 @@ class Sph:
             raise RuntimeError("the SPH engine needs a ROCm GPU")
         self._torch = torch
         p = LhmmSphParams(**{k: float(params[k]) for k in SPH_KEYS}, n_fixed=int(params.get("n_fixed", 0)),
-                          force_mode=int(params.get("force_mode", 0)), kernel=int(params.get("kernel", 0)))
+                          force_mode=int(params.get("force_mode", 0)), kernel=int(params.get("kernel", 0)),
+                          micro_dim=int(params.get("micro_dim", 3)))
         self.n_fixed = int(params.get("n_fixed", 0))
         r0 = np.ascontiguousarray(r0, dtype=np.float64).reshape(-1, 2)
         v0 = np.ascontiguousarray(v0, dtype=np.float64).reshape(-1, 2)

@@ -28,7 +28,7 @@ class Micro:
     """
 
     def __init__(self, params: dict, boxes: Sequence, precision: str = "fp32", graphs: bool = True,
-                 stream=None):
+                 stream=None, components: bool = False):
         import torch
 
         if not torch.cuda.is_available():
@@ -40,7 +40,7 @@ class Micro:
         p.seed = int(params["seed"]) & ((1 << 64) - 1)
         p.chain_len = int(params["chain_len"])
         p.precision = {"fp32": _lib.FP32, "fp64": _lib.FP64}[precision]
-        p.flags = 0 if graphs else _lib.OPT_NO_GRAPH
+        p.flags = (0 if graphs else _lib.OPT_NO_GRAPH) | (_lib.OPT_COMPONENTS if components else 0)
         arr = (LhmmBox * len(boxes))()
         for k, spec in enumerate(boxes):
             n, nch, h0 = spec[0], spec[1], spec[2]
@@ -182,6 +182,23 @@ class Micro:
         check(lib().lhmm_micro_pair_counts(self._h, out.ctypes.data_as(C.POINTER(C.c_uint64))))
         return out
 
+    def pair_total(self):
+        """Unordered pairs within the cutoff over every step since create, per box."""
+        out = np.zeros(self.n_boxes, dtype=np.uint64)
+        check(lib().lhmm_micro_pair_total(self._h, out.ctypes.data_as(C.POINTER(C.c_uint64))))
+        return out
+
+    def components(self):
+        """(n_boxes, 5, 6) mean stress of the last step call by part: kinetic,
+        conservative, dissipative, random, FENE (engine created with components=True)."""
+        out = np.zeros((self.n_boxes, 5, 6))
+        check(lib().lhmm_micro_components(self._h, _dptr(out)))
+        return out
+
+    def prepare(self, n_steps: int):
+        """Capture the graphs a step call of n_steps will replay, without stepping."""
+        check(lib().lhmm_micro_prepare(self._h, int(n_steps)))
+
     def flags(self, clear: bool = False):
         out = np.zeros(self.n_boxes, dtype=np.uint32)
         check(lib().lhmm_micro_flags(self._h, out.ctypes.data_as(C.POINTER(C.c_uint32)), 1 if clear else 0))
@@ -199,11 +216,11 @@ class Micro:
             pass
 
 
-def from_workload(wl, precision: str = "fp32", graphs: bool = True, rng_ids=None) -> Micro:
+def from_workload(wl, precision: str = "fp32", graphs: bool = True, rng_ids=None, components: bool = False) -> Micro:
     """Engine holding every box of an ``inputs.Workload`` with its initial state loaded."""
     ids = range(len(wl.boxes)) if rng_ids is None else rng_ids
     boxes = [(b.N, b.n_chains, b.h, k) for b, k in zip(wl.boxes, ids)]
-    m = Micro(wl.params, boxes, precision=precision, graphs=graphs)
+    m = Micro(wl.params, boxes, precision=precision, graphs=graphs, components=components)
     s = np.concatenate([b.s for b in wl.boxes])
     c = np.concatenate([b.c for b in wl.boxes])
     h = np.stack([b.h.reshape(9) for b in wl.boxes])

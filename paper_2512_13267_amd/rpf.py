@@ -125,6 +125,8 @@ def run(force: float = 1.0e-2, alpha: float = 0.02, eta_p_guess: float = 0.02, n
     # dimension: for planar cells the engine's (volume) stress times the z edge
     alpha_feed = alpha * (inputs.PLANAR_THICKNESS if planar else 1.0)
     q["alpha"] = alpha_feed
+    # planar cells carry no zz stress: their deviatoric part is taken in the plane
+    q["micro_dim"] = 2 if planar else 3
     m_bar, k_micro = int(q["m_bar"]), int(q["k_micro"])
     delta_t = m_bar * q["dt"]
     dt_micro = delta_t / k_micro

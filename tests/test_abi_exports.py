@@ -35,7 +35,7 @@ def test_binding_struct_layout_matches_header():
     # lhmm_params: 9 doubles, uint64, three int32 (+4 padding) ; lhmm_box: 4 x 4 bytes + 9 doubles
     assert ctypes.sizeof(_lib.LhmmParams) == 9 * 8 + 8 + 3 * 4 + 4
     assert ctypes.sizeof(_lib.LhmmBox) == 16 + 72
-    assert ctypes.sizeof(_lib.LhmmSphParams) == 13 * 8 + 4 * 4  # three int32 and the tail padding
+    assert ctypes.sizeof(_lib.LhmmSphParams) == 13 * 8 + 4 * 4  # four int32
     assert ctypes.sizeof(_lib.LhmmSurParams) == 5 * 4
     assert ctypes.sizeof(_lib.LhmmMicroConfig) == 8 * 4
     assert ctypes.sizeof(_lib.LhmmHybridParams) == 8 * 4

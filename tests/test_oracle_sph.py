@@ -248,3 +248,121 @@ def test_viscous_term_realises_the_moments_of_its_friction_coefficients(orc, ker
     nu_long = -np.dot(acc[:, 1], s) / (k * k * A * np.dot(s, s))
     assert nu_long * q["rho0"] == pytest.approx(a / 2 + 3 * b / 8, rel=0.01)
     print(kernel, "shear", nu_shear * q["rho0"] / eta, "longitudinal", (nu_long * q["rho0"] - zeta) / eta)
+
+
+def _sine_lattice(kernel):
+    """Uniform lattice, 16 x 128 spacings, support 6 spacings (the continuum
+    moments of the kernel hold to ~0.5 %), no body force, fluid at rest."""
+    m = inputs.reverse_poiseuille(nx=16, ny=128, force=0.0, kernel=kernel)
+    q = dict(m.params, F=0.0, h=6.0 * m.params["Lx"] / 16)
+    return m, q
+
+
+@pytest.mark.parametrize("kernel", ["quintic", "lucy"])
+def test_polymer_term_is_the_divergence_of_the_stress(orc, kernel):
+    """The micro-to-macro term of Eq. (sph_continuity),
+    -sum_J (pi_I/d_I^2 + pi_J/d_J^2) F_IJ r_IJ, is the SPH form of
+    +div(pi): on a uniform lattice (d_I = d, sum_J F_IJ r_IJ = 0) a linear
+    variation pi_J = pi_I - r_IJ . grad pi gives
+    sum_J F_IJ r_a r_b = d delta_ab (the second moment of a unit-integral
+    kernel, int F r^2 dA = 2, halved by the angular mean), so
+    m a = div(pi) / d and a = div(pi) / rho with rho = m d.  Measured on
+    stress waves along y: pi_xy = A sin(k y) drives a_x = A k cos(k y)/rho,
+    pi_yy = C sin(k y) drives a_y = C k cos(k y)/rho, and pi_xx(y) drives
+    nothing (d pi_xx / dx = 0).  A flipped sign, a lost 1/d^2 or a
+    transposed stress fails it."""
+    m, q = _sine_lattice(kernel)
+    k = 2 * math.pi / q["Ly"]
+    y = m.r[:, 1]
+    s, c = np.sin(k * y), np.cos(k * y)
+    d, p = orc.sph_density(q, m.r)
+    rho = q["mass"] * d.mean()
+    v = np.zeros_like(m.r)
+    base = orc.sph_accel(q, m.r, v, d, p, np.zeros((m.n, 3)))
+    assert np.abs(base).max() < 1e-9  # uniform pressure on the lattice exerts no force
+    A, B, Cc = 2e-3, 3e-3, -1.5e-3
+    for comp, amp in ((1, A), (2, Cc), (0, B)):
+        pi = np.zeros((m.n, 3))
+        pi[:, comp] = amp * s
+        a = orc.sph_accel(q, m.r, v, d, p, pi)
+        proj = a.T @ c / (c @ c)  # cos(ky) content of (a_x, a_y)
+        other = a - np.outer(c, proj)
+        if comp == 1:  # pi_xy -> a_x
+            assert proj[0] == pytest.approx(amp * k / rho, rel=0.01)
+            assert abs(proj[1]) < 1e-6 * abs(amp * k / rho)
+        elif comp == 2:  # pi_yy -> a_y
+            assert proj[1] == pytest.approx(amp * k / rho, rel=0.01)
+            assert abs(proj[0]) < 1e-6 * abs(amp * k / rho)
+        else:  # pi_xx(y) -> nothing
+            assert np.abs(a).max() < 1e-6 * abs(amp * k / rho)
+        assert np.abs(other).max() < 1e-3 * abs(amp * k / rho)
+
+
+@pytest.mark.parametrize("kernel", ["quintic", "lucy"])
+def test_micro_shear_stress_feeds_back_with_alpha_over_lambda(orc, kernel):
+    """From the micro-domains' mean stress to the macro acceleration
+    (Eq. pip, then Eq. sph_continuity): a micro shear stress
+    sigma_xy = S sin(k y) gives pi_xy = (alpha / lambda*) sigma_xy and the
+    acceleration a_x = (alpha / lambda*) S k cos(k y) / rho.  Positive
+    tension-positive micro shear stress feeds back with the sign of the
+    solvent's own stress 2 eta_s d."""
+    m, q = _sine_lattice(kernel)
+    q = dict(q, alpha=0.07, lambda_star=0.2)
+    k = 2 * math.pi / q["Ly"]
+    c = np.cos(k * m.r[:, 1])
+    S = 0.01
+    sig = np.zeros((m.n, 6))
+    sig[:, 3] = S * np.sin(k * m.r[:, 1])
+    sig[:, :3] = 2.0  # an isotropic part (micro pressure) changes nothing
+    pi = orc.sph_polymer_stress(q, sig)
+    assert np.allclose(pi[:, 1], q["alpha"] / q["lambda_star"] * sig[:, 3], rtol=1e-14, atol=0)
+    assert np.abs(pi[:, [0, 2]]).max() < 1e-14
+    d, p = orc.sph_density(q, m.r)
+    a = orc.sph_accel(q, m.r, np.zeros_like(m.r), d, p, pi)
+    rho = q["mass"] * d.mean()
+    assert (a[:, 0] @ c) / (c @ c) == pytest.approx(q["alpha"] / q["lambda_star"] * S * k / rho, rel=0.01)
+
+
+@pytest.mark.parametrize("micro_dim", [3, 2])
+def test_isotropic_micro_stress_exerts_no_polymer_force(orc, micro_dim):
+    """Only the deviatoric part of the micro stress feeds back (the macro EOS
+    supplies the pressure).  A 3-D micro-domain's isotropic stress is
+    p (1, 1, 1); a planar micro-domain has no zz stress (its particles and
+    forces lie in the plane) and its isotropic stress is p (1, 1, 0): with
+    the matching micro_dim either gives pi = 0 and an acceleration equal to
+    that without polymer stress, particle by particle, on a disordered
+    particle set with a different p on every particle.  Anisotropy passes
+    through unchanged: sigma_xx - sigma_yy and sigma_xy."""
+    rng = np.random.default_rng(17)
+    m = inputs.reverse_poiseuille(nx=8, ny=32)
+    q = dict(m.params, micro_dim=micro_dim, alpha=0.3, lambda_star=0.5)
+    r = m.r + rng.normal(scale=0.2 / 32, size=m.r.shape)
+    r[:, 0] %= q["Lx"]
+    r[:, 1] %= q["Ly"]
+    v = rng.normal(scale=0.05, size=r.shape)
+    pr = rng.uniform(0.5, 3.0, size=m.n)
+    sig = np.zeros((m.n, 6))
+    sig[:, 0] = sig[:, 1] = pr
+    if micro_dim == 3:
+        sig[:, 2] = pr
+    pi = orc.sph_polymer_stress(q, sig)
+    assert np.abs(pi).max() < 1e-14 * pr.max()
+    d, p = orc.sph_density(q, r)
+    a0 = orc.sph_accel(q, r, v, d, p, np.zeros((m.n, 3)))
+    a = orc.sph_accel(q, r, v, d, p, pi)
+    assert np.abs(a - a0).max() < 1e-12 * np.abs(a0).max()
+    if micro_dim == 2:
+        # read as 3-D, a planar cell's stress would lose only tr/3 = 2p/3,
+        # leaving a spurious isotropic p/3 on both in-plane diagonals
+        other = orc.sph_polymer_stress(dict(q, micro_dim=3), sig)
+        expect = q["alpha"] / q["lambda_star"] * pr / 3
+        assert np.allclose(other[:, 0], expect, rtol=1e-12) and np.allclose(other[:, 2], expect, rtol=1e-12)
+    # anisotropic parts pass through unchanged
+    sig2 = sig.copy()
+    sig2[:, 0] += 0.4
+    sig2[:, 1] -= 0.4
+    sig2[:, 3] = 0.25
+    pi2 = orc.sph_polymer_stress(q, sig2)
+    s_ = q["alpha"] / q["lambda_star"]
+    assert np.allclose(pi2[:, 0] - pi2[:, 2], s_ * 0.8, rtol=1e-12)
+    assert np.allclose(pi2[:, 1], s_ * 0.25, rtol=1e-14)
