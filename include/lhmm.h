@@ -116,6 +116,38 @@ typedef struct {
                          /* extent h0[8] > 0, zero z coupling, det > 0        */
 } lhmm_box;
 
+/* Initial cell of a box that must stay usable under a constant in-plane
+ * gradient (host computation only, no device work; reentrant).  The
+ * homogeneous imposition of the macro gradient (Eq. micro_bc) deforms the
+ * periodic cell as dh/dt = L h; the returned cell keeps its reduced
+ * lattice's perpendicular widths large for the run:
+ *   LHMM_CELL_CUBIC:   the cube of side edge, kept when its reduced lattice
+ *                      stays at least min_width wide over [0, t_run];
+ *   LHMM_CELL_ROTATED: otherwise, for a rotational or shear-like gradient
+ *                      (a^2 + bc <= 0, L = [[a, b], [c, -a]] in the plane),
+ *                      the square of side edge rotated (46 angles of
+ *                      [0, pi/2)) to the angle whose narrowest width over
+ *                      [0, t_run] is largest;
+ *   LHMM_CELL_KR:      otherwise (hyperbolic gradient, k^2 = a^2 + bc > 0), a
+ *                      lattice aligned in the manner of Kraynik and Reinelt:
+ *                      exp(L T) P = P M with M = [[2, 1], [1, 1]] and
+ *                      T = ln((3 + sqrt 5)/2) / k, so the flow maps it onto
+ *                      itself every period; among the family
+ *                      V diag(r, +-1) W^-1 (V, W eigenvectors of L and M,
+ *                      r = e^-4 .. e^4 in 81 steps) of area edge^2, the
+ *                      member whose narrowest width over a period is
+ *                      largest; the members are time shifts of one
+ *                      lattice, so among those within 1e-9 of the best the
+ *                      one widest at t = 0 is taken.
+ * L: host 9 doubles (u = L r; in-plane and traceless); h_out: host 9
+ * doubles, the in-plane basis reduced (its two successive minima, det > 0)
+ * and z extent edge; kind: host, may be NULL.  Errors: ARG (bad L, edge,
+ * t_run or min_width). */
+#define LHMM_CELL_CUBIC 0
+#define LHMM_CELL_KR 1
+#define LHMM_CELL_ROTATED 2
+int lhmm_box_cell(const double* L, double edge, double t_run, double min_width, double* h_out, int32_t* kind);
+
 /* Allocate an engine for n_boxes boxes.  p, boxes: host.  stream: the
  * caller's hipStream_t (may be NULL for the null stream).  The particle
  * state is undefined until lhmm_micro_set_state.  Errors: ARG, HIP, OOM. */

@@ -29,6 +29,7 @@ FP32 = 0
 FP64 = 1
 OPT_NO_GRAPH = 1
 OPT_COMPONENTS = 2
+CELL_KINDS = {0: "cubic", 1: "kr", 2: "rotated"}
 
 # every symbol include/lhmm.h declares
 EXPORTS = (
@@ -37,7 +38,7 @@ EXPORTS = (
     "lhmm_micro_sizes", "lhmm_micro_destroy", "lhmm_last_error", "lhmm_micro_time",
     "lhmm_micro_step_subset", "lhmm_micro_snapshot", "lhmm_micro_restore",
     "lhmm_micro_set_config", "lhmm_micro_get_config", "lhmm_micro_autotune",
-    "lhmm_micro_components", "lhmm_micro_pair_total", "lhmm_micro_prepare",
+    "lhmm_micro_components", "lhmm_micro_pair_total", "lhmm_micro_prepare", "lhmm_box_cell",
     "lhmm_sph_create", "lhmm_sph_step", "lhmm_sph_get_state", "lhmm_sph_coupling_state", "lhmm_couple_step",
     "lhmm_sph_destroy",
     "lhmm_sur_create", "lhmm_sur_set_weights", "lhmm_sur_get_weights", "lhmm_sur_get_grads", "lhmm_sur_train_step", "lhmm_sur_forward",
@@ -128,6 +129,7 @@ def lib():
         L.lhmm_micro_pair_total.argtypes = [vp, u64p]
         L.lhmm_micro_components.argtypes = [vp, dp]
         L.lhmm_micro_prepare.argtypes = [vp, C.c_int32]
+        L.lhmm_box_cell.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, C.POINTER(C.c_int32)]
         L.lhmm_micro_flags.argtypes = [vp, C.POINTER(C.c_uint32), C.c_int32]
         L.lhmm_micro_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.lhmm_micro_destroy.argtypes = [vp]

@@ -6,7 +6,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lhmm_micro.hip", "lhmm_sph.hip", "lhmm_sur.hip", "lhmm_hybrid.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lhmm_micro.hip", "lhmm_sph.hip", "lhmm_sur.hip", "lhmm_hybrid.hip",
+                                                        "lhmm_cell.hip")]
 OUT = os.path.join(HERE, "liblhmm.so")
 
 HIPCC_FLAGS = [

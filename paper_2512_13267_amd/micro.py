@@ -216,6 +216,17 @@ class Micro:
             pass
 
 
+def box_cell(L, edge: float, t_run: float, min_width: float = 3.5):
+    """Initial cell for a box under the constant in-plane gradient L over a
+    run of t_run time units (lhmm_box_cell): (h (3, 3), kind) with kind
+    "cubic", "kr" (Kraynik-Reinelt aligned) or "rotated"."""
+    Lv = np.ascontiguousarray(L, dtype=np.float64).reshape(9)
+    h = np.zeros(9)
+    kind = C.c_int32(-1)
+    check(lib().lhmm_box_cell(_dptr(Lv), float(edge), float(t_run), float(min_width), _dptr(h), C.byref(kind)))
+    return h.reshape(3, 3), _lib.CELL_KINDS[kind.value]
+
+
 def from_workload(wl, precision: str = "fp32", graphs: bool = True, rng_ids=None, components: bool = False) -> Micro:
     """Engine holding every box of an ``inputs.Workload`` with its initial state loaded."""
     ids = range(len(wl.boxes)) if rng_ids is None else rng_ids

@@ -83,7 +83,8 @@ def test_components_fp32_trajectory_equals_default_kernel(torch_gpu):
     assert np.array_equal(s1, s0) and np.array_equal(c1, c0)
     assert np.abs(out0 - out).max() <= 1e-12 * np.abs(out0).max()
     comps = m.components()
-    assert np.abs(comps.sum(axis=1) - out).max() <= 1e-12 * np.abs(out).max()
+    # each part is summed in single precision per lane on its own
+    assert np.abs(comps.sum(axis=1) - out).max() <= 1e-6 * np.abs(out).max()
     m.close()
     m0.close()
 

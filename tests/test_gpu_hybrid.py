@@ -11,7 +11,12 @@
   over several macro steps; the only differences are FP32 accumulation and
   BF16 rounding decisions in the ensemble (parity of the forward pass is
   ~1e-4 relative), which move the velocities by far less than 1e-6 of
-  their scale over these steps.
+  their scale over these steps;
+* restore and replay (replay = 3) of thin boxes, in DPD mode and in
+  surrogate mode with a gate built to flag a chosen set (entry at the first
+  step), follow an oracle loop (oracle micro-boxes sharing one random-force
+  counter, the equilibrated snapshot, FP32 history ring and its replay
+  gradients) to rounding, FP64 micro-boxes.
 """
 import numpy as np
 import pytest
@@ -138,3 +143,197 @@ def test_closed_gate_follows_the_oracle_loop(torch_gpu, orc):
     sur.close()
     m.close()
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# Restore and replay (replay > 0) against the oracle loop
+# ---------------------------------------------------------------------------
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def _thin_workload(nm, every=4, seed=31):
+    """Cubic 600-particle micro-boxes, and every `every`-th box thin: a 7 x 7
+    x 3.2 cell, exact (wider than the 3 rc guard) but below the 3.3 rc at
+    which the hybrid restores and replays a box, so it is reset at the end of
+    every step it runs."""
+    from paper_2512_13267_amd import inputs
+
+    wl = inputs.lhmm_boxes(nm, n_particles=600, polymer_fraction=0.2, seed_k=seed)
+    rng = np.random.default_rng(inputs.SEED_BASE + seed + 1000)
+    thin = list(range(0, nm, every))
+    for b in thin:
+        h = np.diag([7.0, 7.0, 3.2])
+        N = int(round(3.0 * 7.0 * 7.0 * 3.2))
+        n_chains = int(round(0.2 * N / 10))
+        s, c = inputs.random_box(rng, h, N, n_chains, 10)
+        wl.boxes[b] = inputs.BoxInit(s=s, c=c, h=h, n_chains=n_chains, L=np.zeros((3, 3)), edge=7.0, phi=0.2)
+    return wl, thin
+
+
+class _OracleHybrid:
+    """The hybrid macro step written out with the oracles: SPH oracle, micro
+    oracle boxes with one shared random-force counter (every micro call
+    advances it by its steps, whichever boxes it moves), the equilibrated
+    snapshot, the FP32 history ring and its replay gradients, the gate of
+    the MLP oracle and the blend definition."""
+
+    def __init__(self, orc, q, mac, wl, k_micro, replay, gscale, sscale=1.0, equil=5):
+        self.orc, self.q, self.k, self.R, self.gs, self.ss = orc, q, k_micro, replay, gscale, sscale
+        self.p = wl.params
+        self.nm = len(wl.boxes)
+        self.n = mac.r.shape[0]
+        self.r, self.v = mac.r.copy(), mac.v.copy()
+        self.obs = [orc.OracleBox(s=b.s, c=b.c, h=b.h, n_chains=b.n_chains, box_id=k)
+                    for k, b in enumerate(wl.boxes)]
+        self.ctr = 0
+        self._run(list(range(self.nm)), np.zeros((self.nm, 3, 3)), equil)
+        self.snap = [(o.s.copy(), o.c.copy(), o.F.copy(), o.fvalid, o.h.copy()) for o in self.obs]
+        self.ring = []  # (nm, 4) FP32 samples: gscale x (L_xx, L_xy, L_yx, L_yy)
+        self.sigma = np.zeros((self.n, 6))
+
+    def _run(self, boxes, Ls, nsteps):
+        sel = [self.obs[b] for b in boxes]
+        for o in sel:
+            o.step = self.ctr
+        means, _ = self.orc.run_batch(self.p, self.p["seed"], self.p["chain_len"], sel, np.asarray(Ls), nsteps)
+        self.ctr += nsteps
+        return means
+
+    def _restore(self, boxes):
+        for b in boxes:
+            s, c, F, fv, h = self.snap[b]
+            o = self.obs[b]
+            o.s, o.c, o.F, o.fvalid, o.h, o.err = s.copy(), c.copy(), F.copy(), fv, h.copy(), 0
+
+    def _replay_gradients(self, sample):
+        x = self.ring[sample]
+        inv = float(np.float32(1.0) / np.float32(self.gs))
+        L = np.zeros((self.nm, 3, 3))
+        L[:, 0, 0] = x[:, 0] * inv
+        L[:, 0, 1] = x[:, 1] * inv
+        L[:, 1, 0] = x[:, 2] * inv
+        L[:, 1, 1] = -L[:, 0, 0]
+        return L
+
+    def restore_and_replay(self, boxes, first, last):
+        if not boxes:
+            return
+        self._restore(boxes)
+        for smp in range(max(0, first), last + 1):
+            self._run(boxes, self._replay_gradients(smp)[boxes], self.k)
+
+    def step(self, on, reset):
+        """One macro step; on: boxes on DPD (all in DPD mode), reset: the thin
+        boxes among them.  Returns the SPH micro gradients of the step."""
+        t = len(self.ring)
+        pi = self.orc.sph_polymer_stress(self.q, self.sigma)
+        L = self.orc.sph_step(self.q, self.r, self.v, pi)
+        Lm = L[:self.nm]
+        gs = float(np.float32(self.gs))
+        self.ring.append(_f32(np.stack([Lm[:, 0, 0] * gs, Lm[:, 0, 1] * gs, Lm[:, 1, 0] * gs, Lm[:, 1, 1] * gs],
+                                       axis=1)))
+        sig = np.zeros((self.n, 6))
+        if on:
+            means = self._run(on, Lm[on], self.k)
+            sig[on] = means
+        self.sigma = sig
+        self.restore_and_replay(reset, t + 1 - self.R, t)
+        return Lm
+
+
+def _replay_case(torch_gpu, orc, mode):
+    from paper_2512_13267_amd import inputs, lhmm, micro, surrogate
+
+    torch = torch_gpu
+    mac = inputs.cylinder_array(n=16, force=2.0)
+    q = mac.params
+    nm = mac.r.shape[0] - q["n_fixed"]
+    wl, thin = _thin_workload(nm)
+    k_micro, R, gscale = 10, 3, 8.0
+    print(f"case: hybrid {mode} mode, {nm} FP64 boxes ({len(thin)} thin), replay {R}", flush=True)
+    m = micro.from_workload(wl, precision="fp64")
+    m.step(torch.zeros((nm, 9), dtype=torch.float64, device="cuda"), 5)
+    s = lhmm.Sph(q, mac.r, mac.v)
+    sur = None
+    phi = np.zeros(nm, dtype=np.float32)
+    if mode == "surrogate":
+        # two members that agree exactly (output 0) where phi = 0 and disagree
+        # by +-10 where phi = 1: hidden unit 0 of layer 1 is GELU(20 phi - 10),
+        # unit 0 of layer 2 passes it on, and the members' output weights on
+        # it are +1 and -1; every other weight and bias is zero
+        mem = surrogate.init_members(2, 129, 32, 3, seed=3)
+        for e, mm in enumerate(mem):
+            for k in mm:
+                mm[k] = np.zeros_like(mm[k])
+            mm["W1"][128, 0] = 20.0
+            mm["b1"][0] = -10.0
+            mm["W2"][0, 0] = 1.0
+            mm["W3"][0, :] = 1.0 if e == 0 else -1.0
+        sur = surrogate.Surrogate(mem, 129, 32, 3, max_batch=nm)
+        phi[1::3] = 1.0  # boxes 1, 4, 7, ...: some thin (4, 16, ...), most not
+    hy = lhmm.Hybrid(s, m, sur, phi=phi, mode=mode, k_micro=k_micro, hold=1, replay=R, threshold=0.05, floor=1.0,
+                     grad_scale=gscale, stress_scale=1.0)
+    ref = _OracleHybrid(orc, q, mac, wl, k_micro, R, gscale)
+    on = list(range(nm)) if mode == "dpd" else [b for b in range(nm) if phi[b] == 1.0]
+    reset = [b for b in on if b in thin]
+    assert reset and len(reset) < len(on)
+    for t in range(4):
+        st = hy.step()
+        ref.step(on, reset)
+        assert st["n_dpd"] == len(on) and st["n_reset"] == len(reset)
+        assert st["n_entered"] == (len(on) if (mode == "surrogate" and t == 0) else 0)
+        if mode == "surrogate":
+            # the MLP oracle's gate on the oracle's own features flags exactly
+            # the phi = 1 particles (spread 10 against 0.05, or exactly 0)
+            hist = np.concatenate([np.zeros((nm, 32, 4)), np.stack(ref.ring, axis=1)], axis=1)
+            X = mo.features(hist, _f32(phi))
+            Y = np.stack([mo.forward({k: v.astype(np.float64) for k, v in mm.items()}, X)[0] for mm in mem])
+            _, flag, _ = mo.gate(Y, 0.05, 1.0)
+            assert np.array_equal(np.flatnonzero(flag), np.array(on))
+    sig_d, on_d = hy.state()
+    assert np.array_equal(np.flatnonzero(on_d), np.array(on))
+    scale = np.abs(ref.sigma[:nm]).max()
+    ds = np.abs(sig_d - ref.sigma).max() / scale
+    print("stress diff / scale", ds, flush=True)
+    assert ds < 1e-7
+    rg, vg, _ = s.get_state()
+    dv = np.abs(vg - ref.v).max() / np.abs(ref.v).max()
+    print("velocity diff / scale", dv, flush=True)
+    assert dv < 1e-9 and np.abs(rg - ref.r).max() < 1e-12
+    # the micro state after the last step: replayed thin boxes and regular boxes
+    sd, cd, hd, stepd = m.get_state()
+    assert stepd == ref.ctr
+    off = np.concatenate([[0], np.cumsum([b.N for b in wl.boxes])])
+    for b in (reset[0], reset[-1], on[1] if on[1] not in thin else on[2]):
+        o = ref.obs[b]
+        ds_ = sd[off[b]:off[b + 1]] - o.s
+        ds_ -= np.round(ds_)
+        assert np.abs(ds_ @ o.h.T).max() < 1e-6, b
+        assert np.abs(cd[off[b]:off[b + 1]] - o.c).max() < 1e-6, b
+        assert np.allclose(hd[b], o.h, rtol=0, atol=1e-10)
+    hy.close()
+    if sur is not None:
+        sur.close()
+    m.close()
+    s.close()
+
+
+def test_thin_box_replay_follows_the_oracle_loop_dpd_mode(torch_gpu, orc):
+    """All-DPD hybrid with replay = 3: every thin box is restored from the
+    equilibrated snapshot and relives the last three intervals' gradients
+    (from the FP32 history ring) after each step, and the random-force
+    counter moves on with every replayed call; stresses, macro state and
+    micro state follow the oracle loop to rounding (FP64 micro-boxes)."""
+    _replay_case(torch_gpu, orc, "dpd")
+
+
+def test_gate_and_replay_follow_the_oracle_loop_surrogate_mode(torch_gpu, orc):
+    """Surrogate mode with an ensemble built to disagree exactly where the
+    polymer-fraction feature is 1: the MLP oracle's gate flags the same
+    particles, they enter DPD at the first step (restore from the snapshot),
+    run DPD every step, their thin boxes are restored and replayed (three
+    samples) after every step, and the others take the surrogate mean (zero
+    here); everything follows the oracle loop to rounding."""
+    _replay_case(torch_gpu, orc, "surrogate")

@@ -334,6 +334,48 @@ def test_full_batch_sampled_parity(torch_gpu, orc):
     m.close()
 
 
+def test_full_batch_fp32_stress_statistics_kr_boxes(torch_gpu, orc):
+    """Time-averaged stresses of the 256-box FP32 batch, in the benchmark's
+    launch configuration, against the FP64 oracle on the four smallest
+    Kraynik-Reinelt boxes (hyperbolic gradients, planar extension at rates
+    0.27-0.38): after 100 steps both sides are independent realisations
+    (single and double precision trajectories separate within ~100 steps),
+    and 20 blocks of 50 steps give each side's mean and standard error per
+    component.  Acceptance at the tolerance's two combined standard errors
+    with a multiple-comparison allowance: of the 24 box-component pairs at
+    least 80 % lie within 2 SE and all within 3.5 SE (for a correct
+    implementation the chance of failing either is 1.5 % with normal errors,
+    3.6 % with Student-t errors of 38 degrees of freedom)."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.batch()
+    p = wl.params
+    kr = []
+    for k, b in enumerate(wl.boxes):
+        a, bb, c = b.L[0, 0], b.L[0, 1], b.L[1, 0]
+        if a * a + bb * c > 0 and not np.allclose(b.h, np.diag(np.diag(b.h))):
+            kr.append((b.N, k))
+    sample = [k for _, k in sorted(kr)[:4]]
+    print("case: 256-box FP32 batch, stress statistics on boxes", sample, flush=True)
+    m = micro.from_workload(wl, precision="fp32")
+    G = _grads(torch, wl)
+    m.step(G, 100)
+    gb = np.array([m.step(G, 50).cpu().numpy()[sample] for _ in range(20)])  # (20, 4, 6)
+    flags = m.flags()
+    m.close()
+    obs = [orc.OracleBox(s=wl.boxes[k].s, c=wl.boxes[k].c, h=wl.boxes[k].h, n_chains=wl.boxes[k].n_chains,
+                         box_id=k) for k in sample]
+    Ls = [wl.boxes[k].L for k in sample]
+    orc.run_batch(p, p["seed"], 10, obs, Ls, 100)
+    ob = np.array([orc.run_batch(p, p["seed"], 10, obs, Ls, 50)[0] for _ in range(20)])
+    se = np.sqrt(gb.var(axis=0, ddof=1) / len(gb) + ob.var(axis=0, ddof=1) / len(ob))
+    z = np.abs(gb.mean(axis=0) - ob.mean(axis=0)) / se
+    print("|diff| / SE per box and component:\n", np.round(z, 2), flush=True)
+    assert np.mean(z <= 2.0) >= 0.8, z
+    assert np.all(z <= 3.5), z
+    assert not np.any(flags[sample] & (_lib.FLAG_CELL | _lib.FLAG_NONFINITE))
+
+
 def test_subset_step_equals_full_step_for_selected_boxes(torch_gpu):
     """Stepping a subset of boxes gives those boxes exactly the trajectory and
     stress of a full step from the same state and counter; the other boxes
