@@ -485,6 +485,24 @@ int lhmm_sur_train_step(lhmm_sur* s, const float* X, const float* T, int32_t B, 
  * n_members x B x n_out.  Asynchronous.  Errors: ARG, HIP. */
 int lhmm_sur_forward(lhmm_sur* s, const float* X, int32_t B, float* Y);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lhmm_sur_forward with
+ * the same kernels and results, whose activations (padded BF16 inputs,
+ * both hidden layers of every member, FP32 outputs) live in a 32 MiB
+ * device array of the library instead of the engine's buffers.  It calls
+ * no hipMalloc, hipFree or allocating routine and launches kernels only.
+ * B is limited by that array, not by max_batch: Bp = B rounded up to 32
+ * needs 2 Bp n_in_p + 4 n_members Bp n_hidden + 128 n_members Bp bytes
+ * (n_in_p = n_in rounded up to 32, each part rounded up to 256 bytes), e.g.
+ * B <= 5504 for 5 members of 129 -> 256 -> 256 -> 3; a larger B returns
+ * ARG.  Call it with the device the engine was created on current (else
+ * ARG).  Every call on a device shares that device's array, which keeps the
+ * last call's contents: calls that overlap on one device (two streams, or
+ * two threads) race and must be ordered by the caller.  X: DEVICE
+ * B x n_in; Y: DEVICE n_members x B x n_out.  Asynchronous on the engine's
+ * stream.  Errors: ARG, HIP. */
+int lhmm_sur_forward_static(lhmm_sur* s, const float* X, int32_t B, float* Y);
+
 /* Record sample t (t = 0, 1, ...) of the micro gradients of n particles:
  * ring is DEVICE n x LHMM_SUR_HIST x 4 FP32 (caller-owned), slot t mod
  * LHMM_SUR_HIST of particle b receives scale x (L_xx, L_xy, L_yx, L_yy) of

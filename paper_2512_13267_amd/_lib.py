@@ -42,6 +42,7 @@ EXPORTS = (
     "lhmm_sph_create", "lhmm_sph_step", "lhmm_sph_get_state", "lhmm_sph_coupling_state", "lhmm_couple_step",
     "lhmm_sph_destroy",
     "lhmm_sur_create", "lhmm_sur_set_weights", "lhmm_sur_get_weights", "lhmm_sur_get_grads", "lhmm_sur_train_step", "lhmm_sur_forward",
+    "lhmm_sur_forward_static",
     "lhmm_sur_push_history", "lhmm_sur_features", "lhmm_sur_gate", "lhmm_sur_destroy", "lhmm_sur_targets",
     "lhmm_sur_blend", "lhmm_sur_history_gradient", "lhmm_sur_augment",
     "lhmm_hybrid_create", "lhmm_hybrid_step", "lhmm_hybrid_state", "lhmm_hybrid_destroy", "lhmm_hybrid_mean_stress",
@@ -147,6 +148,7 @@ def lib():
         L.lhmm_sur_get_grads.argtypes = [vp, fp]
         L.lhmm_sur_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp]
         L.lhmm_sur_forward.argtypes = [vp, vp, C.c_int32, vp]
+        L.lhmm_sur_forward_static.argtypes = [vp, vp, C.c_int32, vp]
         L.lhmm_sur_push_history.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_float, vp]
         L.lhmm_sur_augment.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
         L.lhmm_sur_targets.argtypes = [vp, C.c_int32, C.c_float, vp, vp]

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -407,6 +408,7 @@ int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 struct lhmm_sur {
     int E = 0, nin = 0, nin_p = 0, nh = 0, nout = 0, nout_p = 32, Bmax = 0, step = 0;
+    int device = 0;  // the device current at create
     hipStream_t stream = nullptr;
     std::vector<void*> bufs;
     // FP32 masters, grads, Adam moments, per member (stride = size of one member's tensor)
@@ -477,32 +479,75 @@ long szW1(const lhmm_sur* s) { return (long)s->nin_p * s->nh; }
 long szW2(const lhmm_sur* s) { return (long)s->nh * s->nh; }
 long szW3(const lhmm_sur* s) { return (long)s->nh * s->nout_p; }
 
-// forward of every member on the first Bp rows of s->X / s->Xt; `train`
-// also keeps the pre-activations and transposed activations for backward
-void forward(lhmm_sur* s, int Bp, bool train) {
+// Activations of a forward pass: padded BF16 inputs X [Bp x nin_p], per
+// member the BF16 hidden activations H1, H2 (member stride sh), their FP32
+// pre-activations Z1, Z2 and transposes H1t, H2t (training only, else
+// null), and the FP32 outputs Y (member stride sy).
+struct Act {
+    bf16 *X, *H1, *H1t, *H2, *H2t;
+    float *Z1, *Z2, *Y;
+    long sh, sy;
+};
+
+Act engine_act(const lhmm_sur* s, bool train) {
+    Act a{};
+    a.X = s->X;
+    a.H1 = s->H1;
+    a.H2 = s->H2;
+    if (train) {
+        a.H1t = s->H1t;
+        a.H2t = s->H2t;
+        a.Z1 = s->Z1;
+        a.Z2 = s->Z2;
+    }
+    a.Y = s->Y;
+    a.sh = (long)s->Bmax * s->nh;
+    a.sy = (long)s->Bmax * s->nout_p;
+    return a;
+}
+
+// forward of every member on the first Bp rows of act.X; with the
+// pre-activations and transposed activations set (training) they are kept
+// for backward
+void forward(lhmm_sur* s, int Bp, const Act& act) {
+    const bool train = act.Z1 != nullptr;
     Gemm g{};
     // layer 1: Z1 = X W1 + b1
-    g.A = s->X; g.lda = s->nin_p; g.sA = 0;
+    g.A = act.X; g.lda = s->nin_p; g.sA = 0;
     g.B = s->W1t; g.ldb = s->nin_p; g.sB = szW1(s);
     g.M = Bp; g.N = s->nh; g.K = s->nin_p;
     g.bias = s->b1; g.sBias = s->nh;
-    g.Cf = train ? s->Z1 : nullptr; g.Cb = s->H1; g.Ct = s->H1t; g.ldt = Bp; g.sC = (long)s->Bmax * s->nh;
-    g.sCt = g.sC;
+    g.Cf = train ? act.Z1 : nullptr; g.Cb = act.H1; g.Ct = act.H1t; g.ldt = Bp; g.sC = act.sh;
+    g.sCt = act.sh;
     gemm<EPI_BIAS_GELU>(s, g);
     // layer 2
-    g.A = s->H1; g.lda = s->nh; g.sA = (long)s->Bmax * s->nh;
+    g.A = act.H1; g.lda = s->nh; g.sA = act.sh;
     g.B = s->W2t; g.ldb = s->nh; g.sB = szW2(s);
     g.M = Bp; g.N = s->nh; g.K = s->nh;
     g.bias = s->b2; g.sBias = s->nh;
-    g.Cf = train ? s->Z2 : nullptr; g.Cb = s->H2; g.Ct = s->H2t; g.ldt = Bp;
+    g.Cf = train ? act.Z2 : nullptr; g.Cb = act.H2; g.Ct = act.H2t; g.ldt = Bp;
     gemm<EPI_BIAS_GELU>(s, g);
     // layer 3: Y = H2 W3 + b3
-    g.A = s->H2; g.lda = s->nh; g.sA = (long)s->Bmax * s->nh;
+    g.A = act.H2; g.lda = s->nh; g.sA = act.sh;
     g.B = s->W3t; g.ldb = s->nh; g.sB = szW3(s);
     g.M = Bp; g.N = s->nout_p; g.K = s->nh;
     g.bias = s->b3; g.sBias = s->nout_p;
-    g.Cf = s->Y; g.sC = (long)s->Bmax * s->nout_p; g.Cb = nullptr; g.Ct = nullptr;
+    g.Cf = act.Y; g.sC = act.sy; g.Cb = nullptr; g.Ct = nullptr;
     gemm<EPI_BIAS_F32>(s, g);
+}
+
+constexpr size_t SUR_SCRATCH_BYTES = size_t(32) << 20;  // see `scratch` below
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// bytes of scratch a forward pass of Bp padded rows needs
+size_t static_scratch_bytes(const lhmm_sur* s, int Bp) {
+    return align256((size_t)Bp * s->nin_p * sizeof(bf16)) + 2 * align256((size_t)s->E * Bp * s->nh * sizeof(bf16)) +
+           align256((size_t)s->E * Bp * s->nout_p * sizeof(float));
 }
 
 int check_dims(const lhmm_sur_params* p) {
@@ -514,6 +559,14 @@ int check_dims(const lhmm_sur_params* p) {
 }
 
 }  // namespace
+
+// Scratch of lhmm_sur_forward_static: the activations of one forward pass
+// (padded inputs, both hidden layers of every member, outputs) in a
+// file-scope device array instead of engine buffers.  Each device holds its
+// own copy at its own address until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns on that device (the
+// array's name on the host is a stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[SUR_SCRATCH_BYTES];
 
 hipStream_t lhmm_sur_caller_stream(const lhmm_sur* s) { return s->stream; }
 
@@ -541,6 +594,10 @@ int lhmm_sur_create(const lhmm_sur_params* p, const float* weights, void* stream
     s->nout = p->n_out;
     s->Bmax = round_up(p->max_batch, 32);
     s->stream = (hipStream_t)stream;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return lhmm_fail(LHMM_ERR_HIP, "hipGetDevice failed");
+    }
     const long E = s->E, w1 = szW1(s), w2 = szW2(s), w3 = szW3(s), nh = s->nh, no = s->nout_p;
     const long Bm = s->Bmax;
     float** f32s[] = {&s->W1, &s->gW1, &s->mW1, &s->vW1};
@@ -681,9 +738,9 @@ int lhmm_sur_get_grads(lhmm_sur* s, float* grads) {
 
 // B rows of f32 features (device, B x n_in) into the padded BF16 inputs
 // (and their transpose, for training)
-static int load_inputs(lhmm_sur* s, const float* X, int B, int Bp, bool train) {
+static int load_inputs(lhmm_sur* s, const float* X, int B, int Bp, bf16* Xp, bf16* Xt) {
     const long n = (long)Bp * s->nin_p;
-    k_inputs<<<(n + 255) / 256, 256, 0, s->stream>>>(X, B, s->nin, Bp, s->nin_p, s->X, train ? s->Xt : nullptr);
+    k_inputs<<<(n + 255) / 256, 256, 0, s->stream>>>(X, B, s->nin, Bp, s->nin_p, Xp, Xt);
     LHMM_HIPCHK(hipGetLastError());
     return LHMM_OK;
 }
@@ -695,9 +752,9 @@ int lhmm_sur_train_step(lhmm_sur* s, const float* X, const float* T, int32_t B, 
     if (!(lr >= 0.0f) || !std::isfinite(lr)) return lhmm_fail(LHMM_ERR_ARG, "bad learning rate");
     const int Bp = round_up(B, 32), E = s->E, nh = s->nh, no = s->nout_p;
     const long Bm = s->Bmax;
-    int rc = load_inputs(s, X, B, Bp, true);
+    int rc = load_inputs(s, X, B, Bp, s->X, s->Xt);
     if (rc != LHMM_OK) return rc;
-    forward(s, Bp, true);
+    forward(s, Bp, engine_act(s, true));
     // dY and loss
     const long nY = (long)Bp * no;
     const int nparts = (int)((nY + 255) / 256);
@@ -770,11 +827,59 @@ int lhmm_sur_forward(lhmm_sur* s, const float* X, int32_t B, float* Y) {
     if (!s || !X || !Y) return lhmm_fail(LHMM_ERR_ARG, "null argument");
     if (B < 1 || B > s->Bmax) return lhmm_fail(LHMM_ERR_ARG, "batch %d outside 1..%d", B, s->Bmax);
     const int Bp = round_up(B, 32);
-    int rc = load_inputs(s, X, B, Bp, false);
+    int rc = load_inputs(s, X, B, Bp, s->X, nullptr);
     if (rc != LHMM_OK) return rc;
-    forward(s, Bp, false);
+    const Act act = engine_act(s, false);
+    forward(s, Bp, act);
     const long n = (long)s->E * B * s->nout;
-    k_outputs<<<(n + 255) / 256, 256, 0, s->stream>>>(s->Y, (long)s->Bmax * s->nout_p, s->nout_p, s->E, B, s->nout, Y);
+    k_outputs<<<(n + 255) / 256, 256, 0, s->stream>>>(act.Y, act.sy, s->nout_p, s->E, B, s->nout, Y);
+    LHMM_HIPCHK(hipGetLastError());
+    return LHMM_OK;
+}
+
+int lhmm_sur_forward_static(lhmm_sur* s, const float* X, int32_t B, float* Y) {
+    lhmm_clear_error();
+    if (!s || !X || !Y) return lhmm_fail(LHMM_ERR_ARG, "null argument");
+    if (B < 1) return lhmm_fail(LHMM_ERR_ARG, "batch %d must be positive", B);
+    const int Bp = round_up(B, 32);
+    const size_t need = static_scratch_bytes(s, Bp);
+    if (need > SUR_SCRATCH_BYTES)
+        return lhmm_fail(LHMM_ERR_ARG, "batch %d needs %zu bytes of scratch, more than the %zu this entry point holds",
+                         B, need, SUR_SCRATCH_BYTES);
+    int dev = -1;
+    LHMM_HIPCHK(hipGetDevice(&dev));
+    if (dev != s->device) return lhmm_fail(LHMM_ERR_ARG, "call with the engine's device %d current (got %d)", s->device, dev);
+    if (dev < 0 || dev >= MAX_DEVICES) return lhmm_fail(LHMM_ERR_ARG, "device %d beyond the %d supported", dev, MAX_DEVICES);
+    unsigned char* base = nullptr;
+    {
+        // the scratch's device address, looked up once per device (with that device current)
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* ptr = nullptr;
+            LHMM_HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return lhmm_fail(LHMM_ERR_HIP, "hipGetSymbolAddress returned no address");
+            g_scratch_ptr[dev] = ptr;
+        }
+        base = (unsigned char*)g_scratch_ptr[dev];
+    }
+    Act act{};
+    size_t off = 0;
+    act.X = (bf16*)(base + off);
+    off += align256((size_t)Bp * s->nin_p * sizeof(bf16));
+    act.H1 = (bf16*)(base + off);
+    off += align256((size_t)s->E * Bp * s->nh * sizeof(bf16));
+    act.H2 = (bf16*)(base + off);
+    off += align256((size_t)s->E * Bp * s->nh * sizeof(bf16));
+    act.Y = (float*)(base + off);
+    act.sh = (long)Bp * s->nh;
+    act.sy = (long)Bp * s->nout_p;
+    // every scratch word the pass reads is written by it first (inputs and
+    // their zero padding, then each layer), so nothing needs clearing
+    int rc = load_inputs(s, X, B, Bp, act.X, nullptr);
+    if (rc != LHMM_OK) return rc;
+    forward(s, Bp, act);
+    const long n = (long)s->E * B * s->nout;
+    k_outputs<<<(n + 255) / 256, 256, 0, s->stream>>>(act.Y, act.sy, s->nout_p, s->E, B, s->nout, Y);
     LHMM_HIPCHK(hipGetLastError());
     return LHMM_OK;
 }

@@ -124,6 +124,18 @@ class Surrogate:
             check(lib().lhmm_sur_forward(self._h, self._dev(X, self.n_in, "X"), B, C.c_void_p(out.data_ptr())))
         return out
 
+    def forward_static(self, X, out):
+        """As forward, through the entry point that allocates nothing (its
+        activations live in the library's static device scratch); out is the
+        caller's (E, B, n_out) cuda float32 tensor."""
+        B = X.shape[0]
+        if out.dtype != self._torch.float32 or not out.is_contiguous() or out.numel() != self.E * B * self.n_out:
+            raise ValueError("out must be contiguous cuda float32 of E x B x n_out")
+        with self._torch.cuda.stream(self.stream):
+            check(lib().lhmm_sur_forward_static(self._h, self._dev(X, self.n_in, "X"), B,
+                                                C.c_void_p(out.data_ptr())))
+        return out
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             check(lib().lhmm_sur_destroy(self._h))
