@@ -10,8 +10,11 @@ from .oracle import (  # noqa: F401
     ERR_CELL,
     ERR_NONFINITE,
     OracleBox,
+    afbc_noise,
+    afbc_region,
     build,
     check_gradient,
+    core_fraction,
     expL,
     forces,
     lib,
@@ -21,6 +24,7 @@ from .oracle import (  # noqa: F401
     reduce_cell,
     run_batch,
     run_box,
+    run_box_afbc,
     sph_accel,
     sph_density,
     sph_F,

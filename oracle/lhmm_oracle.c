@@ -21,8 +21,11 @@
  *     uniform weight over the whole periodic cell the bond function equals
  *     1/V and the Irving-Kirkwood stress is the cell's virial stress;
  *   - imposed flow: Sec. "Macro-to-Micro Coupling", Eq. (micro_bc) imposes
- *     v = L r.  Here it is imposed homogeneously: the periodic cell deforms
- *     with dh/dt = L h and particles carry peculiar velocities c = v - L r.
+ *     v = L r.  Two forms: homogeneously, the periodic cell deforming with
+ *     dh/dt = L h and particles carrying peculiar velocities c = v - L r
+ *     (oracle_run_box); or, as the paper's micro-domain does (Tab. 2), on
+ *     the boundary-condition ring of a fixed cell only, with the stress
+ *     sampled over the core (oracle_run_box_afbc).
  *
  * Readings taken where the paper is silent or garbled:
  *   - the discrete random force carries 1/sqrt(dt);
@@ -35,7 +38,21 @@
  *   - a bond reaching r >= R0 raises a sticky BOND flag and its denominator
  *     is clamped at 0.01;
  *   - the in-plane cell basis is kept Lagrange-Gauss reduced; a perpendicular
- *     width below 3 rc raises a sticky CELL flag.
+ *     width below 3 rc raises a sticky CELL flag;
+ *   - boundary regions: a particle's position r' is taken relative to the
+ *     cell's centre (the domain's mean velocity is removed, so its centre of
+ *     mass stays there); the regions are squares in the plane; on the
+ *     boundary-condition ring the in-plane velocity relaxes, after each half
+ *     kick, toward the imposed field of Eq. (micro_bc) at rate zeta with the
+ *     matching thermal noise (an Ornstein-Uhlenbeck step), so the ring's mean
+ *     flow is v' = G r' while its particles keep kBT and feel the forces (a
+ *     velocity overwritten with G r' would freeze the ring's particles in
+ *     place and let it absorb the core's); the noise is a Box-Muller pair
+ *     from Philox4x32-10 with counter (id, 0xFFFFFFF0 + half kick, step,
+ *     box); the weight of the Irving-Kirkwood stress is uniform over the
+ *     core and zero outside, so the kinetic part sums the core's particles
+ *     (velocity relative to the imposed field) and a pair's bond function
+ *     is the fraction of its segment inside the core over the core's volume.
  */
 #include <math.h>
 #include <stdint.h>
@@ -384,14 +401,27 @@ long oracle_pairs(int N, const double *s, const double h[9], double rc, int mode
 /* Forces and virial                                                      */
 /* --------------------------------------------------------------------- */
 
+double oracle_core_fraction(const double a[2], const double b[2], double hc);
+
+/* in-plane position of fractional coordinate s relative to the cell centre */
+static void centred(const double h[9], const double *s, double out[2])
+{
+    out[0] = h[0] * (s[0] - 0.5) + h[1] * (s[1] - 0.5);
+    out[1] = h[3] * (s[0] - 0.5) + h[4] * (s[1] - 0.5);
+}
+
 /* F (N x 3) and the virial sum_pairs d (x) f of each part:
  * W[0] conservative, W[1] dissipative, W[2] random, W[3] FENE (6 comps each).
  * Particles 0 .. n_chains*chain_len-1 form chains of chain_len consecutive
  * ids; the rest are solvent.  mode: 0 brute force, 1 cell grid (falls back
- * to brute force when the grid has fewer than 3 cells along an axis). */
-int oracle_forces(const double *P, uint64_t seed, int chain_len, uint32_t box, int N, int n_chains,
-                  const double *s, const double *c, const double h[9], const double L[9], uint32_t step,
-                  double *F, double W[24], uint32_t *err, int mode, long long *npairs)
+ * to brute force when the grid has fewer than 3 cells along an axis).
+ * hc >= 0: each pair's (and bond's) virial term is weighted by the
+ * fraction of its segment inside the core |x'|, |y'| <= hc (positions
+ * relative to the cell centre), the bond function of Eq. (potential_stress)
+ * for a weight uniform over the core, times the core's volume. */
+static int forces_impl(const double *P, uint64_t seed, int chain_len, uint32_t box, int N, int n_chains,
+                       const double *s, const double *c, const double h[9], const double L[9], uint32_t step,
+                       double *F, double W[24], uint32_t *err, int mode, long long *npairs, double hc)
 {
     const double a = P[P_A], gamma = P[P_GAMMA], sigma = P[P_SIGMA], rc = P[P_RC], dt = P[P_DT];
     const double Hf = P[P_H], R0 = P[P_R0];
@@ -424,13 +454,21 @@ int oracle_forces(const double *P, uint64_t seed, int chain_len, uint32_t box, i
         mag[0] = a * wR;                  /* conservative */
         mag[1] = -gamma * wD * ev;        /* dissipative  */
         mag[2] = sigma * wR * th * rdt;   /* random       */
+        double wgt = 1.0;
+        if (hc >= 0.0) {
+            double ri[2], rj[2];
+            centred(h, &s[3 * i], ri);
+            rj[0] = ri[0] - d[0];
+            rj[1] = ri[1] - d[1];
+            wgt = oracle_core_fraction(ri, rj, hc);
+        }
         for (int part = 0; part < 3; ++part) {
             double f[3] = {mag[part] * e[0], mag[part] * e[1], mag[part] * e[2]};
             for (int k = 0; k < 3; ++k) {
                 F[3 * i + k] += f[k];
                 F[3 * j + k] -= f[k];
             }
-            for (int q6 = 0; q6 < 6; ++q6) W[6 * part + q6] += d[SI[q6]] * f[SJ[q6]];
+            for (int q6 = 0; q6 < 6; ++q6) W[6 * part + q6] += wgt * d[SI[q6]] * f[SJ[q6]];
         }
     }
     free(pl.p);
@@ -463,10 +501,26 @@ int oracle_forces(const double *P, uint64_t seed, int chain_len, uint32_t box, i
                 F[3 * i + k] += f[k];
                 F[3 * j + k] -= f[k];
             }
-            for (int q6 = 0; q6 < 6; ++q6) W[18 + q6] += best[SI[q6]] * f[SJ[q6]];
+            double wgt = 1.0;
+            if (hc >= 0.0) {
+                double ri[2], rj[2];
+                centred(h, &s[3 * i], ri);
+                rj[0] = ri[0] - best[0];
+                rj[1] = ri[1] - best[1];
+                wgt = oracle_core_fraction(ri, rj, hc);
+            }
+            for (int q6 = 0; q6 < 6; ++q6) W[18 + q6] += wgt * best[SI[q6]] * f[SJ[q6]];
         }
     return 0;
 }
+
+int oracle_forces(const double *P, uint64_t seed, int chain_len, uint32_t box, int N, int n_chains,
+                  const double *s, const double *c, const double h[9], const double L[9], uint32_t step,
+                  double *F, double W[24], uint32_t *err, int mode, long long *npairs)
+{
+    return forces_impl(P, seed, chain_len, box, N, n_chains, s, c, h, L, step, F, W, err, mode, npairs, -1.0);
+}
+
 
 /* --------------------------------------------------------------------- */
 /* Time stepping                                                          */
@@ -607,6 +661,168 @@ int oracle_run_batch(const double *P, uint64_t seed, int chain_len, int n_boxes,
         if (rc != 0) status = 1;
     }
     return status ? -1 : 0;
+}
+
+/* --------------------------------------------------------------------- */
+/* Micro-domain with adaptive boundary regions                           */
+/* --------------------------------------------------------------------- */
+
+/* The micro-domain of Sec. "Macro-to-Micro Coupling" and Tab. 2: a periodic
+ * cell split, by the in-plane position r' of a particle relative to the
+ * cell's centre, into the core |x'|, |y'| < hc, the boundary-condition ring
+ * hc <= max(|x'|, |y'|) < hb and the buffer outside it.  The cell itself
+ * does not deform; in the boundary-condition ring every particle's
+ * velocity is the imposed field of Eq. (micro_bc), v' = G r' (G = lambda*
+ * (grad v)^T, u = G r); the core and the buffer move freely.  The stress is
+ * the Irving-Kirkwood stress of Eqs. (IKtotal), (kinetic_stress),
+ * (potential_stress) with a weight uniform over the core and zero outside:
+ * the kinetic part sums the core's particles with their velocity relative to
+ * the imposed field, and the bond function of a pair (or bond) is the
+ * fraction of the segment joining the two particles that lies inside the
+ * core, over the core's volume. */
+
+/* region of an in-plane position relative to the cell centre: 0 core,
+ * 1 boundary-condition ring, 2 buffer */
+int oracle_afbc_region(double x, double y, double hc, double hb)
+{
+    double m = fmax(fabs(x), fabs(y));
+    return m < hc ? 0 : (m < hb ? 1 : 2);
+}
+
+/* Fraction of the segment from a to b (in-plane) inside the square
+ * |x|, |y| <= hc: the bond function of a uniform core weight times the
+ * core's volume.  Parametrise p(t) = a + t (b - a), t in [0, 1], and keep
+ * the t where both coordinates are within the square. */
+double oracle_core_fraction(const double a[2], const double b[2], double hc)
+{
+    double t0 = 0.0, t1 = 1.0;
+    for (int k = 0; k < 2; ++k) {
+        double dk = b[k] - a[k];
+        if (dk == 0.0) {
+            if (a[k] < -hc || a[k] > hc) return 0.0;
+            continue;
+        }
+        double ta = (-hc - a[k]) / dk, tb = (hc - a[k]) / dk;
+        if (ta > tb) {
+            double x = ta;
+            ta = tb;
+            tb = x;
+        }
+        if (ta > t0) t0 = ta;
+        if (tb < t1) t1 = tb;
+    }
+    return t1 > t0 ? t1 - t0 : 0.0;
+}
+
+/* the pair of standard normals (Box-Muller, cosine and sine branches) that
+ * particle id draws at half kick `half` of the step ending at `step` */
+void oracle_afbc_noise(uint64_t seed, uint32_t id, uint32_t half, uint32_t step, uint32_t box, double xi[2])
+{
+    uint32_t ctr[4] = {id, 0xFFFFFFF0u + half, step, box}, key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    double r = sqrt(-2.0 * log(oracle_uniform23(out[0])));
+    xi[0] = r * cos(2.0 * M_PI * oracle_uniform23(out[1]));
+    xi[1] = r * sin(2.0 * M_PI * oracle_uniform23(out[1]));
+}
+
+/* the ring's in-plane velocities relax toward the imposed field over half a
+ * step: c <- u + (c - u) exp(-zeta dt/2) + sqrt(kBT/m (1 - exp(-zeta dt))) xi,
+ * u = G r' (an exact Ornstein-Uhlenbeck step of dc = -zeta (c - u) dt + noise) */
+static void afbc_relax(const double *P, uint64_t seed, uint32_t box, uint32_t step, uint32_t half, int N,
+                       const double *s, double *c, const double h[9], const double G[9], double hc, double hb,
+                       double zeta)
+{
+    const double dt = P[P_DT], kT = P[P_KBT], m = P[P_MASS];
+    const double damp = exp(-0.5 * zeta * dt), amp = sqrt(kT / m * (1.0 - exp(-zeta * dt)));
+    for (int i = 0; i < N; ++i) {
+        double x = h[0] * (s[3 * i] - 0.5) + h[1] * (s[3 * i + 1] - 0.5);
+        double y = h[3] * (s[3 * i] - 0.5) + h[4] * (s[3 * i + 1] - 0.5);
+        if (oracle_afbc_region(x, y, hc, hb) != 1) continue;
+        double u[2] = {G[0] * x + G[1] * y, G[3] * x + G[4] * y}, xi[2];
+        oracle_afbc_noise(seed, (uint32_t)i, half, step, box, xi);
+        for (int k = 0; k < 2; ++k) c[3 * i + k] = u[k] + (c[3 * i + k] - u[k]) * damp + amp * xi[k];
+    }
+}
+
+/* Advance one micro-domain with boundary regions (core half-width hc,
+ * boundary-condition ring out to half-width hb, relaxation rate zeta of the
+ * ring toward the imposed field) by nsteps velocity-Verlet steps under the
+ * imposed gradient G; the cell h stays fixed and c is the particles'
+ * velocity.  Each step: half kick c += dt/2 F/m, the ring's relaxation,
+ * drift s += dt h^-1 c and wrap, forces, half kick, the ring's relaxation
+ * again, then the core's stress sample
+ *   sigma = -(sum_{i in core} m dv_i (x) dv_i + sum_pairs f_frac d (x) f) / V_core,
+ * dv_i = c_i - G r'_i, f_frac the fraction of the pair's segment inside the
+ * core, V_core = (2 hc)^2 h_zz.  Outputs as oracle_run_box (mean stress,
+ * parts kinetic, conservative, dissipative, random, FENE). */
+int oracle_run_box_afbc(const double *P, uint64_t seed, int chain_len, uint32_t box, int N, int n_chains,
+                        double *s, double *c, double *F, int *fvalid, const double h[9], uint64_t *step,
+                        const double G[9], double hc, double hb, double zeta, int nsteps,
+                        double *stress_mean, double *parts_mean, uint32_t *err, int mode)
+{
+    const double m = P[P_MASS], dt = P[P_DT];
+    const double L0[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double W[24];
+    if (!oracle_check_gradient(G) || nsteps <= 0 || !(hc > 0.0) || !(hb >= hc) || !(zeta >= 0.0)) {
+        *err |= ORACLE_ERR_ARG;
+        return -1;
+    }
+    if (N > 0) {
+        double mean[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) mean[k] += c[3 * i + k];
+        for (int k = 0; k < 3; ++k) mean[k] /= N;
+        for (int i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) c[3 * i + k] -= mean[k];
+    }
+    if (!*fvalid) {
+        forces_impl(P, seed, chain_len, box, N, n_chains, s, c, h, L0, (uint32_t)*step, F, W, err, mode, NULL,
+                    -1.0);
+        *fvalid = 1;
+    }
+    double hi[9];
+    mat_inv(h, hi);
+    const double Vc = 4.0 * hc * hc * h[8];
+    double acc[30];
+    for (int k = 0; k < 30; ++k) acc[k] = 0.0;
+    for (int n = 0; n < nsteps; ++n) {
+        const uint32_t st = (uint32_t)(*step + 1);  /* the step being made */
+        for (int k = 0; k < 3 * N; ++k) c[k] += 0.5 * dt * F[k] / m;
+        afbc_relax(P, seed, box, st, 0, N, s, c, h, G, hc, hb, zeta);
+        for (int i = 0; i < N; ++i) {
+            double ds[3];
+            mat_vec(hi, &c[3 * i], ds);
+            for (int k = 0; k < 3; ++k) s[3 * i + k] += dt * ds[k];
+        }
+        for (int k = 0; k < 3 * N; ++k) wrap01(&s[k]);
+        *step += 1;
+        forces_impl(P, seed, chain_len, box, N, n_chains, s, c, h, L0, (uint32_t)*step, F, W, err, mode, NULL, hc);
+        for (int k = 0; k < 3 * N; ++k) c[k] += 0.5 * dt * F[k] / m;
+        afbc_relax(P, seed, box, st, 1, N, s, c, h, G, hc, hb, zeta);
+        double K[6] = {0, 0, 0, 0, 0, 0};
+        for (int i = 0; i < N; ++i) {
+            double x = h[0] * (s[3 * i] - 0.5) + h[1] * (s[3 * i + 1] - 0.5);
+            double y = h[3] * (s[3 * i] - 0.5) + h[4] * (s[3 * i + 1] - 0.5);
+            if (oracle_afbc_region(x, y, hc, hb) != 0) continue;
+            double dv[3] = {c[3 * i] - (G[0] * x + G[1] * y), c[3 * i + 1] - (G[3] * x + G[4] * y), c[3 * i + 2]};
+            for (int q6 = 0; q6 < 6; ++q6) K[q6] += m * dv[SI[q6]] * dv[SJ[q6]];
+        }
+        for (int q6 = 0; q6 < 6; ++q6) {
+            double tot = K[q6] + W[q6] + W[6 + q6] + W[12 + q6] + W[18 + q6];
+            if (!isfinite(tot / Vc)) *err |= ORACLE_ERR_NONFINITE;
+            acc[q6] += -K[q6] / Vc;
+            for (int part = 0; part < 4; ++part) acc[6 * (part + 1) + q6] += -W[6 * part + q6] / Vc;
+        }
+    }
+    for (int q6 = 0; q6 < 6; ++q6) {
+        double tot = 0.0;
+        for (int part = 0; part < 5; ++part) tot += acc[6 * part + q6];
+        if (stress_mean) stress_mean[q6] = tot / nsteps;
+    }
+    if (parts_mean)
+        for (int k = 0; k < 30; ++k) parts_mean[k] = acc[k] / nsteps;
+    return 0;
 }
 
 int oracle_max_threads(void)

@@ -77,6 +77,15 @@ def lib():
                                        u64p, dp, C.c_int, dp, dp, up, C.c_int, C.POINTER(C.c_longlong)]
         L.oracle_run_batch.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
+        L.oracle_afbc_region.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.oracle_afbc_region.restype = C.c_int
+        L.oracle_core_fraction.argtypes = [dp, dp, C.c_double]
+        L.oracle_core_fraction.restype = C.c_double
+        L.oracle_run_box_afbc.argtypes = [dp, C.c_uint64, C.c_int, C.c_uint32, C.c_int, C.c_int, dp, dp, dp,
+                                          ip, dp, u64p, dp, C.c_double, C.c_double, C.c_double, C.c_int, dp, dp,
+                                          up, C.c_int]
+        L.oracle_afbc_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp]
+        L.oracle_run_box_afbc.restype = C.c_int
         L.oracle_sph_W.argtypes = [C.c_double, C.c_double, C.c_int]
         L.oracle_sph_W.restype = C.c_double
         L.oracle_sph_F.argtypes = [C.c_double, C.c_double, C.c_int]
@@ -272,6 +281,49 @@ def run_batch(p, seed, chain_len, boxes, Ls, nsteps, mode=1, count_pairs=False):
     if count_pairs:
         return mean, parts.reshape(B, 5, 6), npairs
     return mean, parts.reshape(B, 5, 6)
+
+
+def afbc_region(x: float, y: float, hc: float, hb: float) -> int:
+    """0 core, 1 boundary-condition ring, 2 buffer (position relative to the cell centre)."""
+    return int(lib().oracle_afbc_region(float(x), float(y), float(hc), float(hb)))
+
+
+def core_fraction(a, b, hc: float) -> float:
+    """Fraction of the in-plane segment a -> b inside the square |x|, |y| <= hc."""
+    return float(lib().oracle_core_fraction(_d(_f64(a, (2,)).copy()), _d(_f64(b, (2,)).copy()), float(hc)))
+
+
+def afbc_noise(seed: int, i: int, half: int, step: int, box: int):
+    """The two normals particle i of the ring draws at a half kick."""
+    xi = np.zeros(2)
+    lib().oracle_afbc_noise(int(seed), int(i), int(half), int(step), int(box), _d(xi))
+    return xi
+
+
+def run_box_afbc(p, seed, chain_len, box: OracleBox, G, hc: float, hb: float, nsteps: int, zeta: float = 10.0,
+                 mode=1):
+    """Advance a micro-domain with boundary regions in place (fixed cell
+    box.h; on the ring hc <= max(|x'|, |y'|) < hb the in-plane velocity
+    relaxes toward the imposed field G r' at rate zeta with thermal noise;
+    core stress); returns (mean stress (6,), parts (5, 6))."""
+    P = params_vector(p)
+    N = box.s.shape[0]
+    fv = np.array([box.fvalid], dtype=np.int32)
+    st = np.array([box.step], dtype=np.uint64)
+    err = np.array([box.err], dtype=np.uint32)
+    h = box.h.reshape(9).copy()
+    mean = np.zeros(6)
+    parts = np.zeros(30)
+    rc = lib().oracle_run_box_afbc(_d(P), int(seed), int(chain_len), int(box.box_id), N, int(box.n_chains),
+                                   _d(box.s), _d(box.c), _d(box.F), _i(fv), _d(h), _u64(st), _d(_f64(G, (9,))),
+                                   float(hc), float(hb), float(zeta), int(nsteps), _d(mean), _d(parts), _u(err),
+                                   int(mode))
+    box.fvalid = int(fv[0])
+    box.step = int(st[0])
+    box.err = int(err[0])
+    if rc != 0:
+        raise ValueError("oracle_run_box_afbc rejected its arguments (error bits %d)" % box.err)
+    return mean, parts.reshape(5, 6)
 
 
 def max_threads() -> int:
