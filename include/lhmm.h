@@ -255,6 +255,29 @@ int lhmm_micro_get_config(lhmm_micro* m, lhmm_micro_config* cfg);
 int lhmm_micro_autotune(lhmm_micro* m, const double* gradL, int32_t trial_steps, lhmm_micro_config* best,
                         double* best_ms);
 
+/* Turn listed boxes into micro-domains with boundary regions (Sec.
+ * "Macro-to-Micro Coupling", Tab. 2: core, boundary-condition region,
+ * buffer).  regions: HOST n_boxes x 2 doubles (hc, hb) per box; (0, 0)
+ * leaves a box as it is.  For a box with 0 < hc <= hb, a particle's in-plane
+ * position r' relative to the cell's centre puts it in the core
+ * (max(|x'|, |y'|) < hc), the boundary-condition ring (hc <= .. < hb) or the
+ * buffer (beyond); hb may not exceed half the cell's in-plane width.  Such a
+ * box's cell no longer deforms: the gradient of each later step call is the
+ * imposed field G of Eq. (micro_bc), v' = G r', toward which the ring's
+ * in-plane velocities relax after each half kick,
+ *   c <- u + (c - u) exp(-zeta dt/2) + sqrt(kBT/m (1 - exp(-zeta dt))) xi,
+ * u = G r' (an exact Ornstein-Uhlenbeck step; xi a normal pair of the
+ * random stream at counter (id, 0xFFFFFFF0 + half kick, step, box)); the
+ * core and the buffer move freely (the buffer is the reservoir between the
+ * ring and its periodic images).  Its stress is the Irving-Kirkwood stress
+ * of the core (Eqs. IKtotal, kinetic_stress, potential_stress with a weight
+ * uniform over the core): the kinetic part over the core's particles with
+ * their velocity relative to G r', each pair's and bond's d (x) f weighted by
+ * the fraction of its segment inside the core, over the core's volume
+ * (2 hc)^2 h_zz.  zeta >= 0 is shared by the engine's boxes.  Synchronous;
+ * drops captured graphs.  Errors: ARG, HIP. */
+int lhmm_micro_set_afbc(lhmm_micro* m, const double* regions, double zeta);
+
 /* Keep a device copy of the current state of every box (positions,
  * velocities, forces, cell).  Ordered on the caller's stream.  Errors:
  * STATE (no state loaded), OOM, HIP. */

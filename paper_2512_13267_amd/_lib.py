@@ -39,6 +39,7 @@ EXPORTS = (
     "lhmm_micro_step_subset", "lhmm_micro_snapshot", "lhmm_micro_restore",
     "lhmm_micro_set_config", "lhmm_micro_get_config", "lhmm_micro_autotune",
     "lhmm_micro_components", "lhmm_micro_pair_total", "lhmm_micro_prepare", "lhmm_box_cell",
+    "lhmm_micro_set_afbc",
     "lhmm_sph_create", "lhmm_sph_step", "lhmm_sph_get_state", "lhmm_sph_coupling_state", "lhmm_couple_step",
     "lhmm_sph_destroy",
     "lhmm_sur_create", "lhmm_sur_set_weights", "lhmm_sur_get_weights", "lhmm_sur_get_grads", "lhmm_sur_train_step", "lhmm_sur_forward",
@@ -130,6 +131,7 @@ def lib():
         L.lhmm_micro_pair_total.argtypes = [vp, u64p]
         L.lhmm_micro_components.argtypes = [vp, dp]
         L.lhmm_micro_prepare.argtypes = [vp, C.c_int32]
+        L.lhmm_micro_set_afbc.argtypes = [vp, dp, C.c_double]
         L.lhmm_box_cell.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, C.POINTER(C.c_int32)]
         L.lhmm_micro_flags.argtypes = [vp, C.POINTER(C.c_uint32), C.c_int32]
         L.lhmm_micro_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]

@@ -23,6 +23,13 @@
 //   k_box_stress   one wave per box: virial stress of the step (Eqs.
 //                  IKtotal, kinetic_stress, potential_stress with a uniform
 //                  weight over the cell), accumulated over the call.
+// A box may instead be a micro-domain with boundary regions (Sec.
+// "Macro-to-Micro Coupling", Tab. 2): its cell stays fixed, the particles of
+// the boundary-condition ring relax toward the imposed field v' = G r' of
+// Eq. micro_bc after each half kick (an Ornstein-Uhlenbeck step with thermal
+// noise), and its stress is the Irving-Kirkwood stress of the core (kinetic
+// part over the core's particles relative to the imposed field, each pair's
+// virial weighted by the fraction of its segment inside the core).
 // The per-particle kernels run over work blocks of BS particles; a block
 // never straddles two boxes, so per-box quantities are uniform in a block
 // and reductions stay deterministic.  The step loop is captured in HIP
@@ -48,7 +55,7 @@ namespace {
 
 constexpr int BS = 256;                 // particles per work block
 constexpr int BIN_THREADS_MAX = 1024;   // largest binning workgroup (256, 512 or 1024 threads)
-constexpr int MAX_CELLS_PER_BOX = 15360;  // binning LDS: cell starts and three per-column offsets (120 KiB)
+constexpr int MAX_CELLS_PER_BOX = 17424;  // binning LDS: cell starts and three per-column offsets (136 KiB)
 constexpr int GRAPH_CHUNK = 50;         // default steps per captured graph
 constexpr int MAX_GROUPS = 4;           // overlapped box groups of a captured step
 constexpr int ACC = 36;                 // per-box stress sums: kinetic, pair, FENE, C, D, R (6 each)
@@ -94,6 +101,11 @@ struct BoxDyn {  // per-box FP64 state, rewritten every step
     int U[4];       // in-plane reduction of this step, h_new = h U
     int nc[3];      // cell grid of this step
     int changed;
+    // boundary regions (hc > 0): core |x'|, |y'| < hc, ring hc <= max(|x'|, |y'|)
+    // < hb, positions relative to the cell centre; G: the imposed in-plane
+    // gradient (xx, xy, yx, yy), while the cell's own L stays zero
+    double hc, hb;
+    double G[4];
 };
 
 struct Ctx {
@@ -137,6 +149,7 @@ struct Ctx {
     unsigned long long* tot_pairs;  // n_boxes, every step since the engine was created
     unsigned long long* step;       // completed steps
     double a, gamma, sigma, rdt, dt, mass, inv_mass, rc, rc2, H, inv_R02;
+    double ou_damp, ou_amp;  // ring relaxation over half a step: exp(-zeta dt/2), sqrt(kBT/m (1 - exp(-zeta dt)))
     unsigned key0, key1;
 };
 
@@ -181,6 +194,28 @@ __device__ __forceinline__ double box_muller<double>(unsigned w0, unsigned w1) {
     const double u0 = ((double)(w0 >> 9) + 0.5) * 1.1920928955078125e-07;
     const double u1 = ((double)(w1 >> 9) + 0.5) * 1.1920928955078125e-07;
     return sqrt(-2.0 * log(u0)) * cos(2.0 * M_PI * u1);
+}
+
+// both Box-Muller normals (cosine and sine branches) of two output words
+template <typename real>
+__device__ __forceinline__ void box_muller2(unsigned w0, unsigned w1, real& x, real& y);
+
+template <>
+__device__ __forceinline__ void box_muller2<float>(unsigned w0, unsigned w1, float& x, float& y) {
+    const float u0 = ((float)(w0 >> 9) + 0.5f) * 1.1920928955078125e-07f;
+    const float u1 = ((float)(w1 >> 9) + 0.5f) * 1.1920928955078125e-07f;
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+    x = r * __builtin_amdgcn_cosf(u1);
+    y = r * __builtin_amdgcn_sinf(u1);
+}
+
+template <>
+__device__ __forceinline__ void box_muller2<double>(unsigned w0, unsigned w1, double& x, double& y) {
+    const double u0 = ((double)(w0 >> 9) + 0.5) * 1.1920928955078125e-07;
+    const double u1 = ((double)(w1 >> 9) + 0.5) * 1.1920928955078125e-07;
+    const double r = sqrt(-2.0 * log(u0));
+    x = r * cos(2.0 * M_PI * u1);
+    y = r * sin(2.0 * M_PI * u1);
 }
 
 template <typename real>
@@ -371,6 +406,10 @@ __global__ void k_setup_call(Ctx C, const double* __restrict__ gradL) {
         for (int k = 0; k < 9; ++k) L[k] = 0.0;
         C.flags[b] |= LHMM_FLAG_ARG;
     }
+    if (D.hc > 0.0) {  // boundary regions: the gradient drives the ring, the cell stays fixed
+        D.G[0] = L[0]; D.G[1] = L[1]; D.G[2] = L[3]; D.G[3] = L[4];
+        for (int k = 0; k < 9; ++k) L[k] = 0.0;
+    }
     for (int k = 0; k < 9; ++k) D.L[k] = L[k];
     expm_planar(L, C.dt, D.E);
     expm_planar(L, 0.5 * C.dt, D.Eh);
@@ -435,7 +474,8 @@ __device__ void cell_step_box(const Ctx& C, int b, int advance) {
     }
     for (int k = 0; k < 4; ++k) D.U[k] = U[k];
     D.changed = changed;
-    D.vol = fabs(m3_det(h));
+    // the stress is averaged over the core of a boundary-region box
+    D.vol = D.hc > 0.0 ? 4.0 * D.hc * D.hc * h[8] : fabs(m3_det(h));
     double w[3];
     m3_widths(h, w);
     int nc[3];
@@ -486,13 +526,38 @@ __device__ __forceinline__ real wrap01(real x) {
     return x >= (real)1 ? (real)0 : x;
 }
 
+// The ring of a boundary-region box (Eq. micro_bc): a particle at in-plane
+// position (x, y) relative to the cell centre with hc <= max(|x|, |y|) < hb
+// has its in-plane velocity relaxed toward the imposed field u = G r' over
+// half a step, c <- u + (c - u) damp + amp xi, with the normal pair xi of
+// Philox4x32-10 at counter (id, 0xFFFFFFF0 + half, step, box).
+template <typename real>
+__device__ __forceinline__ void ring_relax(real x, real y, real hc, real hb, const real (&G)[4], real damp, real amp,
+                                           unsigned id, unsigned half, unsigned step, unsigned box, unsigned k0,
+                                           unsigned k1, real& c0, real& c1) {
+    const real mx = fmax(fabs(x), fabs(y));
+    if (!(mx >= hc && mx < hb)) return;
+    unsigned x0 = id, x1 = 0xFFFFFFF0u + half, x2 = step, x3 = box;
+    philox4x32_10(x0, x1, x2, x3, k0, k1);
+    real n0, n1;
+    box_muller2<real>(x0, x1, n0, n1);
+    const real u0 = G[0] * x + G[1] * y, u1 = G[2] * x + G[3] * y;
+    c0 = u0 + (c0 - u0) * damp + amp * n0;
+    c1 = u1 + (c1 - u1) * damp + amp * n1;
+}
+
 // A box's step constants for the half kick and drift, read once into
 // registers (the per-particle stores could otherwise force reloads).
 template <typename real>
 struct KickDrift {
     real hdt, im, dt, L0, L1, L3, L4, M[9];
     int changed, U[4], nc[3];
-    __device__ explicit KickDrift(const Ctx& C, const BoxDyn& D) {
+    // boundary regions: half-widths, imposed gradient, the cell's in-plane
+    // basis and random-stream words of the first half kick
+    bool afbc;
+    real hc, hb, G[4], h00, h01, h10, h11, damp, amp;
+    unsigned step, box, k0, k1;
+    __device__ explicit KickDrift(const Ctx& C, const BoxDyn& D, unsigned box_rng = 0) {
         hdt = (real)(0.5 * C.dt);
         im = (real)C.inv_mass;
         dt = (real)C.dt;
@@ -501,18 +566,31 @@ struct KickDrift {
         changed = D.changed;
         for (int k = 0; k < 4; ++k) U[k] = D.U[k];
         for (int k = 0; k < 3; ++k) nc[k] = D.nc[k];
+        afbc = D.hc > 0.0;
+        hc = (real)D.hc; hb = (real)D.hb;
+        for (int k = 0; k < 4; ++k) G[k] = (real)D.G[k];
+        h00 = (real)D.h[0]; h01 = (real)D.h[1]; h10 = (real)D.h[3]; h11 = (real)D.h[4];
+        damp = (real)C.ou_damp; amp = (real)C.ou_amp;
+        step = (unsigned)(*C.step + 1ull);  // the step being made
+        box = box_rng; k0 = C.key0; k1 = C.key1;
     }
 };
 
 // Half kick c += dt/2 (F/m - L c), drift of the fractional coordinate with
 // the mid-step cell, remap after a reduction, wrap (in registers).
 template <typename real>
-__device__ __forceinline__ void kick_drift(const KickDrift<real>& K, real (&sv)[3], real (&cv)[3], const real (&fv)[3]) {
+__device__ __forceinline__ void kick_drift(const KickDrift<real>& K, real (&sv)[3], real (&cv)[3], const real (&fv)[3],
+                                           int id) {
     // in-plane L: (L c)_z = 0
     const real lc0 = K.L0 * cv[0] + K.L1 * cv[1], lc1 = K.L3 * cv[0] + K.L4 * cv[1];
     cv[0] += K.hdt * (fv[0] * K.im - lc0);
     cv[1] += K.hdt * (fv[1] * K.im - lc1);
     cv[2] += K.hdt * (fv[2] * K.im);
+    if (K.afbc) {
+        const real x = K.h00 * (sv[0] - (real)0.5) + K.h01 * (sv[1] - (real)0.5);
+        const real y = K.h10 * (sv[0] - (real)0.5) + K.h11 * (sv[1] - (real)0.5);
+        ring_relax<real>(x, y, K.hc, K.hb, K.G, K.damp, K.amp, (unsigned)id, 0u, K.step, K.box, K.k0, K.k1, cv[0], cv[1]);
+    }
     real s0 = sv[0] + K.dt * (K.M[0] * cv[0] + K.M[1] * cv[1] + K.M[2] * cv[2]);
     real s1 = sv[1] + K.dt * (K.M[3] * cv[0] + K.M[4] * cv[1] + K.M[5] * cv[2]);
     const real s2 = sv[2] + K.dt * (K.M[6] * cv[0] + K.M[7] * cv[1] + K.M[8] * cv[2]);
@@ -527,7 +605,7 @@ __device__ __forceinline__ void kick_drift(const KickDrift<real>& K, real (&sv)[
 // Half kick and drift of particle i (advance = 1) and its cell; returns the
 // cell (stored to pcell when store_cell is set).
 template <typename real>
-__device__ __forceinline__ int kick_drift_particle(const Ctx& C, const KickDrift<real>& K, int i, int advance,
+__device__ __forceinline__ int kick_drift_particle(const Ctx& C, const KickDrift<real>& K, int i, int local, int advance,
                                                    bool store_cell = true) {
     const int N = C.n_total;
     real* s = (real*)C.s;
@@ -537,7 +615,7 @@ __device__ __forceinline__ int kick_drift_particle(const Ctx& C, const KickDrift
     if (advance) {
         real cv[3] = {c[i], c[N + i], c[2 * N + i]};
         const real fv[3] = {f[i], f[N + i], f[2 * N + i]};
-        kick_drift<real>(K, sv, cv, fv);
+        kick_drift<real>(K, sv, cv, fv, local);
         c[i] = cv[0]; c[N + i] = cv[1]; c[2 * N + i] = cv[2];
         s[i] = sv[0]; s[N + i] = sv[1]; s[2 * N + i] = sv[2];
     }
@@ -553,8 +631,8 @@ __global__ __launch_bounds__(BS) void k_kick_drift(Ctx C, int advance) {
     const BoxInfo B = C.box[b];
     const int i = C.blk_first[blk] + (int)threadIdx.x;
     if (i >= B.off + B.n) return;
-    const KickDrift<real> K(C, C.dyn[b]);
-    kick_drift_particle<real>(C, K, i, advance);
+    const KickDrift<real> K(C, C.dyn[b], B.rng_id);
+    kick_drift_particle<real>(C, K, i, i - B.off, advance);
 }
 
 // Exclusive scan over k in [0, n) of val(k) by a workgroup of BT threads:
@@ -647,7 +725,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     int mycell[KEEP];
     const bool keep = B.n <= lds_parts && B.n <= KEEP * BIN_THREADS;
     if (fuse >= 0) {
-        const KickDrift<real> K(C, D);
+        const KickDrift<real> K(C, D, B.rng_id);
         real* s = (real*)C.s;
         real* c = (real*)C.c;
         const real* f = (const real*)C.f;
@@ -676,7 +754,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
                 cell[u] = -1;
                 if (k < B.n) {
                     if (fuse) {
-                        kick_drift<real>(K, sv[u], cv[u], fv[u]);
+                        kick_drift<real>(K, sv[u], cv[u], fv[u], k);
                         for (int a = 0; a < 3; ++a) {
                             c[a * N + i] = cv[u][a];
                             s[a * N + i] = sv[u][a];
@@ -693,7 +771,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
             }
         }
         for (int k = (int)threadIdx.x + KEEP * BIN_THREADS; k < B.n; k += BIN_THREADS)
-            atomicAdd(&cnt[kick_drift_particle<real>(C, K, B.off + k, fuse)], 1);
+            atomicAdd(&cnt[kick_drift_particle<real>(C, K, B.off + k, k, fuse)], 1);
         __threadfence_block();
     } else {
 #pragma unroll
@@ -898,12 +976,41 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 // records tested per lane and search iteration for a queue of depth QD
 __host__ __device__ constexpr int scan_unroll(int qd) { return qd >= 8 ? 4 : (qd >= 4 ? 2 : 1); }
 
+// Fraction of the in-plane segment a + t e, t in [0, 1], inside the square
+// |x|, |y| <= hc (the bond function of a weight uniform over a
+// boundary-region box's core, times the core's volume).
+template <typename real>
+__device__ __forceinline__ real core_fraction(real ax, real ay, real ex, real ey, real hc) {
+    real t0 = (real)0, t1 = (real)1;
+    const real a[2] = {ax, ay}, e[2] = {ex, ey};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (e[k] == (real)0) {
+            if (a[k] < -hc || a[k] > hc) return (real)0;
+            continue;
+        }
+        real ta = (-hc - a[k]) / e[k], tb = (hc - a[k]) / e[k];
+        if (ta > tb) {
+            const real x = ta;
+            ta = tb;
+            tb = x;
+        }
+        t0 = fmax(t0, ta);
+        t1 = fmin(t1, tb);
+    }
+    return t1 > t0 ? t1 - t0 : (real)0;
+}
+
 // PRUNE selects the stencil-pruning variant; without it the float kernel
 // fits 80 VGPRs, six waves per SIMD.  COMP keeps the virials of the
 // conservative, dissipative and random forces apart as well (their sum is
 // accumulated as in the default variant), at the cost of 18 more registers.
-template <typename real, int QD, bool PRUNE, bool COMP = false>
-__global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (PRUNE ? 5 : 6)) : 1) void k_forces(
+// AF handles boxes with boundary regions: each pair's and bond's virial is
+// weighted by the fraction of its segment inside the core, and the second
+// half kick relaxes the ring toward the imposed field; the core's kinetic
+// sums use the velocity relative to that field.
+template <typename real, int QD, bool PRUNE, bool COMP = false, bool AF = false>
+__global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (AF ? 4 : (PRUNE ? 5 : 6))) : 1) void k_forces(
     Ctx C, int step_offset, int drain, int busy, int kick) {
     constexpr bool prune = PRUNE;
     constexpr int NV = COMP ? 37 : 19;  // block partial sums
@@ -949,6 +1056,10 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (PRUNE ? 5 : 6)
         cell_position<real>(own_s0, own_s1, own_s2, h00, h01, h10, h11, h22, ri0, ri1, ri2);
     }
     const real L00 = (real)D.L[0], L01 = (real)D.L[1], L10 = (real)D.L[3], L11 = (real)D.L[4];
+    // boundary regions: core half-width, the cell centre (r' = r - centre)
+    const bool afbc = AF && D.hc > 0.0;
+    const real hcr = AF ? (real)D.hc : (real)0;
+    const real cx = AF ? (real)(0.5 * (D.h[0] + D.h[1])) : (real)0, cy = AF ? (real)(0.5 * (D.h[3] + D.h[4])) : (real)0;
     const int n0 = D.nc[0], n1 = D.nc[1], n2 = D.nc[2], zs = B.zsub;
     const real dzc = h22 / (real)n2;  // cell height
     auto sqr = [](real x) { return x * x; };
@@ -1013,12 +1124,15 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (PRUNE ? 5 : 6)
             const real mag = wR * (a - gam * wR * ev + sig * th);
             const real gx = mag * ex, gy = mag * ey, gz = mag * ez;
             fx += gx; fy += gy; fz += gz;
-            w[0] += dx * gx; w[1] += dy * gy; w[2] += dz * gz;
-            w[3] += dx * gy; w[4] += dx * gz; w[5] += dy * gz;
+            // a boundary-region box weighs the pair by its segment's share of the core
+            const real wgt = afbc ? core_fraction<real>(ri0 - cx, ri1 - cy, -dx, -dy, hcr) : (real)1;
+            const real dxw = AF ? dx * wgt : dx, dyw = AF ? dy * wgt : dy, dzw = AF ? dz * wgt : dz;
+            w[0] += dxw * gx; w[1] += dyw * gy; w[2] += dzw * gz;
+            w[3] += dxw * gy; w[4] += dxw * gz; w[5] += dyw * gz;
             if constexpr (COMP) {
                 // d (x) e times each force's magnitude
                 const real mc = wR * a, md = -(wR * gam * wR * ev), mr = wR * sig * th;
-                const real de[6] = {dx * ex, dy * ey, dz * ez, dx * ey, dx * ez, dy * ez};
+                const real de[6] = {dxw * ex, dyw * ey, dzw * ez, dxw * ey, dxw * ez, dyw * ez};
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     wc[k] += mc * de[k];
@@ -1139,8 +1253,10 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (PRUNE ? 5 : 6)
                 const real gx = k * dx, gy = k * dy, gz = k * dz;
                 fx += gx; fy += gy; fz += gz;
                 if (side == 1) {  // each bond's virial once, by its lower bead
-                    wf[0] += dx * gx; wf[1] += dy * gy; wf[2] += dz * gz;
-                    wf[3] += dx * gy; wf[4] += dx * gz; wf[5] += dy * gz;
+                    const real wgt = afbc ? core_fraction<real>(ri0 - cx, ri1 - cy, -dx, -dy, hcr) : (real)1;
+                    const real dxw = AF ? dx * wgt : dx, dyw = AF ? dy * wgt : dy, dzw = AF ? dz * wgt : dz;
+                    wf[0] += dxw * gx; wf[1] += dyw * gy; wf[2] += dzw * gz;
+                    wf[3] += dxw * gy; wf[4] += dxw * gz; wf[5] += dyw * gz;
                 }
             }
         }
@@ -1169,10 +1285,24 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (PRUNE ? 5 : 6)
         c0 += hdt * (fx * im - lc0);
         c1 += hdt * (fy * im - lc1);
         c2 += hdt * (fz * im);
+        bool in_core = true;
+        real u0 = (real)0, u1 = (real)0;  // imposed field at the particle (boundary regions)
+        if (afbc) {
+            const real x = h00 * (own_s0 - (real)0.5) + h01 * (own_s1 - (real)0.5);
+            const real y = h10 * (own_s0 - (real)0.5) + h11 * (own_s1 - (real)0.5);
+            const real G[4] = {(real)D.G[0], (real)D.G[1], (real)D.G[2], (real)D.G[3]};
+            ring_relax<real>(x, y, hcr, (real)D.hb, G, (real)C.ou_damp, (real)C.ou_amp, (unsigned)own_id, 1u, stepc,
+                             B.rng_id, C.key0, C.key1, c0, c1);
+            in_core = fmax(fabs(x), fabs(y)) < hcr;
+            u0 = G[0] * x + G[1] * y;
+            u1 = G[2] * x + G[3] * y;
+        }
         c[i] = c0; c[N + i] = c1; c[2 * N + i] = c2;
-        const double mm = C.mass, x = (double)c0, y = (double)c1, z = (double)c2;
-        v[13] = mm * x * x; v[14] = mm * y * y; v[15] = mm * z * z;
-        v[16] = mm * x * y; v[17] = mm * x * z; v[18] = mm * y * z;
+        if (in_core) {
+            const double mm = C.mass, x = (double)(c0 - u0), y = (double)(c1 - u1), z = (double)c2;
+            v[13] = mm * x * x; v[14] = mm * y * y; v[15] = mm * z * z;
+            v[16] = mm * x * y; v[17] = mm * x * z; v[18] = mm * y * z;
+        }
     }
     block_sum<NV>(v, red);
     if (threadIdx.x == 0) {
@@ -1301,6 +1431,7 @@ struct lhmm_micro {
     BoxDyn* d_snap_dyn = nullptr;
     bool have_snapshot = false;
     bool have_state = false, forces_valid = false;
+    bool afbc = false;  // some box has boundary regions (lhmm_micro_set_afbc)
     std::map<int, hipGraphExec_t> graphs;
     // graphs of subset steps, keyed by (boxes, blocks, steps): a shape is
     // captured the second time it is asked for (history replays repeat it)
@@ -1340,14 +1471,18 @@ void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse,
 template <typename real>
 void launch_forces(lhmm_micro* m, const Ctx& C, int nblk, int step_offset, int kick, hipStream_t st) {
     const int drain = m->cfg.drain, busy = m->cfg.busy_lanes;
-#define LHMM_FORCES(QD)                                                                       \
-    do {                                                                                      \
-        if (C.pv_stride > 12)                                                                 \
-            k_forces<real, QD, false, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick); \
-        else if (m->cfg.prune)                                                                \
-            k_forces<real, QD, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);        \
-        else                                                                                  \
-            k_forces<real, QD, false><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);       \
+#define LHMM_FORCES(QD)                                                                              \
+    do {                                                                                             \
+        if (m->afbc && C.pv_stride > 12)                                                             \
+            k_forces<real, QD, false, true, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);  \
+        else if (m->afbc)                                                                            \
+            k_forces<real, QD, false, false, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick); \
+        else if (C.pv_stride > 12)                                                                   \
+            k_forces<real, QD, false, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);        \
+        else if (m->cfg.prune)                                                                       \
+            k_forces<real, QD, true><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);               \
+        else                                                                                         \
+            k_forces<real, QD, false><<<nblk, BS, 0, st>>>(C, step_offset, drain, busy, kick);              \
     } while (0)
     switch (m->cfg.queue_depth) {
         case 2: LHMM_FORCES(2); break;
@@ -2069,6 +2204,44 @@ int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg) {
     const bool regroup = cfg->groups != m->cfg.groups;
     m->cfg = *cfg;
     return regroup ? prepare_groups(m, cfg->groups) : LHMM_OK;
+}
+
+int lhmm_micro_set_afbc(lhmm_micro* m, const double* regions, double zeta) {
+    g_err.clear();
+    if (!m || !regions) return fail(LHMM_ERR_ARG, "null argument");
+    if (!(zeta >= 0.0) || !std::isfinite(zeta)) return fail(LHMM_ERR_ARG, "zeta must be finite and >= 0");
+    HIPCHK(hipStreamSynchronize(m->stream));
+    std::vector<BoxDyn> dyn(m->n_boxes);
+    HIPCHK(hipMemcpy(dyn.data(), m->d_dyn, m->n_boxes * sizeof(BoxDyn), hipMemcpyDeviceToHost));
+    bool any = false;
+    for (int b = 0; b < m->n_boxes; ++b) {
+        const double hc = regions[2 * b], hb = regions[2 * b + 1];
+        if (hc == 0.0 && hb == 0.0) continue;
+        double w[3];
+        m3_widths(dyn[b].h, w);
+        if (!(hc > 0.0) || !(hb >= hc) || !(hb <= 0.5 * std::min(w[0], w[1])) || !std::isfinite(hb))
+            return fail(LHMM_ERR_ARG, "box %d: need 0 < hc <= hb <= half the cell's in-plane width (%g)", b,
+                        0.5 * std::min(w[0], w[1]));
+        any = true;
+    }
+    for (int b = 0; b < m->n_boxes; ++b) {
+        dyn[b].hc = regions[2 * b];
+        dyn[b].hb = regions[2 * b + 1];
+        if (dyn[b].hc == 0.0)
+            for (int k = 0; k < 4; ++k) dyn[b].G[k] = 0.0;
+    }
+    HIPCHK(hipMemcpy(m->d_dyn, dyn.data(), m->n_boxes * sizeof(BoxDyn), hipMemcpyHostToDevice));
+    m->afbc = any;
+    const double dt = m->p.dt;
+    m->ctx.ou_damp = std::exp(-0.5 * zeta * dt);
+    m->ctx.ou_amp = std::sqrt(m->p.kBT / m->p.mass * (1.0 - std::exp(-zeta * dt)));
+    // captured graphs hold the kernel variant and the context
+    for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
+    m->graphs.clear();
+    for (auto& kv : m->sub_graphs) (void)hipGraphExecDestroy(kv.second);
+    m->sub_graphs.clear();
+    m->sub_seen.clear();
+    return LHMM_OK;
 }
 
 int lhmm_micro_get_config(lhmm_micro* m, lhmm_micro_config* cfg) {

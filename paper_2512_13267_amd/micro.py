@@ -195,6 +195,13 @@ class Micro:
         check(lib().lhmm_micro_components(self._h, _dptr(out)))
         return out
 
+    def set_afbc(self, regions, zeta: float = 10.0):
+        """Boundary regions per box: regions (n_boxes, 2) of (core half-width,
+        ring outer half-width), (0, 0) for a plain box; zeta: the ring's
+        relaxation rate toward the imposed field (lhmm_micro_set_afbc)."""
+        r = np.ascontiguousarray(regions, dtype=np.float64).reshape(self.n_boxes, 2)
+        check(lib().lhmm_micro_set_afbc(self._h, _dptr(r), float(zeta)))
+
     def prepare(self, n_steps: int):
         """Capture the graphs a step call of n_steps will replay, without stepping."""
         check(lib().lhmm_micro_prepare(self._h, int(n_steps)))
