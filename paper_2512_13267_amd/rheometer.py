@@ -20,14 +20,16 @@ total = kinetic + pair + bond parts).
 Two micro models: the engine's 3-D boxes (DPD with FENE chains at density
 3), and --planar, the paper's 2-D melt (Tab. 1 parameters, n = 4 per unit
 area, no solvent) held in the plane z = 0 of a periodic cell and sheared
-homogeneously.  The paper measures its melts in open micro-domains with
-adaptive boundary conditions; the planar sweep is the same material in a
-periodic sheared cell, so its Carreau-Yasuda parameters are compared with
+homogeneously.  With --afbc the planar melt fills the paper's own
+micro-domain instead (Tab. 2: 76 x 76, core 24, boundary-condition region
+13, buffer 13): the cell stays fixed, the shear is imposed on the
+boundary-condition ring (Eq. micro_bc) and the stress is the core's
+Irving-Kirkwood stress.  Planar Carreau-Yasuda parameters are compared with
 the paper's table (PAPER_CY).
 
-Command line: ``python -m paper_2512_13267_amd.rheometer [--planar]
+Command line: ``python -m paper_2512_13267_amd.rheometer [--planar | --afbc]
 [--rates ...] [--replicas 16] [--chain-len 10] [--edge E] [--equil 5000]
-[--steps 20000] [--out FILE]``; ``--report a.json,b.json --md FILE`` writes
+[--steps 20000] [--zeta 10] [--out FILE]``; ``--report a.json,b.json --md FILE`` writes
 a summary of earlier runs.
 """
 from __future__ import annotations
@@ -110,6 +112,10 @@ def normal_stress_and_relaxation(gdot, sigma):
 
 
 PLANAR_THICKNESS = inputs.PLANAR_THICKNESS
+# the paper's micro-domain (Tab. 2): total 76, core 24, boundary-condition
+# region 13 and buffer 13 on each side -> half-widths of the core and of the
+# ring's outer edge
+AFBC_EDGE, AFBC_CORE_HALF, AFBC_RING_HALF = 76.0, 12.0, 25.0
 
 
 def sweep_workload(rates, replicas: int = 16, chain_len: int = 10, edge: float = 10.0, density: float = 3.0,
@@ -142,11 +148,13 @@ def sweep_workload(rates, replicas: int = 16, chain_len: int = 10, edge: float =
 
 def run_sweep(rates, replicas: int = 16, chain_len: int = 10, equil: int = 5000, steps: int = 20000,
               edge: float = 10.0, seed_k: int = 60, planar: bool = False, density: float | None = None,
-              log=print) -> dict:
+              afbc=None, zeta: float = 10.0, log=print) -> dict:
     """Shear every box of the sweep for `equil` steps, then average the
     stress over `steps` more; per-rate means and standard errors.  Planar
     sweeps report the 2-D stress (force per length: the cell stress times
-    its z edge)."""
+    its z edge).  afbc = (core half-width, ring half-width): planar boxes
+    with boundary regions, the shear imposed on the ring (relaxation rate
+    zeta) and the core's stress measured."""
     import torch
 
     from . import micro
@@ -156,6 +164,10 @@ def run_sweep(rates, replicas: int = 16, chain_len: int = 10, equil: int = 5000,
         density = 4.0 if planar else 3.0
     wl = sweep_workload(rates, replicas, chain_len, edge, density=density, seed_k=seed_k, planar=planar)
     m = micro.from_workload(wl, precision="fp32")
+    if afbc is not None:
+        if not planar:
+            raise ValueError("boundary regions are for the planar melt")
+        m.set_afbc(np.tile(np.asarray(afbc, dtype=np.float64), (len(wl.boxes), 1)), zeta=zeta)
     G = torch.tensor(np.stack([b.L for b in wl.boxes]), dtype=torch.float64, device="cuda").contiguous()
     t0 = time.time()
     chunk = 1000
@@ -181,6 +193,7 @@ def run_sweep(rates, replicas: int = 16, chain_len: int = 10, equil: int = 5000,
     eta, n1, psi1, lam = normal_stress_and_relaxation(rates, mean)
     out = {"rates": rates.tolist(), "replicas": replicas, "chain_len": chain_len, "edge": edge,
            "dims": 2 if planar else 3, "density": density,
+           "afbc": None if afbc is None else {"core_half": afbc[0], "ring_half": afbc[1], "zeta": zeta},
            "equil_steps": equil, "avg_steps": steps, "dt": wl.params["dt"],
            "n_particles": wl.n_particles, "seconds": time.time() - t0,
            "flagged_boxes": int(np.count_nonzero(flags)),
@@ -217,7 +230,19 @@ def chain_scaling(chain_lens, lams) -> dict:
 def report(results, command: str) -> str:
     """Markdown summary of one or more sweeps (one per chain length)."""
     planar = results[0].get("dims", 3) == 2
-    if planar:
+    af = results[0].get("afbc")
+    if planar and af:
+        box = ("Micro-domains: the paper's 2-D melt (Tab. 1: DPD a = 25, gamma = 4.5, kBT = 1, FENE H = 50, "
+               "R0 = 1.5, dt = 0.005; n = 4 per unit area, polymer fraction 1) in the paper's micro-domain of "
+               "Tab. 2, {edge} x {edge} rc (core {core:g}, boundary-condition region {bc:g}, buffer {buf:g}), held "
+               "in the plane z = 0 of a fixed periodic cell of z edge {th} rc; the shear is imposed on the "
+               "boundary-condition region (Eq. micro_bc; velocities relax toward the imposed field at rate "
+               "zeta = {zeta:g} with thermal noise) and the stress is the core's Irving-Kirkwood stress, 2-D "
+               "(times the z edge)").format(edge=results[0]["edge"], core=2 * af["core_half"],
+                                            bc=af["ring_half"] - af["core_half"],
+                                            buf=results[0]["edge"] / 2 - af["ring_half"], th=PLANAR_THICKNESS,
+                                            zeta=af["zeta"])
+    elif planar:
         box = ("Boxes: the paper's 2-D melt (Tab. 1: DPD a = 25, gamma = 4.5, kBT = 1, FENE H = 50, R0 = 1.5, "
                "dt = 0.005; n = 4 per unit area, polymer fraction 1), {edge} x {edge} rc periodic, held in the "
                "plane z = 0 of a cell of z edge {th} rc and sheared homogeneously (Lees-Edwards); stresses are 2-D "
@@ -284,6 +309,9 @@ def main(argv=None):
     ap.add_argument("--replicas", type=int, default=16)
     ap.add_argument("--chain-len", type=int, default=10)
     ap.add_argument("--planar", action="store_true", help="the paper's 2-D melt (Tab. 1, n = 4)")
+    ap.add_argument("--afbc", action="store_true",
+                    help="the 2-D melt in the paper's micro-domain with boundary regions (Tab. 2)")
+    ap.add_argument("--zeta", type=float, default=10.0, help="relaxation rate of the boundary-condition region")
     ap.add_argument("--edge", type=float, default=None, help="box edge (default 10, planar 32)")
     ap.add_argument("--equil", type=int, default=5000)
     ap.add_argument("--steps", type=int, default=20000)
@@ -308,8 +336,11 @@ def main(argv=None):
     if not torch.cuda.is_available():
         raise SystemExit("needs the GPU")
     rates = [float(x) for x in args.rates.split(",")]
-    edge = args.edge if args.edge is not None else (32.0 if args.planar else 10.0)
-    res = run_sweep(rates, args.replicas, args.chain_len, args.equil, args.steps, edge=edge, planar=args.planar)
+    planar = args.planar or args.afbc
+    edge = args.edge if args.edge is not None else (AFBC_EDGE if args.afbc else (32.0 if planar else 10.0))
+    afbc = (AFBC_CORE_HALF * edge / AFBC_EDGE, AFBC_RING_HALF * edge / AFBC_EDGE) if args.afbc else None
+    res = run_sweep(rates, args.replicas, args.chain_len, args.equil, args.steps, edge=edge, planar=planar,
+                    afbc=afbc, zeta=args.zeta)
     print(json.dumps(res), flush=True)
     if args.out:
         with open(args.out, "w") as f:
