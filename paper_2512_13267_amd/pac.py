@@ -17,8 +17,17 @@ the per-particle in-plane deviatoric stress averaged over the last
 ``avg`` macro steps, surrogate versus ``dpd`` (and versus the mean of
 ``dpd`` and ``dpd2``), next to ``dpd2`` versus ``dpd``.
 
-Command line: ``python -m paper_2512_13267_amd.pac [--steps 500] [--avg 100]
-[--runs dpd,dpd2,surrogate] [--out FILE]``.
+The gate's floor is calibrated on held-out data of the training
+distribution (``--calibrate``): the ensemble flags a row when its spread
+exceeds threshold x max(|mean|, floor), and threshold x floor is the spread
+that 99% of in-distribution rows stay below, so the gate reacts to inputs
+the ensemble has not seen rather than to the members' ordinary
+disagreement on rows whose predicted stress is near zero (the relative test
+alone flags 0.8% of in-distribution rows, but every row of a flow at rest).
+
+Command line: ``python -m paper_2512_13267_amd.pac [--steps 500]
+[--avg 100,400] [--runs dpd,dpd2,surrogate] [--out FILE]``;
+``--calibrate`` prints the in-distribution floor.
 """
 from __future__ import annotations
 
@@ -69,21 +78,31 @@ def close(ctx):
 
 def run(ctx, steps, avg, log=print, label=""):
     """Advance `steps` macro steps; returns timing, counters and the mean
-    stress over the last `avg` steps."""
+    stress over the last `avg` steps (avg: an int, or a list of ints: then a
+    dict of means by window)."""
     import torch
 
     hy = ctx["hy"]
     nm = ctx["nm"]
+    windows = sorted({int(a) for a in (avg if isinstance(avg, (list, tuple)) else [avg])})
+    longest = windows[-1]
+    partial = {}  # mean over [steps - longest, steps - a) for the shorter windows a
     n_dpd = 0
     entered = 0
     resets = 0
+    dpd_steps = []  # macro steps (1-based) with any particle on DPD
     t0 = time.time()
     st = None
     for k in range(steps):
-        if k == steps - avg:
+        if k == steps - longest:
             hy.mean_stress(reset=True)
+        for a in windows[:-1]:
+            if k == steps - a:
+                partial[a] = hy.mean_stress()
         st = hy.step()
         n_dpd += st["n_dpd"]
+        if st["n_dpd"]:
+            dpd_steps.append(k + 1)
         entered += st["n_entered"]
         resets += st["n_reset"]
         if (k + 1) % 50 == 0:
@@ -92,10 +111,50 @@ def run(ctx, steps, avg, log=print, label=""):
                 f"resets so far {resets}", flush=True)
     torch.cuda.synchronize()
     secs = time.time() - t0
-    mean = hy.mean_stress()
-    return {"steps": steps, "seconds": secs, "macro_steps_per_s": steps / secs,
-            "micro_box_steps": st["micro_box_steps"], "fallback_rate": n_dpd / (steps * nm),
-            "entered": entered, "resets": resets}, mean
+    full = hy.mean_stress()
+    means = {longest: full}
+    for a in windows[:-1]:
+        # the last a steps: the long window's sum less its first longest - a steps
+        means[a] = (longest * full - (longest - a) * partial[a]) / a
+    out = {"steps": steps, "seconds": secs, "macro_steps_per_s": steps / secs,
+           "micro_box_steps": st["micro_box_steps"], "fallback_rate": n_dpd / (steps * nm),
+           "entered": entered, "resets": resets, "macro_steps_with_dpd": len(dpd_steps),
+           "last_macro_step_with_dpd": dpd_steps[-1] if dpd_steps else 0}
+    return out, (means if isinstance(avg, (list, tuple)) else full)
+
+
+def calibrate_floor(threshold=GATE_THRESHOLD, n_boxes=512, n_macro=120, max_rate=0.01, seed_k=99, weights=None,
+                    log=print):
+    """The smallest gate floor for which at most `max_rate` of held-out rows
+    of the training distribution (fresh micro-DPD data, seeds never used in
+    training) are flagged.  Returns the floor and the spread statistics."""
+    import torch
+
+    from . import train
+
+    X, T, _, _, info = train.generate(n_boxes, n_macro, equil=300, seed_k=seed_k, log=log)
+    members, nh, _, _ = surrogate.load_trained(weights or surrogate.TRAINED)
+    sur = surrogate.Surrogate(members, X.shape[1], nh, 3, max_batch=4096)
+    spread, norm = [], []
+    for k in range(0, X.shape[0], 4096):
+        Y = sur.forward(X[k:k + 4096].contiguous())
+        mu = Y.mean(dim=0)
+        spread.append(((Y - mu) ** 2).mean(dim=0).mean(dim=1).sqrt())
+        norm.append(mu.norm(dim=1))
+    sur.close()
+    spread = torch.cat(spread).double().cpu().numpy()
+    norm = torch.cat(norm).double().cpu().numpy()
+    # flagged at floor f where spread > threshold max(norm, f): rows with
+    # spread <= threshold norm never are; the others are for f < spread / threshold
+    # the floor: spread / threshold at the in-distribution quantile 1 - max_rate,
+    # so a flagged row's spread exceeds both threshold x |mean| and what
+    # (1 - max_rate) of the training distribution's rows show
+    floor = float(np.quantile(spread, 1.0 - max_rate)) / threshold
+    rate_at = lambda f: float(np.mean(spread > threshold * np.maximum(norm, f)))
+    return {"floor": floor, "threshold": threshold, "max_rate": max_rate, "rows": int(spread.size),
+            "flag_rate_at_floor": rate_at(floor), "flag_rate_without_floor": rate_at(0.0),
+            "spread_quantiles": {q: float(np.quantile(spread, q)) for q in (0.5, 0.9, 0.99, 0.999)},
+            "mean_norm_median": float(np.median(norm)), "samples": info["samples"]}
 
 
 def deviatoric(sigma):
@@ -111,7 +170,7 @@ def compare(a, b, nm):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--avg", type=int, default=100)
+    ap.add_argument("--avg", default="100", help="comma-separated averaging windows (macro steps)")
     ap.add_argument("--runs", default="dpd,dpd2,surrogate")
     ap.add_argument("--out", default=None)
     ap.add_argument("--weights", default=None, help="surrogate weights (default: the packaged ones)")
@@ -119,11 +178,23 @@ def main(argv=None):
                     help="comma-separated gate thresholds, one surrogate run each")
     ap.add_argument("--floor", type=float, default=GATE_FLOOR)
     ap.add_argument("--hold", type=int, default=HOLD)
+    ap.add_argument("--calibrate", action="store_true", help="print the in-distribution gate floor and exit")
+    ap.add_argument("--replay", type=int, default=REPLAY)
+    ap.add_argument("--means-out", default=None, help="save the runs' mean stresses (npz)")
+    ap.add_argument("--ref", default=None, help="npz of earlier dpd / dpd2 means to compare against")
     args = ap.parse_args(argv)
     import torch
 
     if not torch.cuda.is_available():
         raise SystemExit("needs the GPU")
+    if args.calibrate:
+        cal = calibrate_floor(threshold=float(args.thresholds.split(",")[0]), weights=args.weights)
+        print(json.dumps(cal), flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(cal, f, indent=1)
+        return
+    windows = [int(a) for a in args.avg.split(",")]
     res, means = {}, {}
     names = []
     for name in args.runs.split(","):
@@ -135,26 +206,34 @@ def main(argv=None):
         mode = "surrogate" if name.startswith("surrogate") else "dpd"
         th = float(name.split("@")[1]) if "@" in name else GATE_THRESHOLD
         ctx = build(mode, seed_k=42 if name == "dpd2" else 41, threshold=th, floor=args.floor, hold=args.hold,
-                    weights=args.weights)
+                    replay=args.replay, weights=args.weights)
         print(f"{name}: {ctx['nm']} micro-domains", flush=True)
-        res[name], means[name] = run(ctx, args.steps, args.avg, label=name)
+        res[name], means[name] = run(ctx, args.steps, windows, label=name)
         res[name]["n_mobile"] = ctx["nm"]
         print(json.dumps({name: res[name]}), flush=True)
         close(ctx)
     nm = next(iter(res.values()))["n_mobile"]
+    if args.means_out:
+        np.savez(args.means_out, **{f"{name}_{w}": means[name][w] for name in means for w in windows})
+    if args.ref:
+        ref = np.load(args.ref)
+        for name in ("dpd", "dpd2"):
+            if name not in means and all(f"{name}_{w}" in ref for w in windows):
+                means[name] = {w: ref[f"{name}_{w}"] for w in windows}
+                res.setdefault(name, {"n_mobile": nm, "from": args.ref})
     if "dpd" in means:
         for name in means:
             if name != "dpd":
-                res[name]["stress_rel_l2_vs_dpd"] = compare(means[name], means["dpd"], nm)
+                res[name]["stress_rel_l2_vs_dpd"] = {w: compare(means[name][w], means["dpd"][w], nm) for w in windows}
         for name in names:
-            if name.startswith("surrogate"):
+            if name.startswith("surrogate") and "macro_steps_per_s" in res["dpd"]:
                 res[name]["speedup_vs_dpd"] = res[name]["macro_steps_per_s"] / res["dpd"]["macro_steps_per_s"]
         if "dpd2" in means:
             # against the mean of the two DPD runs: half the noise variance of one
-            ref = 0.5 * (means["dpd"] + means["dpd2"])
             for name in names:
                 if name.startswith("surrogate"):
-                    res[name]["stress_rel_l2_vs_dpd_mean"] = compare(means[name], ref, nm)
+                    res[name]["stress_rel_l2_vs_dpd_mean"] = {
+                        w: compare(means[name][w], 0.5 * (means["dpd"][w] + means["dpd2"][w]), nm) for w in windows}
     print(json.dumps(res), flush=True)
     if args.out:
         with open(args.out, "w") as f:
