@@ -165,8 +165,9 @@ __device__ __forceinline__ void philox4x32_10(unsigned& x0, unsigned& x1, unsign
     for (int r = 0; r < 10; ++r) {
         const unsigned long long p0 = (unsigned long long)0xD2511F53u * x0;
         const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * x2;
-        const unsigned y0 = (unsigned)(p1 >> 32) ^ x1 ^ k0;
-        const unsigned y2 = (unsigned)(p0 >> 32) ^ x3 ^ k1;
+        // three-input xors as one v_bitop3_b32 each (truth table 0x96)
+        const unsigned y0 = __builtin_amdgcn_bitop3_b32((unsigned)(p1 >> 32), x1, k0, 0x96);
+        const unsigned y2 = __builtin_amdgcn_bitop3_b32((unsigned)(p0 >> 32), x3, k1, 0x96);
         x1 = (unsigned)p1;
         x3 = (unsigned)p0;
         x0 = y0;
@@ -244,6 +245,29 @@ struct Rec<double> {
     __device__ static T make(double x, double y, double z, int id) { return make_double4(x, y, z, (double)id); }
     __device__ static int id(T v) { return (int)v.w; }
 };
+
+// Raw buffer view of a record array (stride 0, no range limit in practice):
+// a float record is read by one 16-byte buffer load, which the compiler keeps
+// whole, so the loads of a search step are issued together and none is
+// deferred into the branch that queues a neighbour.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rec_rsrc(const char* base) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7fffffff, 0x00020000);
+}
+
+template <typename real>
+__device__ __forceinline__ typename Rec<real>::T load_rec(__amdgpu_buffer_rsrc_t r, const char* base, unsigned off);
+
+template <>
+__device__ __forceinline__ float4 load_rec<float>(__amdgpu_buffer_rsrc_t r, const char*, unsigned off) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 x = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_float4(__uint_as_float(x.x), __uint_as_float(x.y), __uint_as_float(x.z), __uint_as_float(x.w));
+}
+
+template <>
+__device__ __forceinline__ double4 load_rec<double>(__amdgpu_buffer_rsrc_t, const char* base, unsigned off) {
+    return *(const double4*)(base + off);
+}
 
 // ---------------------------------------------------------------------------
 // FP64 cell algebra (row-major 3x3; columns are lattice vectors)
@@ -1010,7 +1034,7 @@ __device__ __forceinline__ real core_fraction(real ax, real ay, real ex, real ey
 // half kick relaxes the ring toward the imposed field; the core's kinetic
 // sums use the velocity relative to that field.
 template <typename real, int QD, bool PRUNE, bool COMP = false, bool AF = false>
-__global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (AF ? 4 : (PRUNE ? 5 : 6))) : 1) void k_forces(
+__global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP || AF || QD >= 32 ? 4 : (PRUNE ? 5 : 6)) : 1) void k_forces(
     Ctx C, int step_offset, int drain, int busy, int kick) {
     constexpr bool prune = PRUNE;
     constexpr int NV = COMP ? 37 : 19;  // block partial sums
@@ -1036,6 +1060,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (AF ? 4 : (PRUN
     const bool act = pos < B.n;
     const V4* pv = (const V4*)C.cell_pv + 2 * (size_t)B.off;
     const char* sbase = (const char*)((const V4*)C.srec + 2 * B.off);
+    const __amdgpu_buffer_rsrc_t srsrc = rec_rsrc(sbase);
     const real* s = (const real*)C.s;
     real* f = (real*)C.f;
 
@@ -1106,12 +1131,16 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (AF ? 4 : (PRUN
             const int e = qbuf[qh & (QD - 1)][wv][lane];
             ++qh;
             const int qj = e >> 6, zi = (e >> 4) & 3;
-            const V4 pj = pv[2 * qj];
-            const V4 cj = pv[2 * qj + 1];
+            // one 32-bit byte offset from the box's records (scalar base)
+            const unsigned po = (unsigned)qj * (unsigned)(2 * sizeof(V4));
+            const V4 pj = *(const V4*)((const char*)pv + po);
+            const V4 cj = *(const V4*)((const char*)pv + po + sizeof(V4));
             const real sx = shift_tab[e & 15][0], sy = shift_tab[e & 15][1];
-            const real zj = zi == 0 ? pj.z : (zi == 1 ? pj.z - h22 : pj.z + h22);
+            // z image without a branch: one rounding of z + (0, -1, +1) h22
+            // for zi = 0, 1, 2, the same as the binning's z - h22, z + h22
+            const real zj = fma(h22, (real)((zi >> 1) - (zi & 1)), pj.z);
             const real dx = (ri0 - sx) - pj.x, dy = (ri1 - sy) - pj.y, dz = ri2 - zj;
-            const real r2 = dx * dx + dy * dy + dz * dz;
+            const real r2 = fma(dz, dz, fma(dx, dx, dy * dy));  // fixed association
             const real ir = inv_sqrt(r2);
             const real r = r2 * ir;
             const real ex = dx * ir, ey = dy * ir, ez = dz * ir;
@@ -1147,8 +1176,11 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (AF ? 4 : (PRUN
     // position minus the image shift of the range scanned; queue it if accepted
     auto push = [&](bool valid, const V4& v, real px, real py, real pz) {
         const real dx = px - v.x, dy = py - v.y, dz = pz - v.z;
-        const real r2 = dx * dx + dy * dy + dz * dz;
-        if (valid && r2 < rc2 && r2 > (real)0) {
+        // the acceptance test's rounding is fixed by explicit fmas, whatever the
+        // surrounding code lets the compiler contract
+        const real r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        // one branch per candidate: the tests combined without short-circuit
+        if (valid & (r2 < rc2) & (r2 > (real)0)) {
             qbuf[qt & (QD - 1)][wv][lane] = (R::id(v) << 4) | ic;
             ++qt;
         }
@@ -1212,7 +1244,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP ? 4 : (AF ? 4 : (PRUN
             const unsigned qo = (unsigned)q * (unsigned)sizeof(V4);
             const int rem = qe - q;
 #pragma unroll
-            for (int u = 0; u < SU; ++u) cand[u] = *(const V4*)(sbase + qo + u * sizeof(V4));
+            for (int u = 0; u < SU; ++u) cand[u] = load_rec<real>(srsrc, sbase, qo + u * (unsigned)sizeof(V4));
 #pragma unroll
             for (int u = 0; u < SU; ++u) push(u < rem, cand[u], bx, by, ri2);
             q += SU;
@@ -1423,6 +1455,7 @@ struct lhmm_micro {
     unsigned* d_part_pairs = nullptr;
     double *d_acc = nullptr, *d_parts = nullptr, *d_gradL = nullptr;
     unsigned long long *d_acc_pairs = nullptr, *d_tot_pairs = nullptr, *d_step = nullptr;
+    unsigned long long* d_gstep = nullptr;  // step counters of the groups inside a captured chunk
     // selection lists (device) and their pinned staging, reused once ev_sel completes
     int *d_sel = nullptr, *d_blk_list = nullptr, *h_sel = nullptr;
     hipEvent_t ev_sel = nullptr;
@@ -1438,8 +1471,9 @@ struct lhmm_micro {
     std::map<std::tuple<int, int, int>, hipGraphExec_t> sub_graphs;
     std::map<std::tuple<int, int, int>, int> sub_seen;
     // overlapped groups of boxes (cfg.groups > 1): boxes by particle count,
-    // smallest first; each group's binning and forces run on their own
-    // stream inside the captured step, joined before the stress
+    // smallest first; inside a captured chunk of steps each group runs all
+    // its steps (binning, forces, stress) on its own stream with its own step
+    // counter, and the groups join at the chunk's end
     struct Group {
         int* d_sel = nullptr;
         int* d_blk = nullptr;
@@ -1538,11 +1572,22 @@ void launch_step_timed(lhmm_micro* m, hipEvent_t* ev) {
     (void)hipEventRecord(ev[11], st);
 }
 
-// One captured step with the boxes in overlapped groups: fork, each group's
-// fused binning and forces on its own stream, join, then every box's stress.
+// Copy the step counter *src to dst[0 .. n-1].
+__global__ void k_step_copy(unsigned long long* __restrict__ dst, const unsigned long long* __restrict__ src, int n) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = *src;
+}
+
+// A captured chunk of nsteps steps with the boxes in overlapped groups.  The
+// boxes of one group never read another group's data, so each group runs
+// its whole chunk (fused binning, forces, stress) on its own stream with its
+// own copy of the step counter: a group with small boxes does not wait each
+// step for the binning of the largest ones.  The counters fork from the
+// engine's at the start and join into it at the end; every box computes
+// exactly what the stepwise order computes.
 template <typename real>
-void launch_step_grouped(lhmm_micro* m) {
+void launch_chunk_grouped(lhmm_micro* m, int nsteps) {
     const int G = (int)m->groups.size();
+    k_step_copy<<<1, 64, 0, m->stream>>>(m->d_gstep, m->d_step, G);
     (void)hipEventRecord(m->ev_fork, m->stream);
     for (int g = 1; g < G; ++g) (void)hipStreamWaitEvent(m->aux[g - 1], m->ev_fork, 0);
     for (int g = 0; g < G; ++g) {
@@ -1552,14 +1597,18 @@ void launch_step_grouped(lhmm_micro* m) {
         C.sel = gr.d_sel;
         C.blk_list = gr.d_blk;
         C.n_sel = gr.n_sel;
-        launch_bin<real>(m, C, gr.n_sel, st, 1, gr.lds_cells, gr.lds_parts);
-        launch_forces<real>(m, C, gr.nblk, 1, 1, st);
+        C.step = m->d_gstep + g;
+        for (int k = 0; k < nsteps; ++k) {
+            launch_bin<real>(m, C, gr.n_sel, st, 1, gr.lds_cells, gr.lds_parts);
+            launch_forces<real>(m, C, gr.nblk, 1, 1, st);
+            k_box_stress<<<gr.n_sel, 64, 0, st>>>(C);
+        }
     }
     for (int g = 1; g < G; ++g) {
         (void)hipEventRecord(m->ev_join[g - 1], m->aux[g - 1]);
         (void)hipStreamWaitEvent(m->stream, m->ev_join[g - 1], 0);
     }
-    k_box_stress<<<m->n_boxes, 64, 0, m->stream>>>(m->ctx);
+    k_step_copy<<<1, 64, 0, m->stream>>>(m->d_step, m->d_gstep, 1);
 }
 
 void launch_one_step(lhmm_micro* m) {
@@ -1599,14 +1648,12 @@ int get_graph(lhmm_micro* m, int nsteps, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     const bool grouped = m->groups.size() > 1 && m->cfg.fuse_bin;
     HIPCHK(hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < nsteps; ++k) {
-        if (!grouped)
-            launch_one_step(m);
-        else if (m->precision == LHMM_FP64)
-            launch_step_grouped<double>(m);
-        else
-            launch_step_grouped<float>(m);
-    }
+    if (!grouped)
+        for (int k = 0; k < nsteps; ++k) launch_one_step(m);
+    else if (m->precision == LHMM_FP64)
+        launch_chunk_grouped<double>(m, nsteps);
+    else
+        launch_chunk_grouped<float>(m, nsteps);
     HIPCHK(hipStreamEndCapture(m->stream, &g));
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -1642,7 +1689,7 @@ void release(lhmm_micro* m) {
     void* bufs[] = {m->d_box, m->d_dyn, m->d_flags, m->d_blk_box, m->d_blk_first, m->d_s, m->d_c, m->d_f,
                     m->d_pcell, m->d_cell_start, m->d_gcell_start, m->d_cell_pv, m->d_srec,
                     m->d_part_vir, m->d_part_kin,
-                    m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_tot_pairs, m->d_step,
+                    m->d_part_pairs, m->d_acc, m->d_parts, m->d_gradL, m->d_acc_pairs, m->d_tot_pairs, m->d_step, m->d_gstep,
                     m->d_sel, m->d_blk_list, m->d_snap_s, m->d_snap_c, m->d_snap_f, m->d_snap_dyn};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -1962,6 +2009,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     ALLOC(m->d_acc_pairs, (size_t)n_boxes);
     ALLOC(m->d_tot_pairs, (size_t)n_boxes);
     ALLOC(m->d_step, (size_t)1);
+    ALLOC(m->d_gstep, (size_t)MAX_GROUPS);
 #undef ALLOC
     if (rc == LHMM_OK) {
         const size_t bytes = 3 * N * m->real_size;
