@@ -139,7 +139,8 @@ def bench_pac(macro_steps: int, windows):
     out = {"workload": "flow past a periodic square array of cylinders (radius 0.2), 64 x 64 SPH lattice, "
                        "one 4000-particle micro-domain per mobile particle, 50 micro steps per macro step",
            "macro_steps": macro_steps, "avg_windows": windows, "gate_threshold": pac.GATE_THRESHOLD,
-           "gate_floor": pac.GATE_FLOOR, "hold": pac.HOLD, "replay": pac.REPLAY}
+           "gate_floor": pac.GATE_FLOOR, "gate_max_grad": pac.gate_max_grad(), "gate_input_quantile": pac.GATE_INPUT_Q,
+           "hold": pac.HOLD, "replay": pac.REPLAY}
     means = {}
     for mode in ("dpd", "surrogate"):
         ctx = pac.build(mode)
@@ -149,7 +150,8 @@ def bench_pac(macro_steps: int, windows):
         pac.close(ctx)
         torch.cuda.synchronize()
         out[mode] = {"macro_steps_per_s": r["macro_steps_per_s"], "fallback_rate": r["fallback_rate"],
-                     "micro_box_steps": r["micro_box_steps"], "resets": r["resets"], "entered": r["entered"]}
+                     "out_of_range_rate": r["out_of_range_rate"], "micro_box_steps": r["micro_box_steps"],
+                     "resets": r["resets"], "entered": r["entered"]}
     out["speedup"] = out["surrogate"]["macro_steps_per_s"] / out["dpd"]["macro_steps_per_s"]
     out["stress_rel_l2_vs_dpd"] = {str(w): pac.compare(means["surrogate"][w], means["dpd"][w], out["n_mobile"])
                                    for w in windows}

@@ -582,7 +582,8 @@ int lhmm_sur_destroy(lhmm_sur* s);
  * micro-domains).  Per step: SPH step with the stresses of the last
  * interval; each mobile particle's micro gradient enters its history ring;
  * in LHMM_HYBRID_SURROGATE mode the ensemble predicts the deviatoric stress
- * and the gate flags particles whose members disagree; a flagged particle
+ * and the gate flags particles whose members disagree or (max_grad > 0)
+ * whose gradient lies outside the given input range; a flagged particle
  * runs plain micro-DPD for the next `hold` steps.  A particle entering DPD
  * gets its micro-domain back from the equilibrated snapshot taken at
  * create time and replays its last `replay` gradient samples (k_micro micro
@@ -614,6 +615,10 @@ typedef struct {
     float floor;        /* gate floor on |mean| (surrogate output units)      */
     float grad_scale;   /* history holds L x grad_scale                      */
     float stress_scale; /* deviatoric stress = surrogate output x this       */
+    float max_grad;     /* input-range gate: a particle whose micro gradient
+                           L has Frobenius norm above this is flagged too
+                           (the ensemble's spread does not grow where all
+                           members extrapolate alike); 0 disables it        */
 } lhmm_hybrid_params;
 
 typedef struct {
@@ -623,6 +628,7 @@ typedef struct {
     int32_t n_entered;       /* of which entered DPD in it                    */
     int32_t n_flagged;       /* gate flags in it                              */
     int32_t n_reset;         /* thin boxes restored after it                  */
+    int32_t n_out_of_range;  /* flags of the input-range gate in it           */
 } lhmm_hybrid_stats;
 
 /* phi: HOST n_mobile FP32, the polymer-fraction feature of each

@@ -53,6 +53,19 @@ struct lhmm_hybrid {
 
 namespace {
 
+// Input-range gate: bit 1 of flag[b] is set when the micro gradient of
+// particle b (row-major 3 x 3, FP64) has squared Frobenius norm above max2;
+// the sum of squares is formed in this fixed order without fused products,
+// so a host computation in FP64 takes the same decision.
+__global__ void k_input_gate(const double* __restrict__ L, int n, double max2, unsigned* __restrict__ flag) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const double* l = L + 9 * (long)b;
+    double q = 0.0;
+    for (int k = 0; k < 9; ++k) q = __dadd_rn(q, __dmul_rn(l[k], l[k]));
+    if (q > max2) flag[b] |= 2u;
+}
+
 __global__ void k_accumulate(const double* __restrict__ x, long n, double* __restrict__ sum) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) sum[i] += x[i];
@@ -112,8 +125,9 @@ int lhmm_hybrid_create(const lhmm_hybrid_params* p, lhmm_sph* sph, lhmm_micro* m
     if (p->mode == LHMM_HYBRID_SURROGATE && !sur) return lhmm_fail(LHMM_ERR_ARG, "surrogate mode needs a surrogate");
     if (p->k_micro < 1 || p->hold < 1 || p->replay < 0 || p->replay > LHMM_SUR_HIST - 1)
         return lhmm_fail(LHMM_ERR_ARG, "need k_micro >= 1, hold >= 1, 0 <= replay < %d", LHMM_SUR_HIST);
-    if (!(p->grad_scale > 0.0f) || !(p->stress_scale > 0.0f) || !(p->threshold >= 0.0f) || !(p->floor >= 0.0f))
-        return lhmm_fail(LHMM_ERR_ARG, "scales must be positive, threshold and floor non-negative");
+    if (!(p->grad_scale > 0.0f) || !(p->stress_scale > 0.0f) || !(p->threshold >= 0.0f) || !(p->floor >= 0.0f) ||
+        !(p->max_grad >= 0.0f))
+        return lhmm_fail(LHMM_ERR_ARG, "scales must be positive, threshold, floor and max_grad non-negative");
     int n = 0, nm = 0;
     lhmm_sph_counts(sph, &n, &nm);
     int32_t nb = 0;
@@ -213,12 +227,18 @@ int lhmm_hybrid_step(lhmm_hybrid* h, lhmm_hybrid_stats* stats) {
         if (rc == LHMM_OK)
             rc = lhmm_sur_gate(h->Y, h->E, nm, 3, h->p.threshold, h->p.floor, h->mean, h->gflag, h->stream);
         if (rc != LHMM_OK) return rc;
+        if (h->p.max_grad > 0.0f) {
+            const double mg = (double)h->p.max_grad;
+            k_input_gate<<<(nm + 255) / 256, 256, 0, h->stream>>>(h->gradL, nm, mg * mg, h->gflag);
+            LHMM_HIPCHK(hipGetLastError());
+        }
         LHMM_HIPCHK(hipMemcpyAsync(h->gflag_h, h->gflag, nm * sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
         LHMM_HIPCHK(hipStreamSynchronize(h->stream));
         for (int b = 0; b < nm; ++b) {
             if (h->gflag_h[b]) {
                 h->hold_left[b] = h->p.hold;
                 S.n_flagged += 1;
+                if (h->gflag_h[b] & 2u) S.n_out_of_range += 1;
             }
             const bool is_on = h->hold_left[b] > 0;
             if (is_on) {

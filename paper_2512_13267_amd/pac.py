@@ -17,13 +17,21 @@ the per-particle in-plane deviatoric stress averaged over the last
 ``avg`` macro steps, surrogate versus ``dpd`` (and versus the mean of
 ``dpd`` and ``dpd2``), next to ``dpd2`` versus ``dpd``.
 
-The gate's floor is calibrated on held-out data of the training
-distribution (``--calibrate``): the ensemble flags a row when its spread
-exceeds threshold x max(|mean|, floor), and threshold x floor is the spread
-that 99% of in-distribution rows stay below, so the gate reacts to inputs
-the ensemble has not seen rather than to the members' ordinary
-disagreement on rows whose predicted stress is near zero (the relative test
-alone flags 0.8% of in-distribution rows, but every row of a flow at rest).
+The gate has two parts.  The spread gate flags a particle when the
+ensemble's spread exceeds threshold x max(|mean|, floor); its floor is
+calibrated on held-out data of the training distribution (``--calibrate``):
+threshold x floor is the spread that 99% of in-distribution rows stay below
+(0.0176 in surrogate output units on 44,960 rows, so floor = 0.35), and the
+gate reacts to disagreement beyond the ordinary rather than to rows whose
+predicted stress is near zero (the relative test alone flags 0.8% of
+in-distribution rows, but every particle of a flow at rest).  The members
+were trained on the same data and extrapolate alike, so their spread stays
+small where the inputs leave the training range; the input-range gate
+flags a particle whose current gradient has a Frobenius norm above the
+0.9999 quantile of the training set's (train.input_quantile: 0.353 for the
+packaged weights).  In this flow the surrogate's error beyond the DPD
+noise sits mostly in the particles next to the cylinder, whose shear rates
+reach twice that bound.
 
 Command line: ``python -m paper_2512_13267_amd.pac [--steps 500]
 [--avg 100,400] [--runs dpd,dpd2,surrogate] [--out FILE]``;
@@ -42,13 +50,27 @@ from .train import phi_feature
 
 PHI = 0.1
 GATE_THRESHOLD = 0.05
-GATE_FLOOR = 1.0  # surrogate output units (targets / stress_scale): ~ the RMS training target
+GATE_FLOOR = 0.35  # surrogate output units: the in-distribution 0.99 quantile of the spread / GATE_THRESHOLD
+GATE_INPUT_Q = 0.9999  # input-range gate: this quantile of the training set's gradient norms
 HOLD = 10
-REPLAY = 31
+# history samples a restored micro-domain relives (on entry to DPD and after a
+# thin cell): at 31 the boxes next to the cylinder, under shear rates up to
+# 0.7, thin again during their own replays (1958 restores in the surrogate
+# run against 193 at 10), with the same stress error
+REPLAY = 10
+
+
+def gate_max_grad(q=GATE_INPUT_Q):
+    """The input-range bound of the packaged weights' training set."""
+    from . import train
+
+    return train.input_quantile(q, **surrogate.TRAINED_DATA)
 
 
 def build(mode, seed_k=41, n_lattice=64, n_particles=4000, equil=500, k_micro=50, threshold=GATE_THRESHOLD,
-          floor=GATE_FLOOR, hold=HOLD, replay=REPLAY, weights=None):
+          floor=GATE_FLOOR, hold=HOLD, replay=REPLAY, weights=None, max_grad=None):
+    """max_grad: the input-range gate's bound (None: gate_max_grad() for the
+    packaged weights, 0 for other weights; 0 disables it)."""
     import torch
 
     mac = inputs.cylinder_array(n=n_lattice)
@@ -62,11 +84,13 @@ def build(mode, seed_k=41, n_lattice=64, n_particles=4000, equil=500, k_micro=50
     sur = None
     if mode == "surrogate":
         sur = surrogate.Surrogate(members, members[0]["W1"].shape[0], nh, 3, max_batch=nm)
+    if max_grad is None:
+        max_grad = gate_max_grad() if weights is None else 0.0
     hy = lhmm.Hybrid(s, m, sur, phi=np.full(nm, phi_feature(PHI), dtype=np.float32),
                      mode="surrogate" if mode == "surrogate" else "dpd", k_micro=k_micro, hold=hold, replay=replay,
-                     threshold=threshold, floor=floor, grad_scale=gscale, stress_scale=sscale)
+                     threshold=threshold, floor=floor, grad_scale=gscale, stress_scale=sscale, max_grad=max_grad)
     torch.cuda.synchronize()
-    return {"mac": mac, "micro": m, "sph": s, "sur": sur, "hy": hy, "nm": nm}
+    return {"mac": mac, "micro": m, "sph": s, "sur": sur, "hy": hy, "nm": nm, "max_grad": max_grad}
 
 
 def close(ctx):
@@ -91,6 +115,7 @@ def run(ctx, steps, avg, log=print, label=""):
     entered = 0
     resets = 0
     dpd_steps = []  # macro steps (1-based) with any particle on DPD
+    n_range = 0
     t0 = time.time()
     st = None
     for k in range(steps):
@@ -103,6 +128,7 @@ def run(ctx, steps, avg, log=print, label=""):
         n_dpd += st["n_dpd"]
         if st["n_dpd"]:
             dpd_steps.append(k + 1)
+        n_range += st["n_out_of_range"]
         entered += st["n_entered"]
         resets += st["n_reset"]
         if (k + 1) % 50 == 0:
@@ -118,7 +144,8 @@ def run(ctx, steps, avg, log=print, label=""):
         means[a] = (longest * full - (longest - a) * partial[a]) / a
     out = {"steps": steps, "seconds": secs, "macro_steps_per_s": steps / secs,
            "micro_box_steps": st["micro_box_steps"], "fallback_rate": n_dpd / (steps * nm),
-           "entered": entered, "resets": resets, "macro_steps_with_dpd": len(dpd_steps),
+           "entered": entered, "resets": resets, "out_of_range_rate": n_range / (steps * nm),
+           "macro_steps_with_dpd": len(dpd_steps),
            "last_macro_step_with_dpd": dpd_steps[-1] if dpd_steps else 0}
     return out, (means if isinstance(avg, (list, tuple)) else full)
 
@@ -180,6 +207,8 @@ def main(argv=None):
     ap.add_argument("--hold", type=int, default=HOLD)
     ap.add_argument("--calibrate", action="store_true", help="print the in-distribution gate floor and exit")
     ap.add_argument("--replay", type=int, default=REPLAY)
+    ap.add_argument("--max-grad", type=float, default=None,
+                    help="input-range gate bound (default: the packaged weights' training quantile; 0 disables)")
     ap.add_argument("--means-out", default=None, help="save the runs' mean stresses (npz)")
     ap.add_argument("--ref", default=None, help="npz of earlier dpd / dpd2 means to compare against")
     args = ap.parse_args(argv)
@@ -206,10 +235,13 @@ def main(argv=None):
         mode = "surrogate" if name.startswith("surrogate") else "dpd"
         th = float(name.split("@")[1]) if "@" in name else GATE_THRESHOLD
         ctx = build(mode, seed_k=42 if name == "dpd2" else 41, threshold=th, floor=args.floor, hold=args.hold,
-                    replay=args.replay, weights=args.weights)
+                    replay=args.replay, weights=args.weights, max_grad=args.max_grad)
         print(f"{name}: {ctx['nm']} micro-domains", flush=True)
         res[name], means[name] = run(ctx, args.steps, windows, label=name)
         res[name]["n_mobile"] = ctx["nm"]
+        if mode == "surrogate":
+            res[name]["gate"] = {"threshold": th, "floor": args.floor, "max_grad": ctx["max_grad"], "hold": args.hold,
+                                 "replay": args.replay}
         print(json.dumps({name: res[name]}), flush=True)
         close(ctx)
     nm = next(iter(res.values()))["n_mobile"]

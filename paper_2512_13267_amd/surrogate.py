@@ -212,6 +212,9 @@ def gate(Y, threshold, floor, mean, flag, stream):
 
 
 TRAINED = __import__("os").path.join(__import__("os").path.dirname(__file__), "weights", "surrogate_e5_h256.npz")
+# the training set of the packaged weights: train.generate(n_boxes, n_macro, seed_k) with the default
+# gradient amplitudes and correlation time (train.input_quantile reproduces its inputs)
+TRAINED_DATA = {"n_boxes": 8192, "n_macro": 520, "seed_k": 3}
 
 
 def load_trained(path: str = TRAINED):

@@ -65,33 +65,78 @@ def phi_feature(phi):
 
 def ou_gradients(n_boxes, n_macro, sd=GRAD_SD, corr=CORR_STEPS, seed=0):
     """(n_macro, n_boxes, 9) piecewise-constant gradients [[a, b, 0], [c, -a, 0], 0]
-    with (a, b, c) stationary OU sequences; sd: a number or one per box."""
+    with (a, b, c) stationary OU sequences; sd and corr (macro steps): a
+    number or one per box."""
     rng = np.random.default_rng(seed)
-    rho = math.exp(-1.0 / corr)
+    rho = np.exp(-1.0 / np.broadcast_to(np.asarray(corr, dtype=np.float64), (n_boxes,)))[:, None]
     sd = np.broadcast_to(np.asarray(sd, dtype=np.float64), (n_boxes,))[:, None]
     x = rng.normal(size=(n_boxes, 3)) * sd
     out = np.zeros((n_macro, n_boxes, 9))
     for t in range(n_macro):
         out[t, :, 0], out[t, :, 1], out[t, :, 3], out[t, :, 4] = x[:, 0], x[:, 1], x[:, 2], -x[:, 0]
-        x = rho * x + math.sqrt(1.0 - rho * rho) * sd * rng.normal(size=(n_boxes, 3))
+        x = rho * x + np.sqrt(1.0 - rho * rho) * sd * rng.normal(size=(n_boxes, 3))
     return out
 
 
-def generate(n_boxes, n_macro, k_micro=K_MICRO, equil=500, seed_k=3, replicas=1, log=print):
+def gradient_histories(n_unique, n_macro, seed_k=3, amp_range=AMP_RANGE, corr_range=(CORR_STEPS, CORR_STEPS),
+                       shear=None):
+    """The polymer fractions and gradient sequences of generate's boxes
+    (its arguments are described there): phis (n_unique,), G
+    (n_macro, n_unique, 9), the per-box amplitudes, correlation times and
+    shear amplitudes."""
+    rng = np.random.default_rng(inputs.SEED_BASE + seed_k)
+    phis_u = rng.uniform(*PHI_RANGE, size=n_unique)
+    sd_u = GRAD_SD * 10.0 ** rng.uniform(*amp_range, size=n_unique)
+    if corr_range[0] == corr_range[1]:
+        corr_u = np.full(n_unique, float(corr_range[0]))
+    else:
+        rng_c = np.random.default_rng(inputs.SEED_BASE + seed_k + 2)
+        corr_u = np.exp(rng_c.uniform(math.log(corr_range[0]), math.log(corr_range[1]), size=n_unique))
+    G_u = ou_gradients(n_unique, n_macro, sd=sd_u, corr=corr_u, seed=inputs.SEED_BASE + seed_k + 1)
+    shear_sd = np.zeros(n_unique)
+    if shear is not None:
+        frac, lo, hi = shear
+        rng_s = np.random.default_rng(inputs.SEED_BASE + seed_k + 3)
+        pick = rng_s.uniform(size=n_unique) < frac
+        shear_sd = np.where(pick, GRAD_SD * 10.0 ** rng_s.uniform(lo, hi, size=n_unique), 0.0)
+        S = ou_gradients(n_unique, n_macro, sd=shear_sd, corr=corr_u, seed=inputs.SEED_BASE + seed_k + 4)
+        G_u[:, :, 1] += S[:, :, 1]
+    return phis_u, G_u, sd_u, corr_u, shear_sd
+
+
+def input_quantile(q, n_boxes, n_macro, seed_k=3, amp_range=AMP_RANGE, corr_range=(CORR_STEPS, CORR_STEPS),
+                   shear=None):
+    """The q-quantile of the Frobenius norm of the newest gradient over the
+    rows of a training set made by generate(n_boxes, n_macro, seed_k, ...)
+    (every box from the step its history is full; boxes restored after a
+    thin cell drop a few rows, which this ignores).  It bounds the inputs the
+    ensemble has seen: the hybrid's input-range gate takes it as max_grad."""
+    _, G, _, _, _ = gradient_histories(n_boxes, n_macro, seed_k, amp_range, corr_range, shear)
+    G = G[HIST - 1:]
+    norm = np.sqrt((G * G).sum(axis=2)).ravel()
+    return float(np.quantile(norm, q))
+
+
+def generate(n_boxes, n_macro, k_micro=K_MICRO, equil=500, seed_k=3, replicas=1, amp_range=AMP_RANGE,
+             corr_range=(CORR_STEPS, CORR_STEPS), shear=None, log=print):
     """Run the micro engine and return device tensors X (n, 129), T (n, 3),
     box (n,) int32, step (n,) int32 and a summary dict.  With replicas = R,
-    boxes come in groups of R sharing start and gradients."""
+    boxes come in groups of R sharing start and gradients.  amp_range: the
+    range of u in the per-box amplitude GRAD_SD x 10^u; corr_range: the range
+    of the per-box correlation time (log-uniform; one value: fixed); shear =
+    (frac, lo, hi): a fraction frac of the boxes also get a simple shear
+    along x, an OU sequence of amplitude GRAD_SD x 10^u, u uniform in
+    [lo, hi], added to the gradient's xy entry (shear-dominated flows at
+    higher rates, as near walls, without the chain stretch of sustained
+    strong extension)."""
     import torch
 
     n_unique = n_boxes // replicas
-    rng = np.random.default_rng(inputs.SEED_BASE + seed_k)
-    phis_u = rng.uniform(*PHI_RANGE, size=n_unique)
+    phis_u, G_u, sd_u, corr_u, shear_sd = gradient_histories(n_unique, n_macro, seed_k, amp_range, corr_range, shear)
     wl_u = inputs.lhmm_boxes(n_unique, polymer_fraction=phis_u, seed_k=seed_k)
     boxes = [b for b in wl_u.boxes for _ in range(replicas)]
     wl = inputs.Workload("surrogate_data", wl_u.params, boxes, 0)
     phis = np.repeat(phis_u, replicas)
-    sd_u = GRAD_SD * 10.0 ** rng.uniform(*AMP_RANGE, size=n_unique)
-    G_u = ou_gradients(n_unique, n_macro, sd=sd_u, seed=inputs.SEED_BASE + seed_k + 1)
     G_host = np.repeat(G_u, replicas, axis=1)
     t0 = time.time()
     m = from_workload(wl, precision="fp32", rng_ids=list(range(n_boxes)))
@@ -148,7 +193,10 @@ def generate(n_boxes, n_macro, k_micro=K_MICRO, equil=500, seed_k=3, replicas=1,
     torch.cuda.synchronize()
     info = {"n_boxes": n_boxes, "replicas": replicas, "n_macro": n_macro, "k_micro": k_micro, "equil": equil,
             "samples": n, "resets": resets, "bad_samples": bad, "seconds": time.time() - t0,
-            "grad_sd_range": [float(sd_u.min()), float(sd_u.max())], "corr_steps": CORR_STEPS}
+            "grad_sd_range": [float(sd_u.min()), float(sd_u.max())],
+            "corr_steps_range": [float(corr_u.min()), float(corr_u.max())],
+            "shear": None if shear is None else {"frac": float(shear[0]), "u_range": [float(shear[1]), float(shear[2])],
+                                                 "boxes": int(np.count_nonzero(shear_sd))}}
     m.close()
     return X[:n], T[:n], box_id[:n], step_id[:n], info
 
@@ -233,8 +281,8 @@ def write_summary(metrics, path, command):
          "Command (MI355X, one GPU):", "", "```", command, "```", "",
          "## Data generation (batched micro-DPD on the GPU)", "", "| quantity | value |", "|---|---|"]
     for k in ("n_boxes", "n_macro", "k_micro", "equil", "samples", "resets", "bad_samples", "grad_sd_range",
-              "corr_steps"):
-        L.append(f"| {k} | {d[k]} |")
+              "corr_steps_range", "shear"):
+        L.append(f"| {k} | {d.get(k)} |")
     steps = d["n_macro"] * d["k_micro"] + d["equil"]
     L += [f"| wall time (s) | {d['seconds']:.1f} |",
           f"| particle-steps/s | {d['n_boxes'] * 4000 * steps / d['seconds']:.3e} |", "",
@@ -275,6 +323,13 @@ def main(argv=None):
     ap.add_argument("--replica-groups", type=int, default=32)
     ap.add_argument("--replicas", type=int, default=8)
     ap.add_argument("--summary", default=None, help="also write a markdown summary here")
+    ap.add_argument("--amp-range", default=f"{AMP_RANGE[0]},{AMP_RANGE[1]}",
+                    help="range of u in the per-box gradient amplitude GRAD_SD x 10^u")
+    ap.add_argument("--corr-range", default=f"{CORR_STEPS},{CORR_STEPS}",
+                    help="range of the per-box gradient correlation time in macro steps (log-uniform)")
+    ap.add_argument("--shear", default=None,
+                    help="frac,lo,hi: that fraction of the boxes also gets a simple-shear OU of amplitude "
+                         "GRAD_SD x 10^u, u in [lo, hi]")
     args = ap.parse_args(argv)
     import torch
 
@@ -282,7 +337,10 @@ def main(argv=None):
         raise SystemExit("the training pipeline runs on the GPU")
     os.makedirs(args.out, exist_ok=True)
     print(f"generating: {args.boxes} boxes x {args.macro} macro steps", flush=True)
-    X, T, box_id, step_id, info = generate(args.boxes, args.macro)
+    amp = tuple(float(v) for v in args.amp_range.split(","))
+    corr = tuple(float(v) for v in args.corr_range.split(","))
+    shear = tuple(float(v) for v in args.shear.split(",")) if args.shear else None
+    X, T, box_id, step_id, info = generate(args.boxes, args.macro, amp_range=amp, corr_range=corr, shear=shear)
     print(json.dumps(info), flush=True)
     sur, metrics = train(X, T, box_id, epochs=args.epochs, augment=not args.no_augment)
     metrics["data"] = info
@@ -291,7 +349,8 @@ def main(argv=None):
     if args.replica_groups > 0:
         nb = args.replica_groups * args.replicas
         print(f"replicas: {args.replica_groups} groups x {args.replicas}", flush=True)
-        Xr, Tr, br, sr, rinfo = generate(nb, min(args.macro, 200), seed_k=5, replicas=args.replicas)
+        Xr, Tr, br, sr, rinfo = generate(nb, min(args.macro, 200), seed_k=5, replicas=args.replicas, amp_range=amp,
+                                         corr_range=corr, shear=shear)
         M, _ = evaluate(sur, Xr, Tr, 4096)
         grp = (br // args.replicas).long() * 1000000 + sr.long()
         uniq, inv, counts = torch.unique(grp, return_inverse=True, return_counts=True)

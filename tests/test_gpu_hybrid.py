@@ -337,3 +337,42 @@ def test_gate_and_replay_follow_the_oracle_loop_surrogate_mode(torch_gpu, orc):
     samples) after every step, and the others take the surrogate mean (zero
     here); everything follows the oracle loop to rounding."""
     _replay_case(torch_gpu, orc, "surrogate")
+
+
+def test_input_range_gate_flags_the_gradients_above_max_grad(torch_gpu, orc):
+    """The input-range gate (max_grad > 0) flags exactly the particles whose
+    micro gradient, from the oracle's SPH step, has Frobenius norm above
+    max_grad; the spread gate is kept shut (floor 1e30).  max_grad sits in a
+    gap of the sorted norms, so rounding cannot move a particle across it."""
+    from paper_2512_13267_amd import inputs, lhmm, micro, surrogate
+
+    mac = inputs.cylinder_array(n=16, force=2.0)
+    q = mac.params
+    nm = mac.r.shape[0] - q["n_fixed"]
+    v0 = mac.v.copy()
+    v0[:nm, 0] += 0.4 * np.sin(2.0 * np.pi * mac.r[:nm, 1])  # a sheared start, so gradients differ
+    r_o, v_o = mac.r.copy(), v0.copy()
+    L = orc.sph_step(q, r_o, v_o, orc.sph_polymer_stress(q, np.zeros((mac.r.shape[0], 6))))
+    norm = np.sqrt((L[:nm].reshape(nm, 9) ** 2).sum(axis=1))
+    srt = np.sort(norm)
+    gaps = [(srt[k + 1] - srt[k], k) for k in range(nm // 4, 3 * nm // 4)]
+    g, k = max(gaps)
+    assert g > 1e-6 * srt[k + 1]
+    max_grad = 0.5 * (srt[k] + srt[k + 1])
+    expect = norm > max_grad
+    wl = inputs.lhmm_boxes(nm, n_particles=600, polymer_fraction=0.2, seed_k=11)
+    m = micro.from_workload(wl, precision="fp32")
+    m.step(torch_gpu.zeros((nm, 9), dtype=torch_gpu.float64, device="cuda"), 5)
+    s = lhmm.Sph(q, mac.r, v0)
+    mem = surrogate.init_members(3, 129, 64, 3, seed=1)
+    sur = surrogate.Surrogate(mem, 129, 64, 3, max_batch=nm)
+    hy = lhmm.Hybrid(s, m, sur, phi=np.zeros(nm), mode="surrogate", k_micro=10, hold=1, replay=0, threshold=1.0,
+                     floor=1e30, max_grad=max_grad)
+    st = hy.step()
+    _, on = hy.state()
+    print(f"max_grad {max_grad:.6g}: {int(expect.sum())} of {nm} above it", flush=True)
+    assert st["n_out_of_range"] == int(expect.sum()) == st["n_flagged"] == st["n_dpd"]
+    assert np.array_equal(on.astype(bool), expect)
+    hy.close()
+    for e in (sur, m, s):
+        e.close()
