@@ -585,14 +585,17 @@ int lhmm_sur_destroy(lhmm_sur* s);
  * and the gate flags particles whose members disagree or (max_grad > 0)
  * whose gradient lies outside the given input range; a flagged particle
  * runs plain micro-DPD for the next `hold` steps.  A particle entering DPD
- * gets its micro-domain back from the equilibrated snapshot taken at
- * create time and replays its last `replay` gradient samples (k_micro micro
- * steps each) before the interval, so the polymer memory of its box matches
- * its history.  Boxes on DPD advance k_micro steps and their mean stress is
- * used for their particles; the others take the surrogate's mean.  In
- * LHMM_HYBRID_DPD mode every box runs every step (the reference run).  In
- * both modes a box whose cell became thin (LHMM_FLAG_THIN) is restored and
- * replayed the same way after its stress has been used.
+ * without a live box gets its micro-domain back from the equilibrated
+ * snapshot taken at create time and replays its last `replay` gradient
+ * samples (k_micro micro steps each) before the interval, so the polymer
+ * memory of its box matches its history.  Boxes on DPD advance k_micro steps
+ * and their mean stress is used for their particles; the others take the
+ * surrogate's mean.  With a warm band (warm_frac > 0) the boxes of unflagged
+ * particles whose |L| lies in the band advance too, unused, and start from
+ * the snapshot without replay when they join.  In LHMM_HYBRID_DPD mode every
+ * box runs every step (the reference run).  In both modes a box whose cell
+ * became thin (LHMM_FLAG_THIN) is restored and replayed the same way after
+ * its stress has been used (a warming box: restored only).
  *
  * The SPH, micro and surrogate engines must share one stream; the micro
  * engine holds one box per mobile SPH particle and must already be
@@ -619,6 +622,12 @@ typedef struct {
                            L has Frobenius norm above this is flagged too
                            (the ensemble's spread does not grow where all
                            members extrapolate alike); 0 disables it        */
+    float warm_frac;    /* warm band (with max_grad > 0; 0 disables it): a
+                           particle whose |L| lies above warm_frac x
+                           max_grad but is not flagged keeps its box live
+                           on DPD without using its stress, so that a later
+                           flag finds the box's memory built (no replay);
+                           0 <= warm_frac <= 1                              */
 } lhmm_hybrid_params;
 
 typedef struct {
@@ -629,6 +638,7 @@ typedef struct {
     int32_t n_flagged;       /* gate flags in it                              */
     int32_t n_reset;         /* thin boxes restored after it                  */
     int32_t n_out_of_range;  /* flags of the input-range gate in it           */
+    int32_t n_warm;          /* boxes advanced in the warm band in it         */
 } lhmm_hybrid_stats;
 
 /* phi: HOST n_mobile FP32, the polymer-fraction feature of each

@@ -85,13 +85,13 @@ class LhmmSurParams(C.Structure):
 class LhmmHybridParams(C.Structure):
     _fields_ = [("mode", C.c_int32), ("k_micro", C.c_int32), ("hold", C.c_int32), ("replay", C.c_int32),
                 ("threshold", C.c_float), ("floor", C.c_float), ("grad_scale", C.c_float),
-                ("stress_scale", C.c_float), ("max_grad", C.c_float)]
+                ("stress_scale", C.c_float), ("max_grad", C.c_float), ("warm_frac", C.c_float)]
 
 
 class LhmmHybridStats(C.Structure):
     _fields_ = [("macro_step", C.c_int64), ("micro_box_steps", C.c_int64), ("n_dpd", C.c_int32),
                 ("n_entered", C.c_int32), ("n_flagged", C.c_int32), ("n_reset", C.c_int32),
-                ("n_out_of_range", C.c_int32)]
+                ("n_out_of_range", C.c_int32), ("n_warm", C.c_int32)]
 
 
 HYBRID_SURROGATE = 0

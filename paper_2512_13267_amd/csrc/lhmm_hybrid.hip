@@ -47,23 +47,27 @@ struct lhmm_hybrid {
     // host (pinned)
     unsigned *gflag_h = nullptr, *on_h = nullptr;
     std::vector<int> hold_left;
-    std::vector<unsigned char> was_on;
+    std::vector<unsigned char> was_on;   // DPD stress used in the last step
+    std::vector<unsigned char> was_run;  // box advanced in the last step (used or warming)
     std::vector<uint32_t> mflags;
 };
 
 namespace {
 
 // Input-range gate: bit 1 of flag[b] is set when the micro gradient of
-// particle b (row-major 3 x 3, FP64) has squared Frobenius norm above max2;
-// the sum of squares is formed in this fixed order without fused products,
-// so a host computation in FP64 takes the same decision.
-__global__ void k_input_gate(const double* __restrict__ L, int n, double max2, unsigned* __restrict__ flag) {
+// particle b (row-major 3 x 3, FP64) has squared Frobenius norm above max2,
+// bit 2 when above warm2 (the warm band below it); the sum of squares is
+// formed in this fixed order without fused products, so a host computation
+// in FP64 takes the same decisions.
+__global__ void k_input_gate(const double* __restrict__ L, int n, double max2, double warm2,
+                             unsigned* __restrict__ flag) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
     const double* l = L + 9 * (long)b;
     double q = 0.0;
     for (int k = 0; k < 9; ++k) q = __dadd_rn(q, __dmul_rn(l[k], l[k]));
     if (q > max2) flag[b] |= 2u;
+    if (q > warm2) flag[b] |= 4u;
 }
 
 __global__ void k_accumulate(const double* __restrict__ x, long n, double* __restrict__ sum) {
@@ -128,6 +132,8 @@ int lhmm_hybrid_create(const lhmm_hybrid_params* p, lhmm_sph* sph, lhmm_micro* m
     if (!(p->grad_scale > 0.0f) || !(p->stress_scale > 0.0f) || !(p->threshold >= 0.0f) || !(p->floor >= 0.0f) ||
         !(p->max_grad >= 0.0f))
         return lhmm_fail(LHMM_ERR_ARG, "scales must be positive, threshold, floor and max_grad non-negative");
+    if (!(p->warm_frac >= 0.0f && p->warm_frac <= 1.0f))
+        return lhmm_fail(LHMM_ERR_ARG, "warm_frac must lie in [0, 1]");
     int n = 0, nm = 0;
     lhmm_sph_counts(sph, &n, &nm);
     int32_t nb = 0;
@@ -198,6 +204,7 @@ int lhmm_hybrid_create(const lhmm_hybrid_params* p, lhmm_sph* sph, lhmm_micro* m
     }
     h->hold_left.assign(m, 0);
     h->was_on.assign(m, 0);
+    h->was_run.assign(m, 0);
     *out = h;
     return LHMM_OK;
 }
@@ -228,38 +235,57 @@ int lhmm_hybrid_step(lhmm_hybrid* h, lhmm_hybrid_stats* stats) {
             rc = lhmm_sur_gate(h->Y, h->E, nm, 3, h->p.threshold, h->p.floor, h->mean, h->gflag, h->stream);
         if (rc != LHMM_OK) return rc;
         if (h->p.max_grad > 0.0f) {
-            const double mg = (double)h->p.max_grad;
-            k_input_gate<<<(nm + 255) / 256, 256, 0, h->stream>>>(h->gradL, nm, mg * mg, h->gflag);
+            const double mg = (double)h->p.max_grad, wg = mg * (h->p.warm_frac > 0.0f ? (double)h->p.warm_frac : 1.0);
+            k_input_gate<<<(nm + 255) / 256, 256, 0, h->stream>>>(h->gradL, nm, mg * mg, wg * wg, h->gflag);
             LHMM_HIPCHK(hipGetLastError());
         }
         LHMM_HIPCHK(hipMemcpyAsync(h->gflag_h, h->gflag, nm * sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
         LHMM_HIPCHK(hipStreamSynchronize(h->stream));
+        // run: boxes advanced this step, the flagged ones (their DPD stress
+        // is used) and, with a warm band, those whose gradient lies in it
+        // (kept live so that a later flag finds their memory built);
+        // entering: flagged boxes that were not live, restored and replayed;
+        // warming: band boxes that were not live, restored only
+        std::vector<int> run, warming;
+        const bool band = h->p.max_grad > 0.0f && h->p.warm_frac > 0.0f;
         for (int b = 0; b < nm; ++b) {
-            if (h->gflag_h[b]) {
+            const unsigned fl = h->gflag_h[b];
+            if (fl & 3u) {
                 h->hold_left[b] = h->p.hold;
                 S.n_flagged += 1;
-                if (h->gflag_h[b] & 2u) S.n_out_of_range += 1;
+                if (fl & 2u) S.n_out_of_range += 1;
             }
             const bool is_on = h->hold_left[b] > 0;
+            const bool is_warm = !is_on && band && (fl & 4u);
             if (is_on) {
                 on.push_back(b);
-                if (!h->was_on[b]) entering.push_back(b);
+                if (!h->was_run[b]) entering.push_back(b);
                 h->hold_left[b] -= 1;
             }
+            if (is_warm) {
+                S.n_warm += 1;
+                if (!h->was_run[b]) warming.push_back(b);
+            }
+            if (is_on || is_warm) run.push_back(b);
             h->was_on[b] = is_on;
+            h->was_run[b] = is_on || is_warm;
             h->on_h[b] = is_on ? 1u : 0u;
         }
         S.n_dpd = (int)on.size();
         S.n_entered = (int)entering.size();
-        // entering boxes relive the intervals before this one
+        // entering boxes relive the intervals before this one; warming boxes
+        // start from the snapshot
         rc = restore_and_replay(h, entering, t - h->p.replay, t - 1);
+        if (rc == LHMM_OK) rc = restore_and_replay(h, warming, 0, -1);
         if (rc != LHMM_OK) return rc;
-        // 4: DPD where the gate asked for it
-        if (!on.empty()) {
-            rc = lhmm_micro_step_subset(h->micro, h->gradL, h->p.k_micro, h->sigma_dpd, on.data(), (int32_t)on.size());
+        // 4: DPD where the gate asked for it, and in the warm band
+        if (!run.empty()) {
+            rc = lhmm_micro_step_subset(h->micro, h->gradL, h->p.k_micro, h->sigma_dpd, run.data(),
+                                        (int32_t)run.size());
             if (rc != LHMM_OK) return rc;
-            h->box_steps += (long long)h->p.k_micro * (long long)on.size();
+            h->box_steps += (long long)h->p.k_micro * (long long)run.size();
         }
+        on.swap(run);  // the thin-cell check below covers every box that moved
         LHMM_HIPCHK(hipMemcpyAsync(h->on_d, h->on_h, nm * sizeof(unsigned), hipMemcpyHostToDevice, h->stream));
         rc = lhmm_sur_blend(h->mean, h->on_d, h->sigma_dpd, nm, h->p.stress_scale, h->sigma, h->stream);
         if (rc != LHMM_OK) return rc;
@@ -268,11 +294,15 @@ int lhmm_hybrid_step(lhmm_hybrid* h, lhmm_hybrid_stats* stats) {
     if (!on.empty()) {
         rc = lhmm_micro_flags(h->micro, h->mflags.data(), 1);
         if (rc != LHMM_OK) return rc;
-        std::vector<int> reset;
+        // a box whose stress is used relives its history; a warming box
+        // starts again from the snapshot
+        std::vector<int> reset, reset_warm;
         for (int b : on)
-            if (h->mflags[b] & (LHMM_FLAG_THIN | LHMM_FLAG_CELL)) reset.push_back(b);
-        S.n_reset = (int)reset.size();
+            if (h->mflags[b] & (LHMM_FLAG_THIN | LHMM_FLAG_CELL))
+                (h->p.mode == LHMM_HYBRID_DPD || h->was_on[b] ? reset : reset_warm).push_back(b);
+        S.n_reset = (int)(reset.size() + reset_warm.size());
         rc = restore_and_replay(h, reset, t + 1 - h->p.replay, t);
+        if (rc == LHMM_OK) rc = restore_and_replay(h, reset_warm, 0, -1);
         if (rc != LHMM_OK) return rc;
     }
     const long n6 = 6L * h->n;

@@ -96,13 +96,14 @@ class Hybrid:
     micro engine must be equilibrated."""
 
     def __init__(self, sph: Sph, micro: Micro, sur=None, phi=None, mode="surrogate", k_micro=50, hold=10,
-                 replay=31, threshold=0.05, floor=1.0, grad_scale=1.0, stress_scale=1.0, max_grad=0.0):
+                 replay=31, threshold=0.05, floor=1.0, grad_scale=1.0, stress_scale=1.0, max_grad=0.0,
+                 warm_frac=0.0):
         from ._lib import HYBRID_DPD, HYBRID_SURROGATE, LhmmHybridParams
 
         p = LhmmHybridParams(mode={"surrogate": HYBRID_SURROGATE, "dpd": HYBRID_DPD}[mode], k_micro=int(k_micro),
                              hold=int(hold), replay=int(replay), threshold=float(threshold), floor=float(floor),
                              grad_scale=float(grad_scale), stress_scale=float(stress_scale),
-                             max_grad=float(max_grad))
+                             max_grad=float(max_grad), warm_frac=float(warm_frac))
         n_mobile = micro.n_boxes
         phi = np.ascontiguousarray(np.zeros(n_mobile) if phi is None else phi, dtype=np.float32)
         if phi.size != n_mobile:

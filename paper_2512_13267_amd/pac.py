@@ -52,6 +52,7 @@ PHI = 0.1
 GATE_THRESHOLD = 0.05
 GATE_FLOOR = 0.35  # surrogate output units: the in-distribution 0.99 quantile of the spread / GATE_THRESHOLD
 GATE_INPUT_Q = 0.9999  # input-range gate: this quantile of the training set's gradient norms
+GATE_WARM = 0.9  # warm band: boxes of particles above this fraction of the bound stay live, unused
 HOLD = 10
 # history samples a restored micro-domain relives (on entry to DPD and after a
 # thin cell): at 31 the boxes next to the cylinder, under shear rates up to
@@ -68,7 +69,7 @@ def gate_max_grad(q=GATE_INPUT_Q):
 
 
 def build(mode, seed_k=41, n_lattice=64, n_particles=4000, equil=500, k_micro=50, threshold=GATE_THRESHOLD,
-          floor=GATE_FLOOR, hold=HOLD, replay=REPLAY, weights=None, max_grad=None):
+          floor=GATE_FLOOR, hold=HOLD, replay=REPLAY, weights=None, max_grad=None, warm_frac=GATE_WARM):
     """max_grad: the input-range gate's bound (None: gate_max_grad() for the
     packaged weights, 0 for other weights; 0 disables it)."""
     import torch
@@ -88,7 +89,8 @@ def build(mode, seed_k=41, n_lattice=64, n_particles=4000, equil=500, k_micro=50
         max_grad = gate_max_grad() if weights is None else 0.0
     hy = lhmm.Hybrid(s, m, sur, phi=np.full(nm, phi_feature(PHI), dtype=np.float32),
                      mode="surrogate" if mode == "surrogate" else "dpd", k_micro=k_micro, hold=hold, replay=replay,
-                     threshold=threshold, floor=floor, grad_scale=gscale, stress_scale=sscale, max_grad=max_grad)
+                     threshold=threshold, floor=floor, grad_scale=gscale, stress_scale=sscale, max_grad=max_grad,
+                     warm_frac=warm_frac if max_grad > 0 else 0.0)
     torch.cuda.synchronize()
     return {"mac": mac, "micro": m, "sph": s, "sur": sur, "hy": hy, "nm": nm, "max_grad": max_grad}
 
@@ -116,6 +118,7 @@ def run(ctx, steps, avg, log=print, label=""):
     resets = 0
     dpd_steps = []  # macro steps (1-based) with any particle on DPD
     n_range = 0
+    n_warm = 0
     t0 = time.time()
     st = None
     for k in range(steps):
@@ -129,6 +132,7 @@ def run(ctx, steps, avg, log=print, label=""):
         if st["n_dpd"]:
             dpd_steps.append(k + 1)
         n_range += st["n_out_of_range"]
+        n_warm += st["n_warm"]
         entered += st["n_entered"]
         resets += st["n_reset"]
         if (k + 1) % 50 == 0:
@@ -145,6 +149,7 @@ def run(ctx, steps, avg, log=print, label=""):
     out = {"steps": steps, "seconds": secs, "macro_steps_per_s": steps / secs,
            "micro_box_steps": st["micro_box_steps"], "fallback_rate": n_dpd / (steps * nm),
            "entered": entered, "resets": resets, "out_of_range_rate": n_range / (steps * nm),
+           "warm_rate": n_warm / (steps * nm),
            "macro_steps_with_dpd": len(dpd_steps),
            "last_macro_step_with_dpd": dpd_steps[-1] if dpd_steps else 0}
     return out, (means if isinstance(avg, (list, tuple)) else full)
@@ -207,6 +212,7 @@ def main(argv=None):
     ap.add_argument("--hold", type=int, default=HOLD)
     ap.add_argument("--calibrate", action="store_true", help="print the in-distribution gate floor and exit")
     ap.add_argument("--replay", type=int, default=REPLAY)
+    ap.add_argument("--warm", type=float, default=GATE_WARM, help="warm band as a fraction of max_grad (0: none)")
     ap.add_argument("--max-grad", type=float, default=None,
                     help="input-range gate bound (default: the packaged weights' training quantile; 0 disables)")
     ap.add_argument("--means-out", default=None, help="save the runs' mean stresses (npz)")
@@ -235,13 +241,13 @@ def main(argv=None):
         mode = "surrogate" if name.startswith("surrogate") else "dpd"
         th = float(name.split("@")[1]) if "@" in name else GATE_THRESHOLD
         ctx = build(mode, seed_k=42 if name == "dpd2" else 41, threshold=th, floor=args.floor, hold=args.hold,
-                    replay=args.replay, weights=args.weights, max_grad=args.max_grad)
+                    replay=args.replay, weights=args.weights, max_grad=args.max_grad, warm_frac=args.warm)
         print(f"{name}: {ctx['nm']} micro-domains", flush=True)
         res[name], means[name] = run(ctx, args.steps, windows, label=name)
         res[name]["n_mobile"] = ctx["nm"]
         if mode == "surrogate":
-            res[name]["gate"] = {"threshold": th, "floor": args.floor, "max_grad": ctx["max_grad"], "hold": args.hold,
-                                 "replay": args.replay}
+            res[name]["gate"] = {"threshold": th, "floor": args.floor, "max_grad": ctx["max_grad"], "warm": args.warm,
+                                 "hold": args.hold, "replay": args.replay}
         print(json.dumps({name: res[name]}), flush=True)
         close(ctx)
     nm = next(iter(res.values()))["n_mobile"]

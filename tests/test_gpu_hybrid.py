@@ -16,7 +16,9 @@
   surrogate mode with a gate built to flag a chosen set (entry at the first
   step), follow an oracle loop (oracle micro-boxes sharing one random-force
   counter, the equilibrated snapshot, FP32 history ring and its replay
-  gradients) to rounding, FP64 micro-boxes.
+  gradients) to rounding, FP64 micro-boxes;
+* the input-range gate flags exactly the particles whose oracle gradient
+  norm exceeds max_grad.
 """
 import numpy as np
 import pytest
@@ -339,12 +341,10 @@ def test_gate_and_replay_follow_the_oracle_loop_surrogate_mode(torch_gpu, orc):
     _replay_case(torch_gpu, orc, "surrogate")
 
 
-def test_input_range_gate_flags_the_gradients_above_max_grad(torch_gpu, orc):
-    """The input-range gate (max_grad > 0) flags exactly the particles whose
-    micro gradient, from the oracle's SPH step, has Frobenius norm above
-    max_grad; the spread gate is kept shut (floor 1e30).  max_grad sits in a
-    gap of the sorted norms, so rounding cannot move a particle across it."""
-    from paper_2512_13267_amd import inputs, lhmm, micro, surrogate
+def _sheared_start(orc):
+    """The cylinder array started with a sheared velocity field, and the
+    oracle's gradient norms of the first SPH step (mobile particles)."""
+    from paper_2512_13267_amd import inputs
 
     mac = inputs.cylinder_array(n=16, force=2.0)
     q = mac.params
@@ -354,25 +354,66 @@ def test_input_range_gate_flags_the_gradients_above_max_grad(torch_gpu, orc):
     r_o, v_o = mac.r.copy(), v0.copy()
     L = orc.sph_step(q, r_o, v_o, orc.sph_polymer_stress(q, np.zeros((mac.r.shape[0], 6))))
     norm = np.sqrt((L[:nm].reshape(nm, 9) ** 2).sum(axis=1))
+    return mac, q, nm, v0, norm
+
+
+def _gap_value(norm, lo, hi):
+    """A value inside the widest gap of the sorted norms between the
+    quantiles lo and hi, so rounding cannot move a particle across it."""
     srt = np.sort(norm)
-    gaps = [(srt[k + 1] - srt[k], k) for k in range(nm // 4, 3 * nm // 4)]
-    g, k = max(gaps)
+    n = srt.size
+    g, k = max((srt[k + 1] - srt[k], k) for k in range(int(lo * n), int(hi * n)))
     assert g > 1e-6 * srt[k + 1]
-    max_grad = 0.5 * (srt[k] + srt[k + 1])
-    expect = norm > max_grad
+    return 0.5 * (srt[k] + srt[k + 1])
+
+
+def _hybrid_one_step(torch, mac, q, nm, v0, max_grad, warm_frac):
+    from paper_2512_13267_amd import inputs, lhmm, micro, surrogate
+
     wl = inputs.lhmm_boxes(nm, n_particles=600, polymer_fraction=0.2, seed_k=11)
     m = micro.from_workload(wl, precision="fp32")
-    m.step(torch_gpu.zeros((nm, 9), dtype=torch_gpu.float64, device="cuda"), 5)
+    m.step(torch.zeros((nm, 9), dtype=torch.float64, device="cuda"), 5)
     s = lhmm.Sph(q, mac.r, v0)
     mem = surrogate.init_members(3, 129, 64, 3, seed=1)
     sur = surrogate.Surrogate(mem, 129, 64, 3, max_batch=nm)
     hy = lhmm.Hybrid(s, m, sur, phi=np.zeros(nm), mode="surrogate", k_micro=10, hold=1, replay=0, threshold=1.0,
-                     floor=1e30, max_grad=max_grad)
+                     floor=1e30, max_grad=max_grad, warm_frac=warm_frac)
     st = hy.step()
-    _, on = hy.state()
-    print(f"max_grad {max_grad:.6g}: {int(expect.sum())} of {nm} above it", flush=True)
-    assert st["n_out_of_range"] == int(expect.sum()) == st["n_flagged"] == st["n_dpd"]
-    assert np.array_equal(on.astype(bool), expect)
+    sig, on = hy.state()
     hy.close()
     for e in (sur, m, s):
         e.close()
+    return st, sig, on
+
+
+def test_input_range_gate_flags_the_gradients_above_max_grad(torch_gpu, orc):
+    """The input-range gate (max_grad > 0) flags exactly the particles whose
+    micro gradient, from the oracle's SPH step, has Frobenius norm above
+    max_grad; the spread gate is kept shut (floor 1e30)."""
+    mac, q, nm, v0, norm = _sheared_start(orc)
+    max_grad = _gap_value(norm, 0.25, 0.75)
+    expect = norm > max_grad
+    st, _, on = _hybrid_one_step(torch_gpu, mac, q, nm, v0, max_grad, 0.0)
+    print(f"max_grad {max_grad:.6g}: {int(expect.sum())} of {nm} above it", flush=True)
+    assert st["n_out_of_range"] == int(expect.sum()) == st["n_flagged"] == st["n_dpd"]
+    assert st["n_warm"] == 0
+    assert np.array_equal(on.astype(bool), expect)
+
+
+def test_warm_band_advances_boxes_without_using_them(torch_gpu, orc):
+    """With a warm band the particles whose gradient norm lies between
+    warm_frac x max_grad and max_grad get their boxes advanced (n_warm of
+    them, k_micro box-steps each) while the stress handed to SPH and the DPD
+    mask stay exactly those of the run without the band."""
+    mac, q, nm, v0, norm = _sheared_start(orc)
+    max_grad = _gap_value(norm, 0.6, 0.9)
+    lo = _gap_value(norm[norm < max_grad], 0.4, 0.8)
+    warm_frac = lo / max_grad
+    warm_frac = float(np.float32(warm_frac))
+    band = (norm > warm_frac * max_grad) & ~(norm > max_grad)
+    st0, sig0, on0 = _hybrid_one_step(torch_gpu, mac, q, nm, v0, max_grad, 0.0)
+    st1, sig1, on1 = _hybrid_one_step(torch_gpu, mac, q, nm, v0, max_grad, warm_frac)
+    print(f"band: {int(band.sum())} particles, flagged {st1['n_dpd']}", flush=True)
+    assert band.sum() > 0 and st1["n_warm"] == int(band.sum())
+    assert st1["micro_box_steps"] - st0["micro_box_steps"] == 10 * int(band.sum())
+    assert np.array_equal(on0, on1) and np.array_equal(sig0, sig1)
