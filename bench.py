@@ -206,8 +206,10 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the engine's default launch parameters instead of the tuned (cached) ones")
+    ap.add_argument("--autotune", action="store_true",
+                    help="search the launch parameters (lhmm_micro_autotune, cached) instead of keeping the engine's "
+                         "defaults; its 20-step trials are noisier than the differences between the best configurations")
+    ap.add_argument("--no-autotune", action="store_true", help="the default (kept for older command lines)")
     ap.add_argument("--timing-steps", type=int, default=100)
     ap.add_argument("--lhmm-steps", type=int, default=200,
                     help="macro steps of the coupled reverse-Poiseuille run (0 skips it)")
@@ -249,7 +251,7 @@ def main():
     G = torch.tensor(np.stack([b.L for b in wl.boxes]), dtype=torch.float64, device="cuda").contiguous()
 
     tuning = None
-    if not args.no_autotune:
+    if args.autotune and not args.no_autotune:
         from paper_2512_13267_amd import autotune
 
         tuning = autotune.tune(m, G, [b.N for b in wl.boxes], "fp32")
