@@ -223,7 +223,11 @@ int lhmm_micro_step_subset(lhmm_micro* m, const double* gradL, int32_t n_steps, 
  *                boxes, two thirds of the particles, in the last), each
  *                binned and force-evaluated on its own stream, so that the
  *                force pass of small boxes runs while large boxes are still
- *                being binned (1: one stream). */
+ *                being binned (1: one stream);
+ *   bin_split:   0, or 256 .. 4096: with groups > 1 the group of the largest
+ *                boxes is binned by several workgroups per box, over chunks
+ *                of this many particles (count, scan and scatter passes), so
+ *                that one box's sort is not held by one compute unit. */
 typedef struct {
     int32_t queue_depth;
     int32_t drain;
@@ -233,11 +237,12 @@ typedef struct {
     int32_t prune;
     int32_t fuse_bin;
     int32_t groups;
+    int32_t bin_split;
 } lhmm_micro_config;
 
 /* Set / read the launch parameters (defaults: depth 16, drain 12; busy rule
- * off; 1024 binning threads; fused binning; two box groups;
- * 50-step graphs; no pruning: with
+ * off; 1024 binning threads; fused binning; two box groups; no split
+ * binning (measured slower); 50-step graphs; no pruning: with
  * cells barely wider than the cutoff it skips little and costs more).  Set waits for the
  * engine and drops its captured graphs.  Errors: ARG. */
 int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg);

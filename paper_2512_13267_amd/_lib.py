@@ -75,7 +75,7 @@ class LhmmSphParams(C.Structure):
 
 class LhmmMicroConfig(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("queue_depth", "drain", "busy_lanes", "bin_threads", "graph_chunk", "prune", "fuse_bin",
-                                         "groups")]
+                                         "groups", "bin_split")]
 
 
 class LhmmSurParams(C.Structure):

@@ -703,6 +703,57 @@ __device__ __forceinline__ void cell_position(real s0, real s1, real s2, real h0
     z = h22 * s2;
 }
 
+// From the cell counts cnt[0 .. ncell) of box b (LDS): the cell starts
+// (cell_start and cnt[k] <- start of cell k, cnt[ncell] <- n), then the
+// search layout's starts (gcell_start) and every column's offsets from cell
+// order to its three segments of the search layout (col_off: the column's
+// cells, lo_off: the image of its top zsub cells below it, hi_off: the image
+// of its bottom zsub cells above it).  Ends with a barrier.
+template <int BT>
+__device__ void search_layout(const Ctx& C, const BoxInfo& B, const BoxDyn& D, int ncell, int* cnt, int* col_off,
+                              int* lo_off, int* hi_off, int* wsum) {
+    int* start = C.cell_start + B.cell_off;
+    int* gstart = C.gcell_start + B.gcell_off;
+    block_scan<BT>(ncell, wsum, [&](int k) { return cnt[k]; }, [&](int k, int excl) {
+        start[k] = excl;
+        cnt[k] = excl;
+    });
+    __syncthreads();
+    const int n2 = D.nc[2], zs = B.zsub, gn2 = n2 + 2 * zs, ncol = D.nc[0] * D.nc[1];
+    const float inv_gn2 = 1.0f / (float)gn2;
+    // images before each column (its top and bottom zsub cells' particles
+    // appear once more), scanned over columns
+    __shared__ int n_images;
+    block_scan<BT>(
+        ncol, wsum,
+        [&](int col) {
+            const int k = col * n2;
+            return (cnt[k + n2] - cnt[k + n2 - zs]) + (cnt[k + zs] - cnt[k]);
+        },
+        [&](int col, int excl) {
+            if (col == ncol) {
+                n_images = excl;
+                return;
+            }
+            const int k = col * n2;
+            const int first = cnt[k] + excl, top = cnt[k + n2] - cnt[k + n2 - zs];
+            lo_off[col] = first - cnt[k + n2 - zs];
+            col_off[col] = first + top - cnt[k];
+            hi_off[col] = first + top + (cnt[k + n2] - cnt[k]) - cnt[k];
+        });
+    __syncthreads();
+    // starts of the search-layout cells: a segment's offset plus the start
+    // of the cell it repeats
+    for (int g = threadIdx.x; g < ncol * gn2; g += BT) {
+        const int col = div_small(g, inv_gn2), zg = g - col * gn2, k = col * n2;
+        gstart[g] = zg < zs ? lo_off[col] + cnt[k + n2 - zs + zg]
+                            : (zg < zs + n2 ? col_off[col] + cnt[k + zg - zs] : hi_off[col] + cnt[k + zg - zs - n2]);
+    }
+    if (threadIdx.x == 0) gstart[ncol * gn2] = B.n + n_images;
+    __threadfence_block();
+    __syncthreads();
+}
+
 // One workgroup per box: counting sort by cell in LDS, writing each
 // particle's velocity record (velocity, local index) in cell order, sorted by
 // index inside every cell so all later sums have a fixed order, and its
@@ -813,49 +864,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
         for (int k = (int)threadIdx.x + KEEP * BIN_THREADS; k < B.n; k += BIN_THREADS) atomicAdd(&cnt[pc[k]], 1);
     }
     __syncthreads();
-    // cell starts (cnt[k] <- start of cell k, cnt[ncell] <- n), then the
-    // search layout's starts and every cell's offsets into it
-    int* start = C.cell_start + B.cell_off;
-    int* gstart = C.gcell_start + B.gcell_off;
-    block_scan<BIN_THREADS>(ncell, wsum, [&](int k) { return cnt[k]; }, [&](int k, int excl) {
-        start[k] = excl;
-        cnt[k] = excl;
-    });
-    __syncthreads();
-    const int n2 = D.nc[2], zs = B.zsub, gn2 = n2 + 2 * zs, ncol = D.nc[0] * D.nc[1];
-    const float inv_gn2 = 1.0f / (float)gn2;
-    // images before each column (its top and bottom zsub cells' particles
-    // appear once more), scanned over columns; each column's offsets from
-    // cell order to its three segments of the search layout
-    __shared__ int n_images;
-    block_scan<BIN_THREADS>(
-        ncol, wsum,
-        [&](int col) {
-            const int k = col * n2;
-            return (cnt[k + n2] - cnt[k + n2 - zs]) + (cnt[k + zs] - cnt[k]);
-        },
-        [&](int col, int excl) {
-            if (col == ncol) {
-                n_images = excl;
-                return;
-            }
-            const int k = col * n2;
-            const int first = cnt[k] + excl, top = cnt[k + n2] - cnt[k + n2 - zs];
-            lo_off[col] = first - cnt[k + n2 - zs];
-            col_off[col] = first + top - cnt[k];
-            hi_off[col] = first + top + (cnt[k + n2] - cnt[k]) - cnt[k];
-        });
-    __syncthreads();
-    // starts of the search-layout cells: a segment's offset plus the start
-    // of the cell it repeats
-    for (int g = threadIdx.x; g < ncol * gn2; g += BIN_THREADS) {
-        const int col = div_small(g, inv_gn2), zg = g - col * gn2, k = col * n2;
-        gstart[g] = zg < zs ? lo_off[col] + cnt[k + n2 - zs + zg]
-                            : (zg < zs + n2 ? col_off[col] + cnt[k + zg - zs] : hi_off[col] + cnt[k + zg - zs - n2]);
-    }
-    if (threadIdx.x == 0) gstart[ncol * gn2] = B.n + n_images;
-    __threadfence_block();
-    __syncthreads();
+    search_layout<BIN_THREADS>(C, B, D, ncell, cnt, col_off, lo_off, hi_off, wsum);
+    const int* start = C.cell_start + B.cell_off;
+    const int n2 = D.nc[2], zs = B.zsub;
     typename R::T* pv = (typename R::T*)C.cell_pv + 2 * (size_t)B.off;
     typename R::T* srec = (typename R::T*)C.srec + 2 * B.off;
     const real* s = (const real*)C.s;
@@ -953,6 +964,162 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
         const int k = R::id(v), g = B.off + k;
         pv[2 * q + 1] = R::make(c[g], c[N + g], c[2 * N + g], k);
         write_search(q, pc[k], v.x, v.y, v.z);
+    }
+}
+
+// Binning of large boxes over several workgroups each.  The selected boxes
+// (C.sel) are cut into chunks of `chunk` consecutive particles; per step:
+//   k_cell_step (one thread per box), then
+//   k_bin_count   (one workgroup per chunk): half kick and drift of the
+//                 chunk's particles, their cells (pcell), the chunk's cell
+//                 counts (cnt, one row of `cap` ints per chunk);
+//   k_bin_scan    (one workgroup per box): the box's cell starts and search
+//                 layout from the summed counts, each chunk's first position
+//                 in every cell (off: the cell's start plus the counts of the
+//                 box's earlier chunks) and the column offsets (col);
+//   k_bin_scatter (one workgroup per chunk): each particle's position is its
+//                 chunk's offset in its cell plus the number of the chunk's
+//                 particles in that cell with a smaller index, so every cell
+//                 is in index order as in k_bin_box, and the records are
+//                 stored as k_bin_box stores them.
+// The results equal k_bin_box's bit for bit.
+struct SplitArgs {
+    const int* box_chunk0;  // n_sel + 1: first chunk of each selected box
+    const int* chunk_boxj;  // n_chunks: the selected box (index into C.sel) of each chunk
+    int* cnt;               // n_chunks x cap: the chunk's particles per cell
+    int* off;               // n_chunks x cap: the chunk's first position in each cell
+    int* col;               // n_sel x 3 colcap: col_off, lo_off, hi_off per column
+    int chunk, cap, colcap;
+};
+
+constexpr int SPLIT_BT = 1024;  // threads per workgroup of the split binning
+constexpr int SPLIT_PER = 4;    // particles per thread and chunk at most (chunk <= 4096)
+
+template <typename real>
+__global__ __launch_bounds__(SPLIT_BT) void k_bin_count(Ctx C, SplitArgs S) {
+    extern __shared__ int lds[];
+    int* cnt = lds;
+    const int k = blockIdx.x, j = S.chunk_boxj[k], b = C.sel[j];
+    const BoxInfo B = C.box[b];
+    const BoxDyn& D = C.dyn[b];
+    const int first = (k - S.box_chunk0[j]) * S.chunk, last = min(first + S.chunk, B.n);
+    const int ncell = D.nc[0] * D.nc[1] * D.nc[2];
+    for (int q = threadIdx.x; q < ncell; q += SPLIT_BT) cnt[q] = 0;
+    __syncthreads();
+    const KickDrift<real> K(C, D, B.rng_id);
+    for (int q = first + (int)threadIdx.x; q < last; q += SPLIT_BT)
+        atomicAdd(&cnt[kick_drift_particle<real>(C, K, B.off + q, q, 1)], 1);
+    __syncthreads();
+    int* out = S.cnt + (size_t)k * S.cap;
+    for (int q = threadIdx.x; q < ncell; q += SPLIT_BT) out[q] = cnt[q];
+}
+
+__global__ __launch_bounds__(SPLIT_BT) void k_bin_scan(Ctx C, SplitArgs S, int lds_cells) {
+    extern __shared__ int lds[];
+    const int lds_cols = lds_cells / 3 + 1;
+    int* cnt = lds;
+    int* col_off = lds + lds_cells;
+    int* lo_off = col_off + lds_cols;
+    int* hi_off = lo_off + lds_cols;
+    __shared__ int wsum[SPLIT_BT / 64];
+    const int j = blockIdx.x, b = C.sel[j];
+    const BoxInfo B = C.box[b];
+    const BoxDyn& D = C.dyn[b];
+    const int ncell = D.nc[0] * D.nc[1] * D.nc[2];
+    const int k0 = S.box_chunk0[j], k1 = S.box_chunk0[j + 1];
+    for (int q = threadIdx.x; q < ncell; q += SPLIT_BT) {
+        int t = 0;
+        for (int k = k0; k < k1; ++k) t += S.cnt[(size_t)k * S.cap + q];
+        cnt[q] = t;
+    }
+    __syncthreads();
+    search_layout<SPLIT_BT>(C, B, D, ncell, cnt, col_off, lo_off, hi_off, wsum);
+    for (int q = threadIdx.x; q < ncell; q += SPLIT_BT) {
+        int run = cnt[q];
+        for (int k = k0; k < k1; ++k) {
+            S.off[(size_t)k * S.cap + q] = run;
+            run += S.cnt[(size_t)k * S.cap + q];
+        }
+    }
+    const int ncol = D.nc[0] * D.nc[1];
+    int* col = S.col + (size_t)j * 3 * S.colcap;
+    for (int q = threadIdx.x; q < ncol; q += SPLIT_BT) {
+        col[q] = col_off[q];
+        col[S.colcap + q] = lo_off[q];
+        col[2 * S.colcap + q] = hi_off[q];
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(SPLIT_BT) void k_bin_scatter(Ctx C, SplitArgs S) {
+    using R = Rec<real>;
+    extern __shared__ int lds[];
+    int* lst = lds;          // cap: the chunk's local cell starts, then ends
+    int* ent = lds + S.cap;  // chunk: local indices in local cell order
+    __shared__ int wsum[SPLIT_BT / 64];
+    const int k = blockIdx.x, j = S.chunk_boxj[k], b = C.sel[j];
+    const BoxInfo B = C.box[b];
+    const BoxDyn& D = C.dyn[b];
+    const int first = (k - S.box_chunk0[j]) * S.chunk, last = min(first + S.chunk, B.n);
+    const int ncell = D.nc[0] * D.nc[1] * D.nc[2];
+    const int* ccnt = S.cnt + (size_t)k * S.cap;
+    const int* coff = S.off + (size_t)k * S.cap;
+    block_scan<SPLIT_BT>(ncell, wsum, [&](int q) { return ccnt[q]; }, [&](int q, int excl) {
+        if (q < ncell) lst[q] = excl;
+    });
+    __syncthreads();
+    const int* pc = C.pcell + B.off;
+    int mycell[SPLIT_PER], slot[SPLIT_PER];
+#pragma unroll
+    for (int u = 0; u < SPLIT_PER; ++u) {
+        const int q = first + (int)threadIdx.x + u * SPLIT_BT;
+        mycell[u] = q < last ? pc[q] : -1;
+        slot[u] = q < last ? atomicAdd(&lst[mycell[u]], 1) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < SPLIT_PER; ++u)
+        if (slot[u] >= 0) ent[slot[u]] = first + (int)threadIdx.x + u * SPLIT_BT;
+    __syncthreads();
+    // lst[c] now ends the chunk's entries of cell c
+#pragma unroll
+    for (int u = 0; u < SPLIT_PER; ++u) {
+        if (slot[u] < 0) continue;
+        const int c = mycell[u], me = first + (int)threadIdx.x + u * SPLIT_BT;
+        const int e1 = lst[c], e0 = e1 - ccnt[c];
+        int rank = 0;
+        for (int e = e0; e < e1; ++e) rank += ent[e] < me;
+        slot[u] = coff[c] + rank;
+    }
+    typename R::T* pv = (typename R::T*)C.cell_pv + 2 * (size_t)B.off;
+    typename R::T* srec = (typename R::T*)C.srec + 2 * B.off;
+    const real* s = (const real*)C.s;
+    const real* cv = (const real*)C.c;
+    const int N = C.n_total;
+    const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
+    const real h22 = (real)D.h[8];
+    const int n2 = D.nc[2], zs = B.zsub;
+    const float inv_n2 = 1.0f / (float)n2;
+    const int* col = S.col + (size_t)j * 3 * S.colcap;
+    real v[SPLIT_PER][6];
+#pragma unroll
+    for (int u = 0; u < SPLIT_PER; ++u) {
+        const int q = first + (int)threadIdx.x + u * SPLIT_BT;
+        const int g = B.off + (q < last ? q : first);
+        v[u][0] = s[g]; v[u][1] = s[N + g]; v[u][2] = s[2 * N + g];
+        v[u][3] = cv[g]; v[u][4] = cv[N + g]; v[u][5] = cv[2 * N + g];
+    }
+#pragma unroll
+    for (int u = 0; u < SPLIT_PER; ++u) {
+        if (slot[u] < 0) continue;
+        const int q = first + (int)threadIdx.x + u * SPLIT_BT, pos = slot[u];
+        real x, y, z;
+        cell_position<real>(v[u][0], v[u][1], v[u][2], h00, h01, h10, h11, h22, x, y, z);
+        pv[2 * pos] = R::make(x, y, z, q);
+        pv[2 * pos + 1] = R::make(v[u][3], v[u][4], v[u][5], q);
+        const int cc = div_small(mycell[u], inv_n2), zc = mycell[u] - cc * n2;
+        srec[pos + col[cc]] = R::make(x, y, z, pos << 2);
+        if (zc >= n2 - zs) srec[pos + col[S.colcap + cc]] = R::make(x, y, z - h22, (pos << 2) | 1);
+        if (zc < zs) srec[pos + col[2 * S.colcap + cc]] = R::make(x, y, z + h22, (pos << 2) | 2);
     }
 }
 
@@ -1478,6 +1645,10 @@ struct lhmm_micro {
         int* d_sel = nullptr;
         int* d_blk = nullptr;
         int n_sel = 0, nblk = 0, lds_cells = 0, lds_parts = 0;
+        // split binning (cfg.bin_split > 0, the group of the largest boxes)
+        int n_chunks = 0;
+        int* d_split = nullptr;  // box_chunk0, chunk_boxj, cnt, off, col in one allocation
+        SplitArgs S{};
     };
     std::vector<Group> groups;
     hipStream_t aux[MAX_GROUPS - 1] = {};
@@ -1599,7 +1770,16 @@ void launch_chunk_grouped(lhmm_micro* m, int nsteps) {
         C.n_sel = gr.n_sel;
         C.step = m->d_gstep + g;
         for (int k = 0; k < nsteps; ++k) {
-            launch_bin<real>(m, C, gr.n_sel, st, 1, gr.lds_cells, gr.lds_parts);
+            if (gr.n_chunks > 0) {
+                const SplitArgs& S = gr.S;
+                const size_t scan_lds = sizeof(int) * ((size_t)gr.lds_cells + 3 * (size_t)(gr.lds_cells / 3 + 1));
+                k_cell_step<<<(gr.n_sel + 255) / 256, 256, 0, st>>>(C, 1);
+                k_bin_count<real><<<gr.n_chunks, SPLIT_BT, sizeof(int) * (size_t)S.cap, st>>>(C, S);
+                k_bin_scan<<<gr.n_sel, SPLIT_BT, scan_lds, st>>>(C, S, gr.lds_cells);
+                k_bin_scatter<real><<<gr.n_chunks, SPLIT_BT, sizeof(int) * ((size_t)S.cap + S.chunk), st>>>(C, S);
+            } else {
+                launch_bin<real>(m, C, gr.n_sel, st, 1, gr.lds_cells, gr.lds_parts);
+            }
             launch_forces<real>(m, C, gr.nblk, 1, 1, st);
             k_box_stress<<<gr.n_sel, 64, 0, st>>>(C);
         }
@@ -1696,6 +1876,7 @@ void release(lhmm_micro* m) {
     for (auto& gr : m->groups) {
         if (gr.d_sel) (void)hipFree(gr.d_sel);
         if (gr.d_blk) (void)hipFree(gr.d_blk);
+        if (gr.d_split) (void)hipFree(gr.d_split);
     }
     m->groups.clear();
     for (int g = 0; g < MAX_GROUPS - 1; ++g) {
@@ -1754,6 +1935,7 @@ int prepare_groups(lhmm_micro* m, int G) {
     for (auto& gr : m->groups) {
         if (gr.d_sel) (void)hipFree(gr.d_sel);
         if (gr.d_blk) (void)hipFree(gr.d_blk);
+        if (gr.d_split) (void)hipFree(gr.d_split);
     }
     m->groups.clear();
     if (G <= 1) return LHMM_OK;
@@ -1801,6 +1983,38 @@ int prepare_groups(lhmm_micro* m, int G) {
         if (rc != LHMM_OK) {
             if (gr.d_sel) (void)hipFree(gr.d_sel);
             return rc;
+        }
+        if (g == G - 1 && m->cfg.bin_split > 0) {
+            // chunks of the largest boxes for the split binning
+            const int chunk = m->cfg.bin_split;
+            std::vector<int> box_chunk0(gr.n_sel + 1, 0), chunk_boxj;
+            for (int q = 0; q < gr.n_sel; ++q) {
+                const int nck = std::max(1, (m->box[members[g][q]].n + chunk - 1) / chunk);
+                box_chunk0[q + 1] = box_chunk0[q] + nck;
+                for (int c = 0; c < nck; ++c) chunk_boxj.push_back(q);
+            }
+            gr.n_chunks = box_chunk0[gr.n_sel];
+            const int cap = max_cells, colcap = max_cells / 3 + 1;
+            const size_t ints = (size_t)(gr.n_sel + 1) + gr.n_chunks + 2 * (size_t)gr.n_chunks * cap +
+                                3 * (size_t)gr.n_sel * colcap;
+            rc = dalloc(&gr.d_split, ints);
+            if (rc != LHMM_OK) {
+                (void)hipFree(gr.d_sel);
+                (void)hipFree(gr.d_blk);
+                return rc;
+            }
+            int* base = gr.d_split;
+            gr.S.box_chunk0 = base;
+            gr.S.chunk_boxj = base + gr.n_sel + 1;
+            gr.S.cnt = base + gr.n_sel + 1 + gr.n_chunks;
+            gr.S.off = gr.S.cnt + (size_t)gr.n_chunks * cap;
+            gr.S.col = gr.S.off + (size_t)gr.n_chunks * cap;
+            gr.S.chunk = chunk;
+            gr.S.cap = cap;
+            gr.S.colcap = colcap;
+            HIPCHK(hipMemcpy(base, box_chunk0.data(), sizeof(int) * box_chunk0.size(), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(base + gr.n_sel + 1, chunk_boxj.data(), sizeof(int) * chunk_boxj.size(),
+                             hipMemcpyHostToDevice));
         }
         m->groups.push_back(gr);
         HIPCHK(hipMemcpy(gr.d_sel, members[g].data(), sizeof(int) * gr.n_sel, hipMemcpyHostToDevice));
@@ -1892,6 +2106,7 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     m->cfg.prune = 0;
     m->cfg.fuse_bin = 1;
     m->cfg.groups = 2;
+    m->cfg.bin_split = 0;
     m->real_size = p->precision == LHMM_FP64 ? sizeof(double) : sizeof(float);
     m->user_stream = (hipStream_t)stream;
 
@@ -1986,6 +2201,20 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
                 return fail(LHMM_ERR_HIP, "binning LDS of %zu bytes: %s", bytes, hipGetErrorString(e));
             }
         }
+        // split binning: cells + column offsets (scan), cells + a chunk (scatter), cells (count)
+        const size_t split_bytes[] = {sizeof(int) * (size_t)fixed, sizeof(int) * ((size_t)max_cells + SPLIT_PER * SPLIT_BT),
+                                      sizeof(int) * (size_t)max_cells};
+        const void* split_kernels[][2] = {{(const void*)&k_bin_scan, (const void*)&k_bin_scan},
+                                          {(const void*)&k_bin_scatter<float>, (const void*)&k_bin_scatter<double>},
+                                          {(const void*)&k_bin_count<float>, (const void*)&k_bin_count<double>}};
+        for (int q = 0; q < 3; ++q)
+            for (const void* k : split_kernels[q]) {
+                hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_bytes[q]);
+                if (e != hipSuccess) {
+                    delete m;
+                    return fail(LHMM_ERR_HIP, "split binning LDS of %zu bytes: %s", split_bytes[q], hipGetErrorString(e));
+                }
+            }
     }
     const size_t N = (size_t)m->n_total;
     int rc = LHMM_OK;
@@ -2243,13 +2472,15 @@ int lhmm_micro_set_config(lhmm_micro* m, const lhmm_micro_config* cfg) {
     if (cfg->prune != 0 && cfg->prune != 1) return fail(LHMM_ERR_ARG, "prune must be 0 or 1");
     if (cfg->fuse_bin != 0 && cfg->fuse_bin != 1) return fail(LHMM_ERR_ARG, "fuse_bin must be 0 or 1");
     if (cfg->groups < 1 || cfg->groups > MAX_GROUPS) return fail(LHMM_ERR_ARG, "groups must be 1..%d", MAX_GROUPS);
+    if (cfg->bin_split != 0 && (cfg->bin_split < 256 || cfg->bin_split > SPLIT_PER * SPLIT_BT))
+        return fail(LHMM_ERR_ARG, "bin_split must be 0 or 256..%d", SPLIT_PER * SPLIT_BT);
     HIPCHK(hipStreamSynchronize(m->stream));
     for (auto& kv : m->graphs) (void)hipGraphExecDestroy(kv.second);
     m->graphs.clear();
     for (auto& kv : m->sub_graphs) (void)hipGraphExecDestroy(kv.second);
     m->sub_graphs.clear();
     m->sub_seen.clear();
-    const bool regroup = cfg->groups != m->cfg.groups;
+    const bool regroup = cfg->groups != m->cfg.groups || cfg->bin_split != m->cfg.bin_split;
     m->cfg = *cfg;
     return regroup ? prepare_groups(m, cfg->groups) : LHMM_OK;
 }

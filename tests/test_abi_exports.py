@@ -37,7 +37,7 @@ def test_binding_struct_layout_matches_header():
     assert ctypes.sizeof(_lib.LhmmBox) == 16 + 72
     assert ctypes.sizeof(_lib.LhmmSphParams) == 13 * 8 + 4 * 4  # four int32
     assert ctypes.sizeof(_lib.LhmmSurParams) == 5 * 4
-    assert ctypes.sizeof(_lib.LhmmMicroConfig) == 8 * 4
+    assert ctypes.sizeof(_lib.LhmmMicroConfig) == 9 * 4
     assert ctypes.sizeof(_lib.LhmmHybridParams) == 10 * 4
     assert ctypes.sizeof(_lib.LhmmHybridStats) == 2 * 8 + 6 * 4
     assert _lib.LhmmBox.h0.offset == 16

@@ -520,16 +520,17 @@ def test_pruning_keeps_every_pair_on_the_full_batch(torch_gpu):
 def test_fused_binning_and_box_groups_on_the_full_batch_and_subsets(torch_gpu):
     """Fused cell step + kick-drift + binning equals the separate kernels on
     the benchmark batch (graph replays) and on subset steps, with the boxes
-    on one stream or in two or three overlapped groups."""
+    on one stream or in two or three overlapped groups, and with the largest
+    boxes binned over several workgroups each (bin_split)."""
     torch = torch_gpu
     _lib, inputs, micro = _mod()
     wl = inputs.batch()
     G = _grads(torch, wl)
     res = []
-    for fuse, groups in ((0, 1), (1, 1), (1, 2), (1, 3)):
-        print(f"fuse={fuse} groups={groups}", flush=True)
+    for fuse, groups, split in ((0, 1, 0), (1, 1, 0), (1, 2, 0), (1, 3, 0), (1, 2, 2048), (1, 3, 1000)):
+        print(f"fuse={fuse} groups={groups} bin_split={split}", flush=True)
         m = micro.from_workload(wl, precision="fp32")
-        m.set_config(fuse_bin=fuse, groups=groups)
+        m.set_config(fuse_bin=fuse, groups=groups, bin_split=split)
         out = m.step(G, 30).cpu().numpy()
         sub = m.step_subset(G, 10, [0, 7, 100, 255]).cpu().numpy()
         out2 = m.step(G, 7).cpu().numpy()
