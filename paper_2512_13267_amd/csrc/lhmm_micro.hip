@@ -760,7 +760,7 @@ __device__ void search_layout(const Ctx& C, const BoxInfo& B, const BoxDyn& D, i
 // position record (position, cell-order position) in the search layout: the
 // same order per cell, plus the z images of bottom and top cells.
 // LDS (dynamic): lds_cells cell counters / starts, three arrays of
-// lds_cells / 3 + 1 column offsets (from cell order to the search layout:
+// lds_cols column offsets (from cell order to the search layout:
 // the column's cells, the image of its top cell, the image of its bottom
 // cell), then room for lds_parts ints.  A box with at most lds_parts
 // particles is scattered as entries into LDS, each thread ranks its own
@@ -772,10 +772,9 @@ __device__ void search_layout(const Ctx& C, const BoxInfo& B, const BoxDyn& D, i
 // and drift of its particles (advance = fuse), counting cells as it goes;
 // fuse < 0: k_cell_step and k_kick_drift have run.
 template <typename real, int BIN_THREADS>
-__global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, int lds_parts, int fuse) {
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, int lds_cols, int lds_parts, int fuse) {
     using R = Rec<real>;
     extern __shared__ int lds[];
-    const int lds_cols = lds_cells / 3 + 1;  // columns n0 n1 <= cells / 3
     int* cnt = lds;
     int* col_off = lds + lds_cells;
     int* lo_off = col_off + lds_cols;
@@ -1014,9 +1013,8 @@ __global__ __launch_bounds__(SPLIT_BT) void k_bin_count(Ctx C, SplitArgs S) {
     for (int q = threadIdx.x; q < ncell; q += SPLIT_BT) out[q] = cnt[q];
 }
 
-__global__ __launch_bounds__(SPLIT_BT) void k_bin_scan(Ctx C, SplitArgs S, int lds_cells) {
+__global__ __launch_bounds__(SPLIT_BT) void k_bin_scan(Ctx C, SplitArgs S, int lds_cells, int lds_cols) {
     extern __shared__ int lds[];
-    const int lds_cols = lds_cells / 3 + 1;
     int* cnt = lds;
     int* col_off = lds + lds_cells;
     int* lo_off = col_off + lds_cols;
@@ -1601,7 +1599,7 @@ __global__ void k_finalize(Ctx C, double* __restrict__ stress_out, double* __res
 struct lhmm_micro {
     lhmm_params p{};
     lhmm_micro_config cfg{};
-    int bin_lds_cells = 0, bin_lds_parts = 0;  // dynamic LDS of the binning kernel (ints)
+    int bin_lds_cells = 0, bin_lds_cols = 0, bin_lds_parts = 0;  // dynamic LDS of the binning kernel (ints)
     int n_boxes = 0, n_blocks = 0, precision = LHMM_FP32;
     long long n_total = 0;
     size_t real_size = 4;
@@ -1644,7 +1642,7 @@ struct lhmm_micro {
     struct Group {
         int* d_sel = nullptr;
         int* d_blk = nullptr;
-        int n_sel = 0, nblk = 0, lds_cells = 0, lds_parts = 0;
+        int n_sel = 0, nblk = 0, lds_cells = 0, lds_cols = 0, lds_parts = 0;
         // split binning (cfg.bin_split > 0, the group of the largest boxes)
         int n_chunks = 0;
         int* d_split = nullptr;  // box_chunk0, chunk_boxj, cnt, off, col in one allocation
@@ -1658,17 +1656,23 @@ struct lhmm_micro {
 
 namespace {
 
+// Column capacity of a box's cell grid: n0 n1 n2 <= cell_cap with
+// n2 >= 2 zsub + 1, or n0, n1 <= 3 when the grid had to be clipped.
+int box_cols(const BoxInfo& B) { return std::max(B.cell_cap / (2 * B.zsub + 1), 9) + 1; }
+
 template <typename real>
-void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse, int lc = 0, int lp = 0) {
+void launch_bin(lhmm_micro* m, const Ctx& C, int nbox, hipStream_t st, int fuse, int lc = 0, int lcol = 0,
+                int lp = 0) {
     if (lc == 0) {
         lc = m->bin_lds_cells;
+        lcol = m->bin_lds_cols;
         lp = m->bin_lds_parts;
     }
-    const size_t bytes = sizeof(int) * ((size_t)lc + 3 * (size_t)(lc / 3 + 1) + (size_t)lp);
+    const size_t bytes = sizeof(int) * ((size_t)lc + 3 * (size_t)lcol + (size_t)lp);
     switch (m->cfg.bin_threads) {
-        case 256: k_bin_box<real, 256><<<nbox, 256, bytes, st>>>(C, lc, lp, fuse); break;
-        case 512: k_bin_box<real, 512><<<nbox, 512, bytes, st>>>(C, lc, lp, fuse); break;
-        default: k_bin_box<real, 1024><<<nbox, 1024, bytes, st>>>(C, lc, lp, fuse); break;
+        case 256: k_bin_box<real, 256><<<nbox, 256, bytes, st>>>(C, lc, lcol, lp, fuse); break;
+        case 512: k_bin_box<real, 512><<<nbox, 512, bytes, st>>>(C, lc, lcol, lp, fuse); break;
+        default: k_bin_box<real, 1024><<<nbox, 1024, bytes, st>>>(C, lc, lcol, lp, fuse); break;
     }
 }
 
@@ -1772,13 +1776,13 @@ void launch_chunk_grouped(lhmm_micro* m, int nsteps) {
         for (int k = 0; k < nsteps; ++k) {
             if (gr.n_chunks > 0) {
                 const SplitArgs& S = gr.S;
-                const size_t scan_lds = sizeof(int) * ((size_t)gr.lds_cells + 3 * (size_t)(gr.lds_cells / 3 + 1));
+                const size_t scan_lds = sizeof(int) * ((size_t)gr.lds_cells + 3 * (size_t)gr.lds_cols);
                 k_cell_step<<<(gr.n_sel + 255) / 256, 256, 0, st>>>(C, 1);
                 k_bin_count<real><<<gr.n_chunks, SPLIT_BT, sizeof(int) * (size_t)S.cap, st>>>(C, S);
-                k_bin_scan<<<gr.n_sel, SPLIT_BT, scan_lds, st>>>(C, S, gr.lds_cells);
+                k_bin_scan<<<gr.n_sel, SPLIT_BT, scan_lds, st>>>(C, S, gr.lds_cells, gr.lds_cols);
                 k_bin_scatter<real><<<gr.n_chunks, SPLIT_BT, sizeof(int) * ((size_t)S.cap + S.chunk), st>>>(C, S);
             } else {
-                launch_bin<real>(m, C, gr.n_sel, st, 1, gr.lds_cells, gr.lds_parts);
+                launch_bin<real>(m, C, gr.n_sel, st, 1, gr.lds_cells, gr.lds_cols, gr.lds_parts);
             }
             launch_forces<real>(m, C, gr.nblk, 1, 1, st);
             k_box_stress<<<gr.n_sel, 64, 0, st>>>(C);
@@ -1965,18 +1969,20 @@ int prepare_groups(lhmm_micro* m, int G) {
         std::sort(members[g].begin(), members[g].end());
         lhmm_micro::Group gr;
         std::vector<int> blks;
-        int max_cells = 0, max_n = 0;
+        int max_cells = 0, max_cols = 0, max_n = 0;
         for (int b : members[g]) {
             const BoxInfo& B = m->box[b];
             for (int k = 0; k < B.nblk; ++k) blks.push_back(B.blk_off + k);
             max_cells = std::max(max_cells, B.cell_cap + 1);
+            max_cols = std::max(max_cols, box_cols(B));
             max_n = std::max(max_n, B.n);
         }
         gr.n_sel = (int)members[g].size();
         gr.nblk = (int)blks.size();
         gr.lds_cells = max_cells;
-        const int fixed = max_cells + 3 * (max_cells / 3 + 1);
-        const int room = m->bin_lds_cells + 3 * (m->bin_lds_cells / 3 + 1) + m->bin_lds_parts - fixed;
+        gr.lds_cols = max_cols;
+        const int fixed = max_cells + 3 * max_cols;
+        const int room = m->bin_lds_cells + 3 * m->bin_lds_cols + m->bin_lds_parts - fixed;
         gr.lds_parts = std::max(0, std::min(max_n, room));
         int rc = dalloc(&gr.d_sel, gr.n_sel);
         if (rc == LHMM_OK) rc = dalloc(&gr.d_blk, gr.nblk);
@@ -1994,7 +2000,7 @@ int prepare_groups(lhmm_micro* m, int G) {
                 for (int c = 0; c < nck; ++c) chunk_boxj.push_back(q);
             }
             gr.n_chunks = box_chunk0[gr.n_sel];
-            const int cap = max_cells, colcap = max_cells / 3 + 1;
+            const int cap = max_cells, colcap = max_cols;
             const size_t ints = (size_t)(gr.n_sel + 1) + gr.n_chunks + 2 * (size_t)gr.n_chunks * cap +
                                 3 * (size_t)gr.n_sel * colcap;
             rc = dalloc(&gr.d_split, ints);
@@ -2173,9 +2179,10 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
     {
         // binning LDS: three arrays over every box's cells, and entries for
         // the boxes that fit in what the workgroup may still use
-        int max_cells = 0, max_n = 0;
+        int max_cells = 0, max_cols = 0, max_n = 0;
         for (const BoxInfo& B : m->box) {
             max_cells = std::max(max_cells, B.cell_cap + 1);
+            max_cols = std::max(max_cols, box_cols(B));
             max_n = std::max(max_n, B.n);
         }
         int dev = 0, max_lds = 65536;
@@ -2183,12 +2190,13 @@ int lhmm_micro_create(const lhmm_params* p, const lhmm_box* boxes, int32_t n_box
             hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             max_lds = 65536;
         const int budget = (int)((max_lds - 64 * (int)sizeof(int)) / sizeof(int));  // less the scan's wave sums
-        const int fixed = max_cells + 3 * (max_cells / 3 + 1);  // cells and column offsets
+        const int fixed = max_cells + 3 * max_cols;  // cells and column offsets
         if (fixed > budget) {
             delete m;
             return fail(LHMM_ERR_ARG, "boxes need %d cells, more than the binning LDS holds", max_cells - 1);
         }
         m->bin_lds_cells = max_cells;
+        m->bin_lds_cols = max_cols;
         m->bin_lds_parts = std::max(0, std::min(max_n, budget - fixed));
         const size_t bytes = sizeof(int) * ((size_t)fixed + (size_t)m->bin_lds_parts);
         const void* kernels[] = {(const void*)&k_bin_box<float, 256>, (const void*)&k_bin_box<float, 512>,
