@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--relax-steps", type=int, default=500,
+                    help="untimed steps at rest from the random initial positions before the workload starts")
     ap.add_argument("--warmup-seconds", type=float, default=0.3,
                     help="the warm-up also lasts at least this long (in calls of the timed call's graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -239,9 +241,10 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the micro-boxes are independent and "
               "would shard by box across GPUs, which is not implemented.", file=sys.stderr)
         sys.exit(2)
-    if args.steps < 1 or args.warmup < 0 or args.warmup_seconds < 0 or (args.timing_steps is not None and args.timing_steps < 1):
-        print("bench.py needs --steps >= 1, --warmup >= 0, --warmup-seconds >= 0 and --timing-steps >= 1",
-              file=sys.stderr)
+    if (args.steps < 1 or args.warmup < 0 or args.warmup_seconds < 0 or args.relax_steps < 0
+            or (args.timing_steps is not None and args.timing_steps < 1)):
+        print("bench.py needs --steps >= 1, --warmup >= 0, --warmup-seconds >= 0, --relax-steps >= 0 and "
+              "--timing-steps >= 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -257,6 +260,18 @@ def main():
     m = micro.from_workload(wl, precision="fp32")
     G = torch.tensor(np.stack([b.L for b in wl.boxes]), dtype=torch.float64, device="cuda").contiguous()
 
+    # Set-up, untimed: the random initial positions (overlapping soft
+    # spheres) relax at rest, as a micro-domain does before it is coupled.
+    # The workload is then the first --steps steps under the gradients from
+    # that relaxed state (forces included), kept on the device; the
+    # warm-up, the timed call and the per-kernel timing all start from it.
+    all_boxes = np.arange(len(wl.boxes), dtype=np.int32)
+    if args.relax_steps > 0:
+        m.step(torch.zeros_like(G), args.relax_steps)
+    m.snapshot()
+    torch.cuda.synchronize()
+    print(f"[bench] relaxed {args.relax_steps} steps at rest", file=sys.stderr, flush=True)
+
     tuning = None
     if args.autotune and not args.no_autotune:
         from paper_2512_13267_amd import autotune
@@ -264,11 +279,7 @@ def main():
         tuning = autotune.tune(m, G, [b.N for b in wl.boxes], "fp32")
         print(f"[bench] launch parameters {tuning['config']} (cached: {tuning['cached']})", file=sys.stderr,
               flush=True)
-    # The workload is the first --steps steps from the initial state (forces
-    # included), kept on the device; the warm-up and the per-kernel timing
-    # both start from it again.
-    all_boxes = np.arange(len(wl.boxes), dtype=np.int32)
-    m.snapshot()
+        m.restore(all_boxes)
     # The warm-up replays the timed call's own graph (captured here, outside
     # the clock) until it has run at least --warmup steps and at least
     # --warmup-seconds: from idle the GPU needs some tens of milliseconds of
@@ -330,8 +341,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "256 DPD/FENE micro-boxes, edge U(8,16) rc, density 3, polymer fraction "
-                               "U(0.1,0.3) in 10-bead chains, constant planar gradients U(-0.5,0.5), "
-                               "FP32 forces / FP64 stress",
+                               "U(0.1,0.3) in 10-bead chains, random positions relaxed at rest (untimed), then "
+                               "constant planar gradients U(-0.5,0.5), FP32 forces / FP64 stress",
+                   "relax_steps": args.relax_steps,
                    "n_boxes": len(wl.boxes), "n_particles": n_particles,
                    "pairs_per_step": pairs / args.steps,
                    "launch": m.config(), "tuned": tuning is not None,
