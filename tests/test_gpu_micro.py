@@ -611,3 +611,39 @@ def test_calls_start_from_zero_mean_peculiar_velocity(torch_gpu):
         assert not a.flags().any() and not b.flags().any()
         a.close()
         b.close()
+
+
+def test_fastest_extension_box_heats_as_the_oracle_does(torch_gpu, orc):
+    """The batch box under the fastest planar extension (rate 0.66) has no
+    steady state: its kinetic temperature grows without bound from t ~ 5
+    (velocity perturbations along the compressing axis outgrow the DPD
+    viscosity at this box Reynolds number).  Both precisions follow the
+    FP64 oracle through it, over 1000 steps with Kraynik-Reinelt cell
+    remaps: <c^2> after 250, 500, 750 and 1000 steps within 5, 5, 10 and
+    20 % of the oracle's (the trajectories separate by chaos after ~300
+    steps, the temperature does not)."""
+    torch = torch_gpu
+    _lib, inputs, micro = _mod()
+    wl = inputs.batch()
+    p = wl.params
+    disc = np.array([b.L[0, 0] ** 2 + b.L[0, 1] * b.L[1, 0] for b in wl.boxes])
+    k = int(np.argmax(disc))
+    b = wl.boxes[k]
+    assert disc[k] > 0.4
+    ob = orc.OracleBox(s=b.s, c=b.c, h=b.h, n_chains=b.n_chains, box_id=k)
+    t_orc = []
+    for _ in range(4):
+        orc.run_box(p, p["seed"], p["chain_len"], ob, b.L, 250)
+        t_orc.append(float(np.mean(ob.c ** 2)))
+    assert t_orc[3] > 10.0 * t_orc[1] and t_orc[1] < 1.6
+    one = inputs.Workload("fastest_extension", p, [b], 1000)
+    G = torch.tensor(b.L.reshape(1, 9), dtype=torch.float64, device="cuda")
+    for prec in ("fp64", "fp32"):
+        m = micro.from_workload(one, precision=prec, rng_ids=[k])
+        for q, tol in enumerate((0.05, 0.05, 0.10, 0.20)):
+            m.step(G, 250)
+            _, c, _, _ = m.get_state()
+            t = float(np.mean(c ** 2))
+            print(f"{prec} box {k} step {250 * (q + 1)}: <c^2> {t:.4f}, oracle {t_orc[q]:.4f}", flush=True)
+            assert abs(t / t_orc[q] - 1.0) <= tol, (prec, q, t, t_orc[q])
+        m.close()
