@@ -135,8 +135,8 @@ struct Ctx {
     // [images of its bottom zsub cells shifted by +h_z], so the z cells
     // k2 - zsub .. k2 + zsub around any cell are one contiguous range;
     // gcell_start holds the range starts of these n0 n1 (n2 + 2 zsub) cells.
-    // srec: (x, y, z, cell-order position << 2 | z image: 0 none, 1 below,
-    // 2 above), r = h s; padded by four records.
+    // srec: (x, y, z, cell-order position << 5 | 9 x z image: 0 none,
+    // 1 below, 2 above), r = h s; padded by four records.
     int* gcell_start;
     void* srec;
     double* part_vir;   // n_blocks x pv_stride: pair virial, FENE virial (+ C, D, R parts)
@@ -177,13 +177,61 @@ __device__ __forceinline__ void philox4x32_10(unsigned& x0, unsigned& x1, unsign
     }
 }
 
+// The pair stream's generator: counter (x0, x1, step, box), where step,
+// box and the key are the same for a whole workgroup.  In the first two
+// rounds two of the three inputs of one or both xors are then uniform; the
+// xors are grouped so that the scalar unit combines those two (one vector
+// xor, where a v_bitop3_b32 would need one of them moved to a vector
+// register first).  The output equals philox4x32_10's.
+__device__ __forceinline__ void philox_pair(unsigned& x0, unsigned& x1, unsigned step, unsigned box, unsigned k0,
+                                            unsigned k1) {
+    // round 1: M1 step and key are uniform, and so are box and key
+    unsigned long long p0 = (unsigned long long)0xD2511F53u * x0;
+    unsigned long long p1 = (unsigned long long)0xCD9E8D57u * step;
+    unsigned y0 = ((unsigned)(p1 >> 32) ^ k0) ^ x1;
+    unsigned y2 = (box ^ k1) ^ (unsigned)(p0 >> 32);
+    const unsigned u1 = (unsigned)p1;  // the second word is uniform after round 1
+    unsigned x3 = (unsigned)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    // round 2: the second word and key are uniform
+    p0 = (unsigned long long)0xD2511F53u * y0;
+    p1 = (unsigned long long)0xCD9E8D57u * y2;
+    x0 = (u1 ^ k0) ^ (unsigned)(p1 >> 32);
+    unsigned x2 = __builtin_amdgcn_bitop3_b32((unsigned)(p0 >> 32), x3, k1, 0x96);
+    x1 = (unsigned)p1;
+    x3 = (unsigned)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+#pragma unroll
+    for (int r = 2; r < 10; ++r) {
+        p0 = (unsigned long long)0xD2511F53u * x0;
+        p1 = (unsigned long long)0xCD9E8D57u * x2;
+        const unsigned z0 = __builtin_amdgcn_bitop3_b32((unsigned)(p1 >> 32), x1, k0, 0x96);
+        const unsigned z2 = __builtin_amdgcn_bitop3_b32((unsigned)(p0 >> 32), x3, k1, 0x96);
+        x1 = (unsigned)p1;
+        x3 = (unsigned)p0;
+        x0 = z0;
+        x2 = z2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
 template <typename real>
 __device__ __forceinline__ real box_muller(unsigned w0, unsigned w1);
 
+// (m + 1/2) 2^-23 for the top 23 bits m of w: the float 1 + m 2^-23 (exponent
+// bits 0x7F above m, one funnel shift) less 1 - 2^-24, a subtraction without
+// rounding since both lie in [1/2, 2)
+__device__ __forceinline__ float unit_open(unsigned w) {
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u)) - 0x1.fffffep-1f;
+}
+
 template <>
 __device__ __forceinline__ float box_muller<float>(unsigned w0, unsigned w1) {
-    const float u0 = ((float)(w0 >> 9) + 0.5f) * 1.1920928955078125e-07f;  // 2^-23
-    const float u1 = ((float)(w1 >> 9) + 0.5f) * 1.1920928955078125e-07f;
+    const float u0 = unit_open(w0);
+    const float u1 = unit_open(w1);
     // v_log_f32 is log2; v_cos_f32 takes its argument in revolutions
     // -2 ln u0 lies in [1e-7, 35]: the hardware square root (1 ulp) needs no range handling
     const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));  // -2 ln u0
@@ -222,8 +270,8 @@ __device__ __forceinline__ void box_muller2<double>(unsigned w0, unsigned w1, do
 template <typename real>
 __device__ __forceinline__ real pair_theta(unsigned id_i, unsigned id_j, unsigned step, unsigned box,
                                            unsigned k0, unsigned k1) {
-    unsigned x0 = min(id_i, id_j), x1 = max(id_i, id_j), x2 = step, x3 = box;
-    philox4x32_10(x0, x1, x2, x3, k0, k1);
+    unsigned x0 = min(id_i, id_j), x1 = max(id_i, id_j);
+    philox_pair(x0, x1, step, box, k0, k1);
     return box_muller<real>(x0, x1);
 }
 
@@ -878,9 +926,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_box(Ctx C, int lds_cells, i
     const float inv_n2 = 1.0f / (float)n2;
     auto write_search = [&](int q, int cell, real x, real y, real z) {
         const int col = div_small(cell, inv_n2), zc = cell - col * n2;
-        srec[q + col_off[col]] = R::make(x, y, z, q << 2);
-        if (zc >= n2 - zs) srec[q + lo_off[col]] = R::make(x, y, z - h22, (q << 2) | 1);
-        if (zc < zs) srec[q + hi_off[col]] = R::make(x, y, z + h22, (q << 2) | 2);
+        srec[q + col_off[col]] = R::make(x, y, z, q << 5);
+        if (zc >= n2 - zs) srec[q + lo_off[col]] = R::make(x, y, z - h22, (q << 5) | 9);
+        if (zc < zs) srec[q + hi_off[col]] = R::make(x, y, z + h22, (q << 5) | 18);
     };
     if (keep) {
         // LDS entries: cell << 14 | local index (cells < 2^14, particles < 2^14)
@@ -1115,9 +1163,9 @@ __global__ __launch_bounds__(SPLIT_BT) void k_bin_scatter(Ctx C, SplitArgs S) {
         pv[2 * pos] = R::make(x, y, z, q);
         pv[2 * pos + 1] = R::make(v[u][3], v[u][4], v[u][5], q);
         const int cc = div_small(mycell[u], inv_n2), zc = mycell[u] - cc * n2;
-        srec[pos + col[cc]] = R::make(x, y, z, pos << 2);
-        if (zc >= n2 - zs) srec[pos + col[S.colcap + cc]] = R::make(x, y, z - h22, (pos << 2) | 1);
-        if (zc < zs) srec[pos + col[2 * S.colcap + cc]] = R::make(x, y, z + h22, (pos << 2) | 2);
+        srec[pos + col[cc]] = R::make(x, y, z, pos << 5);
+        if (zc >= n2 - zs) srec[pos + col[S.colcap + cc]] = R::make(x, y, z - h22, (pos << 5) | 9);
+        if (zc < zs) srec[pos + col[2 * S.colcap + cc]] = R::make(x, y, z + h22, (pos << 5) | 18);
     }
 }
 
@@ -1150,7 +1198,7 @@ __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt
 //   SU records at a time (lanes of one home cell read the same records) and
 //   appends each accepted neighbour (0 < r < rc; the particle itself has
 //   r = 0) to its own LDS queue of QD four-byte entries: the neighbour's
-//   cell-order position and its image codes.  QD, `drain` and `busy` are
+//   cell-order position and its image code.  QD, `drain` and `busy` are
 //   tuning parameters; none changes the order in which a lane evaluates its
 //   neighbours, so results do not depend on them.
 //   Evaluation: a round pops one queued neighbour per lane, reloads its
@@ -1207,11 +1255,13 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP || AF || QD >= 32 ? 4
     using V4 = typename R::T;
     constexpr int NW = BS / 64;
     constexpr int SU = scan_unroll(QD);
-    // queue entry: cell-order position of j << 6 | z image (0 none, 1 below,
-    // 2 above) << 4 | in-plane image code
+    // queue entry: cell-order position of j << 5 | image code, the code
+    // 9 x z image (0 none, 1 below, 2 above) + in-plane image code (0 .. 8)
     __shared__ int qbuf[QD][NW][64];
     __shared__ double red[NV * NW];
-    __shared__ real shift_tab[9][2];  // image_shift of the block's box for codes 0 .. 8
+    // per image code (0 .. 26) the shift of the block's box: in-plane
+    // image_shift, and 0, -h22 or +h22 along z
+    __shared__ real shift_tab[32][4];
 
     int blk = xcd_local_work(blockIdx.x, gridDim.x);
     if (C.blk_list) blk = C.blk_list[blk];
@@ -1232,7 +1282,10 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP || AF || QD >= 32 ? 4
     // in-plane cell and gradient
     const real h00 = (real)D.h[0], h01 = (real)D.h[1], h10 = (real)D.h[3], h11 = (real)D.h[4];
     const real h22 = (real)D.h[8];
-    if (t < 9) image_shift<real>(t, h00, h01, h10, h11, shift_tab[t][0], shift_tab[t][1]);
+    if (t < 27) {
+        image_shift<real>(t % 9, h00, h01, h10, h11, shift_tab[t][0], shift_tab[t][1]);
+        shift_tab[t][2] = t < 9 ? (real)0 : (t < 18 ? -h22 : h22);
+    }
     __syncthreads();
     real ri0 = 0, ri1 = 0, ri2 = 0, ci0 = 0, ci1 = 0, ci2 = 0;
     real own_s0 = 0, own_s1 = 0, own_s2 = 0;
@@ -1283,27 +1336,32 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP || AF || QD >= 32 ? 4
         zl = fmax(f2, (real)0) * h22 / (real)n2;
         zh = fmax((real)1 - f2, (real)0) * h22 / (real)n2;
     }
-    int qh = 0, qt = 0;  // this lane's queue: popped, pushed
+    // this lane's queue: entries popped and pushed, counted in queue rows
+    // (NW x 64 ints) so that an entry's LDS byte address is one and-or of the
+    // count with the lane's offset
+    constexpr unsigned QROW = NW * 64 * sizeof(int), QMASK = (QD - 1) * QROW;
+    const unsigned qlane = (unsigned)t * sizeof(int);
+    char* const qbase = (char*)&qbuf[0][0][0];
+    unsigned qh = 0, qt = 0;
     real fx = 0, fy = 0, fz = 0;
     real w[6] = {0, 0, 0, 0, 0, 0};
     real wc[COMP ? 6 : 1] = {}, wd[COMP ? 6 : 1] = {}, wr[COMP ? 6 : 1] = {};  // C, D, R parts
-    unsigned npairs = 0;
 
     int ic = 4;  // in-plane image code of the row being scanned
     // one evaluation round: each lane with a queued neighbour takes the oldest
     auto round = [&]() {
         if (qt > qh) {
-            const int e = qbuf[qh & (QD - 1)][wv][lane];
-            ++qh;
-            const int qj = e >> 6, zi = (e >> 4) & 3;
+            const int e = *(const int*)(qbase + ((qh & QMASK) | qlane));
+            qh += QROW;
             // one 32-bit byte offset from the box's records (scalar base)
-            const unsigned po = (unsigned)qj * (unsigned)(2 * sizeof(V4));
+            const unsigned po = ((unsigned)e >> 5) * (unsigned)(2 * sizeof(V4));
             const V4 pj = *(const V4*)((const char*)pv + po);
             const V4 cj = *(const V4*)((const char*)pv + po + sizeof(V4));
-            const real sx = shift_tab[e & 15][0], sy = shift_tab[e & 15][1];
-            // z image without a branch: one rounding of z + (0, -1, +1) h22
-            // for zi = 0, 1, 2, the same as the binning's z - h22, z + h22
-            const real zj = fma(h22, (real)((zi >> 1) - (zi & 1)), pj.z);
+            const int code = e & 31;
+            const real sx = shift_tab[code][0], sy = shift_tab[code][1];
+            // the z image: one rounding of z + (0, -h22, +h22), the same as the
+            // binning's z - h22, z + h22
+            const real zj = pj.z + shift_tab[code][2];
             const real dx = (ri0 - sx) - pj.x, dy = (ri1 - sy) - pj.y, dz = ri2 - zj;
             const real r2 = fma(dz, dz, fma(dx, dx, dy * dy));  // fixed association
             const real ir = inv_sqrt(r2);
@@ -1334,7 +1392,6 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP || AF || QD >= 32 ? 4
                     wr[k] += mr * de[k];
                 }
             }
-            ++npairs;
         }
     };
     // test one candidate record v against (px, py, pz), the lane's
@@ -1346,8 +1403,8 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP || AF || QD >= 32 ? 4
         const real r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         // one branch per candidate: the tests combined without short-circuit
         if (valid & (r2 < rc2) & (r2 > (real)0)) {
-            qbuf[qt & (QD - 1)][wv][lane] = (R::id(v) << 4) | ic;
-            ++qt;
+            *(int*)(qbase + ((qt & QMASK) | qlane)) = R::id(v) + ic;
+            qt += QROW;
         }
     };
 
@@ -1415,7 +1472,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP || AF || QD >= 32 ? 4
             q += SU;
             // evaluate when a queue may not take SU more, or when enough
             // lanes hold a neighbour for a well-filled round
-            if (__ballot(qt - qh > QD - SU) != 0ull || __popcll(__ballot(qt > qh)) >= busy) break;
+            if (__ballot(qt - qh > (QD - SU) * QROW) != 0ull || __popcll(__ballot(qt > qh)) >= busy) break;
         }
         if (!scanning) {
             while (__ballot(qt > qh) != 0ull) round();
@@ -1425,7 +1482,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP || AF || QD >= 32 ? 4
         // than `busy` lanes hold one
         do {
             round();
-        } while (__ballot(qt - qh > drain) != 0ull || __popcll(__ballot(qt > qh)) >= busy);
+        } while (__ballot(qt - qh > (unsigned)drain * QROW) != 0ull || __popcll(__ballot(qt > qh)) >= busy);
     }
 
     real wf[6] = {0, 0, 0, 0, 0, 0};
@@ -1470,7 +1527,7 @@ __global__ __launch_bounds__(BS, sizeof(real) == 4 ? (COMP || AF || QD >= 32 ? 4
             v[31 + k] = (double)wr[k];
         }
     }
-    v[12] = (double)npairs;
+    v[12] = (double)(qt / QROW);  // every queued neighbour was evaluated once
     // second half kick of the velocity-Verlet step, c += dt/2 (F/m - L c),
     // with the particle's final force, and the kinetic partial sums m c c
     if (kick && act) {
