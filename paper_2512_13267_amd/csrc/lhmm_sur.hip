@@ -36,9 +36,27 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int HIST = LHMM_SUR_HIST;  // gradient samples per feature vector
 
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU and its derivative with erf by Abramowitz and Stegun's formula 7.1.26,
+// erf(x) = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p |x|), odd in x,
+// absolute error at most 1.5e-7: with x = z / sqrt(2), exp(-x^2) is also the
+// Gaussian factor of the derivative, so one hardware exponential serves both
+// (about a quarter of the instructions of the library erf and exp, in the
+// GEMM epilogues that the activations make VALU-bound).
+__device__ __forceinline__ float gauss_half(float z) {  // exp(-z^2 / 2)
+    return __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);  // log2(e) / 2
+}
+__device__ __forceinline__ float erf_as(float x, float e) {  // e = exp(-x^2)
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, fabsf(x), 1.0f));
+    const float poly =
+        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+    return copysignf(1.0f - poly * e, x);
+}
+__device__ __forceinline__ float gelu_f(float z) {
+    return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f, gauss_half(z)));
+}
 __device__ __forceinline__ float gelu_grad_f(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    const float e = gauss_half(z);
+    return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f, e)) + z * 0.39894228040143268f * e;
 }
 
 enum Epi {
@@ -208,26 +226,43 @@ __global__ void k_loss_final(const float* __restrict__ part, int nparts, int B, 
     loss[e] = (float)(s / (double)(B * n_out));
 }
 
-// column sums of f32 [rows x cols] per member (bias gradients): 64 columns
-// x 16 row groups per block, row group y sums rows y, y+16, ...; the 16
-// partials are added in a fixed order
-__global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ x, int rows, int cols, long stride,
-                                                float* __restrict__ out, long ostride) {
+// column sums of f32 [rows x cols] per member (bias gradients) in two
+// passes, each in a fixed order.  k_colsum_part: the block of row slice z
+// (64 columns x 16 row groups) sums the slice's rows, row group y taking
+// every 16th, and adds its 16 partials in order; k_colsum_final adds the
+// COLSUM_SLICES slices in order.  Slicing the rows keeps ~16 dependent loads
+// per thread where one block per column tile would chain hundreds.
+constexpr int COLSUM_SLICES = 16;
+
+__global__ __launch_bounds__(1024) void k_colsum_part(const float* __restrict__ x, int rows, int cols, long stride,
+                                                     float* __restrict__ part) {
     __shared__ float sh[16][64];
-    const int e = blockIdx.y;
+    const int e = blockIdx.y, z = blockIdx.z;
     const int c = blockIdx.x * 64 + threadIdx.x;
+    const int len = (rows + COLSUM_SLICES - 1) / COLSUM_SLICES;
+    const int r0 = z * len, r1 = min(rows, r0 + len);
     float s = 0.0f;
     if (c < cols) {
         const float* p = x + e * stride + c;
-        for (int r = threadIdx.y; r < rows; r += 16) s += p[(long)r * cols];
+        for (int r = r0 + (int)threadIdx.y; r < r1; r += 16) s += p[(long)r * cols];
     }
     sh[threadIdx.y][threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.y == 0 && c < cols) {
         float t = 0.0f;
         for (int y = 0; y < 16; ++y) t += sh[y][threadIdx.x];
-        out[e * ostride + c] = t;
+        part[((long)e * COLSUM_SLICES + z) * cols + c] = t;
     }
+}
+
+__global__ void k_colsum_final(const float* __restrict__ part, int cols, int n_members, float* __restrict__ out,
+                               long ostride) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)n_members * cols) return;
+    const int e = (int)(t / cols), c = (int)(t % cols);
+    float s = 0.0f;
+    for (int z = 0; z < COLSUM_SLICES; ++z) s += part[((long)e * COLSUM_SLICES + z) * cols + c];
+    out[e * ostride + c] = s;
 }
 
 // Adam on FP32 masters of one weight matrix [rows x cols] per member, then
@@ -421,6 +456,7 @@ struct lhmm_sur {
     bf16 *X, *Xt, *H1, *H1t, *H2, *H2t, *dY, *dYt, *dZ2, *dZ2t, *dZ1, *dZ1t;
     float *Z1, *Z2, *Y, *dYf, *dZ1f, *dZ2f, *part;
     float* part_k = nullptr;  // k-split partials of the weight gradients
+    float* part_c = nullptr;  // row-slice partials of the bias gradients
 };
 
 namespace {
@@ -473,6 +509,14 @@ void gemm(lhmm_sur* s, Gemm g) {
         return;
     }
     launch_gemm<EPI>(s, g, s->E);
+}
+
+// bias gradients: out[e][c] = sum over the rows of x[e] (both passes on the stream)
+void colsum(lhmm_sur* s, const float* x, int rows, int cols, long stride, float* out, long ostride) {
+    k_colsum_part<<<dim3((cols + 63) / 64, s->E, COLSUM_SLICES), dim3(64, 16), 0, s->stream>>>(x, rows, cols, stride,
+                                                                                              s->part_c);
+    const long n = (long)s->E * cols;
+    k_colsum_final<<<(unsigned)((n + 255) / 256), 256, 0, s->stream>>>(s->part_c, cols, s->E, out, ostride);
 }
 
 long szW1(const lhmm_sur* s) { return (long)s->nin_p * s->nh; }
@@ -627,6 +671,7 @@ int lhmm_sur_create(const lhmm_sur_params* p, const float* weights, void* stream
     rc = rc ? rc : sur_alloc(s, &s->dY, E * Bm * no);
     rc = rc ? rc : sur_alloc(s, &s->dYt, E * Bm * no);
     rc = rc ? rc : sur_alloc(s, &s->part, E * (Bm * no / 256 + 1));
+    rc = rc ? rc : sur_alloc(s, &s->part_c, (size_t)E * COLSUM_SLICES * std::max(nh, no));
     if (Bm >= 2 * KCHUNK) {
         const long mn = std::max(std::max(w1, w2), w3);
         rc = rc ? rc : sur_alloc(s, &s->part_k, E * ((Bm + KCHUNK - 1) / KCHUNK) * mn);
@@ -797,9 +842,9 @@ int lhmm_sur_train_step(lhmm_sur* s, const float* X, const float* T, int32_t B, 
     g.Cf = s->gW1; g.sC = szW1(s);
     gemm<EPI_F32>(s, g);
     // bias gradients
-    k_colsum<<<dim3((no + 63) / 64, E), dim3(64, 16), 0, s->stream>>>(s->dYf, Bp, no, (long)Bp * no, s->gb3, no);
-    k_colsum<<<dim3((nh + 63) / 64, E), dim3(64, 16), 0, s->stream>>>(s->dZ2f, Bp, nh, Bm * nh, s->gb2, nh);
-    k_colsum<<<dim3((nh + 63) / 64, E), dim3(64, 16), 0, s->stream>>>(s->dZ1f, Bp, nh, Bm * nh, s->gb1, nh);
+    colsum(s, s->dYf, Bp, no, (long)Bp * no, s->gb3, no);
+    colsum(s, s->dZ2f, Bp, nh, Bm * nh, s->gb2, nh);
+    colsum(s, s->dZ1f, Bp, nh, Bm * nh, s->gb1, nh);
     // Adam
     s->step += 1;
     const float c1 = 1.0f - powf(0.9f, (float)s->step), c2 = 1.0f - powf(0.999f, (float)s->step);
