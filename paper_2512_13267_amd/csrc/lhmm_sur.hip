@@ -36,27 +36,9 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int HIST = LHMM_SUR_HIST;  // gradient samples per feature vector
 
-// GELU and its derivative with erf by Abramowitz and Stegun's formula 7.1.26,
-// erf(x) = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p |x|), odd in x,
-// absolute error at most 1.5e-7: with x = z / sqrt(2), exp(-x^2) is also the
-// Gaussian factor of the derivative, so one hardware exponential serves both
-// (about a quarter of the instructions of the library erf and exp, in the
-// GEMM epilogues that the activations make VALU-bound).
-__device__ __forceinline__ float gauss_half(float z) {  // exp(-z^2 / 2)
-    return __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);  // log2(e) / 2
-}
-__device__ __forceinline__ float erf_as(float x, float e) {  // e = exp(-x^2)
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, fabsf(x), 1.0f));
-    const float poly =
-        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
-    return copysignf(1.0f - poly * e, x);
-}
-__device__ __forceinline__ float gelu_f(float z) {
-    return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f, gauss_half(z)));
-}
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
-    const float e = gauss_half(z);
-    return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f, e)) + z * 0.39894228040143268f * e;
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
 enum Epi {
