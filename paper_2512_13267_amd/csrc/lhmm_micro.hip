@@ -500,8 +500,23 @@ __global__ __launch_bounds__(256) void k_remove_mean(Ctx C) {
     real* c = (real*)C.c;
     __shared__ double red[3][256];
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < B.n; i += blockDim.x)
-        for (int k = 0; k < 3; ++k) acc[k] += (double)c[(long)k * N + B.off + i];
+    // thread t adds particles t, t + 256, ... in that order; four particles'
+    // loads are issued before their additions
+    const real* cb = c + B.off;
+    int i = threadIdx.x;
+    for (; i + 3 * 256 < B.n; i += 4 * 256) {
+        real v[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[u][k] = cb[(long)k * N + i + u * 256];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k] += (double)v[u][k];
+    }
+    for (; i < B.n; i += 256)
+        for (int k = 0; k < 3; ++k) acc[k] += (double)cb[(long)k * N + i];
     for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -510,8 +525,10 @@ __global__ __launch_bounds__(256) void k_remove_mean(Ctx C) {
         __syncthreads();
     }
     const real mean[3] = {(real)(red[0][0] / B.n), (real)(red[1][0] / B.n), (real)(red[2][0] / B.n)};
-    for (int i = threadIdx.x; i < B.n; i += blockDim.x)
-        for (int k = 0; k < 3; ++k) c[(long)k * N + B.off + i] -= mean[k];
+    real* cw = c + B.off;
+#pragma unroll 4
+    for (int j = threadIdx.x; j < B.n; j += 256)
+        for (int k = 0; k < 3; ++k) cw[(long)k * N + j] -= mean[k];
 }
 
 __global__ void k_zero_acc(Ctx C) {
