@@ -6,9 +6,13 @@ in 10-bead FENE chains; a constant in-plane traceless gradient per box with
 entries ~U(-0.5, 0.5)); single-precision particle state and pair forces,
 double-precision cells and stress sums.  A step is one velocity-Verlet step
 of every box (cell update, kick/drift, binning, pair + bond forces, kick,
-stress).  The timed region is one engine call of K steps (HIP-graph
-replays) on device-resident state; the metric is unordered DPD pairs within
-the cutoff evaluated per second (counted by the engine itself).
+stress).  Untimed set-up: 500 steps at rest relax the random start, the
+relaxed state is kept on the device, the timed call's graph is captured and
+replayed as warm-up, and the relaxed state is restored.  The timed region is
+then one engine call of K steps (HIP-graph replays) on device-resident
+state, the batch's first K steps under its gradients; the metric is
+unordered DPD pairs within the cutoff evaluated per second (counted by the
+engine itself).
 
 Secondary legs (same JSON line): the coupled reverse-Poiseuille LHMM run
 (plain batched DPD, macro steps/s) and the flow past a periodic array of
